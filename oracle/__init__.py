@@ -1,0 +1,197 @@
+"""CPU oracle for the PRNGD method -- TEST INFRASTRUCTURE ONLY.
+
+A plain sequential C implementation (``prngd_oracle.c``) of what the PRNGD
+fill computes, written from Demchik & Gulov, arXiv:1401.8230, Section 2 and
+Algorithm 1, wrapped here with ctypes.  Only ``tests/``, the smoke check and
+the benchmark's CPU-baseline leg may import this package; the product path
+never does.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+GEN_PHILOX = 0
+GEN_MRG32K3A = 1
+GEN_MIXED = 2
+GEN_ENUMERATE = 3
+
+M1 = 4294967087
+M2 = 4294944443
+
+
+class Stream(ctypes.Structure):
+    _fields_ = [
+        ("generator", ctypes.c_int),
+        ("w", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("stream", ctypes.c_uint32),
+        ("counter", ctypes.c_uint64),
+        ("a0", ctypes.c_uint64),
+        ("a", ctypes.c_uint64),
+        ("b0", ctypes.c_uint64),
+        ("b", ctypes.c_uint64),
+        ("D", ctypes.c_uint64),
+        ("S", ctypes.c_double),
+        ("mrg", ctypes.c_uint32 * 6),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load the oracle library, building it only if it is not built yet."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        sp = ctypes.POINTER(Stream)
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_philox_words.argtypes = [ctypes.c_uint64, ctypes.c_uint32,
+                                       ctypes.c_uint64, ctypes.c_uint64, u32p]
+        L.orc_mrg_jump.argtypes = [u32p, u64p, ctypes.c_int]
+        L.orc_mrg_outputs.argtypes = [u32p, ctypes.c_uint64, u32p]
+        L.orc_mrg_matpow.argtypes = [ctypes.c_int, u64p, ctypes.c_int, u64p]
+        L.orc_mrg_stream_base.argtypes = [ctypes.c_uint64, ctypes.c_uint32, u32p]
+        L.orc_init.argtypes = [sp, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                               ctypes.c_uint32, ctypes.c_uint64]
+        L.orc_init.restype = ctypes.c_int
+        L.orc_init_ranges.argtypes = [sp, ctypes.c_int, ctypes.c_uint64,
+                                      ctypes.c_uint64, ctypes.c_uint64,
+                                      ctypes.c_uint64]
+        L.orc_init_ranges.restype = ctypes.c_int
+        L.orc_pair.argtypes = [sp, ctypes.c_uint64, u64p, u64p]
+        L.orc_accept.argtypes = [sp, ctypes.c_uint64]
+        L.orc_accept.restype = ctypes.c_int
+        L.orc_map.argtypes = [sp, ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_map.restype = ctypes.c_double
+        L.orc_fill.argtypes = [sp, ctypes.c_uint64, dp, u64p]
+        L.orc_scale.argtypes = [ctypes.c_int, ctypes.c_uint64]
+        L.orc_scale.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _ptr(arr, ctype):
+    return arr.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _limbs(e):
+    e = int(e)
+    limbs = []
+    while e:
+        limbs.append(e & (2**64 - 1))
+        e >>= 64
+    limbs = limbs or [0]
+    return np.array(limbs, dtype=np.uint64)
+
+
+def philox4x32_10(ctr, key):
+    c = np.array(ctr, dtype=np.uint32)
+    k = np.array(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32),
+                            _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def philox_words(seed, stream, first, count):
+    out = np.zeros(count, dtype=np.uint32)
+    lib().orc_philox_words(seed, stream, first, count, _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def mrg_outputs(state, count):
+    """``count`` outputs starting from the six-word ``state``; returns
+    (outputs, new_state)."""
+    st = np.array(state, dtype=np.uint32)
+    out = np.zeros(count, dtype=np.uint32)
+    lib().orc_mrg_outputs(_ptr(st, ctypes.c_uint32), count,
+                          _ptr(out, ctypes.c_uint32))
+    return out, st
+
+
+def mrg_jump(state, exponent):
+    st = np.array(state, dtype=np.uint32)
+    e = _limbs(exponent)
+    lib().orc_mrg_jump(_ptr(st, ctypes.c_uint32), _ptr(e, ctypes.c_uint64), len(e))
+    return st
+
+
+def mrg_matpow(component, exponent):
+    e = _limbs(exponent)
+    out = np.zeros(9, dtype=np.uint64)
+    lib().orc_mrg_matpow(component, _ptr(e, ctypes.c_uint64), len(e),
+                         _ptr(out, ctypes.c_uint64))
+    return out.reshape(3, 3)
+
+
+def mrg_stream_base(seed, stream):
+    out = np.zeros(6, dtype=np.uint32)
+    lib().orc_mrg_stream_base(seed, stream, _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def scale(w, D):
+    return lib().orc_scale(w, D)
+
+
+class PRNGD:
+    """One oracle stream (sequential, single-threaded)."""
+
+    def __init__(self, generator, w, seed=0, stream=0, counter=0, ranges=None):
+        self.s = Stream()
+        if ranges is not None:
+            a0, a, b0, b = ranges
+            rc = lib().orc_init_ranges(ctypes.byref(self.s), w, a0, a, b0, b)
+        else:
+            rc = lib().orc_init(ctypes.byref(self.s), generator, w, seed, stream,
+                                counter)
+        if rc != 0:
+            raise ValueError("invalid oracle stream parameters")
+
+    @property
+    def counter(self):
+        return int(self.s.counter)
+
+    @counter.setter
+    def counter(self, value):
+        self.s.counter = value
+
+    @property
+    def D(self):
+        return int(self.s.D)
+
+    @property
+    def S(self):
+        return float(self.s.S)
+
+    @property
+    def ranges(self):
+        return int(self.s.a0), int(self.s.a), int(self.s.b0), int(self.s.b)
+
+    def pair(self, p):
+        x1 = ctypes.c_uint64()
+        x2 = ctypes.c_uint64()
+        lib().orc_pair(ctypes.byref(self.s), p, ctypes.byref(x1), ctypes.byref(x2))
+        return int(x1.value), int(x2.value)
+
+    def accept(self, x1):
+        return bool(lib().orc_accept(ctypes.byref(self.s), x1))
+
+    def map(self, x1, x2):
+        return lib().orc_map(ctypes.byref(self.s), x1, x2)
+
+    def fill(self, n, with_index=False):
+        out = np.empty(n, dtype=np.float64)
+        idx = np.empty(n, dtype=np.uint64) if with_index else None
+        lib().orc_fill(ctypes.byref(self.s), n, _ptr(out, ctypes.c_double),
+                       _ptr(idx, ctypes.c_uint64) if with_index else None)
+        return (out, idx) if with_index else out

@@ -1,0 +1,105 @@
+/*
+ * prngd_oracle.h -- CPU oracle for the PRNGD method.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, sequential, obviously
+ * checkable CPU implementation of what the PRNGD fill computes, written from
+ * Demchik & Gulov, "Increasing precision of uniform pseudorandom number
+ * generators" (arXiv:1401.8230), Section 2 and Algorithm 1.  Only the tests,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or constant generator with the GPU library.
+ *
+ * Parity status of each part (what pins it is listed in the tests):
+ *   - Philox4x32-10 block function: pinned against an independent library
+ *     implementation (rocRAND, built from its source headers for the host)
+ *     and by counter-carry / split invariants.
+ *   - MRG32k3a: pinned by stepping == matrix jump-ahead, by the full-period
+ *     identity A^(m^3-1) == I for both components, and against rocRAND.
+ *   - Accept/reject (Section 2, rejection intervals and the discrete
+ *     degeneration to x1 in {a0, a}): exhaustive enumeration at w = 8,
+ *     rejection fraction exactly 2/2^w, brute-force interval checks.
+ *   - Affine map, Eq. (5)/(6): endpoints, closed form within the rounding
+ *     bound (exact rationals), each grid value exactly once at w = 8.
+ *
+ * Conventions that the paper leaves open (the readings are stated here and
+ * in the design notes):
+ *   - Generator words are unsigned integers; the paper's w-bit PRN x in
+ *     [0, 1) with step k = 2^-w is the integer X = x / k.  All formulas below
+ *     are the paper's formulas scaled by 2^w, which changes no ratio.
+ *   - A rejected pair consumes both of its words ("take next pair").
+ *   - The constant part of Eq. (5) is folded into one FP64 constant
+ *     S = RN((1 - k^2) / D); the output is RN(RN(N) * S), clamped below 1.
+ */
+#ifndef PRNGD_ORACLE_H
+#define PRNGD_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Base generators known to the oracle. */
+enum {
+    ORC_GEN_PHILOX    = 0, /* pair p = (word 2p, word 2p+1) >> (32 - w)       */
+    ORC_GEN_MRG32K3A  = 1, /* pair p = (output 2p, output 2p+1), w = 32       */
+    ORC_GEN_MIXED     = 2, /* pair p = (Philox word p, MRG32k3a output p)      */
+    ORC_GEN_ENUMERATE = 3  /* pair p = ((p >> w) mod 2^w, p mod 2^w), tests    */
+};
+
+/* One PRNGD stream: which generator, the ranges of x1 and x2 (integer
+ * units), and the position (pairs consumed so far, rejected ones included). */
+typedef struct {
+    int      generator;
+    int      w;        /* resolution k = 2^-w                          */
+    uint64_t seed;
+    uint32_t stream;
+    uint64_t counter;  /* pairs consumed                               */
+    uint64_t a0, a;    /* x1 in [a0, a]                                */
+    uint64_t b0, b;    /* x2 in [b0, b]                                */
+    uint64_t D;        /* (a - a0 - 2) * 2^w + (b - b0)                */
+    double   S;        /* RN((1 - 2^-2w) / D)                          */
+    uint32_t mrg[6];   /* MRG32k3a state at stream position 0          */
+} orc_stream;
+
+/* ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ---------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                       uint32_t out[4]);
+/* Words [first, first + count) of the Philox stream (seed, stream):
+ * word j is lane j mod 4 of block j / 4, block b has counter
+ * (b mod 2^32, b / 2^32, 0, stream) and key (seed mod 2^32, seed / 2^32). */
+void orc_philox_words(uint64_t seed, uint32_t stream, uint64_t first,
+                      uint64_t count, uint32_t *out);
+
+/* ---- MRG32k3a (L'Ecuyer, Operations Research 47(1), 1999) ------------- */
+/* state: (s10, s11, s12, s20, s21, s22); exponent: little-endian 64-bit
+ * limbs, nlimbs <= 3. */
+void orc_mrg_jump(uint32_t state[6], const uint64_t *exponent, int nlimbs);
+void orc_mrg_outputs(uint32_t state[6], uint64_t count, uint32_t *out);
+void orc_mrg_matpow(int component, const uint64_t *exponent, int nlimbs,
+                    uint64_t out[9]);
+/* State at position 0 of stream (seed, stream): the six-fold 12345 state
+ * advanced by seed * 2^127 + stream * 2^76 steps. */
+void orc_mrg_stream_base(uint64_t seed, uint32_t stream, uint32_t out[6]);
+
+/* ---- PRNGD ------------------------------------------------------------- */
+/* 0 on success, -1 on invalid parameters. */
+int orc_init(orc_stream *s, int generator, int w, uint64_t seed,
+             uint32_t stream, uint64_t counter);
+/* A stream with explicit ranges and no generator (pairs are supplied by
+ * the caller to orc_accept / orc_map). */
+int orc_init_ranges(orc_stream *s, int w, uint64_t a0, uint64_t a,
+                    uint64_t b0, uint64_t b);
+void orc_pair(const orc_stream *s, uint64_t p, uint64_t *x1, uint64_t *x2);
+int orc_accept(const orc_stream *s, uint64_t x1);
+double orc_map(const orc_stream *s, uint64_t x1, uint64_t x2);
+/* The next n outputs of the stream, in order; advances s->counter.
+ * accepted_index, if not NULL, receives the pair index of each output. */
+void orc_fill(orc_stream *s, uint64_t n, double *out,
+              uint64_t *accepted_index);
+/* Exact RN((2^2w - 1) / (D * 2^2w)), the folded constant of Eq. (5). */
+double orc_scale(int w, uint64_t D);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
