@@ -1,0 +1,203 @@
+/*
+ * prngd.h -- C ABI of libprngd, an MI355X (gfx950) library that fills FP64
+ * device buffers with PRNGD uniforms: Demchik & Gulov, "Increasing precision
+ * of uniform pseudorandom number generators", arXiv:1401.8230.
+ *
+ * What one output is (Section 2 of the paper, in integer units):
+ *   - A pair (x1, x2) of w-bit integers is drawn from a base generator
+ *     (the paper's z = x1 + k x2 with k = 2^-w, Eq. (1)).
+ *   - The pair is rejected if x1 lies in the rejection intervals
+ *     x1 < a0 + k(b - b0) or x1 > a - k(b - b0) (Section 2); for integer x1
+ *     with 1 <= b - b0 < 2^w these are exactly x1 = a0 and x1 = a ("drop
+ *     such values and take next pair").  A rejected pair consumes both
+ *     words.
+ *   - An accepted pair is mapped by Eq. (5):
+ *         N  = (x1 - a0 - 1) 2^w + (x2 - b0)         exact 64-bit integer
+ *         D  = (a - a0 - 2) 2^w + (b - b0)
+ *         S  = RN((1 - 2^-2w) / D)                    computed exactly once
+ *         z' = RN(RN(N) * S), and z' = 1 - 2^-53 if that rounds to 1.0
+ *     so z' lies in [0, 1) with z' = 0 for (a0 + 1, b0).  All roundings are
+ *     IEEE round-to-nearest-even; this order of operations is part of the
+ *     definition (other orders differ in the last bit).
+ *   - Outputs of a stream appear in the order of their pairs.  The stream
+ *     position ("pair counter") counts pairs consumed, rejected included.
+ *
+ * Base generators and their word layout:
+ *   PRNGD_PHILOX4X32_10: Philox4x32-10 (Salmon et al., SC'11) with key
+ *       (seed mod 2^32, seed / 2^32) and block counter
+ *       (b mod 2^32, b / 2^32, 0, stream_id); word j is lane j mod 4 of
+ *       block j / 4.  Pair p = (word 2p >> (32 - w), word 2p+1 >> (32 - w)),
+ *       x1, x2 in [0, 2^w - 1], 2 <= w <= 32.
+ *   PRNGD_MRG32K3A: MRG32k3a (L'Ecuyer 1999), integer outputs in
+ *       [1, 4294967087].  Stream (seed, stream_id) starts from the state
+ *       12345 (six times) advanced by seed * 2^127 + stream_id * 2^76 steps.
+ *       Pair p = (output 2p, output 2p + 1); w = 32.
+ *   PRNGD_PHILOX_X1_MRG32K3A_X2: the paper's general case of two different
+ *       generators: x1 = Philox word p in [0, 2^32 - 1], x2 = MRG32k3a output
+ *       p in [1, 4294967087]; w = 32.
+ *   PRNGD_ENUMERATE: a test generator, pair p = ((p >> w) mod 2^w,
+ *       p mod 2^w), 2 <= w <= 16; it visits every pair once per 2^2w.
+ *
+ * Conventions for every call:
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Device pointers are plain device addresses owned by the caller
+ *     (for example torch tensors); the library never frees them.
+ *   - Calls return prngd_status_t; argument errors are detected on the
+ *     host before anything is enqueued.  Work is enqueued asynchronously
+ *     unless a call says it synchronises.
+ *   - A handle must not be used from two host threads at once.
+ *   - Errors detected on the device (a stalled cross-block scan, which a
+ *     correct launch never produces) are reported by the next call on any
+ *     handle as PRNGD_ERR_DEVICE.
+ */
+#ifndef PRNGD_H
+#define PRNGD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PRNGD_OK = 0,
+    PRNGD_ERR_INVALID_ARGUMENT = 1,
+    PRNGD_ERR_UNSUPPORTED = 2,
+    PRNGD_ERR_OUT_OF_MEMORY = 3,
+    PRNGD_ERR_HIP = 4,
+    PRNGD_ERR_DEVICE = 5
+} prngd_status_t;
+
+typedef enum {
+    PRNGD_PHILOX4X32_10 = 0,
+    PRNGD_MRG32K3A = 1,
+    PRNGD_PHILOX_X1_MRG32K3A_X2 = 2,
+    PRNGD_ENUMERATE = 3
+} prngd_generator_t;
+
+typedef struct prngd_handle_s *prngd_handle_t;
+typedef struct prngd_plan_s *prngd_plan_t;
+
+/* One fill request of a batch: the next n outputs of handle h into out. */
+typedef struct {
+    prngd_handle_t h;
+    uint64_t n;
+    double *out;
+} prngd_request_t;
+
+/* Launch shape of the fill kernels.  None of these change the output
+ * bytes; they only change speed.  Zero fields mean "library default". */
+typedef struct {
+    uint32_t pairs_per_lane;  /* 4, 8, 16 or 32 pairs per thread per tile   */
+    uint32_t blocks_per_cu;   /* persistent grid = blocks_per_cu * CUs      */
+    uint32_t store_mode;      /* 0 default, 1 plain 8-byte, 2 nontemporal   */
+    uint32_t slack_mode;      /* 0 plan rejections ahead, 1 plan none (the  */
+                              /* tail path then absorbs every rejection)    */
+} prngd_tuning_t;
+
+/* Human-readable name of a status code (static storage). */
+const char *prngd_status_string(prngd_status_t status);
+
+/* Message of the last error returned to this host thread ("" if none). */
+const char *prngd_last_error(void);
+
+/*
+ * Validate (generator, k, min, max) and return the constants of Eq. (5)
+ * without touching a GPU.  Algorithm 1 of the paper is PRNGD(k, min, max):
+ * k must be exactly 2^-w, and [min, max] must be the extreme values the
+ * generator's x1 can take (its natural range for that w): Philox and
+ * ENUMERATE [0, 2^w - 1], MRG32k3a [1, 4294967087], mixed [0, 2^32 - 1].
+ * Any output pointer may be NULL.
+ * Errors: PRNGD_ERR_INVALID_ARGUMENT (k not a power 2^-w, w out of range
+ * for the generator, range mismatch), PRNGD_ERR_UNSUPPORTED (unknown
+ * generator).
+ */
+prngd_status_t prngd_describe(prngd_generator_t generator, double k,
+                              uint64_t min, uint64_t max, uint32_t *w,
+                              uint64_t *b0, uint64_t *b, uint64_t *D,
+                              double *S);
+
+/*
+ * Create a PRNGD stream handle on the current HIP device: Algorithm 1's
+ * PRNGD(k, min, max) with a base generator and a seed.  Stream id 0, pair
+ * counter 0.  The library allocates the handle and its device state (two
+ * 64-bit counters) and owns both until prngd_destroy.
+ * Errors: as prngd_describe; PRNGD_ERR_INVALID_ARGUMENT for a NULL
+ * out_handle; PRNGD_ERR_OUT_OF_MEMORY; PRNGD_ERR_HIP.
+ */
+prngd_status_t prngd_create(uint64_t seed, prngd_generator_t generator,
+                            double k, uint64_t min, uint64_t max,
+                            prngd_handle_t *out_handle);
+
+/* Wait for the handle's outstanding work, then free it.  NULL is a no-op. */
+prngd_status_t prngd_destroy(prngd_handle_t h);
+
+/*
+ * Move the handle to (stream_id, pair_counter): the next fill starts with
+ * pair pair_counter of substream stream_id (Philox counter word 3; MRG32k3a
+ * jump of stream_id * 2^76).  Enqueued on `stream` after the handle's
+ * previous work.  Errors: PRNGD_ERR_INVALID_ARGUMENT (NULL handle, handle
+ * bound to a live plan), PRNGD_ERR_HIP.
+ */
+prngd_status_t prngd_set_position(prngd_handle_t h, uint32_t stream_id,
+                                  uint64_t pair_counter, void *stream);
+
+/*
+ * Read the handle's position (a checkpoint: a new handle with the same
+ * seed, generator and position continues the same sequence).
+ * SYNCHRONISES `stream` after the handle's previous work.
+ */
+prngd_status_t prngd_get_position(prngd_handle_t h, uint32_t *stream_id,
+                                  uint64_t *pair_counter, void *stream);
+
+/*
+ * out[0 .. n) = the next n outputs of the handle, in sequential order, and
+ * the handle's pair counter advances past the pair of out[n - 1].
+ * `out` is caller-owned device memory, 8-byte aligned, at least 8n bytes.
+ * n = 0 is a no-op.  Asynchronous on `stream`; fills of one handle are
+ * ordered (a fill on a different stream first waits for the handle's
+ * previous work).  Errors: PRNGD_ERR_INVALID_ARGUMENT (NULL handle, NULL or
+ * misaligned out with n > 0, handle bound to a live plan), PRNGD_ERR_HIP,
+ * PRNGD_ERR_DEVICE.
+ */
+prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out,
+                          void *stream);
+
+/*
+ * Fill several handles in one persistent launch: request i receives
+ * exactly what prngd_fill(reqs[i].h, reqs[i].n, reqs[i].out) would give,
+ * bit for bit, and each handle advances as it would.  `reqs` is read
+ * before the call returns.  All handles must be distinct and share the
+ * generator, k, min and max; requests with n = 0 are skipped.
+ * Errors: PRNGD_ERR_INVALID_ARGUMENT (count = 0 with reqs NULL, a NULL or
+ * repeated handle, mixed configurations, bad out), PRNGD_ERR_HIP.
+ */
+prngd_status_t prngd_fill_batch(const prngd_request_t *reqs, uint32_t count,
+                                void *stream);
+
+/*
+ * A resident batch: the request descriptors are uploaded once and the
+ * persistent fill kernel is captured in a HIP graph.  Each
+ * prngd_plan_launch replays the graph and is equivalent to
+ * prngd_fill_batch(reqs, count) with the handles' positions at that
+ * moment.  While the plan lives, its handles may only be advanced through
+ * it (other fills on them return PRNGD_ERR_INVALID_ARGUMENT).  A plan must
+ * not be launched concurrently with itself.
+ */
+prngd_status_t prngd_plan_create(const prngd_request_t *reqs, uint32_t count,
+                                 prngd_plan_t *out_plan);
+prngd_status_t prngd_plan_launch(prngd_plan_t plan, void *stream);
+prngd_status_t prngd_plan_destroy(prngd_plan_t plan);
+
+/* Process-wide launch shape for one (generator, w); tuning never changes
+ * output bytes.  prngd_get_tuning returns the shape in effect. */
+prngd_status_t prngd_set_tuning(prngd_generator_t generator, uint32_t w,
+                                const prngd_tuning_t *tuning);
+prngd_status_t prngd_get_tuning(prngd_generator_t generator, uint32_t w,
+                                prngd_tuning_t *tuning);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PRNGD_H */

@@ -1,0 +1,1102 @@
+// prngd_runtime.cpp -- host runtime of libprngd: validation, the constants
+// of Eq. (5), device state, launch planning, batches, graphs, tuning.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/prngd.h"
+#include "prngd_internal.hpp"
+
+namespace prngd {
+const void *fill_kernel_for(uint32_t fam, uint32_t ppl);
+hipError_t launch_fill(const void *kernel, uint32_t grid, const LaunchArgs &args,
+                       hipStream_t stream);
+hipError_t launch_set_counter(uint64_t *slot, uint64_t value, hipStream_t stream);
+hipError_t launch_zero_words(uint64_t *p, size_t n, hipStream_t stream);
+}  // namespace prngd
+
+using namespace prngd;
+
+namespace {
+
+// ----------------------------------------------------------------- errors
+thread_local std::string g_last_error;
+
+prngd_status_t fail(prngd_status_t st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+prngd_status_t hip_fail(hipError_t e, const char *what)
+{
+    return fail(PRNGD_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess)                           \
+            return hip_fail(e_, #expr);                 \
+    } while (0)
+
+std::recursive_mutex g_mutex;
+
+// ------------------------------------------------------------ constants
+constexpr uint64_t kM1 = 4294967087ull;
+constexpr uint64_t kM2 = 4294944443ull;
+
+struct Config {
+    uint32_t fam;
+    uint32_t w;
+    uint64_t a0, a, b0, b;
+    uint64_t D;
+    double S;
+};
+
+// RN((1 - 2^-2w) / D): long division of (2^2w - 1) by D to 64 significant
+// bits plus a sticky bit, rounded half-to-even to 53 bits, scaled by 2^-2w.
+// (2^2w - 1) > D for every valid configuration, so the quotient is >= 1.
+double folded_constant(uint32_t w, uint64_t D)
+{
+    const uint64_t num = w == 32 ? ~uint64_t(0) : (uint64_t(1) << (2 * w)) - 1;
+    uint64_t q = num / D;
+    uint64_t r = num % D;
+    int bits = 64 - __builtin_clzll(q);
+    int frac = 0;
+    while (bits + frac < 64) {
+        const unsigned __int128 r2 = static_cast<unsigned __int128>(r) << 1;
+        const bool bit = r2 >= D;
+        r = static_cast<uint64_t>(bit ? r2 - D : r2);
+        q = (q << 1) | uint64_t(bit);
+        ++frac;
+    }
+    uint64_t keep = q >> 11;
+    const uint64_t dropped = q & 0x7FFu;
+    const bool sticky = r != 0;
+    if (dropped > 0x400u || (dropped == 0x400u && (sticky || (keep & 1u))))
+        ++keep;
+    return std::ldexp(static_cast<double>(keep), 11 - frac - int(2 * w));
+}
+
+prngd_status_t make_config(prngd_generator_t gen, double k, uint64_t min, uint64_t max,
+                           Config *c)
+{
+    if (gen < PRNGD_PHILOX4X32_10 || gen > PRNGD_ENUMERATE)
+        return fail(PRNGD_ERR_UNSUPPORTED, "unknown generator %d", int(gen));
+    if (!(k > 0) || !std::isfinite(k))
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "k must be 2^-w");
+    int e = 0;
+    const double m = std::frexp(k, &e);
+    if (m != 0.5)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "k = %a is not a power of two", k);
+    const int w = 1 - e;
+    const uint32_t fams[] = {FAM_PHILOX, FAM_MRG, FAM_MIXED, FAM_ENUM};
+    c->fam = fams[gen];
+    c->w = uint32_t(w);
+    const int wmax = gen == PRNGD_ENUMERATE ? 16 : 32;
+    const int wmin = (gen == PRNGD_MRG32K3A || gen == PRNGD_PHILOX_X1_MRG32K3A_X2) ? 32 : 2;
+    if (w < wmin || w > wmax)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "k = 2^-%d out of range for this generator", w);
+    const uint64_t top = (uint64_t(1) << w) - 1;
+    switch (gen) {
+    case PRNGD_PHILOX4X32_10:
+    case PRNGD_ENUMERATE:
+        c->a0 = 0; c->a = top; c->b0 = 0; c->b = top;
+        break;
+    case PRNGD_MRG32K3A:
+        c->a0 = 1; c->a = kM1; c->b0 = 1; c->b = kM1;
+        break;
+    default:
+        c->a0 = 0; c->a = top; c->b0 = 1; c->b = kM1;
+        break;
+    }
+    if (min != c->a0 || max != c->a)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT,
+                    "[min, max] = [%llu, %llu] must be the generator's range [%llu, %llu]",
+                    (unsigned long long)min, (unsigned long long)max,
+                    (unsigned long long)c->a0, (unsigned long long)c->a);
+    c->D = (c->a - c->a0 - 2) * (uint64_t(1) << w) + (c->b - c->b0);
+    c->S = folded_constant(c->w, c->D);
+    return PRNGD_OK;
+}
+
+// ---------------------------------------------------- MRG32k3a matrices
+struct Mat {
+    uint64_t e[9];
+};
+
+Mat mat_identity()
+{
+    return Mat{{1, 0, 0, 0, 1, 0, 0, 0, 1}};
+}
+
+Mat mat_mul(const Mat &x, const Mat &y, uint64_t m)
+{
+    Mat z;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            unsigned __int128 s = 0;
+            for (int l = 0; l < 3; ++l)
+                s += static_cast<unsigned __int128>(x.e[3 * i + l]) * y.e[3 * l + j];
+            z.e[3 * i + j] = static_cast<uint64_t>(s % m);
+        }
+    return z;
+}
+
+// The companion matrices of the two recurrences of L'Ecuyer's MRG32k3a
+// acting on (x[n-3], x[n-2], x[n-1]).
+Mat mrg_step_matrix(int comp)
+{
+    if (comp == 0)
+        return Mat{{0, 1, 0, 0, 0, 1, kM1 - 810728, 1403580, 0}};
+    return Mat{{0, 1, 0, 0, 0, 1, kM2 - 1370589, 0, 527612}};
+}
+
+Mat mat_pow(Mat base, uint64_t e, uint64_t m)
+{
+    Mat r = mat_identity();
+    while (e) {
+        if (e & 1)
+            r = mat_mul(r, base, m);
+        base = mat_mul(base, base, m);
+        e >>= 1;
+    }
+    return r;
+}
+
+Mat mat_pow2k(Mat base, int k, uint64_t m)   // base^(2^k)
+{
+    for (int i = 0; i < k; ++i)
+        base = mat_mul(base, base, m);
+    return base;
+}
+
+void mat_apply(const Mat &M, uint32_t *v, uint64_t m)
+{
+    uint64_t r[3];
+    for (int i = 0; i < 3; ++i) {
+        unsigned __int128 s = 0;
+        for (int l = 0; l < 3; ++l)
+            s += static_cast<unsigned __int128>(M.e[3 * i + l]) * v[l];
+        r[i] = static_cast<uint64_t>(s % m);
+    }
+    for (int i = 0; i < 3; ++i)
+        v[i] = uint32_t(r[i]);
+}
+
+// Powers A^(2^127 * 2^i) (i < 64) and A^(2^76 * 2^i) (i < 32) per component.
+struct StreamJumps {
+    Mat seq[2][64];
+    Mat sub[2][32];
+    StreamJumps()
+    {
+        for (int c = 0; c < 2; ++c) {
+            const uint64_t m = c == 0 ? kM1 : kM2;
+            Mat p = mat_pow2k(mrg_step_matrix(c), 76, m);
+            for (int i = 0; i < 32; ++i) {
+                sub[c][i] = p;
+                p = mat_mul(p, p, m);
+            }
+            p = mat_pow2k(mrg_step_matrix(c), 127, m);
+            for (int i = 0; i < 64; ++i) {
+                seq[c][i] = p;
+                p = mat_mul(p, p, m);
+            }
+        }
+    }
+};
+
+const StreamJumps &stream_jumps()
+{
+    static const StreamJumps j;
+    return j;
+}
+
+// State at position 0 of substream (seed, stream): 12345 six times advanced
+// by seed * 2^127 + stream * 2^76 steps (L'Ecuyer et al. 2002 streams and
+// substreams).
+void mrg_stream_base(uint64_t seed, uint32_t stream, uint32_t out[6])
+{
+    const StreamJumps &J = stream_jumps();
+    for (int i = 0; i < 6; ++i)
+        out[i] = 12345u;
+    for (int c = 0; c < 2; ++c) {
+        const uint64_t m = c == 0 ? kM1 : kM2;
+        for (int i = 0; i < 64; ++i)
+            if ((seed >> i) & 1u)
+                mat_apply(J.seq[c][i], out + 3 * c, m);
+        for (int i = 0; i < 32; ++i)
+            if ((stream >> i) & 1u)
+                mat_apply(J.sub[c][i], out + 3 * c, m);
+    }
+}
+
+void put_entry(uint32_t *dst, const Mat &m1, const Mat &m2)
+{
+    for (int i = 0; i < 9; ++i) {
+        dst[i] = uint32_t(m1.e[i]);
+        dst[9 + i] = uint32_t(m2.e[i]);
+    }
+}
+
+// Jump tables of the MRG kernels for `r` MRG outputs per pair and
+// pairs-per-lane `ppl`: thread[tid] = A^(r ppl tid), window[d][v] =
+// A^(r T v 256^d) with T = 256 ppl.
+void build_mrg_tables(uint32_t r, uint32_t ppl, std::vector<uint32_t> &thread,
+                      std::vector<uint32_t> &window)
+{
+    thread.assign(size_t(kBlockThreads) * kMrgMatWords, 0);
+    window.assign(size_t(kMrgDigits) * 256 * kMrgMatWords, 0);
+    const uint64_t T = uint64_t(kBlockThreads) * ppl;
+    Mat step[2], cur[2];
+    for (int c = 0; c < 2; ++c) {
+        const uint64_t m = c == 0 ? kM1 : kM2;
+        step[c] = mat_pow(mrg_step_matrix(c), uint64_t(r) * ppl, m);
+        cur[c] = mat_identity();
+    }
+    for (int t = 0; t < kBlockThreads; ++t) {
+        put_entry(&thread[size_t(t) * kMrgMatWords], cur[0], cur[1]);
+        cur[0] = mat_mul(cur[0], step[0], kM1);
+        cur[1] = mat_mul(cur[1], step[1], kM2);
+    }
+    Mat digit_base[2];
+    for (int c = 0; c < 2; ++c)
+        digit_base[c] = mat_pow(mrg_step_matrix(c), uint64_t(r) * T, c == 0 ? kM1 : kM2);
+    for (int d = 0; d < kMrgDigits; ++d) {
+        Mat acc[2] = {mat_identity(), mat_identity()};
+        for (int v = 0; v < 256; ++v) {
+            put_entry(&window[(size_t(d) * 256 + v) * kMrgMatWords], acc[0], acc[1]);
+            acc[0] = mat_mul(acc[0], digit_base[0], kM1);
+            acc[1] = mat_mul(acc[1], digit_base[1], kM2);
+        }
+        // digit_base <- digit_base^256
+        for (int c = 0; c < 2; ++c)
+            digit_base[c] = mat_pow2k(digit_base[c], 8, c == 0 ? kM1 : kM2);
+    }
+}
+
+// ---------------------------------------------------------- device info
+struct DeviceInfo {
+    int cus = 0;
+    uint32_t *error_host = nullptr;      // mapped pinned word
+    uint32_t *error_dev = nullptr;
+    std::vector<uint64_t *> slot_chunks;
+    std::vector<uint64_t *> clean_slots;   // zero since their chunk was cleared
+    std::vector<uint64_t *> free_slots;    // returned by destroyed handles
+    std::map<std::pair<uint32_t, uint32_t>, std::pair<uint32_t *, uint32_t *>> mrg_tables;
+    std::map<const void *, int> occupancy;
+};
+
+std::map<int, DeviceInfo> g_devices;
+
+prngd_status_t device_info(int dev, DeviceInfo **out)
+{
+    auto it = g_devices.find(dev);
+    if (it != g_devices.end()) {
+        *out = &it->second;
+        return PRNGD_OK;
+    }
+    DeviceInfo d;
+    HIP_TRY(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    void *p = nullptr;
+    HIP_TRY(hipHostMalloc(&p, 64, hipHostMallocMapped | hipHostMallocCoherent));
+    d.error_host = static_cast<uint32_t *>(p);
+    *d.error_host = 0;
+    void *dp = nullptr;
+    HIP_TRY(hipHostGetDevicePointer(&dp, p, 0));
+    d.error_dev = static_cast<uint32_t *>(dp);
+    *out = &g_devices.emplace(dev, std::move(d)).first->second;
+    return PRNGD_OK;
+}
+
+prngd_status_t check_device_errors(DeviceInfo *d)
+{
+    const uint32_t e = __atomic_load_n(d->error_host, __ATOMIC_ACQUIRE);
+    if (e) {
+        __atomic_store_n(d->error_host, 0u, __ATOMIC_RELEASE);
+        return fail(PRNGD_ERR_DEVICE, "a previous fill reported device error 0x%x", e);
+    }
+    return PRNGD_OK;
+}
+
+// Position slots (two 64-bit counters) come from 4096-slot chunks; a slot
+// handed out again after its handle was destroyed is zeroed first.
+prngd_status_t alloc_slot(DeviceInfo *d, uint64_t **slot)
+{
+    if (d->clean_slots.empty() && d->free_slots.empty()) {
+        constexpr size_t kChunk = 4096;
+        void *p = nullptr;
+        HIP_TRY(hipMalloc(&p, kChunk * 2 * sizeof(uint64_t)));
+        HIP_TRY(hipMemset(p, 0, kChunk * 2 * sizeof(uint64_t)));
+        HIP_TRY(hipDeviceSynchronize());
+        uint64_t *base = static_cast<uint64_t *>(p);
+        d->slot_chunks.push_back(base);
+        for (size_t i = kChunk; i-- > 0;)
+            d->clean_slots.push_back(base + 2 * i);
+    }
+    if (!d->clean_slots.empty()) {
+        *slot = d->clean_slots.back();
+        d->clean_slots.pop_back();
+        return PRNGD_OK;
+    }
+    uint64_t *s = d->free_slots.back();
+    const uint64_t zero[2] = {0, 0};
+    HIP_TRY(hipMemcpy(s, zero, sizeof zero, hipMemcpyHostToDevice));
+    d->free_slots.pop_back();
+    *slot = s;
+    return PRNGD_OK;
+}
+
+prngd_status_t mrg_tables_for(DeviceInfo *d, uint32_t r, uint32_t ppl, const uint32_t **thread,
+                              const uint32_t **window)
+{
+    auto key = std::make_pair(r, ppl);
+    auto it = d->mrg_tables.find(key);
+    if (it == d->mrg_tables.end()) {
+        std::vector<uint32_t> th, wi;
+        build_mrg_tables(r, ppl, th, wi);
+        void *pt = nullptr, *pw = nullptr;
+        HIP_TRY(hipMalloc(&pt, th.size() * 4));
+        HIP_TRY(hipMalloc(&pw, wi.size() * 4));
+        HIP_TRY(hipMemcpy(pt, th.data(), th.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(pw, wi.data(), wi.size() * 4, hipMemcpyHostToDevice));
+        it = d->mrg_tables.emplace(key, std::make_pair(static_cast<uint32_t *>(pt),
+                                                       static_cast<uint32_t *>(pw))).first;
+    }
+    *thread = it->second.first;
+    *window = it->second.second;
+    return PRNGD_OK;
+}
+
+// ---------------------------------------------------------------- tuning
+std::map<std::pair<uint32_t, uint32_t>, prngd_tuning_t> g_tuning;
+
+prngd_tuning_t tuning_for(uint32_t fam, uint32_t w)
+{
+    prngd_tuning_t t{};
+    auto it = g_tuning.find(std::make_pair(fam, w));
+    if (it != g_tuning.end())
+        t = it->second;
+    const bool philox = fam == FAM_PHILOX || fam == FAM_ENUM;
+    if (t.pairs_per_lane == 0)
+        t.pairs_per_lane = philox ? 16 : 8;
+    return t;
+}
+
+bool valid_ppl(uint32_t fam, uint32_t ppl)
+{
+    return fill_kernel_for(fam, ppl) != nullptr;
+}
+
+// ------------------------------------------------------------ workspaces
+// Launch control and tile status words for launches that follow each
+// other in stream order (one per stream, one per plan).
+struct Workspace {
+    int device = 0;
+    Control *ctl = nullptr;
+    uint64_t *status = nullptr;
+    size_t status_cap = 0;
+    uint64_t launches = 0;
+    hipEvent_t last = nullptr;            // recorded after every launch
+    // batch descriptors
+    Segment *dsegs = nullptr;
+    size_t dsegs_cap = 0;
+    Segment *hsegs[2] = {nullptr, nullptr};
+    size_t hsegs_cap[2] = {0, 0};
+    hipEvent_t hsegs_done[2] = {nullptr, nullptr};
+    int hcur = 0;
+};
+
+prngd_status_t ws_init(Workspace *ws, int dev)
+{
+    ws->device = dev;
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, sizeof(Control)));
+    ws->ctl = static_cast<Control *>(p);
+    const Control init{0, 0, 1, 0, 0};
+    HIP_TRY(hipMemcpy(ws->ctl, &init, sizeof init, hipMemcpyHostToDevice));
+    HIP_TRY(hipEventCreateWithFlags(&ws->last, hipEventDisableTiming));
+    for (int i = 0; i < 2; ++i)
+        HIP_TRY(hipEventCreateWithFlags(&ws->hsegs_done[i], hipEventDisableTiming));
+    return PRNGD_OK;
+}
+
+// Make room for `tiles` status words and clear them when the 24-bit epoch
+// wraps, so that no stale word can carry the epoch of a later launch.
+prngd_status_t ws_prepare(Workspace *ws, size_t tiles, hipStream_t stream)
+{
+    if (tiles > ws->status_cap) {
+        size_t cap = std::max<size_t>(tiles, 1 << 16);
+        if (ws->status) {
+            HIP_TRY(hipStreamSynchronize(stream));
+            HIP_TRY(hipEventSynchronize(ws->last));
+            HIP_TRY(hipFree(ws->status));
+            ws->status = nullptr;
+        }
+        void *p = nullptr;
+        HIP_TRY(hipMalloc(&p, cap * sizeof(uint64_t)));
+        ws->status = static_cast<uint64_t *>(p);
+        ws->status_cap = cap;
+        HIP_TRY(launch_zero_words(ws->status, cap, stream));
+    }
+    if (ws->launches > 0 && ws->launches % kEpochMask == 0)
+        HIP_TRY(launch_zero_words(ws->status, ws->status_cap, stream));
+    return PRNGD_OK;
+}
+
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_stream_ws;
+
+prngd_status_t stream_workspace(int dev, hipStream_t stream, Workspace **out)
+{
+    auto key = std::make_pair(dev, stream);
+    auto it = g_stream_ws.find(key);
+    if (it == g_stream_ws.end()) {
+        std::unique_ptr<Workspace> ws(new Workspace);
+        prngd_status_t st = ws_init(ws.get(), dev);
+        if (st != PRNGD_OK)
+            return st;
+        it = g_stream_ws.emplace(key, std::move(ws)).first;
+    }
+    *out = it->second.get();
+    return PRNGD_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- handle
+struct prngd_handle_s {
+    int device = 0;
+    prngd_generator_t gen = PRNGD_PHILOX4X32_10;
+    Config cfg{};
+    uint64_t seed = 0;
+    uint32_t stream_id = 0;
+    uint32_t mrg[6] = {0, 0, 0, 0, 0, 0};
+    uint64_t *slot = nullptr;          // device: counter[2]
+    uint32_t parity = 0;               // counter[parity] is current
+    hipEvent_t last_event = nullptr;   // borrowed: last work on this handle
+    hipStream_t last_stream = nullptr;
+    prngd_plan_s *plan = nullptr;      // live plan the handle is bound to
+};
+
+struct prngd_plan_s {
+    int device = 0;
+    std::vector<prngd_handle_t> handles;
+    std::vector<uint32_t> base_parity;
+    Workspace ws;
+    Segment *dsegs = nullptr;
+    LaunchArgs args{};
+    const void *kernel = nullptr;
+    uint32_t grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t launches = 0;
+};
+
+namespace {
+
+// Order work on `stream` after the handle's previous work elsewhere.
+prngd_status_t order_after(prngd_handle_t h, hipStream_t stream)
+{
+    if (h->last_event && h->last_stream != stream)
+        HIP_TRY(hipStreamWaitEvent(stream, h->last_event, 0));
+    return PRNGD_OK;
+}
+
+uint64_t planned_pairs(const Config &c, uint64_t n, uint32_t slack_mode)
+{
+    if (slack_mode == 1)
+        return n;
+    // expected rejections before n acceptances (x1 uniform on [a0, a])
+    const double rho = 2.0 / double(c.a - c.a0 + 1);
+    const double mean = double(n) * rho / (1.0 - rho);
+    const double extra = std::floor(mean + 4.0 * std::sqrt(mean) + 0.5);
+    return n + static_cast<uint64_t>(extra);
+}
+
+int occupancy_of(DeviceInfo *d, const void *kernel)
+{
+    auto it = d->occupancy.find(kernel);
+    if (it != d->occupancy.end())
+        return it->second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlockThreads, 0) != hipSuccess ||
+        nb <= 0)
+        nb = 1;
+    d->occupancy[kernel] = nb;
+    return nb;
+}
+
+struct LaunchPlan {
+    const void *kernel;
+    uint32_t grid;
+    uint64_t T;
+};
+
+prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, uint64_t total_tiles,
+                           LaunchArgs *args, LaunchPlan *lp)
+{
+    const prngd_tuning_t tune = tuning_for(cfg.fam, cfg.w);
+    lp->kernel = fill_kernel_for(cfg.fam, tune.pairs_per_lane);
+    if (!lp->kernel)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u pairs per lane",
+                    tune.pairs_per_lane);
+    lp->T = uint64_t(kBlockThreads) * tune.pairs_per_lane;
+    const int occ = occupancy_of(d, lp->kernel);
+    uint64_t per_cu = tune.blocks_per_cu ? std::min<uint64_t>(tune.blocks_per_cu, occ) : occ;
+    uint64_t grid = per_cu * uint64_t(d->cus);
+    grid = std::max<uint64_t>(1, std::min<uint64_t>(grid, total_tiles));
+    lp->grid = uint32_t(grid);
+    args->store_mode = tune.store_mode;
+    args->w = cfg.w;
+    args->a0 = uint32_t(cfg.a0);
+    args->a = uint32_t(cfg.a);
+    args->b0 = uint32_t(cfg.b0);
+    args->S = cfg.S;
+    args->error = d->error_dev;
+    args->mrg_thread = nullptr;
+    args->mrg_window = nullptr;
+    if (cfg.fam == FAM_MRG || cfg.fam == FAM_MIXED) {
+        const uint32_t r = cfg.fam == FAM_MRG ? 2u : 1u;
+        prngd_status_t st = mrg_tables_for(d, r, tune.pairs_per_lane, &args->mrg_thread,
+                                           &args->mrg_window);
+        if (st != PRNGD_OK)
+            return st;
+    }
+    return PRNGD_OK;
+}
+
+// Fill the descriptor of one request; returns tiles allotted.
+prngd_status_t make_segment(prngd_handle_t h, uint64_t n, double *out, uint64_t T,
+                            uint32_t slack_mode, uint64_t tile_begin, Segment *s,
+                            uint64_t *ntiles)
+{
+    if (n > kMaxOutputs)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "n = %llu exceeds 2^38 - 1 outputs per fill",
+                    (unsigned long long)n);
+    if (!out || (reinterpret_cast<uintptr_t>(out) & 7u))
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "out must be a non-null 8-byte aligned pointer");
+    const uint64_t planned = planned_pairs(h->cfg, n, slack_mode);
+    const uint64_t tiles = (planned + T - 1) / T + 1;
+    if (tile_begin + tiles > 0xFFFFFFFFull)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "launch too large (more than 2^32 tiles)");
+    s->seed = h->seed;
+    s->n = n;
+    s->planned = planned;
+    s->out = out;
+    s->counter = h->slot;
+    s->stream_id = h->stream_id;
+    s->parity = h->parity;
+    s->tile_begin = uint32_t(tile_begin);
+    s->ntiles = uint32_t(tiles);
+    std::memcpy(s->mrg, h->mrg, sizeof s->mrg);
+    *ntiles = tiles;
+    return PRNGD_OK;
+}
+
+bool same_config(const Config &x, const Config &y)
+{
+    return x.fam == y.fam && x.w == y.w && x.a0 == y.a0 && x.a == y.a && x.b0 == y.b0 &&
+           x.b == y.b;
+}
+
+prngd_status_t current_device(int *dev)
+{
+    HIP_TRY(hipGetDevice(dev));
+    return PRNGD_OK;
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+extern "C" {
+
+const char *prngd_status_string(prngd_status_t s)
+{
+    switch (s) {
+    case PRNGD_OK: return "PRNGD_OK";
+    case PRNGD_ERR_INVALID_ARGUMENT: return "PRNGD_ERR_INVALID_ARGUMENT";
+    case PRNGD_ERR_UNSUPPORTED: return "PRNGD_ERR_UNSUPPORTED";
+    case PRNGD_ERR_OUT_OF_MEMORY: return "PRNGD_ERR_OUT_OF_MEMORY";
+    case PRNGD_ERR_HIP: return "PRNGD_ERR_HIP";
+    case PRNGD_ERR_DEVICE: return "PRNGD_ERR_DEVICE";
+    }
+    return "PRNGD_ERR_UNKNOWN";
+}
+
+const char *prngd_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+prngd_status_t prngd_describe(prngd_generator_t generator, double k, uint64_t min, uint64_t max,
+                              uint32_t *w, uint64_t *b0, uint64_t *b, uint64_t *D, double *S)
+{
+    Config c;
+    prngd_status_t st = make_config(generator, k, min, max, &c);
+    if (st != PRNGD_OK)
+        return st;
+    if (w) *w = c.w;
+    if (b0) *b0 = c.b0;
+    if (b) *b = c.b;
+    if (D) *D = c.D;
+    if (S) *S = c.S;
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_create(uint64_t seed, prngd_generator_t generator, double k, uint64_t min,
+                            uint64_t max, prngd_handle_t *out_handle)
+{
+    if (!out_handle)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "out_handle is NULL");
+    *out_handle = nullptr;
+    Config cfg;
+    prngd_status_t st = make_config(generator, k, min, max, &cfg);
+    if (st != PRNGD_OK)
+        return st;
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    int dev = 0;
+    if ((st = current_device(&dev)) != PRNGD_OK)
+        return st;
+    DeviceInfo *d = nullptr;
+    if ((st = device_info(dev, &d)) != PRNGD_OK)
+        return st;
+    std::unique_ptr<prngd_handle_s> h(new prngd_handle_s);
+    h->device = dev;
+    h->gen = generator;
+    h->cfg = cfg;
+    h->seed = seed;
+    if (cfg.fam == FAM_MRG || cfg.fam == FAM_MIXED)
+        mrg_stream_base(seed, 0, h->mrg);
+    if ((st = alloc_slot(d, &h->slot)) != PRNGD_OK)
+        return st;
+    *out_handle = h.release();
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_destroy(prngd_handle_t h)
+{
+    if (!h)
+        return PRNGD_OK;
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    if (h->plan)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle is bound to a live plan");
+    if (h->last_event)
+        HIP_TRY(hipEventSynchronize(h->last_event));
+    auto it = g_devices.find(h->device);
+    if (it != g_devices.end())
+        it->second.free_slots.push_back(h->slot);
+    delete h;
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_set_position(prngd_handle_t h, uint32_t stream_id, uint64_t pair_counter,
+                                  void *stream)
+{
+    if (!h)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "NULL handle");
+    if (h->plan)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle is bound to a live plan");
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    prngd_status_t st = stream_workspace(h->device, s, &ws);
+    if (st != PRNGD_OK)
+        return st;
+    if ((st = order_after(h, s)) != PRNGD_OK)
+        return st;
+    h->stream_id = stream_id;
+    if (h->cfg.fam == FAM_MRG || h->cfg.fam == FAM_MIXED)
+        mrg_stream_base(h->seed, stream_id, h->mrg);
+    HIP_TRY(launch_set_counter(h->slot, pair_counter, s));
+    HIP_TRY(hipEventRecord(ws->last, s));
+    h->last_event = ws->last;
+    h->last_stream = s;
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_get_position(prngd_handle_t h, uint32_t *stream_id, uint64_t *pair_counter,
+                                  void *stream)
+{
+    if (!h)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "NULL handle");
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    prngd_status_t st = order_after(h, s);
+    if (st != PRNGD_OK)
+        return st;
+    uint32_t parity = h->parity;
+    if (h->plan) {
+        // position after the plan's launches so far
+        const prngd_plan_s *p = h->plan;
+        for (size_t i = 0; i < p->handles.size(); ++i)
+            if (p->handles[i] == h)
+                parity = p->base_parity[i] ^ uint32_t(p->launches & 1u);
+    }
+    uint64_t value = 0;
+    HIP_TRY(hipMemcpyAsync(&value, h->slot + parity, sizeof value, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (stream_id)
+        *stream_id = h->stream_id;
+    if (pair_counter)
+        *pair_counter = value;
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *stream)
+{
+    if (!h)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "NULL handle");
+    if (h->plan)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle is bound to a live plan");
+    if (n == 0)
+        return PRNGD_OK;
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    DeviceInfo *d = nullptr;
+    prngd_status_t st = device_info(h->device, &d);
+    if (st != PRNGD_OK)
+        return st;
+    if ((st = check_device_errors(d)) != PRNGD_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    if ((st = stream_workspace(h->device, s, &ws)) != PRNGD_OK)
+        return st;
+    LaunchArgs args{};
+    LaunchPlan lp{};
+    // the tile size is needed to allot tiles, so plan the kernel first
+    if ((st = plan_launch(d, h->cfg, 1, &args, &lp)) != PRNGD_OK)
+        return st;
+    uint64_t ntiles = 0;
+    const prngd_tuning_t tune = tuning_for(h->cfg.fam, h->cfg.w);
+    if ((st = make_segment(h, n, out, lp.T, tune.slack_mode, 0, &args.seg0, &ntiles)) != PRNGD_OK)
+        return st;
+    const int occ = occupancy_of(d, lp.kernel);
+    const uint64_t per_cu = tune.blocks_per_cu ? std::min<uint64_t>(tune.blocks_per_cu, occ) : occ;
+    lp.grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(per_cu * d->cus, ntiles)));
+    args.segs = nullptr;
+    args.nseg = 1;
+    args.total_tiles = uint32_t(ntiles);
+    args.ctl = ws->ctl;
+    args.use_flip = 0;
+    if ((st = order_after(h, s)) != PRNGD_OK)
+        return st;
+    if ((st = ws_prepare(ws, ntiles, s)) != PRNGD_OK)
+        return st;
+    args.status = ws->status;
+    HIP_TRY(launch_fill(lp.kernel, lp.grid, args, s));
+    ws->launches++;
+    HIP_TRY(hipEventRecord(ws->last, s));
+    h->parity ^= 1u;
+    h->last_event = ws->last;
+    h->last_stream = s;
+    return PRNGD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Validate a request list and build its descriptors.
+prngd_status_t build_batch(const prngd_request_t *reqs, uint32_t count, uint64_t T,
+                           uint32_t slack_mode, std::vector<Segment> &segs,
+                           std::vector<prngd_handle_t> &handles, uint64_t *total)
+{
+    if (!reqs || count == 0)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "empty request list");
+    std::unordered_set<prngd_handle_t> seen;
+    segs.clear();
+    handles.clear();
+    uint64_t tiles = 0;
+    const prngd_handle_t first = reqs[0].h;
+    if (!first)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "request 0 has a NULL handle");
+    for (uint32_t i = 0; i < count; ++i) {
+        const prngd_request_t &r = reqs[i];
+        if (!r.h)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "request %u has a NULL handle", i);
+        if (!seen.insert(r.h).second)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle of request %u repeats", i);
+        if (!same_config(r.h->cfg, first->cfg) || r.h->device != first->device)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT,
+                        "request %u: all handles of a batch must share generator, k, min, max",
+                        i);
+        if (r.h->plan)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "request %u: handle bound to a plan", i);
+        if (r.n == 0)
+            continue;
+        Segment s;
+        uint64_t nt = 0;
+        prngd_status_t st = make_segment(r.h, r.n, r.out, T, slack_mode, tiles, &s, &nt);
+        if (st != PRNGD_OK)
+            return st;
+        tiles += nt;
+        segs.push_back(s);
+        handles.push_back(r.h);
+    }
+    *total = tiles;
+    return PRNGD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+prngd_status_t prngd_fill_batch(const prngd_request_t *reqs, uint32_t count, void *stream)
+{
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    if (!reqs || count == 0)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "empty request list");
+    if (!reqs[0].h)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "request 0 has a NULL handle");
+    const int dev = reqs[0].h->device;
+    DeviceInfo *d = nullptr;
+    prngd_status_t st = device_info(dev, &d);
+    if (st != PRNGD_OK)
+        return st;
+    if ((st = check_device_errors(d)) != PRNGD_OK)
+        return st;
+    const Config cfg = reqs[0].h->cfg;
+    LaunchArgs args{};
+    LaunchPlan lp{};
+    if ((st = plan_launch(d, cfg, 1, &args, &lp)) != PRNGD_OK)
+        return st;
+    const prngd_tuning_t tune = tuning_for(cfg.fam, cfg.w);
+    std::vector<Segment> segs;
+    std::vector<prngd_handle_t> handles;
+    uint64_t total = 0;
+    if ((st = build_batch(reqs, count, lp.T, tune.slack_mode, segs, handles, &total)) != PRNGD_OK)
+        return st;
+    if (segs.empty())
+        return PRNGD_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    if ((st = stream_workspace(dev, s, &ws)) != PRNGD_OK)
+        return st;
+    // order after every handle's previous work on other streams
+    std::unordered_set<hipEvent_t> waited;
+    for (prngd_handle_t h : handles)
+        if (h->last_event && h->last_stream != s && waited.insert(h->last_event).second)
+            HIP_TRY(hipStreamWaitEvent(s, h->last_event, 0));
+    if ((st = ws_prepare(ws, total, s)) != PRNGD_OK)
+        return st;
+    // descriptors: pinned staging ring of two, then one async copy
+    const size_t bytes = segs.size() * sizeof(Segment);
+    const int slot = ws->hcur;
+    ws->hcur ^= 1;
+    HIP_TRY(hipEventSynchronize(ws->hsegs_done[slot]));
+    if (ws->hsegs_cap[slot] < segs.size()) {
+        if (ws->hsegs[slot])
+            HIP_TRY(hipHostFree(ws->hsegs[slot]));
+        void *p = nullptr;
+        const size_t cap = std::max<size_t>(segs.size(), 1024);
+        HIP_TRY(hipHostMalloc(&p, cap * sizeof(Segment), hipHostMallocDefault));
+        ws->hsegs[slot] = static_cast<Segment *>(p);
+        ws->hsegs_cap[slot] = cap;
+    }
+    if (ws->dsegs_cap < segs.size()) {
+        if (ws->dsegs) {
+            HIP_TRY(hipStreamSynchronize(s));
+            HIP_TRY(hipFree(ws->dsegs));
+        }
+        void *p = nullptr;
+        const size_t cap = std::max<size_t>(segs.size(), 1024);
+        HIP_TRY(hipMalloc(&p, cap * sizeof(Segment)));
+        ws->dsegs = static_cast<Segment *>(p);
+        ws->dsegs_cap = cap;
+    }
+    std::memcpy(ws->hsegs[slot], segs.data(), bytes);
+    HIP_TRY(hipMemcpyAsync(ws->dsegs, ws->hsegs[slot], bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(ws->hsegs_done[slot], s));
+    const int occ = occupancy_of(d, lp.kernel);
+    const uint64_t per_cu = tune.blocks_per_cu ? std::min<uint64_t>(tune.blocks_per_cu, occ) : occ;
+    lp.grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(per_cu * d->cus, total)));
+    args.segs = ws->dsegs;
+    args.nseg = uint32_t(segs.size());
+    args.total_tiles = uint32_t(total);
+    args.status = ws->status;
+    args.ctl = ws->ctl;
+    args.use_flip = 0;
+    HIP_TRY(launch_fill(lp.kernel, lp.grid, args, s));
+    ws->launches++;
+    HIP_TRY(hipEventRecord(ws->last, s));
+    for (prngd_handle_t h : handles) {
+        h->parity ^= 1u;
+        h->last_event = ws->last;
+        h->last_stream = s;
+    }
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_plan_create(const prngd_request_t *reqs, uint32_t count,
+                                 prngd_plan_t *out_plan)
+{
+    if (!out_plan)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "out_plan is NULL");
+    *out_plan = nullptr;
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    if (!reqs || count == 0 || !reqs[0].h)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "empty request list");
+    const int dev = reqs[0].h->device;
+    DeviceInfo *d = nullptr;
+    prngd_status_t st = device_info(dev, &d);
+    if (st != PRNGD_OK)
+        return st;
+    const Config cfg = reqs[0].h->cfg;
+    std::unique_ptr<prngd_plan_s> p(new prngd_plan_s);
+    p->device = dev;
+    LaunchPlan lp{};
+    if ((st = plan_launch(d, cfg, 1, &p->args, &lp)) != PRNGD_OK)
+        return st;
+    const prngd_tuning_t tune = tuning_for(cfg.fam, cfg.w);
+    std::vector<Segment> segs;
+    uint64_t total = 0;
+    if ((st = build_batch(reqs, count, lp.T, tune.slack_mode, segs, p->handles, &total)) !=
+        PRNGD_OK)
+        return st;
+    if (segs.empty())
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "a plan needs at least one request with n > 0");
+    if ((st = ws_init(&p->ws, dev)) != PRNGD_OK)
+        return st;
+    // wait for the handles' earlier work before the plan's first use
+    for (prngd_handle_t h : p->handles)
+        if (h->last_event)
+            HIP_TRY(hipEventSynchronize(h->last_event));
+    if ((st = ws_prepare(&p->ws, total, nullptr)) != PRNGD_OK)
+        return st;
+    void *dp = nullptr;
+    HIP_TRY(hipMalloc(&dp, segs.size() * sizeof(Segment)));
+    p->dsegs = static_cast<Segment *>(dp);
+    HIP_TRY(hipMemcpy(p->dsegs, segs.data(), segs.size() * sizeof(Segment),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    const int occ = occupancy_of(d, lp.kernel);
+    const uint64_t per_cu = tune.blocks_per_cu ? std::min<uint64_t>(tune.blocks_per_cu, occ) : occ;
+    p->grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(per_cu * d->cus, total)));
+    p->kernel = lp.kernel;
+    p->args.segs = p->dsegs;
+    p->args.nseg = uint32_t(segs.size());
+    p->args.total_tiles = uint32_t(total);
+    p->args.status = p->ws.status;
+    p->args.ctl = p->ws.ctl;
+    p->args.use_flip = 1;
+    HIP_TRY(hipGraphCreate(&p->graph, 0));
+    hipKernelNodeParams kp{};
+    void *params[] = {&p->args};
+    kp.func = const_cast<void *>(p->kernel);
+    kp.gridDim = dim3(p->grid);
+    kp.blockDim = dim3(kBlockThreads);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = params;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    HIP_TRY(hipGraphAddKernelNode(&node, p->graph, nullptr, 0, &kp));
+    HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    for (prngd_handle_t h : p->handles) {
+        p->base_parity.push_back(h->parity);
+        h->plan = p.get();
+    }
+    *out_plan = p.release();
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_plan_launch(prngd_plan_t p, void *stream)
+{
+    if (!p)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "NULL plan");
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    DeviceInfo *d = nullptr;
+    prngd_status_t st = device_info(p->device, &d);
+    if (st != PRNGD_OK)
+        return st;
+    if ((st = check_device_errors(d)) != PRNGD_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->ws.launches > 0 && p->ws.launches % kEpochMask == 0)
+        HIP_TRY(launch_zero_words(p->ws.status, p->ws.status_cap, s));
+    HIP_TRY(hipGraphLaunch(p->exec, s));
+    p->ws.launches++;
+    p->launches++;
+    HIP_TRY(hipEventRecord(p->ws.last, s));
+    for (prngd_handle_t h : p->handles) {
+        h->last_event = p->ws.last;
+        h->last_stream = s;
+    }
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_plan_destroy(prngd_plan_t p)
+{
+    if (!p)
+        return PRNGD_OK;
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    HIP_TRY(hipEventSynchronize(p->ws.last));
+    for (size_t i = 0; i < p->handles.size(); ++i) {
+        prngd_handle_t h = p->handles[i];
+        h->parity = p->base_parity[i] ^ uint32_t(p->launches & 1u);
+        h->plan = nullptr;
+        h->last_event = nullptr;
+        h->last_stream = nullptr;
+    }
+    if (p->exec)
+        (void)hipGraphExecDestroy(p->exec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
+    (void)hipFree(p->dsegs);
+    (void)hipFree(p->ws.status);
+    (void)hipFree(p->ws.ctl);
+    (void)hipEventDestroy(p->ws.last);
+    for (int i = 0; i < 2; ++i)
+        (void)hipEventDestroy(p->ws.hsegs_done[i]);
+    delete p;
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_set_tuning(prngd_generator_t generator, uint32_t w,
+                                const prngd_tuning_t *tuning)
+{
+    if (generator < PRNGD_PHILOX4X32_10 || generator > PRNGD_ENUMERATE)
+        return fail(PRNGD_ERR_UNSUPPORTED, "unknown generator %d", int(generator));
+    const uint32_t fams[] = {FAM_PHILOX, FAM_MRG, FAM_MIXED, FAM_ENUM};
+    const uint32_t fam = fams[generator];
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    if (!tuning) {
+        g_tuning.erase(std::make_pair(fam, w));
+        return PRNGD_OK;
+    }
+    if (tuning->pairs_per_lane && !valid_ppl(fam, tuning->pairs_per_lane))
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "pairs_per_lane %u not available",
+                    tuning->pairs_per_lane);
+    if (tuning->store_mode > 2 || tuning->slack_mode > 1)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "bad store_mode or slack_mode");
+    g_tuning[std::make_pair(fam, w)] = *tuning;
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_get_tuning(prngd_generator_t generator, uint32_t w, prngd_tuning_t *tuning)
+{
+    if (generator < PRNGD_PHILOX4X32_10 || generator > PRNGD_ENUMERATE || !tuning)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "bad arguments");
+    const uint32_t fams[] = {FAM_PHILOX, FAM_MRG, FAM_MIXED, FAM_ENUM};
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    *tuning = tuning_for(fams[generator], w);
+    return PRNGD_OK;
+}
+
+}  // extern "C"

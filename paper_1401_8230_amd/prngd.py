@@ -1,0 +1,270 @@
+"""Python binding of libprngd (ctypes).
+
+Argument marshalling only: every step of a fill runs in the library's HIP
+kernels.  PyTorch is used for device memory (tensors) and streams.  The
+library is loaded from this package directory; if it is not built, every
+call raises instead of computing anything elsewhere.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libprngd.so")
+
+PHILOX4X32_10 = 0
+MRG32K3A = 1
+PHILOX_X1_MRG32K3A_X2 = 2
+ENUMERATE = 3
+
+GENERATORS = {
+    "philox": PHILOX4X32_10,
+    "philox4x32_10": PHILOX4X32_10,
+    "mrg32k3a": MRG32K3A,
+    "mixed": PHILOX_X1_MRG32K3A_X2,
+    "philox_x1_mrg32k3a_x2": PHILOX_X1_MRG32K3A_X2,
+    "enumerate": ENUMERATE,
+}
+
+M1 = 4294967087
+
+OK = 0
+ERR_INVALID_ARGUMENT = 1
+ERR_UNSUPPORTED = 2
+ERR_OUT_OF_MEMORY = 3
+ERR_HIP = 4
+ERR_DEVICE = 5
+
+
+class PrngdError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(message)
+        self.status = status
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_void_p), ("n", ctypes.c_uint64), ("out", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("pairs_per_lane", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+                ("store_mode", ctypes.c_uint32), ("slack_mode", ctypes.c_uint32)]
+
+
+# (name, restype, argtypes) of every exported function
+_SIGNATURES = [
+    ("prngd_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("prngd_last_error", ctypes.c_char_p, []),
+    ("prngd_describe", ctypes.c_int,
+     [ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+      ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
+      ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+      ctypes.POINTER(ctypes.c_double)]),
+    ("prngd_create", ctypes.c_int,
+     [ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+      ctypes.POINTER(ctypes.c_void_p)]),
+    ("prngd_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("prngd_set_position", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p]),
+    ("prngd_get_position", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
+      ctypes.c_void_p]),
+    ("prngd_fill", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+    ("prngd_fill_batch", ctypes.c_int,
+     [ctypes.POINTER(Request), ctypes.c_uint32, ctypes.c_void_p]),
+    ("prngd_plan_create", ctypes.c_int,
+     [ctypes.POINTER(Request), ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
+    ("prngd_plan_launch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("prngd_plan_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("prngd_set_tuning", ctypes.c_int,
+     [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(Tuning)]),
+    ("prngd_get_tuning", ctypes.c_int,
+     [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(Tuning)]),
+]
+
+_lib = None
+
+
+def lib():
+    """The loaded libprngd.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PrngdError(ERR_UNSUPPORTED,
+                             f"{LIB_PATH} is not built: run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != OK:
+        L = lib()
+        name = L.prngd_status_string(status).decode()
+        msg = L.prngd_last_error().decode()
+        raise PrngdError(status, f"{name}: {msg}")
+
+
+def _gen(generator):
+    if isinstance(generator, str):
+        return GENERATORS[generator.lower()]
+    return int(generator)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _out_ptr(out, n):
+    import torch
+    if not isinstance(out, torch.Tensor):
+        raise TypeError("out must be a torch tensor")
+    if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 CUDA tensor")
+    if n is None:
+        n = out.numel()
+    if n > out.numel():
+        raise ValueError(f"n = {n} exceeds the {out.numel()} elements of out")
+    return out.data_ptr(), int(n)
+
+
+def describe(generator, k, min, max):
+    """Constants of Eq. (5) for (generator, k, min, max), host only."""
+    w = ctypes.c_uint32()
+    b0 = ctypes.c_uint64()
+    b = ctypes.c_uint64()
+    D = ctypes.c_uint64()
+    S = ctypes.c_double()
+    _check(lib().prngd_describe(_gen(generator), k, min, max, ctypes.byref(w),
+                                ctypes.byref(b0), ctypes.byref(b), ctypes.byref(D),
+                                ctypes.byref(S)))
+    return {"w": w.value, "b0": b0.value, "b": b.value, "D": D.value, "S": S.value}
+
+
+def natural_range(generator, w):
+    """(min, max) that prngd_create expects for a generator at resolution 2^-w."""
+    g = _gen(generator)
+    if g == MRG32K3A:
+        return 1, M1
+    return 0, (1 << w) - 1
+
+
+class Generator:
+    """A PRNGD stream handle: Algorithm 1's PRNGD(k, min, max) with a base
+    generator and a seed, positioned at (stream_id, pair counter)."""
+
+    def __init__(self, seed, generator="philox", w=32, k=None, min=None, max=None):
+        g = _gen(generator)
+        if k is None:
+            k = 2.0 ** -w
+        if min is None or max is None:
+            lo, hi = natural_range(g, w)
+            min = lo if min is None else min
+            max = hi if max is None else max
+        h = ctypes.c_void_p()
+        _check(lib().prngd_create(seed, g, k, min, max, ctypes.byref(h)))
+        self._h = h
+        self.generator = g
+        self.seed = seed
+        self.k = k
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("generator is closed")
+        return self._h
+
+    def fill(self, out, n=None, stream=None):
+        ptr, n = _out_ptr(out, n)
+        _check(lib().prngd_fill(self.handle, n, ptr, _stream_ptr(stream)))
+        return out
+
+    def set_position(self, stream_id, pair_counter, stream=None):
+        _check(lib().prngd_set_position(self.handle, stream_id, pair_counter,
+                                        _stream_ptr(stream)))
+
+    def get_position(self, stream=None):
+        sid = ctypes.c_uint32()
+        ctr = ctypes.c_uint64()
+        _check(lib().prngd_get_position(self.handle, ctypes.byref(sid), ctypes.byref(ctr),
+                                        _stream_ptr(stream)))
+        return sid.value, ctr.value
+
+    def close(self):
+        if self._h is not None:
+            _check(lib().prngd_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _requests(pairs):
+    reqs = (Request * len(pairs))()
+    for i, item in enumerate(pairs):
+        gen, out = item[0], item[1]
+        n = item[2] if len(item) > 2 else None
+        ptr, n = _out_ptr(out, n)
+        reqs[i].h = gen.handle
+        reqs[i].n = n
+        reqs[i].out = ptr
+    return reqs
+
+
+def fill_batch(pairs, stream=None):
+    """pairs: [(Generator, tensor) or (Generator, tensor, n), ...]; one launch."""
+    reqs = _requests(pairs)
+    _check(lib().prngd_fill_batch(reqs, len(pairs), _stream_ptr(stream)))
+
+
+class Plan:
+    """A resident batch replayed through a HIP graph."""
+
+    def __init__(self, pairs):
+        reqs = _requests(pairs)
+        p = ctypes.c_void_p()
+        _check(lib().prngd_plan_create(reqs, len(pairs), ctypes.byref(p)))
+        self._p = p
+        self._keep = pairs
+
+    def launch(self, stream=None):
+        _check(lib().prngd_plan_launch(self._p, _stream_ptr(stream)))
+
+    def close(self):
+        if self._p is not None:
+            _check(lib().prngd_plan_destroy(self._p))
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def set_tuning(generator, w, pairs_per_lane=0, blocks_per_cu=0, store_mode=0, slack_mode=0):
+    t = Tuning(pairs_per_lane, blocks_per_cu, store_mode, slack_mode)
+    _check(lib().prngd_set_tuning(_gen(generator), w, ctypes.byref(t)))
+
+
+def reset_tuning(generator, w):
+    _check(lib().prngd_set_tuning(_gen(generator), w, None))
+
+
+def get_tuning(generator, w):
+    t = Tuning()
+    _check(lib().prngd_get_tuning(_gen(generator), w, ctypes.byref(t)))
+    return {"pairs_per_lane": t.pairs_per_lane, "blocks_per_cu": t.blocks_per_cu,
+            "store_mode": t.store_mode, "slack_mode": t.slack_mode}

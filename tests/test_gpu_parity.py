@@ -1,0 +1,381 @@
+"""GPU parity: libprngd's HIP fills against the CPU oracle, bit for bit.
+
+Integer state (pair counters) must match exactly and every FP64 output must
+match to 0 ulp.  Sizes span several tiles and ragged tails; the high
+rejection rates of small w exercise the compaction and the look-back.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+torch = pytest.importorskip("torch")
+from paper_1401_8230_amd import prngd  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+OGEN = {"philox": O.GEN_PHILOX, "mrg32k3a": O.GEN_MRG32K3A, "mixed": O.GEN_MIXED,
+        "enumerate": O.GEN_ENUMERATE}
+DEV = "cuda:0"
+NAN_BITS = np.uint64(0x7FF8DEADBEEF0001)
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def _reset_tuning():
+    yield
+    for gen, w in [("philox", w) for w in range(2, 33)] + [("enumerate", w) for w in range(2, 17)] \
+            + [("mrg32k3a", 32), ("mixed", 32)]:
+        prngd.reset_tuning(gen, w)
+
+
+def guarded(n, misalign=False):
+    """An output view with guard words around it, pre-filled with a NaN
+    pattern the kernels can never produce."""
+    buf = torch.empty(n + 4, dtype=torch.float64, device=DEV)
+    buf.view(torch.int64).fill_(int(NAN_BITS))
+    off = 1 if misalign else 2
+    return buf, buf[off:off + n]
+
+
+def check_guards(buf, n, misalign=False):
+    host = buf.cpu().numpy().view(np.uint64)
+    off = 1 if misalign else 2
+    assert np.all(host[:off] == NAN_BITS) and np.all(host[off + n:] == NAN_BITS), "guard overwritten"
+
+
+def assert_bits_equal(got, expect, what):
+    g = np.ascontiguousarray(got).view(np.uint64)
+    e = np.ascontiguousarray(expect).view(np.uint64)
+    if not np.array_equal(g, e):
+        bad = np.flatnonzero(g != e)
+        i = int(bad[0])
+        raise AssertionError(f"{what}: {bad.size} mismatches, first at {i}: "
+                             f"{got[i]!r} vs {expect[i]!r}")
+
+
+def gpu_fill(gen, w, seed, stream_id, counter, n, misalign=False):
+    g = prngd.Generator(seed, gen, w=w)
+    if stream_id or counter:
+        g.set_position(stream_id, counter)
+    buf, out = guarded(n, misalign)
+    g.fill(out)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().copy()
+    check_guards(buf, n, misalign)
+    pos = g.get_position()
+    g.close()
+    return res, pos
+
+
+def oracle_fill(gen, w, seed, stream_id, counter, n):
+    s = O.PRNGD(OGEN[gen], w, seed=seed, stream=stream_id, counter=counter)
+    out = s.fill(n)
+    return out, s.counter
+
+
+def parity(gen, w, seed=42, stream_id=0, counter=0, n=10000, misalign=False):
+    note(f"{gen} w={w} seed={seed} stream={stream_id} counter={counter} n={n} misalign={misalign}")
+    got, (sid, ctr) = gpu_fill(gen, w, seed, stream_id, counter, n, misalign)
+    expect, ectr = oracle_fill(gen, w, seed, stream_id, counter, n)
+    assert_bits_equal(got, expect, f"{gen} w={w} n={n}")
+    assert sid == stream_id
+    assert ctr == ectr, f"counter {ctr} vs oracle {ectr}"
+    return got
+
+
+# ------------------------------------------------------------- single fills
+
+def test_c1_philox_w32_2_20_outputs():
+    parity("philox", 32, seed=42, n=1 << 20)
+
+
+@pytest.mark.parametrize("w", [2, 3, 5, 8, 12, 16, 24, 26, 27, 31])
+def test_philox_word_widths(w):
+    parity("philox", w, seed=1000 + w, stream_id=w, n=100003)
+
+
+def test_enumerate_w8_exhaustive():
+    # all 2^16 pairs: 512 rejected, every accepted grid value once, in order
+    got = parity("enumerate", 8, n=254 * 256)
+    assert np.all(np.diff(got) > 0) and got[0] == 0.0
+
+
+@pytest.mark.parametrize("w,n", [(2, 12), (4, 224), (6, 3000), (12, 5_000_000)])
+def test_enumerate_other_widths(w, n):
+    parity("enumerate", w, n=n)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 127, 128, 129, 4095, 4096, 4097,
+                               8191, 8193, 12289, 65537])
+def test_sizes_around_tile_edges(n):
+    parity("philox", 32, seed=7, n=n)
+    parity("philox", 8, seed=7, n=n)
+
+
+@pytest.mark.parametrize("counter", [1, 3, 4095, 4097, 2**33 - 5, 2**33 + 1, 2**40 + 12345,
+                                     2**63 + 7, 2**64 - 2**21])
+def test_start_positions(counter):
+    # odd starts begin mid-Philox-block; 2^33 - 5 crosses the low-word carry
+    parity("philox", 32, seed=9, counter=counter, n=20001)
+    parity("philox", 8, seed=9, counter=counter, n=9001)
+
+
+@pytest.mark.parametrize("stream_id", [1, 2**31, 2**32 - 1])
+def test_substreams(stream_id):
+    parity("philox", 32, seed=2**64 - 1, stream_id=stream_id, n=30000)
+
+
+def test_misaligned_output():
+    parity("philox", 32, seed=5, n=40001, misalign=True)
+    parity("philox", 8, seed=5, n=40001, misalign=True)
+    parity("mixed", 32, seed=5, n=20001, misalign=True)
+
+
+@pytest.mark.parametrize("gen", ["mrg32k3a", "mixed"])
+@pytest.mark.parametrize("seed,stream_id,counter,n", [
+    (0, 0, 0, 1), (0, 0, 0, 50000), (42, 0, 0, 70001), (42, 3, 17, 33333),
+    (2**64 - 1, 2**32 - 1, 2**40 + 5, 20000), (12345, 77, 2**62 + 1, 9999),
+])
+def test_mrg_generators(gen, seed, stream_id, counter, n):
+    parity(gen, 32, seed=seed, stream_id=stream_id, counter=counter, n=n)
+
+
+# ----------------------------------------------------- tails and tuning
+
+@pytest.mark.parametrize("gen,w", [("philox", 2), ("philox", 3), ("philox", 8),
+                                   ("enumerate", 4), ("mixed", 32), ("philox", 32)])
+def test_tail_path_without_planned_slack(gen, w):
+    # plan no rejections at all: every rejection is absorbed by the tail path
+    prngd.set_tuning(gen, w, slack_mode=1)
+    parity(gen, w, seed=11, counter=5, n=50001)
+
+
+@pytest.mark.parametrize("ppl", [4, 8, 16, 32])
+@pytest.mark.parametrize("store_mode", [0, 1, 2])
+def test_launch_shapes_do_not_change_bytes(ppl, store_mode):
+    prngd.set_tuning("philox", 32, pairs_per_lane=ppl, store_mode=store_mode)
+    prngd.set_tuning("philox", 8, pairs_per_lane=ppl, store_mode=store_mode, blocks_per_cu=1)
+    parity("philox", 32, seed=3, counter=1, n=100001)
+    parity("philox", 8, seed=3, counter=1, n=100001)
+
+
+@pytest.mark.parametrize("ppl", [4, 8, 16])
+def test_mrg_launch_shapes(ppl):
+    prngd.set_tuning("mixed", 32, pairs_per_lane=ppl)
+    prngd.set_tuning("mrg32k3a", 32, pairs_per_lane=ppl, blocks_per_cu=1)
+    parity("mixed", 32, seed=3, counter=3, n=30001)
+    parity("mrg32k3a", 32, seed=3, counter=3, n=30001)
+
+
+# ------------------------------------------------ sequences of fills
+
+def test_split_fills_concatenate():
+    rng = np.random.default_rng(1)
+    for gen, w in [("philox", 32), ("philox", 8), ("mixed", 32)]:
+        note(f"split {gen} w={w}")
+        g = prngd.Generator(77, gen, w=w)
+        parts = [int(v) for v in rng.integers(1, 30000, size=12)]
+        outs = []
+        for n in parts:
+            t = torch.empty(n, dtype=torch.float64, device=DEV)
+            g.fill(t)
+            outs.append(t)
+        torch.cuda.synchronize()
+        got = torch.cat(outs).cpu().numpy()
+        expect, ectr = oracle_fill(gen, w, 77, 0, 0, sum(parts))
+        assert_bits_equal(got, expect, f"split {gen}")
+        assert g.get_position()[1] == ectr
+        g.close()
+
+
+def test_checkpoint_resume():
+    g = prngd.Generator(31, "philox", w=8)
+    a = torch.empty(12345, dtype=torch.float64, device=DEV)
+    g.fill(a)
+    sid, ctr = g.get_position()
+    g2 = prngd.Generator(31, "philox", w=8)
+    g2.set_position(sid, ctr)
+    b = torch.empty(5000, dtype=torch.float64, device=DEV)
+    c = torch.empty(5000, dtype=torch.float64, device=DEV)
+    g.fill(b)
+    g2.fill(c)
+    torch.cuda.synchronize()
+    assert_bits_equal(b.cpu().numpy(), c.cpu().numpy(), "resume")
+    assert g.get_position() == g2.get_position()
+
+
+def test_repeated_high_rejection_fills():
+    # many launches in a row: stale status words of earlier launches must
+    # never be taken for the current one
+    rng = np.random.default_rng(2)
+    g = prngd.Generator(5, "philox", w=3)
+    ref = O.PRNGD(O.GEN_PHILOX, 3, seed=5)
+    for i in range(40):
+        n = int(rng.integers(1, 200000))
+        t = torch.empty(n, dtype=torch.float64, device=DEV)
+        g.fill(t)
+        expect = ref.fill(n)
+        assert_bits_equal(t.cpu().numpy(), expect, f"fill {i}")
+    assert g.get_position()[1] == ref.counter
+
+
+def test_fill_on_another_stream_is_ordered():
+    g = prngd.Generator(8, "philox", w=8)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a = torch.empty(300000, dtype=torch.float64, device=DEV)
+    b = torch.empty(300000, dtype=torch.float64, device=DEV)
+    g.fill(a, stream=s1)
+    g.fill(b, stream=s2)
+    torch.cuda.synchronize()
+    expect = O.PRNGD(O.GEN_PHILOX, 8, seed=8).fill(600000)
+    assert_bits_equal(np.concatenate([a.cpu().numpy(), b.cpu().numpy()]), expect, "two streams")
+
+
+# ------------------------------------------------------------- batches
+
+def make_handles(reqs, gen, w):
+    gens = []
+    for r in reqs:
+        g = prngd.Generator(r.seed, gen, w=w)
+        if r.stream_id or r.counter:
+            g.set_position(r.stream_id, r.counter)
+        gens.append(g)
+    return gens
+
+
+@pytest.mark.parametrize("gen,w", [("philox", 32), ("philox", 8), ("mixed", 32), ("mrg32k3a", 32)])
+def test_batch_matches_oracle(gen, w):
+    from paper_1401_8230_amd import workloads
+    note(f"batch {gen} w={w}")
+    reqs = workloads.uneven_batch(count=200, lo=1, hi=3e4, rng_seed=w)
+    gens = make_handles(reqs, gen, w)
+    outs = [torch.empty(r.n, dtype=torch.float64, device=DEV) for r in reqs]
+    prngd.fill_batch(list(zip(gens, outs)))
+    torch.cuda.synchronize()
+    for i, (r, g, o) in enumerate(zip(reqs, gens, outs)):
+        expect, ectr = oracle_fill(gen, w, r.seed, r.stream_id, r.counter, r.n)
+        assert_bits_equal(o.cpu().numpy(), expect, f"request {i}")
+        assert g.get_position() == (r.stream_id, ectr), f"request {i}"
+    for g in gens:
+        g.close()
+
+
+def test_batch_with_empty_requests_and_errors():
+    a = prngd.Generator(1, "philox", w=32)
+    b = prngd.Generator(2, "philox", w=32)
+    c = prngd.Generator(3, "philox", w=8)
+    ta = torch.empty(1000, dtype=torch.float64, device=DEV)
+    tb = torch.empty(10, dtype=torch.float64, device=DEV)
+    prngd.fill_batch([(a, ta, 0), (b, tb)])
+    torch.cuda.synchronize()
+    assert a.get_position()[1] == 0
+    assert_bits_equal(tb.cpu().numpy(), oracle_fill("philox", 32, 2, 0, 0, 10)[0], "b")
+    with pytest.raises(prngd.PrngdError):
+        prngd.fill_batch([(a, ta), (a, ta)])          # repeated handle
+    with pytest.raises(prngd.PrngdError):
+        prngd.fill_batch([(a, ta), (c, tb)])          # mixed configurations
+
+
+def test_plan_replays_advance_handles():
+    from paper_1401_8230_amd import workloads
+    reqs = workloads.uneven_batch(count=64, lo=1, hi=5e4, rng_seed=9)
+    gens = make_handles(reqs, "philox", 8)
+    outs = [torch.empty(r.n, dtype=torch.float64, device=DEV) for r in reqs]
+    plan = prngd.Plan(list(zip(gens, outs)))
+    refs = [O.PRNGD(O.GEN_PHILOX, 8, seed=r.seed, stream=r.stream_id, counter=r.counter)
+            for r in reqs]
+    for rep in range(4):
+        note(f"plan replay {rep}")
+        plan.launch()
+        torch.cuda.synchronize()
+        for i, (r, o) in enumerate(zip(reqs, outs)):
+            assert_bits_equal(o.cpu().numpy(), refs[i].fill(r.n), f"replay {rep} request {i}")
+        assert gens[5].get_position()[1] == refs[5].counter
+    with pytest.raises(prngd.PrngdError):
+        gens[0].fill(outs[0])                          # bound to the plan
+    plan.close()
+    # after the plan, the handles continue where the plan left them
+    t = torch.empty(777, dtype=torch.float64, device=DEV)
+    gens[3].fill(t)
+    assert_bits_equal(t.cpu().numpy(), refs[3].fill(777), "after plan")
+    for g in gens:
+        g.close()
+
+
+# ------------------------------------------------ full-size configurations
+
+def test_many_streams_full_size_sampled():
+    """2^16 substreams of seed 42, 2^14 outputs each (8 GiB), one resident
+    batch as the benchmark launches it; 64 sampled streams are compared in
+    full and every stream's counter and range are checked."""
+    from paper_1401_8230_amd import workloads
+    reqs = workloads.many_streams()
+    n = reqs[0].n
+    note("many streams: creating handles")
+    gens = make_handles(reqs, "philox", 32)
+    out = torch.empty(len(reqs) * n, dtype=torch.float64, device=DEV)
+    views = [out[i * n:(i + 1) * n] for i in range(len(reqs))]
+    plan = prngd.Plan(list(zip(gens, views)))
+    note("many streams: launch")
+    plan.launch()
+    torch.cuda.synchronize()
+    assert float(out.min()) >= 0.0 and float(out.max()) < 1.0
+    rng = np.random.default_rng(0)
+    sample = sorted(set([0, 1, len(reqs) - 1] + [int(v) for v in rng.integers(0, len(reqs), 61)]))
+    for s in sample:
+        expect, ectr = oracle_fill("philox", 32, 42, s, 0, n)
+        assert_bits_equal(views[s].cpu().numpy(), expect, f"stream {s}")
+        assert gens[s].get_position() == (s, ectr)
+    plan.close()
+    counters = [g.get_position()[1] for g in gens[:4096]]
+    assert all(c >= n for c in counters)
+    for g in gens:
+        g.close()
+    del out
+
+
+def _walk_back(s, end, k):
+    """The last k accepted pairs before pair `end` (oracle, one by one)."""
+    vals = []
+    p = end - 1
+    while len(vals) < k:
+        x1, x2 = s.pair(p)
+        if s.accept(x1):
+            vals.append(s.map(x1, x2))
+        p -= 1
+    return np.array(vals[::-1])
+
+
+@pytest.mark.parametrize("gen,w", [("mixed", 32), ("philox", 24)])
+def test_single_stream_2_28_sampled(gen, w):
+    """2^28 outputs of one stream (2 GiB): the first 2^20 and the last 64
+    outputs are compared with the oracle, and sampled outputs in between
+    must be the oracle's output of a pair within the total rejection
+    count of their position."""
+    n = 1 << 28
+    note(f"{gen} w={w} n=2^28")
+    g = prngd.Generator(42, gen, w=w)
+    out = torch.empty(n, dtype=torch.float64, device=DEV)
+    g.fill(out)
+    torch.cuda.synchronize()
+    _, end = g.get_position()
+    rejected = end - n
+    assert 0 <= rejected < 10000
+    assert float(out.min()) >= 0.0 and float(out.max()) < 1.0
+    head, _ = oracle_fill(gen, w, 42, 0, 0, 1 << 20)
+    assert_bits_equal(out[:1 << 20].cpu().numpy(), head, "head")
+    s = O.PRNGD(OGEN[gen], w, seed=42)
+    assert s.accept(s.pair(end - 1)[0])
+    assert_bits_equal(out[n - 64:].cpu().numpy(), _walk_back(s, end, 64), "tail")
+    rng = np.random.default_rng(3)
+    for i in sorted(int(v) for v in rng.integers(1 << 20, n - 64, 40)):
+        v = float(out[i])
+        cands = [s.map(*s.pair(p)) for p in range(i, i + rejected + 1) if s.accept(s.pair(p)[0])]
+        assert v in cands, f"output {i}"
