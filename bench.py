@@ -86,12 +86,7 @@ def main():
     n = args.outputs_per_stream
     S = args.streams
     print(f"[bench] creating {S} handles", file=sys.stderr, flush=True)
-    gens = []
-    for s in range(S):
-        g = prngd.Generator(args.seed, "philox", w=32)
-        if s:
-            g.set_position(s, 0)
-        gens.append(g)
+    gens = prngd.Generator.many(args.seed, S, "philox", w=32)
     out = torch.empty(S * n, dtype=torch.float64, device="cuda:0")
     views = [out[i * n:(i + 1) * n] for i in range(S)]
     plan = prngd.Plan(list(zip(gens, views)))

@@ -89,11 +89,16 @@ typedef struct {
 /* Launch shape of the fill kernels.  None of these change the output
  * bytes; they only change speed.  Zero fields mean "library default". */
 typedef struct {
-    uint32_t pairs_per_lane;  /* 4, 8, 16 or 32 pairs per thread per tile   */
-    uint32_t blocks_per_cu;   /* persistent grid = blocks_per_cu * CUs      */
+    uint32_t pairs_per_lane;  /* pairs per thread per tile: 4, 8, 16, 32    */
+    uint32_t blocks_per_cu;   /* workgroups per CU (0: all that fit)        */
     uint32_t store_mode;      /* 0 default, 1 plain 8-byte, 2 nontemporal   */
     uint32_t slack_mode;      /* 0 plan rejections ahead, 1 plan none (the  */
-                              /* tail path then absorbs every rejection)    */
+                              /* last tile then absorbs every rejection)    */
+    uint32_t block_threads;   /* threads per workgroup: 256, 512, 1024      */
+    uint32_t seq_max_tiles;   /* batch requests of at most this many tiles  */
+                              /* are produced whole by one workgroup; the   */
+                              /* rest are split over workgroups joined by   */
+                              /* the look-back (0: half a fair share)       */
 } prngd_tuning_t;
 
 /* Human-readable name of a status code (static storage). */
@@ -129,6 +134,20 @@ prngd_status_t prngd_describe(prngd_generator_t generator, double k,
 prngd_status_t prngd_create(uint64_t seed, prngd_generator_t generator,
                             double k, uint64_t min, uint64_t max,
                             prngd_handle_t *out_handle);
+
+/*
+ * Create `count` handles on the consecutive substreams first_stream_id,
+ * first_stream_id + 1, ... of one seed, all at pair counter 0 -- the
+ * independent streams of a Monte Carlo run.  Equivalent to prngd_create
+ * followed by prngd_set_position(h, first_stream_id + i, 0) for each, but
+ * enqueues no GPU work.  On error no handle is left allocated.
+ * Errors: as prngd_create; PRNGD_ERR_INVALID_ARGUMENT for a NULL handles
+ * array or substream ids beyond 2^32 - 1.
+ */
+prngd_status_t prngd_create_many(uint64_t seed, prngd_generator_t generator,
+                                 double k, uint64_t min, uint64_t max,
+                                 uint32_t first_stream_id, uint32_t count,
+                                 prngd_handle_t *handles);
 
 /* Wait for the handle's outstanding work, then free it.  NULL is a no-op. */
 prngd_status_t prngd_destroy(prngd_handle_t h);

@@ -1,0 +1,39 @@
+/*
+ * prngd_probe.h -- measurement probes of libprngd: the ceilings that bound a
+ * PRNGD fill on the current GPU.  They compute nothing a user needs; they
+ * price the parts of the fill (stores to HBM, the Philox4x32-10 integer
+ * work of Section 2's base generator) for the roofline report.
+ *
+ * All calls enqueue one kernel on `stream` (a hipStream_t as void*, NULL =
+ * null stream) and return 0 on success, 1 for invalid arguments (nothing
+ * enqueued), 4 if the launch failed.  Buffers are caller-owned device
+ * memory.
+ */
+#ifndef PRNGD_PROBE_H
+#define PRNGD_PROBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Write n doubles (n even; out 16-byte aligned), one 16-byte store per
+ * thread over a one-shot grid: the HBM write ceiling of a fill of n
+ * outputs. */
+int prngd_probe_write(double *out, uint64_t n, void *stream);
+
+/* Compute `blocks` Philox4x32-10 blocks (a fill of n outputs of the single
+ * Philox generator needs n / 2) and fold them into one word per thread of
+ * `sink` (sink_words >= grid * 256; the grid shrinks to fit). */
+int prngd_probe_philox(uint32_t *sink, uint64_t sink_words, uint64_t blocks, void *stream);
+
+/* Philox blocks -> two pairs -> the Eq. (5) map -> 16-byte stores, every
+ * pair kept (n even; out 16-byte aligned): the fill without acceptance,
+ * compaction or the cross-block scan. */
+int prngd_probe_philox_store(double *out, uint64_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libprngd.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["prngd_kernels.hip", "prngd_runtime.cpp"]
+SOURCES = ["prngd_kernels.hip", "prngd_probes.hip", "prngd_runtime.cpp"]
 
 # -ffp-contract=off keeps every FP64 operation of the map a separate IEEE
 # operation; packed FP32 instructions are disabled for the device code.

@@ -11,11 +11,12 @@ enum Family : uint32_t {
     FAM_PHILOX = 0,   // pair p = words 2p, 2p+1 of one Philox4x32-10 stream
     FAM_MRG = 1,      // pair p = MRG32k3a outputs 2p, 2p+1
     FAM_MIXED = 2,    // pair p = (Philox word p, MRG32k3a output p)
-    FAM_ENUM = 3      // pair p = ((p >> w) mod 2^w, p mod 2^w)
+    FAM_ENUM = 3,     // pair p = ((p >> w) mod 2^w, p mod 2^w)
+    FAM_PHILOX32 = 4  // FAM_PHILOX at w = 32 (x in [0, 2^32 - 1], no shift)
 };
 
-constexpr int kBlockThreads = 256;       // 4 waves of 64 lanes
-constexpr int kWavesPerBlock = kBlockThreads / 64;
+constexpr int kMrgBlockThreads = 256;    // MRG kernels: 4 waves of 64 lanes
+constexpr int kMaxBlockThreads = 1024;
 constexpr int kMrgDigits = 8;            // window index = 8 base-256 digits
 constexpr int kMrgMatWords = 18;         // one 3x3 matrix per component
 
@@ -32,43 +33,54 @@ constexpr uint64_t kMaxOutputs = kValueMask;   // per segment (one fill)
 struct Segment {
     uint64_t seed;        // Philox key (seed lo, seed hi)
     uint64_t n;           // outputs wanted
-    uint64_t planned;     // pairs the tiles cover before the tail path
+    uint64_t planned;     // pairs the tiles were planned for (host bookkeeping)
     double *out;          // device output, 8-byte aligned
     uint64_t *counter;    // device position slot: two pair counters
     uint32_t stream_id;   // Philox counter word 3; MRG substream
     uint32_t parity;      // read counter[parity ^ flip], write the other
-    uint32_t tile_begin;  // first global tile index of the segment
-    uint32_t ntiles;      // tiles allotted (planned / T rounded up, + 1)
+    uint32_t tile_begin;  // first launch-local tile index of the segment
+    uint32_t ntiles;      // tiles of the segment; the last one also takes
+                          // every window past its own until n outputs
     uint32_t mrg[6];      // MRG32k3a state at position 0 of the substream
 };
 static_assert(sizeof(Segment) == 80, "Segment layout");
 
-// Per-workspace launch control, device memory, starts as {0, 0, 1, 0, 0}.
+// Per-workspace launch control of the look-back kernel, device memory,
+// zero except epoch = 1.  Tickets grow monotonically across launches: a
+// launch of N tiles on G workgroups consumes exactly N + G tickets (every
+// workgroup ends with one failing draw), and the workgroup that draws the
+// last of them moves `base` and `epoch` on for the next launch.  The
+// ticket counter has a cache line to itself: every tile draws from it.
 struct Control {
-    uint32_t ticket;      // next tile ticket
-    uint32_t done;        // workgroups finished
+    uint64_t ticket;      // next ticket
+    uint64_t pad0[15];
+    uint64_t base;        // first ticket of the current launch
     uint32_t epoch;       // epoch of the current launch (1 .. 2^24 - 1)
-    uint32_t flip;        // replay parity of a resident plan
     uint32_t abort;       // set when a look-back stalls: drain the launch
+    uint64_t pad1[14];
 };
+static_assert(sizeof(Control) == 256, "Control layout");
 
 struct LaunchArgs {
-    const Segment *segs;  // nseg descriptors sorted by tile_begin, or null
-    Segment seg0;         // the descriptor when segs is null (nseg == 1)
+    const Segment *segs;      // nseg descriptors, or null for seg0
+    const uint32_t *tile_seg; // launch-local tile -> segment index (segs only)
+    Segment seg0;             // the descriptor when segs is null
     uint32_t nseg;
     uint32_t total_tiles;
-    uint64_t *status;     // total_tiles status words
+    uint64_t *status;         // total_tiles status words
     Control *ctl;
-    uint32_t *error;      // host-mapped error word
-    uint32_t use_flip;    // 1: parity ^= ctl->flip, toggled per launch
-    uint32_t store_mode;  // 0 default, 1 8-byte stores, 2 nontemporal
+    uint32_t *error;          // host-mapped error word
+    const uint32_t *flip;     // replay parity of a resident plan, or null
+    uint32_t store_mode;      // 0 default, 1 8-byte stores, 2 nontemporal
     uint32_t w;
-    uint32_t a0, a;       // x1 range [a0, a]
-    uint32_t b0;          // x2 lower bound
-    double S;             // RN((1 - 2^-2w) / D)
+    uint32_t a0, a;           // x1 range [a0, a]
+    uint32_t b0;              // x2 lower bound
+    double S;                 // RN((1 - 2^-2w) / D)
     const uint32_t *mrg_thread;  // [256][18]: A^(r * tid * PPL)
     const uint32_t *mrg_window;  // [8][256][18]: A^(r * T * d * 256^i)
 };
+
+constexpr uint32_t kMaxTiles = 0xFFFFFFF0u;
 
 // Device error codes (bit flags in the error word).
 constexpr uint32_t kErrLookbackStall = 1;

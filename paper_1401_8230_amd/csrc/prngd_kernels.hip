@@ -1,10 +1,12 @@
 // prngd_kernels.hip -- gfx950 fill kernels of libprngd.
 //
 // One launch fills one or more segments (a segment = the next n outputs of
-// one handle).  Each segment's pair range is cut into tiles of
-// T = 256 * PPL consecutive pairs aligned to multiples of T; workgroups take
-// tiles in ticket order, so a tile only ever waits for tiles that are
-// already running.  Per tile:
+// one handle).  A segment's pairs are cut into windows of T = B * PPL
+// consecutive pairs aligned to multiples of T (B threads per workgroup,
+// PPL pairs per thread); tile t of a segment is its t-th window, the first
+// one clipped at the start position.  Workgroups draw tiles in ticket
+// order, so a tile only ever waits for tiles that are already running.
+// Per tile:
 //   1. base words in registers (Philox4x32-10, MRG32k3a, or the test
 //      enumeration), the word transform x >> (32 - w);
 //   2. accept/reject of x1 (Section 2 of the paper: x1 = a0 or x1 = a is
@@ -13,10 +15,10 @@
 //   4. order-preserving compaction: wave ballot + popcount, a block scan
 //      in LDS, and a decoupled look-back over the segment's earlier tiles
 //      for the tile's exclusive output offset;
-//   5. coalesced stores, and the tile that writes output n - 1 stores the
+//   5. coalesced stores; the thread that writes output n - 1 stores the
 //      handle's next pair counter.
-// The last real tile of a segment continues past the planned pairs if
-// rejections left the segment short ("take next pair" until n outputs).
+// The segment's last tile continues window by window until n outputs
+// exist ("take next pair" past every rejection).
 #include <hip/hip_runtime.h>
 
 #include "prngd_internal.hpp"
@@ -29,7 +31,9 @@ typedef double double2v __attribute__((ext_vector_type(2)));
 // ---------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies; the high halves are XORed with the other counter
-// words and the round key, the key advances by the Weyl constants.
+// words and the round key, the key advances by the Weyl constants.  Each
+// three-way XOR is one gfx950 v_bitop3_b32 (truth table 0x96 = a ^ b ^ c),
+// and each 32x32->64 product one v_mad_u64_u32.
 constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
 constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kWeyl0 = 0x9E3779B9u;
@@ -46,8 +50,8 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = uint64_t(kPhiloxM0) * c0;
         const uint64_t p1 = uint64_t(kPhiloxM1) * c2;
-        const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(uint32_t(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(uint32_t(p0 >> 32), c3, k1, 0x96);
         c1 = uint32_t(p1);
         c3 = uint32_t(p0);
         c0 = n0;
@@ -113,17 +117,24 @@ struct Mrg {
 
 // ------------------------------------------------------------- the map
 // Eq. (5) in integer units: N = (x1 - a0 - 1) 2^w + (x2 - b0) is rounded to
-// FP64 once (the 2^w scaling of the high part is exact, so this is also
-// what an FMA would give), multiplied by the folded constant S with one
-// rounding, and forced below 1 when the product rounds up to 1.0.
+// FP64 once -- the fused multiply-add of the exact product hi * 2^w and lo
+// rounds once, exactly like converting the 64-bit integer N -- multiplied
+// by the folded constant S with one rounding, and forced below 1: the
+// largest double below 1 is the only value between a product that rounded
+// up to 1.0 and every product that did not.
+constexpr double kBelowOne = 0x1.fffffffffffffp-1;
+
+__device__ __forceinline__ double map_hi_lo(uint32_t hi, uint32_t lo, double two_w, double S)
+{
+    const double N = __builtin_fma(double(hi), two_w, double(lo));
+    const double z = N * S;
+    return z < kBelowOne ? z : kBelowOne;
+}
+
 __device__ __forceinline__ double prngd_map(uint32_t x1, uint32_t x2, const LaunchArgs &a,
                                             double two_w)
 {
-    const double hi = double(x1 - a.a0 - 1u);
-    const double lo = double(x2 - a.b0);
-    const double N = hi * two_w + lo;
-    const double z = N * a.S;
-    return z >= 1.0 ? 0x1.fffffffffffffp-1 : z;
+    return map_hi_lo(x1 - a.a0 - 1u, x2 - a.b0, two_w, a.S);
 }
 
 // ------------------------------------------------------- wave utilities
@@ -149,6 +160,33 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
     for (int d = 32; d >= 1; d >>= 1)
         v += __shfl_xor(v, d, 64);
     return v;
+}
+
+// Exclusive scan of cnt[0 .. E) in place by wave 0 (E <= 64 * K); the
+// total lands in cnt[E].
+template <int E>
+__device__ __forceinline__ void wave0_scan(uint32_t *cnt, uint32_t lane)
+{
+    constexpr int K = (E + 63) / 64;
+    uint32_t loc[K];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint32_t idx = lane * K + k;
+        loc[k] = idx < uint32_t(E) ? cnt[idx] : 0u;
+        sum += loc[k];
+    }
+    const uint32_t inc = wave_incl_scan(sum, lane);
+    uint32_t run = inc - sum;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint32_t idx = lane * K + k;
+        if (idx < uint32_t(E))
+            cnt[idx] = run;
+        run += loc[k];
+    }
+    if (lane == 63)
+        cnt[E] = inc;
 }
 
 // ------------------------------------------------ status words, tickets
@@ -219,186 +257,282 @@ __device__ uint64_t look_back(uint64_t *status, uint32_t g, uint32_t t, uint32_t
     }
 }
 
-__device__ __forceinline__ Segment load_segment(const LaunchArgs &args, uint32_t ticket)
-{
-    if (args.segs == nullptr)
-        return args.seg0;
-    uint32_t lo = 0, hi = args.nseg;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (args.segs[mid].tile_begin <= ticket)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return args.segs[lo];
-}
-
-// Geometry of tile t of a segment whose fill starts at pair c0.
-struct TileGeom {
-    uint64_t win;        // window index: pairs [win * T, (win + 1) * T)
-    uint64_t lo, hi;     // pairs of this fill inside the window
-    uint32_t nreal;      // windows the planned range touches
+// Launch-wide values every workgroup of the look-back kernel reads once at
+// its start.
+struct LaunchState {
+    uint64_t base;
+    uint32_t epoch;
+    uint32_t flip;
 };
 
-template <uint64_t T>
-__device__ __forceinline__ TileGeom tile_geom(uint64_t c0, uint64_t planned, uint32_t t)
+__device__ __forceinline__ uint32_t read_flip(const LaunchArgs &args)
 {
-    TileGeom g;
-    const uint64_t w0 = c0 / T;
-    const uint64_t end = c0 + planned;               // one past the last planned pair
-    g.nreal = uint32_t((end - 1) / T - w0 + 1);
-    g.win = w0 + t;
-    const uint64_t ws = g.win * T;
-    g.lo = ws > c0 ? ws : c0;
-    g.hi = ws + T < end ? ws + T : end;
-    return g;
+    return args.flip ? *args.flip : 0u;
 }
+
+__device__ __forceinline__ LaunchState read_launch_state(const LaunchArgs &args,
+                                                         LaunchState *s_state)
+{
+    if (threadIdx.x == 0) {
+        // acquire: this read completes before this workgroup draws tickets
+        LaunchState st;
+        st.base = __hip_atomic_load(&args.ctl->base, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        st.epoch = __hip_atomic_load(&args.ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st.flip = read_flip(args);
+        *s_state = st;
+    }
+    __syncthreads();
+    return *s_state;
+}
+
+// Tickets are drawn by thread 0 in two halves: issue() sends the atomic
+// without waiting for it, finish() turns the result into a launch-local
+// tile index, or ~0u when the launch has no tiles left.  The draw of the
+// launch's very last ticket moves the control block on for the next
+// launch.
+__device__ __forceinline__ uint64_t issue_ticket(const LaunchArgs &args)
+{
+    return __hip_atomic_fetch_add(&args.ctl->ticket, uint64_t(1), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t finish_ticket(const LaunchArgs &args, const LaunchState &st,
+                                                  uint64_t tk)
+{
+    Control *ctl = args.ctl;
+    const uint64_t local = tk - st.base;
+    const uint64_t total = args.total_tiles;
+    if (local == total + gridDim.x - 1) {
+        const uint32_t next = st.epoch >= kEpochMask ? 1u : st.epoch + 1u;
+        __hip_atomic_store(&ctl->base, st.base + total + gridDim.x, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->epoch, next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->abort, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return local < total ? uint32_t(local) : ~0u;
+}
+
+// Descriptors, the tile map and the start positions are read-only while a
+// launch runs (a fill writes only the other half of each position slot),
+// so they are read through the constant address space: uniform scalar
+// loads into SGPRs instead of vector loads into VGPRs.
+typedef __attribute__((address_space(4))) const uint32_t constant_u32;
+typedef __attribute__((address_space(4))) const uint64_t constant_u64;
+
+__device__ __forceinline__ Segment load_segment(const Segment *segs, uint32_t i)
+{
+    static_assert(sizeof(Segment) % 8 == 0, "Segment is read as 64-bit words");
+    constexpr int kWords = sizeof(Segment) / 8;
+    const constant_u64 *src = (const constant_u64 *)(segs + i);
+    uint64_t w[kWords];
+#pragma unroll
+    for (int k = 0; k < kWords; ++k)
+        w[k] = src[k];
+    Segment s;
+    __builtin_memcpy(&s, w, sizeof s);
+    return s;
+}
+
+__device__ __forceinline__ uint64_t load_start(const Segment &seg, uint32_t par)
+{
+    return ((constant_u64 *)seg.counter)[par];
+}
+
+__device__ __forceinline__ void lookup(const LaunchArgs &args, uint32_t local, Segment *seg,
+                                       uint32_t *t)
+{
+    if (args.segs == nullptr) {
+        *seg = args.seg0;
+        *t = local;
+    } else {
+        const uint32_t si = ((constant_u32 *)args.tile_seg)[local];
+        *seg = load_segment(args.segs, si);
+        *t = local - seg->tile_begin;
+    }
+}
+
+typedef __attribute__((address_space(1))) double global_double;
+typedef __attribute__((address_space(1))) double2v global_double2;
 
 __device__ __forceinline__ void store_one(double *p, double v, uint32_t mode)
 {
+    global_double *g = (global_double *)p;
     if (mode == 2)
-        __builtin_nontemporal_store(v, p);
+        __builtin_nontemporal_store(v, g);
     else
-        *p = v;
+        *g = v;
 }
 
 __device__ __forceinline__ void store_two(double *p, double v0, double v1, uint32_t mode)
 {
-    double2v v = {v0, v1};
+    const double2v v = {v0, v1};
+    global_double2 *g = (global_double2 *)p;
     if (mode == 2)
-        __builtin_nontemporal_store(v, reinterpret_cast<double2v *>(p));
+        __builtin_nontemporal_store(v, g);
     else
-        *reinterpret_cast<double2v *>(p) = v;
-}
-
-__device__ __forceinline__ void finish_launch(const LaunchArgs &args, uint32_t epoch)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        Control *ctl = args.ctl;
-        const uint32_t prev = __hip_atomic_fetch_add(&ctl->done, 1u, __ATOMIC_ACQ_REL,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == gridDim.x - 1) {
-            // every workgroup has taken its last ticket: reset for the next launch
-            const uint32_t next = epoch >= kEpochMask ? 1u : epoch + 1u;
-            __hip_atomic_store(&ctl->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->epoch, next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->abort, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (args.use_flip)
-                __hip_atomic_store(&ctl->flip, ctl->flip ^ 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-}
-
-// Next tile ticket of this workgroup, or ~0 once the launch is aborted.
-__device__ __forceinline__ uint32_t next_ticket(Control *ctl, uint32_t *s_ticket)
-{
-    if (threadIdx.x == 0) {
-        const uint32_t t = __hip_atomic_fetch_add(&ctl->ticket, 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t ab = __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-        *s_ticket = ab ? ~0u : t;
-    }
-    __syncthreads();
-    return __builtin_amdgcn_readfirstlane(*s_ticket);
+        *g = v;
 }
 
 // ======================================================================
-// Philox / enumerate family.  Thread (wave v, lane l) of the block takes
-// Philox block  win * T / 2 + j * 256 + 64 v + l  for j < PPL / 2, i.e. the
-// two consecutive pairs 2b, 2b + 1; for a fixed j a wave covers 128
-// consecutive pairs, so its outputs are contiguous in memory.
+// Philox / enumerate family.  Thread tid of the B-thread workgroup takes
+// Philox block  win * T / 2 + j * B + tid  for j < PPL / 2, i.e. the two
+// consecutive pairs at window offsets q = 2 (j B + tid) and q + 1; for a
+// fixed j a wave covers 128 consecutive pairs, so its outputs are
+// contiguous in memory.
+//
+// A window is "clean" when it starts at offset 0 and keeps every pair --
+// at w = 32 all but a fraction 2^-31 of windows.  Its outputs are then
+// consecutive from the window's offset and need neither ranks nor a scan;
+// only windows with a rejection or a clipped start take the general path
+// (ballots, per-(j, wave) counts, an LDS scan).
 // ======================================================================
-template <int PPL, uint32_t FAM>
+template <int NW, int PPL, uint32_t FAM>
 struct PhiloxTile {
+    static constexpr int B = 64 * NW;
     static constexpr int J = PPL / 2;
-    static constexpr uint64_t T = uint64_t(kBlockThreads) * PPL;
+    static constexpr uint32_t T = uint32_t(B) * PPL;
+    static constexpr int E = J * NW;           // (j, wave) groups in pair order
+    static constexpr uint32_t kAll = PPL == 32 ? 0xFFFFFFFFu : ((1u << PPL) - 1u);
 
     double v[PPL];
-    uint32_t acc;          // bit i: pair i of this thread accepted
+    uint32_t acc;                              // bit i: pair i of this thread kept
+    bool clean;                                // every pair of the window kept
 
-    // Generate, accept and map the pairs of window `win` restricted to
-    // [lo, hi); leaves per-(j, wave) exclusive offsets in s_off and
-    // returns the tile's accepted count.
+    // Generate window `win` from window offset lo_off on and return the
+    // window's number of accepted pairs; for a window that is not clean the
+    // exclusive offset of every (j, wave) group is left in s_off.
     __device__ __forceinline__ uint32_t generate(const LaunchArgs &args, const Segment &seg,
-                                                 uint64_t win, uint64_t lo, uint64_t hi,
-                                                 uint32_t *s_off, uint32_t *s_total)
+                                                 uint64_t win, uint32_t lo_off, uint32_t *s_off)
     {
         const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-        const uint32_t shift = 32u - args.w;
-        const double two_w = double(uint64_t(1) << args.w);
         const uint64_t blk0 = win * (T / 2);
         const uint32_t k0 = uint32_t(seg.seed), k1 = uint32_t(seg.seed >> 32);
         acc = 0;
+        if (FAM == FAM_PHILOX32) {
+            // x in [0, 2^32 - 1]: keep x1 unless x1 + 1 wraps to 0 or is 1
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const uint64_t slab = 2 * (blk0 + uint64_t(j) * kBlockThreads);   // first pair of slab j
-            const uint64_t blk = blk0 + uint64_t(j) * kBlockThreads + tid;
-            const uint64_t p = 2 * blk;
-            uint32_t x1a, x2a, x1b, x2b;
-            if (slab + 2 * kBlockThreads <= lo || slab >= hi) {
-                x1a = x2a = x1b = x2b = args.a0;      // slab outside the fill
-            } else if (FAM == FAM_PHILOX) {
+            for (int j = 0; j < J; ++j) {
+                const uint64_t blk = blk0 + uint32_t(j) * B + tid;
                 const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u,
                                                seg.stream_id, k0, k1);
-                x1a = r.v0 >> shift;
-                x2a = r.v1 >> shift;
-                x1b = r.v2 >> shift;
-                x2b = r.v3 >> shift;
-            } else {
-                const uint64_t mask = (uint64_t(1) << args.w) - 1;
-                x1a = uint32_t((p >> args.w) & mask);
-                x2a = uint32_t(p & mask);
-                x1b = uint32_t(((p + 1) >> args.w) & mask);
-                x2b = uint32_t((p + 1) & mask);
+                const bool oka = r.v0 + 1u >= 2u;
+                const bool okb = r.v2 + 1u >= 2u;
+                v[2 * j] = map_hi_lo(r.v0 - 1u, r.v1, 4294967296.0, args.S);
+                v[2 * j + 1] = map_hi_lo(r.v2 - 1u, r.v3, 4294967296.0, args.S);
+                acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
             }
-            const bool oka = p >= lo && p < hi && x1a != args.a0 && x1a != args.a;
-            const bool okb = p + 1 >= lo && p + 1 < hi && x1b != args.a0 && x1b != args.a;
-            v[2 * j] = prngd_map(x1a, x2a, args, two_w);
-            v[2 * j + 1] = prngd_map(x1b, x2b, args, two_w);
-            acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
-            const uint64_t ba = __ballot(oka), bb = __ballot(okb);
+        } else {
+            const uint32_t shift = 32u - args.w;
+            const double two_w = double(uint64_t(1) << args.w);
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                uint32_t x1a, x2a, x1b, x2b;
+                if (FAM == FAM_PHILOX) {
+                    const uint64_t blk = blk0 + uint32_t(j) * B + tid;
+                    const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u,
+                                                   seg.stream_id, k0, k1);
+                    x1a = r.v0 >> shift;
+                    x2a = r.v1 >> shift;
+                    x1b = r.v2 >> shift;
+                    x2b = r.v3 >> shift;
+                } else {
+                    const uint64_t p = win * T + 2u * (uint32_t(j) * B + tid);
+                    const uint64_t mask = (uint64_t(1) << args.w) - 1;
+                    x1a = uint32_t((p >> args.w) & mask);
+                    x2a = uint32_t(p & mask);
+                    x1b = uint32_t(((p + 1) >> args.w) & mask);
+                    x2b = uint32_t((p + 1) & mask);
+                }
+                const bool oka = x1a != args.a0 && x1a != args.a;
+                const bool okb = x1b != args.a0 && x1b != args.a;
+                v[2 * j] = prngd_map(x1a, x2a, args, two_w);
+                v[2 * j + 1] = prngd_map(x1b, x2b, args, two_w);
+                acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
+            }
+        }
+        if (lo_off != 0) {
+            // clipped first window: pairs before the start position are not
+            // part of this fill
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const uint32_t q = 2u * (uint32_t(j) * B + tid);
+                if (q < lo_off)
+                    acc &= ~(1u << (2 * j));
+                if (q + 1 < lo_off)
+                    acc &= ~(1u << (2 * j + 1));
+            }
+        }
+        clean = !__syncthreads_or(lo_off != 0 || acc != kAll);
+        if (clean)
+            return T;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint64_t ba = __ballot((acc >> (2 * j)) & 1u);
+            const uint64_t bb = __ballot((acc >> (2 * j + 1)) & 1u);
             if (lane == 0)
-                s_off[j * kWavesPerBlock + wave] = uint32_t(__popcll(ba) + __popcll(bb));
+                s_off[j * NW + wave] = uint32_t(__popcll(ba) + __popcll(bb));
         }
         __syncthreads();
-        // exclusive scan over (j, wave) in pair order, by wave 0
-        if (wave == 0) {
-            const uint32_t e = lane;
-            const uint32_t c = e < uint32_t(J * kWavesPerBlock) ? s_off[e] : 0u;
-            const uint32_t inc = wave_incl_scan(c, lane);
-            if (e < uint32_t(J * kWavesPerBlock))
-                s_off[e] = inc - c;
-            if (lane == 63)
-                *s_total = inc;
-        }
+        if (wave == 0)
+            wave0_scan<E>(s_off, lane);
         __syncthreads();
-        return *s_total;
+        return s_off[E];
     }
 
-    // Store the accepted outputs of this tile at segment offset `excl`.
+    // Store the kept outputs of window `win` at segment offset `excl`.
     __device__ __forceinline__ void store(const LaunchArgs &args, const Segment &seg,
                                           uint64_t win, uint64_t excl, uint64_t *next_counter,
                                           const uint32_t *s_off)
     {
-        const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-        const uint64_t lt = lanemask_lt(lane);
-        const uint64_t blk0 = win * (T / 2);
+        const uint32_t tid = threadIdx.x;
         const uint64_t n = seg.n;
+        if (clean) {
+            // pair q of the window is output excl + q
+            double *o = seg.out + excl;
+            const bool aligned = args.store_mode != 1 &&
+                                 (reinterpret_cast<uintptr_t>(o) & 15u) == 0;
+            if (excl + T < n) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const uint32_t q = 2u * (uint32_t(j) * B + tid);
+                    if (aligned) {
+                        store_two(o + q, v[2 * j], v[2 * j + 1], args.store_mode);
+                    } else {
+                        store_one(o + q, v[2 * j], args.store_mode);
+                        store_one(o + q + 1, v[2 * j + 1], args.store_mode);
+                    }
+                }
+            } else {
+                // the window holds output n - 1
+                const uint64_t left = n - excl;
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const uint32_t q = 2u * (uint32_t(j) * B + tid);
+                    if (aligned && q + 1 < left) {
+                        store_two(o + q, v[2 * j], v[2 * j + 1], args.store_mode);
+                    } else {
+                        if (q < left)
+                            store_one(o + q, v[2 * j], args.store_mode);
+                        if (q + 1 < left)
+                            store_one(o + q + 1, v[2 * j + 1], args.store_mode);
+                    }
+                    if (q + 1 == left || q + 2 == left)
+                        *next_counter = win * T + left;
+                }
+            }
+            return;
+        }
+        const uint32_t lane = tid & 63u, wave = tid >> 6;
+        const uint64_t lt = lanemask_lt(lane);
         double *out = seg.out;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             const bool oka = (acc >> (2 * j)) & 1u;
             const bool okb = (acc >> (2 * j + 1)) & 1u;
             const uint64_t ba = __ballot(oka), bb = __ballot(okb);
-            const uint64_t pos_a = excl + s_off[j * kWavesPerBlock + wave] +
+            const uint64_t pos_a = excl + s_off[j * NW + wave] +
                                    uint32_t(__popcll(ba & lt) + __popcll(bb & lt));
             const uint64_t pos_b = pos_a + (oka ? 1u : 0u);
-            const uint64_t pair = 2 * (blk0 + uint64_t(j) * kBlockThreads + tid);
             if (oka && okb && pos_b < n && args.store_mode != 1 &&
                 ((reinterpret_cast<uintptr_t>(out + pos_a) & 15u) == 0)) {
                 store_two(out + pos_a, v[2 * j], v[2 * j + 1], args.store_mode);
@@ -408,11 +542,189 @@ struct PhiloxTile {
                 if (okb && pos_b < n)
                     store_one(out + pos_b, v[2 * j + 1], args.store_mode);
             }
-            if (oka && pos_a == n - 1)
-                *next_counter = pair + 1;
-            if (okb && pos_b == n - 1)
-                *next_counter = pair + 2;
+            const bool last_a = oka && pos_a == n - 1;
+            const bool last_b = okb && pos_b == n - 1;
+            if (last_a || last_b)
+                *next_counter = win * T + 2u * (uint32_t(j) * B + tid) + (last_a ? 1u : 2u);
         }
+    }
+};
+
+// ======================================================================
+// Philox / enumerate family, store-as-you-go form for the segment-
+// sequential kernel, where a window's output offset `excl` is known before
+// the window is generated.  Every pair is mapped and stored at once at
+// excl + q as if the window kept all its pairs, so no value stays in a
+// register.  A window that turns out not to be clean (a rejection, or a
+// clipped start) is redone exactly: counts from the kept-pair bits, a scan,
+// then the pairs are generated again and stored at their true ranks.  The
+// speculative stores it made land either on positions it rewrites or on
+// positions that later windows of the same workgroup own and rewrite
+// after a barrier; positions at or past n are never written.
+// ======================================================================
+template <int NW, int PPL, uint32_t FAM>
+struct SpecTile {
+    static constexpr int B = 64 * NW;
+    static constexpr int J = PPL / 2;
+    static constexpr uint32_t T = uint32_t(B) * PPL;
+    static constexpr int E = J * NW;
+    static constexpr uint32_t kAll = PPL == 32 ? 0xFFFFFFFFu : ((1u << PPL) - 1u);
+
+    // The two pairs of thread slot j, as the Eq. (5) operands
+    // hi = x1 - a0 - 1 and lo = x2 - b0.  A pair is kept iff hi < hmax with
+    // hmax = a - a0 - 1: x1 = a0 wraps hi to 2^32 - 1 and x1 = a gives
+    // hi = hmax, the two rejected values of Section 2.
+    struct HiLo {
+        uint32_t ha, la, hb, lb;
+    };
+
+    __device__ __forceinline__ static HiLo words(const LaunchArgs &args, const Segment &seg,
+                                                 uint64_t win, int j)
+    {
+        const uint32_t tid = threadIdx.x;
+        uint32_t x1a, x2a, x1b, x2b;
+        if (FAM == FAM_ENUM) {
+            const uint64_t q = win * T + 2u * (uint32_t(j) * B + tid);
+            const uint64_t mask = (uint64_t(1) << args.w) - 1;
+            x1a = uint32_t((q >> args.w) & mask);
+            x2a = uint32_t(q & mask);
+            x1b = uint32_t(((q + 1) >> args.w) & mask);
+            x2b = uint32_t((q + 1) & mask);
+        } else {
+            const uint64_t blk = win * (T / 2) + uint32_t(j) * B + tid;
+            const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u,
+                                           seg.stream_id, uint32_t(seg.seed),
+                                           uint32_t(seg.seed >> 32));
+            if (FAM == FAM_PHILOX32) {
+                x1a = r.v0; x2a = r.v1; x1b = r.v2; x2b = r.v3;
+            } else {
+                const uint32_t shift = 32u - args.w;
+                x1a = r.v0 >> shift; x2a = r.v1 >> shift;
+                x1b = r.v2 >> shift; x2b = r.v3 >> shift;
+            }
+        }
+        if (FAM == FAM_PHILOX32)
+            return {x1a - 1u, x2a, x1b - 1u, x2b};
+        return {x1a - args.a0 - 1u, x2a - args.b0, x1b - args.a0 - 1u, x2b - args.b0};
+    }
+
+    __device__ __forceinline__ static double two_w(const LaunchArgs &args)
+    {
+        return FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+    }
+
+    __device__ __forceinline__ static uint32_t hmax(const LaunchArgs &args)
+    {
+        return FAM == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
+    }
+
+    // Produce window `win` (from window offset lo_off on) at segment offset
+    // excl; returns the window's number of accepted pairs.
+    __device__ __forceinline__ uint32_t run(const LaunchArgs &args, const Segment &seg,
+                                            uint64_t win, uint32_t lo_off, uint64_t excl,
+                                            uint64_t *next_counter, uint32_t *s_off)
+    {
+        const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+        const uint64_t n = seg.n;
+        double *o = seg.out + excl;
+        const uint64_t left = n - excl;       // outputs still wanted, >= 1
+        const bool aligned = args.store_mode != 1 && (reinterpret_cast<uintptr_t>(o) & 15u) == 0;
+        const uint32_t hm = hmax(args);
+        const double tw = two_w(args);
+        uint32_t acc = 0;
+        bool dirty;
+        if (lo_off == 0 && left > T) {
+            // a full window that does not hold output n - 1: no bounds, no
+            // counter; one running max of hi finds any rejection
+            uint32_t mx = 0;
+#pragma unroll 2
+            for (int j = 0; j < J; ++j) {
+                const uint32_t q = 2u * (uint32_t(j) * B + tid);
+                const HiLo p = words(args, seg, win, j);
+                mx = max(mx, max(p.ha, p.hb));
+                const double za = map_hi_lo(p.ha, p.la, tw, args.S);
+                const double zb = map_hi_lo(p.hb, p.lb, tw, args.S);
+                if (aligned) {
+                    store_two(o + q, za, zb, args.store_mode);
+                } else {
+                    store_one(o + q, za, args.store_mode);
+                    store_one(o + q + 1, zb, args.store_mode);
+                }
+            }
+            dirty = __syncthreads_or(mx >= hm);
+            if (!dirty)
+                return T;
+#pragma unroll 1
+            for (int j = 0; j < J; ++j) {
+                const HiLo p = words(args, seg, win, j);
+                acc |= (uint32_t(p.ha < hm) << (2 * j)) | (uint32_t(p.hb < hm) << (2 * j + 1));
+            }
+        } else {
+#pragma unroll 2
+            for (int j = 0; j < J; ++j) {
+                const uint32_t q = 2u * (uint32_t(j) * B + tid);
+                const HiLo p = words(args, seg, win, j);
+                const bool oka = p.ha < hm && q >= lo_off;
+                const bool okb = p.hb < hm && q + 1 >= lo_off;
+                acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
+                if (lo_off == 0) {
+                    const double za = map_hi_lo(p.ha, p.la, tw, args.S);
+                    const double zb = map_hi_lo(p.hb, p.lb, tw, args.S);
+                    if (aligned && q + 1 < left) {
+                        store_two(o + q, za, zb, args.store_mode);
+                    } else {
+                        if (q < left)
+                            store_one(o + q, za, args.store_mode);
+                        if (q + 1 < left)
+                            store_one(o + q + 1, zb, args.store_mode);
+                    }
+                    if (q + 1 == left || q + 2 == left)
+                        *next_counter = win * T + left;
+                }
+            }
+            dirty = __syncthreads_or(lo_off != 0 || acc != kAll);
+            if (!dirty)
+                return T;
+        }
+        // not clean: exact ranks, then generate and store again
+#pragma unroll 1
+        for (int j = 0; j < J; ++j) {
+            const uint64_t ba = __ballot((acc >> (2 * j)) & 1u);
+            const uint64_t bb = __ballot((acc >> (2 * j + 1)) & 1u);
+            if (lane == 0)
+                s_off[j * NW + wave] = uint32_t(__popcll(ba) + __popcll(bb));
+        }
+        __syncthreads();
+        if (wave == 0)
+            wave0_scan<E>(s_off, lane);
+        __syncthreads();
+        const uint64_t lt = lanemask_lt(lane);
+#pragma unroll 1
+        for (int j = 0; j < J; ++j) {
+            const bool oka = (acc >> (2 * j)) & 1u;
+            const bool okb = (acc >> (2 * j + 1)) & 1u;
+            const uint64_t ba = __ballot(oka), bb = __ballot(okb);
+            const uint32_t pos_a = s_off[j * NW + wave] +
+                                   uint32_t(__popcll(ba & lt) + __popcll(bb & lt));
+            const uint32_t pos_b = pos_a + (oka ? 1u : 0u);
+            if (oka || okb) {
+                const HiLo p = words(args, seg, win, j);
+                const double za = map_hi_lo(p.ha, p.la, tw, args.S);
+                const double zb = map_hi_lo(p.hb, p.lb, tw, args.S);
+                if (oka && pos_a < left)
+                    store_one(o + pos_a, za, args.store_mode);
+                if (okb && pos_b < left)
+                    store_one(o + pos_b, zb, args.store_mode);
+            }
+            const uint32_t q = 2u * (uint32_t(j) * B + tid);
+            if (oka && pos_a + 1 == left)
+                *next_counter = win * T + q + 1;
+            if (okb && pos_b + 1 == left)
+                *next_counter = win * T + q + 2;
+        }
+        const uint32_t total = s_off[E];
+        __syncthreads();
+        return total;
     }
 };
 
@@ -429,28 +741,28 @@ __device__ __forceinline__ uint32_t pad_index(uint32_t i)
 
 template <int PPL, uint32_t FAM>
 struct MrgTile {
-    static constexpr uint64_t T = uint64_t(kBlockThreads) * PPL;
+    static constexpr int B = kMrgBlockThreads;
+    static constexpr uint32_t T = uint32_t(B) * PPL;
     static constexpr uint32_t R = FAM == FAM_MRG ? 2u : 1u;   // MRG outputs per pair
     static_assert(PPL % 4 == 0, "Philox blocks must not straddle threads");
 
     double v[PPL];
     uint32_t acc;
-    uint32_t thread_off;   // exclusive offset of this thread inside the tile
+    uint32_t thread_off;   // exclusive offset of this thread inside the window
 
     __device__ __forceinline__ uint32_t generate(const LaunchArgs &args, const Segment &seg,
-                                                 uint64_t win, uint64_t lo, uint64_t hi,
-                                                 uint32_t *s_wave, uint32_t *s_total)
+                                                 uint64_t win, uint32_t lo_off, uint32_t *s_wave)
     {
         const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
         const double two_w = double(uint64_t(1) << args.w);
-        const uint64_t p0 = win * T + uint64_t(tid) * PPL;
+        const uint32_t q0 = tid * PPL;             // window offset of the first pair
         acc = 0;
-        if (p0 + PPL > lo && p0 < hi) {
+        if (q0 + PPL > lo_off) {
             Mrg g;
 #pragma unroll
             for (int i = 0; i < 6; ++i)
                 g.s[i] = seg.mrg[i];
-            // jump to MRG position R * p0 = R * T * win + R * PPL * tid
+            // jump to MRG position R * (win * T + q0)
             uint64_t m = win;
             for (int d = 0; d < kMrgDigits && m != 0; ++d, m >>= 8) {
                 const uint32_t digit = uint32_t(m & 255u);
@@ -462,11 +774,10 @@ struct MrgTile {
             Words4 ph = {0, 0, 0, 0};
 #pragma unroll
             for (int i = 0; i < PPL; ++i) {
-                const uint64_t p = p0 + i;
                 uint32_t x1, x2;
                 if (FAM == FAM_MIXED) {
                     if ((i & 3) == 0) {
-                        const uint64_t blk = p >> 2;
+                        const uint64_t blk = (win * T + q0 + i) >> 2;
                         ph = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u,
                                            seg.stream_id, k0, k1);
                     }
@@ -476,7 +787,7 @@ struct MrgTile {
                     x1 = g.next();
                     x2 = g.next();
                 }
-                const bool ok = p >= lo && p < hi && x1 != args.a0 && x1 != args.a;
+                const bool ok = q0 + i >= lo_off && x1 != args.a0 && x1 != args.a;
                 v[i] = prngd_map(ok ? x1 : args.a0 + 1u, ok ? x2 : args.b0, args, two_w);
                 acc |= uint32_t(ok) << i;
             }
@@ -488,14 +799,13 @@ struct MrgTile {
         __syncthreads();
         uint32_t before = 0, total = 0;
 #pragma unroll
-        for (int k = 0; k < kWavesPerBlock; ++k) {
+        for (int k = 0; k < B / 64; ++k) {
             const uint32_t t = s_wave[k];
             before += uint32_t(k) < wave ? t : 0u;
             total += t;
         }
         thread_off = before + inc - c;
-        __syncthreads();       // s_wave is reused by the next tile
-        (void)s_total;
+        __syncthreads();       // s_wave is reused by the next window
         return total;
     }
 
@@ -505,154 +815,278 @@ struct MrgTile {
     {
         const uint32_t tid = threadIdx.x;
         const uint64_t n = seg.n;
-        const uint64_t p0 = win * T + uint64_t(tid) * PPL;
         uint32_t k = thread_off;
 #pragma unroll
         for (int i = 0; i < PPL; ++i) {
             if ((acc >> i) & 1u) {
                 s_vals[pad_index(k)] = v[i];
                 if (excl + k == n - 1)
-                    *next_counter = p0 + i + 1;
+                    *next_counter = win * T + tid * PPL + i + 1;
                 ++k;
             }
         }
         __syncthreads();
         double *out = seg.out;
-        for (uint32_t i = tid; i < total; i += kBlockThreads) {
+        for (uint32_t i = tid; i < total; i += B) {
             const uint64_t pos = excl + i;
             if (pos < n)
                 store_one(out + pos, s_vals[pad_index(i)], args.store_mode == 1 ? 0u : args.store_mode);
         }
-        __syncthreads();       // s_vals is reused by the next tile
+        __syncthreads();       // s_vals is reused by the next window
     }
 };
 
 // ======================================================================
-// Kernels.
+// The look-back fill loop shared by both families: tiles in ticket order,
+// each tile's offset from the decoupled look-back over its segment.
 // ======================================================================
-template <int PPL, uint32_t FAM>
-__global__ __launch_bounds__(kBlockThreads) void fill_philox_kernel(LaunchArgs args)
+template <class Tile, class Scratch>
+__device__ __forceinline__ void lookback_loop(const LaunchArgs &args, Scratch &sh)
 {
-    using Tile = PhiloxTile<PPL, FAM>;
-    constexpr uint64_t T = Tile::T;
-    __shared__ uint32_t s_off[Tile::J * kWavesPerBlock];
-    __shared__ uint32_t s_total;
-    __shared__ uint64_t s_excl;
-    __shared__ uint32_t s_ticket;
-
+    constexpr uint32_t T = Tile::T;
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
-    const uint32_t epoch = args.ctl->epoch;
-    const uint32_t flip = args.use_flip ? args.ctl->flip : 0u;
-
+    const LaunchState st = read_launch_state(args, &sh.state);
+    if (tid == 0)
+        sh.next = finish_ticket(args, st, issue_ticket(args));
+    __syncthreads();
     for (;;) {
-        const uint32_t ticket = next_ticket(args.ctl, &s_ticket);
-        if (ticket >= args.total_tiles)
+        const uint32_t ticket = __builtin_amdgcn_readfirstlane(sh.next);
+        if (ticket == ~0u)
             break;
-        const Segment seg = load_segment(args, ticket);
-        const uint32_t t = ticket - seg.tile_begin;
-        const uint32_t par = seg.parity ^ flip;
-        const uint64_t c0 = seg.counter[par];
+        uint64_t pending = 0;
+        if (tid == 0)
+            pending = issue_ticket(args);              // completes during this tile
+        Segment seg;
+        uint32_t t;
+        lookup(args, ticket, &seg, &t);
+        const uint32_t par = seg.parity ^ st.flip;
+        const uint64_t c0 = load_start(seg, par);
         uint64_t *next_counter = seg.counter + (par ^ 1u);
-        const TileGeom geom = tile_geom<T>(c0, seg.planned, t);
-        if (t < geom.nreal) {
-            Tile tile;
-            const uint32_t agg = tile.generate(args, seg, geom.win, geom.lo, geom.hi, s_off, &s_total);
-            if (t == 0) {
-                if (tid == 0) {
-                    publish(args.status, ticket, pack_status(epoch, kFlagPrefix, agg));
-                    s_excl = 0;
-                }
-            } else {
-                if (tid == 0)
-                    publish(args.status, ticket, pack_status(epoch, kFlagAggregate, agg));
-                if (tid < 64) {
-                    const uint64_t excl = look_back(args.status, ticket, t, epoch, args.ctl, args.error, lane);
-                    if (tid == 0) {
-                        publish(args.status, ticket, pack_status(epoch, kFlagPrefix, excl + agg));
-                        s_excl = excl;
-                    }
-                }
+        const uint64_t w0 = c0 / T;
+        const uint64_t win = w0 + t;
+        const uint32_t lo_off = t == 0 ? uint32_t(c0 - w0 * T) : 0u;
+        Tile tile;
+        const uint32_t agg = sh.generate(tile, args, seg, win, lo_off);
+        if (t == 0) {
+            if (tid == 0) {
+                publish(args.status, ticket, pack_status(st.epoch, kFlagPrefix, agg));
+                sh.excl = 0;
             }
-            __syncthreads();
-            uint64_t running = s_excl;
-            tile.store(args, seg, geom.win, running, next_counter, s_off);
-            running += agg;
-            // tail: the last real tile takes further pairs until n outputs
-            if (t == geom.nreal - 1 && running < seg.n) {
-                const uint64_t from = c0 + seg.planned;
-                for (uint64_t win = from / T; running < seg.n; ++win) {
-                    __syncthreads();
-                    const uint32_t a2 = tile.generate(args, seg, win, from, ~uint64_t(0), s_off, &s_total);
-                    tile.store(args, seg, win, running, next_counter, s_off);
-                    running += a2;
+        } else {
+            if (tid == 0)
+                publish(args.status, ticket, pack_status(st.epoch, kFlagAggregate, agg));
+            if (tid < 64) {
+                const uint64_t excl =
+                    look_back(args.status, ticket, t, st.epoch, args.ctl, args.error, lane);
+                if (tid == 0) {
+                    publish(args.status, ticket, pack_status(st.epoch, kFlagPrefix, excl + agg));
+                    sh.excl = excl;
                 }
             }
         }
         __syncthreads();
+        uint64_t running = sh.excl;
+        sh.store(tile, args, seg, win, running, agg, next_counter);
+        running += agg;
+        // the last tile takes every further window until n outputs
+        for (uint64_t w2 = win + 1; t == seg.ntiles - 1 && running < seg.n; ++w2) {
+            __syncthreads();
+            const uint32_t a2 = sh.generate(tile, args, seg, w2, 0u);
+            sh.store(tile, args, seg, w2, running, a2, next_counter);
+            running += a2;
+        }
+        if (tid == 0)
+            sh.next = finish_ticket(args, st, pending);
+        __syncthreads();
     }
-    finish_launch(args, epoch);
+}
+
+// ======================================================================
+// The segment-sequential loop: workgroups draw whole segments in ticket
+// order and produce each alone, window after window, with an exact
+// running offset -- no cross-workgroup waits.  Ticket order keeps the
+// segments being written at any moment next to each other in memory.
+// The next segment's ticket is drawn while the current one is produced.
+// ======================================================================
+template <class Tile, class Scratch>
+__device__ __forceinline__ void sequential_loop(const LaunchArgs &args, Scratch &sh)
+{
+    constexpr uint32_t T = Tile::T;
+    const uint32_t tid = threadIdx.x;
+    const LaunchState st = read_launch_state(args, &sh.state);
+    if (tid == 0)
+        sh.next = finish_ticket(args, st, issue_ticket(args));
+    __syncthreads();
+    for (;;) {
+        const uint32_t i = __builtin_amdgcn_readfirstlane(sh.next);
+        if (i == ~0u)
+            break;
+        uint64_t pending = 0;
+        if (tid == 0)
+            pending = issue_ticket(args);
+        const Segment seg = load_segment(args.segs, i);
+        const uint32_t par = seg.parity ^ st.flip;
+        const uint64_t c0 = load_start(seg, par);
+        uint64_t *next_counter = seg.counter + (par ^ 1u);
+        uint64_t win = c0 / T;
+        uint32_t lo_off = uint32_t(c0 - win * T);
+        uint64_t running = 0;
+        Tile tile;
+        while (running < seg.n) {
+            const uint32_t agg = sh.generate(tile, args, seg, win, lo_off);
+            sh.store(tile, args, seg, win, running, agg, next_counter);
+            running += agg;
+            ++win;
+            lo_off = 0;
+            __syncthreads();
+        }
+        if (tid == 0)
+            sh.next = finish_ticket(args, st, pending);
+        __syncthreads();
+    }
+}
+
+// The segment-sequential loop for the store-as-you-go Philox tile.  A
+// workgroup never waits for another one here, so it may hold two tickets
+// ahead: while segment k is produced, the descriptor of segment k + 1 is
+// loaded at once, its start position after the first window, and the
+// ticket of segment k + 2 is drawn.  Uniform loads that are in flight
+// complete at the latest at the next barrier, after a window of work.
+template <int NW, int PPL, uint32_t FAM>
+__device__ __forceinline__ void sequential_spec_loop(const LaunchArgs &args, uint32_t *s_off,
+                                                     LaunchState *s_state, uint32_t *s_next)
+{
+    using Tile = SpecTile<NW, PPL, FAM>;
+    constexpr uint32_t T = Tile::T;
+    const uint32_t tid = threadIdx.x;
+    const LaunchState st = read_launch_state(args, s_state);
+    if (tid == 0)
+        s_next[0] = finish_ticket(args, st, issue_ticket(args));
+    __syncthreads();
+    uint32_t cur = __builtin_amdgcn_readfirstlane(s_next[0]);
+    if (cur == ~0u)
+        return;
+    if (tid == 0)
+        s_next[1] = finish_ticket(args, st, issue_ticket(args));
+    Segment seg = load_segment(args.segs, cur);
+    uint64_t c0 = load_start(seg, seg.parity ^ st.flip);
+    __syncthreads();
+    uint32_t nxt = __builtin_amdgcn_readfirstlane(s_next[1]);
+    for (;;) {
+        uint64_t pending = 0;
+        if (tid == 0 && nxt != ~0u)
+            pending = issue_ticket(args);            // ticket of the segment after next
+        Segment nseg = seg;
+        if (nxt != ~0u)
+            nseg = load_segment(args.segs, nxt);
+        uint64_t nc0 = 0;
+        bool nc0_loaded = false;
+        const uint32_t par = seg.parity ^ st.flip;
+        uint64_t *next_counter = seg.counter + (par ^ 1u);
+        uint64_t win = c0 / T;
+        uint32_t lo_off = uint32_t(c0 - win * T);
+        uint64_t running = 0;
+        while (running < seg.n) {
+            running += Tile().run(args, seg, win, lo_off, running, next_counter, s_off);
+            ++win;
+            lo_off = 0;
+            if (!nc0_loaded && nxt != ~0u) {
+                nc0 = load_start(nseg, nseg.parity ^ st.flip);
+                nc0_loaded = true;
+            }
+        }
+        if (nxt == ~0u)
+            break;
+        if (!nc0_loaded)
+            nc0 = load_start(nseg, nseg.parity ^ st.flip);
+        if (tid == 0)
+            s_next[0] = finish_ticket(args, st, pending);
+        __syncthreads();
+        const uint32_t after = __builtin_amdgcn_readfirstlane(s_next[0]);
+        __syncthreads();                              // s_next[0] is rewritten next round
+        seg = nseg;
+        c0 = nc0;
+        cur = nxt;
+        nxt = after;
+    }
+    (void)cur;
+}
+
+template <int NW, int PPL, uint32_t FAM>
+struct PhiloxScratch {
+    using Tile = PhiloxTile<NW, PPL, FAM>;
+    uint32_t off[Tile::E + 1];
+    uint64_t excl;
+    uint32_t next;
+    LaunchState state;
+
+    __device__ __forceinline__ uint32_t generate(Tile &tile, const LaunchArgs &a, const Segment &s,
+                                                 uint64_t win, uint32_t lo)
+    {
+        return tile.generate(a, s, win, lo, off);
+    }
+    __device__ __forceinline__ void store(Tile &tile, const LaunchArgs &a, const Segment &s,
+                                          uint64_t win, uint64_t excl, uint32_t, uint64_t *nc)
+    {
+        tile.store(a, s, win, excl, nc, off);
+    }
+};
+
+template <int PPL, uint32_t FAM>
+struct MrgScratch {
+    using Tile = MrgTile<PPL, FAM>;
+    double vals[Tile::T + Tile::T / 16];
+    uint32_t wave[kMrgBlockThreads / 64];
+    uint64_t excl;
+    uint32_t next;
+    LaunchState state;
+
+    __device__ __forceinline__ uint32_t generate(Tile &tile, const LaunchArgs &a, const Segment &s,
+                                                 uint64_t win, uint32_t lo)
+    {
+        return tile.generate(a, s, win, lo, wave);
+    }
+    __device__ __forceinline__ void store(Tile &tile, const LaunchArgs &a, const Segment &s,
+                                          uint64_t win, uint64_t excl, uint32_t total, uint64_t *nc)
+    {
+        tile.store(a, s, win, excl, total, nc, vals);
+    }
+};
+
+template <int NW, int PPL, uint32_t FAM>
+__global__ __launch_bounds__(64 * NW) void fill_philox_kernel(LaunchArgs args)
+{
+    __shared__ PhiloxScratch<NW, PPL, FAM> sh;
+    lookback_loop<PhiloxTile<NW, PPL, FAM>>(args, sh);
 }
 
 template <int PPL, uint32_t FAM>
-__global__ __launch_bounds__(kBlockThreads) void fill_mrg_kernel(LaunchArgs args)
+__global__ __launch_bounds__(kMrgBlockThreads) void fill_mrg_kernel(LaunchArgs args)
 {
-    using Tile = MrgTile<PPL, FAM>;
-    constexpr uint64_t T = Tile::T;
-    __shared__ double s_vals[T + T / 16];
-    __shared__ uint32_t s_wave[kWavesPerBlock];
-    __shared__ uint32_t s_total;
-    __shared__ uint64_t s_excl;
-    __shared__ uint32_t s_ticket;
+    __shared__ MrgScratch<PPL, FAM> sh;
+    lookback_loop<MrgTile<PPL, FAM>>(args, sh);
+}
 
-    const uint32_t tid = threadIdx.x, lane = tid & 63u;
-    const uint32_t epoch = args.ctl->epoch;
-    const uint32_t flip = args.use_flip ? args.ctl->flip : 0u;
+template <int NW, int PPL, uint32_t FAM>
+__global__ __launch_bounds__(64 * NW) void seq_philox_kernel(LaunchArgs args)
+{
+    __shared__ uint32_t s_off[SpecTile<NW, PPL, FAM>::E + 1];
+    __shared__ LaunchState s_state;
+    __shared__ uint32_t s_next[2];
+    sequential_spec_loop<NW, PPL, FAM>(args, s_off, &s_state, s_next);
+}
 
-    for (;;) {
-        const uint32_t ticket = next_ticket(args.ctl, &s_ticket);
-        if (ticket >= args.total_tiles)
-            break;
-        const Segment seg = load_segment(args, ticket);
-        const uint32_t t = ticket - seg.tile_begin;
-        const uint32_t par = seg.parity ^ flip;
-        const uint64_t c0 = seg.counter[par];
-        uint64_t *next_counter = seg.counter + (par ^ 1u);
-        const TileGeom geom = tile_geom<T>(c0, seg.planned, t);
-        if (t < geom.nreal) {
-            Tile tile;
-            const uint32_t agg = tile.generate(args, seg, geom.win, geom.lo, geom.hi, s_wave, &s_total);
-            if (t == 0) {
-                if (tid == 0) {
-                    publish(args.status, ticket, pack_status(epoch, kFlagPrefix, agg));
-                    s_excl = 0;
-                }
-            } else {
-                if (tid == 0)
-                    publish(args.status, ticket, pack_status(epoch, kFlagAggregate, agg));
-                if (tid < 64) {
-                    const uint64_t excl = look_back(args.status, ticket, t, epoch, args.ctl, args.error, lane);
-                    if (tid == 0) {
-                        publish(args.status, ticket, pack_status(epoch, kFlagPrefix, excl + agg));
-                        s_excl = excl;
-                    }
-                }
-            }
-            __syncthreads();
-            uint64_t running = s_excl;
-            tile.store(args, seg, geom.win, running, agg, next_counter, s_vals);
-            running += agg;
-            if (t == geom.nreal - 1 && running < seg.n) {
-                const uint64_t from = c0 + seg.planned;
-                for (uint64_t win = from / T; running < seg.n; ++win) {
-                    const uint32_t a2 = tile.generate(args, seg, win, from, ~uint64_t(0), s_wave, &s_total);
-                    tile.store(args, seg, win, running, a2, next_counter, s_vals);
-                    running += a2;
-                }
-            }
-        }
-        __syncthreads();
-    }
-    finish_launch(args, epoch);
+template <int PPL, uint32_t FAM>
+__global__ __launch_bounds__(kMrgBlockThreads) void seq_mrg_kernel(LaunchArgs args)
+{
+    __shared__ MrgScratch<PPL, FAM> sh;
+    sequential_loop<MrgTile<PPL, FAM>>(args, sh);
+}
+
+// Toggles a resident plan's replay parity after all of a replay's fills.
+__global__ void toggle_flip_kernel(uint32_t *flip)
+{
+    *flip ^= 1u;
 }
 
 // Sets a handle's position slot (both halves, so either parity reads it).
@@ -669,49 +1103,104 @@ __global__ void zero_words_kernel(uint64_t *p, size_t n)
         p[i] = 0;
 }
 
+// tile_seg[tile_begin .. tile_begin + ntiles) = segment index, one
+// workgroup per segment.
+__global__ void expand_tiles_kernel(const Segment *segs, uint32_t nseg, uint32_t *tile_seg)
+{
+    for (uint32_t s = blockIdx.x; s < nseg; s += gridDim.x) {
+        const uint32_t b = segs[s].tile_begin, c = segs[s].ntiles;
+        for (uint32_t i = threadIdx.x; i < c; i += blockDim.x)
+            tile_seg[b + i] = s;
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- dispatch
-using KernelFn = void (*)(LaunchArgs);
-
-template <int PPL>
-static const void *philox_family(uint32_t fam)
+template <int NW, int PPL, uint32_t FAM>
+static const void *philox_kernel(bool seq)
 {
-    return fam == FAM_ENUM ? reinterpret_cast<const void *>(&fill_philox_kernel<PPL, FAM_ENUM>)
-                           : reinterpret_cast<const void *>(&fill_philox_kernel<PPL, FAM_PHILOX>);
+    return seq ? reinterpret_cast<const void *>(&seq_philox_kernel<NW, PPL, FAM>)
+               : reinterpret_cast<const void *>(&fill_philox_kernel<NW, PPL, FAM>);
+}
+
+template <int NW, int PPL>
+static const void *philox_family(uint32_t fam, bool seq)
+{
+    switch (fam) {
+    case FAM_ENUM: return philox_kernel<NW, PPL, FAM_ENUM>(seq);
+    case FAM_PHILOX32: return philox_kernel<NW, PPL, FAM_PHILOX32>(seq);
+    default: return philox_kernel<NW, PPL, FAM_PHILOX>(seq);
+    }
 }
 
 template <int PPL>
-static const void *mrg_family(uint32_t fam)
+static const void *mrg_family(uint32_t fam, bool seq)
 {
+    if (seq)
+        return fam == FAM_MRG ? reinterpret_cast<const void *>(&seq_mrg_kernel<PPL, FAM_MRG>)
+                              : reinterpret_cast<const void *>(&seq_mrg_kernel<PPL, FAM_MIXED>);
     return fam == FAM_MRG ? reinterpret_cast<const void *>(&fill_mrg_kernel<PPL, FAM_MRG>)
                           : reinterpret_cast<const void *>(&fill_mrg_kernel<PPL, FAM_MIXED>);
 }
 
-// The kernel for (family, pairs per lane), or null if not instantiated.
-const void *fill_kernel_for(uint32_t fam, uint32_t ppl)
+// The kernel for (family, threads per workgroup, pairs per lane), either
+// the look-back kernel or the segment-sequential one (seq), or null if
+// that shape is not instantiated.
+const void *fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool seq)
 {
-    if (fam == FAM_PHILOX || fam == FAM_ENUM) {
-        switch (ppl) {
-        case 4: return philox_family<4>(fam);
-        case 8: return philox_family<8>(fam);
-        case 16: return philox_family<16>(fam);
-        case 32: return philox_family<32>(fam);
-        default: return nullptr;
+    if (fam == FAM_PHILOX || fam == FAM_ENUM || fam == FAM_PHILOX32) {
+        if (threads == 256) {
+            switch (ppl) {
+            case 4: return philox_family<4, 4>(fam, seq);
+            case 8: return philox_family<4, 8>(fam, seq);
+            case 16: return philox_family<4, 16>(fam, seq);
+            case 32: return philox_family<4, 32>(fam, seq);
+            default: return nullptr;
+            }
         }
+        if (threads == 512) {
+            switch (ppl) {
+            case 8: return philox_family<8, 8>(fam, seq);
+            case 16: return philox_family<8, 16>(fam, seq);
+            default: return nullptr;
+            }
+        }
+        if (threads == 1024) {
+            switch (ppl) {
+            case 8: return philox_family<16, 8>(fam, seq);
+            case 16: return philox_family<16, 16>(fam, seq);
+            default: return nullptr;
+            }
+        }
+        return nullptr;
     }
+    if (threads != kMrgBlockThreads)
+        return nullptr;
     switch (ppl) {
-    case 4: return mrg_family<4>(fam);
-    case 8: return mrg_family<8>(fam);
-    case 16: return mrg_family<16>(fam);
+    case 4: return mrg_family<4>(fam, seq);
+    case 8: return mrg_family<8>(fam, seq);
+    case 16: return mrg_family<16>(fam, seq);
     default: return nullptr;
     }
 }
 
-hipError_t launch_fill(const void *kernel, uint32_t grid, const LaunchArgs &args, hipStream_t stream)
+hipError_t launch_toggle_flip(uint32_t *flip, hipStream_t stream)
+{
+    hipLaunchKernelGGL(toggle_flip_kernel, dim3(1), dim3(1), 0, stream, flip);
+    return hipGetLastError();
+}
+
+const void *toggle_flip_kernel_ptr()
+{
+    return reinterpret_cast<const void *>(&toggle_flip_kernel);
+}
+
+hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads, const LaunchArgs &args,
+                       hipStream_t stream)
 {
     void *params[] = {const_cast<LaunchArgs *>(&args)};
-    return hipLaunchKernel(kernel, dim3(grid), dim3(kBlockThreads), params, 0, stream);
+    return hipLaunchKernel(kernel, dim3(grid), dim3(threads), params, 0, stream);
 }
 
 hipError_t launch_set_counter(uint64_t *slot, uint64_t value, hipStream_t stream)
@@ -726,6 +1215,17 @@ hipError_t launch_zero_words(uint64_t *p, size_t n, hipStream_t stream)
         return hipSuccess;
     const size_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
     hipLaunchKernelGGL(zero_words_kernel, dim3(uint32_t(blocks)), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_tiles(const Segment *segs, uint32_t nseg, uint32_t *tile_seg,
+                               hipStream_t stream)
+{
+    if (nseg == 0)
+        return hipSuccess;
+    const uint32_t blocks = nseg < 8192 ? nseg : 8192;
+    hipLaunchKernelGGL(expand_tiles_kernel, dim3(blocks), dim3(256), 0, stream, segs, nseg,
+                       tile_seg);
     return hipGetLastError();
 }
 

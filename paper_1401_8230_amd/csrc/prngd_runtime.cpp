@@ -19,9 +19,13 @@
 #include "prngd_internal.hpp"
 
 namespace prngd {
-const void *fill_kernel_for(uint32_t fam, uint32_t ppl);
-hipError_t launch_fill(const void *kernel, uint32_t grid, const LaunchArgs &args,
-                       hipStream_t stream);
+const void *fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool seq);
+hipError_t launch_toggle_flip(uint32_t *flip, hipStream_t stream);
+const void *toggle_flip_kernel_ptr();
+hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads,
+                       const LaunchArgs &args, hipStream_t stream);
+hipError_t launch_expand_tiles(const Segment *segs, uint32_t nseg, uint32_t *tile_seg,
+                               hipStream_t stream);
 hipError_t launch_set_counter(uint64_t *slot, uint64_t value, hipStream_t stream);
 hipError_t launch_zero_words(uint64_t *p, size_t n, hipStream_t stream);
 }  // namespace prngd
@@ -95,6 +99,17 @@ double folded_constant(uint32_t w, uint64_t D)
     return std::ldexp(static_cast<double>(keep), 11 - frac - int(2 * w));
 }
 
+// The kernel family that serves a generator at resolution 2^-w.
+uint32_t kernel_family(prngd_generator_t gen, uint32_t w)
+{
+    switch (gen) {
+    case PRNGD_MRG32K3A: return FAM_MRG;
+    case PRNGD_PHILOX_X1_MRG32K3A_X2: return FAM_MIXED;
+    case PRNGD_ENUMERATE: return FAM_ENUM;
+    default: return w == 32 ? FAM_PHILOX32 : FAM_PHILOX;
+    }
+}
+
 prngd_status_t make_config(prngd_generator_t gen, double k, uint64_t min, uint64_t max,
                            Config *c)
 {
@@ -107,8 +122,6 @@ prngd_status_t make_config(prngd_generator_t gen, double k, uint64_t min, uint64
     if (m != 0.5)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "k = %a is not a power of two", k);
     const int w = 1 - e;
-    const uint32_t fams[] = {FAM_PHILOX, FAM_MRG, FAM_MIXED, FAM_ENUM};
-    c->fam = fams[gen];
     c->w = uint32_t(w);
     const int wmax = gen == PRNGD_ENUMERATE ? 16 : 32;
     const int wmin = (gen == PRNGD_MRG32K3A || gen == PRNGD_PHILOX_X1_MRG32K3A_X2) ? 32 : 2;
@@ -134,6 +147,7 @@ prngd_status_t make_config(prngd_generator_t gen, double k, uint64_t min, uint64
                     (unsigned long long)c->a0, (unsigned long long)c->a);
     c->D = (c->a - c->a0 - 2) * (uint64_t(1) << w) + (c->b - c->b0);
     c->S = folded_constant(c->w, c->D);
+    c->fam = kernel_family(gen, c->w);
     return PRNGD_OK;
 }
 
@@ -262,16 +276,16 @@ void put_entry(uint32_t *dst, const Mat &m1, const Mat &m2)
 void build_mrg_tables(uint32_t r, uint32_t ppl, std::vector<uint32_t> &thread,
                       std::vector<uint32_t> &window)
 {
-    thread.assign(size_t(kBlockThreads) * kMrgMatWords, 0);
+    thread.assign(size_t(kMrgBlockThreads) * kMrgMatWords, 0);
     window.assign(size_t(kMrgDigits) * 256 * kMrgMatWords, 0);
-    const uint64_t T = uint64_t(kBlockThreads) * ppl;
+    const uint64_t T = uint64_t(kMrgBlockThreads) * ppl;
     Mat step[2], cur[2];
     for (int c = 0; c < 2; ++c) {
         const uint64_t m = c == 0 ? kM1 : kM2;
         step[c] = mat_pow(mrg_step_matrix(c), uint64_t(r) * ppl, m);
         cur[c] = mat_identity();
     }
-    for (int t = 0; t < kBlockThreads; ++t) {
+    for (int t = 0; t < kMrgBlockThreads; ++t) {
         put_entry(&thread[size_t(t) * kMrgMatWords], cur[0], cur[1]);
         cur[0] = mat_mul(cur[0], step[0], kM1);
         cur[1] = mat_mul(cur[1], step[1], kM2);
@@ -388,21 +402,33 @@ prngd_status_t mrg_tables_for(DeviceInfo *d, uint32_t r, uint32_t ppl, const uin
 // ---------------------------------------------------------------- tuning
 std::map<std::pair<uint32_t, uint32_t>, prngd_tuning_t> g_tuning;
 
+bool philox_family(uint32_t fam)
+{
+    return fam == FAM_PHILOX || fam == FAM_ENUM || fam == FAM_PHILOX32;
+}
+
 prngd_tuning_t tuning_for(uint32_t fam, uint32_t w)
 {
     prngd_tuning_t t{};
     auto it = g_tuning.find(std::make_pair(fam, w));
     if (it != g_tuning.end())
         t = it->second;
-    const bool philox = fam == FAM_PHILOX || fam == FAM_ENUM;
+    if (t.block_threads == 0)
+        t.block_threads = philox_family(fam) ? 256 : kMrgBlockThreads;
     if (t.pairs_per_lane == 0)
-        t.pairs_per_lane = philox ? 16 : 8;
+        t.pairs_per_lane = philox_family(fam) ? 16 : 8;
     return t;
 }
 
-bool valid_ppl(uint32_t fam, uint32_t ppl)
+// Segments of a batch with at most this many tiles are produced whole by
+// one workgroup (segment-sequential kernel); longer ones are spread over
+// workgroups and joined by the look-back.  Default: a segment may take up
+// to half a workgroup's fair share of the batch.
+uint64_t seq_limit(const prngd_tuning_t &t, uint64_t total_tiles, uint64_t workgroups)
 {
-    return fill_kernel_for(fam, ppl) != nullptr;
+    if (t.seq_max_tiles)
+        return t.seq_max_tiles;
+    return std::max<uint64_t>(4, total_tiles / std::max<uint64_t>(1, 2 * workgroups));
 }
 
 // ------------------------------------------------------------ workspaces
@@ -410,14 +436,17 @@ bool valid_ppl(uint32_t fam, uint32_t ppl)
 // other in stream order (one per stream, one per plan).
 struct Workspace {
     int device = 0;
-    Control *ctl = nullptr;
+    Control *ctl = nullptr;               // look-back kernel
+    Control *seq_ctl = nullptr;           // segment-sequential kernel
     uint64_t *status = nullptr;
     size_t status_cap = 0;
     uint64_t launches = 0;
     hipEvent_t last = nullptr;            // recorded after every launch
-    // batch descriptors
+    // batch descriptors and the tile -> segment map
     Segment *dsegs = nullptr;
     size_t dsegs_cap = 0;
+    uint32_t *tile_seg = nullptr;
+    size_t tile_seg_cap = 0;
     Segment *hsegs[2] = {nullptr, nullptr};
     size_t hsegs_cap[2] = {0, 0};
     hipEvent_t hsegs_done[2] = {nullptr, nullptr};
@@ -428,14 +457,32 @@ prngd_status_t ws_init(Workspace *ws, int dev)
 {
     ws->device = dev;
     void *p = nullptr;
-    HIP_TRY(hipMalloc(&p, sizeof(Control)));
+    HIP_TRY(hipMalloc(&p, 2 * sizeof(Control)));
     ws->ctl = static_cast<Control *>(p);
-    const Control init{0, 0, 1, 0, 0};
-    HIP_TRY(hipMemcpy(ws->ctl, &init, sizeof init, hipMemcpyHostToDevice));
+    ws->seq_ctl = ws->ctl + 1;
+    Control init[2];
+    std::memset(init, 0, sizeof init);
+    init[0].epoch = 1;
+    init[1].epoch = 1;
+    HIP_TRY(hipMemcpy(ws->ctl, init, sizeof init, hipMemcpyHostToDevice));
     HIP_TRY(hipEventCreateWithFlags(&ws->last, hipEventDisableTiming));
     for (int i = 0; i < 2; ++i)
         HIP_TRY(hipEventCreateWithFlags(&ws->hsegs_done[i], hipEventDisableTiming));
     return PRNGD_OK;
+}
+
+void ws_release(Workspace *ws)
+{
+    (void)hipFree(ws->status);
+    (void)hipFree(ws->ctl);
+    (void)hipFree(ws->dsegs);
+    (void)hipFree(ws->tile_seg);
+    for (int i = 0; i < 2; ++i) {
+        if (ws->hsegs[i])
+            (void)hipHostFree(ws->hsegs[i]);
+        (void)hipEventDestroy(ws->hsegs_done[i]);
+    }
+    (void)hipEventDestroy(ws->last);
 }
 
 // Make room for `tiles` status words and clear them when the 24-bit epoch
@@ -443,7 +490,7 @@ prngd_status_t ws_init(Workspace *ws, int dev)
 prngd_status_t ws_prepare(Workspace *ws, size_t tiles, hipStream_t stream)
 {
     if (tiles > ws->status_cap) {
-        size_t cap = std::max<size_t>(tiles, 1 << 16);
+        const size_t cap = std::max<size_t>(tiles, 1 << 16);
         if (ws->status) {
             HIP_TRY(hipStreamSynchronize(stream));
             HIP_TRY(hipEventSynchronize(ws->last));
@@ -458,6 +505,27 @@ prngd_status_t ws_prepare(Workspace *ws, size_t tiles, hipStream_t stream)
     }
     if (ws->launches > 0 && ws->launches % kEpochMask == 0)
         HIP_TRY(launch_zero_words(ws->status, ws->status_cap, stream));
+    return PRNGD_OK;
+}
+
+// Grow a device buffer that only work on `stream` (or the workspace's
+// earlier launches) uses.
+template <class T>
+prngd_status_t ws_grow(Workspace *ws, T **buf, size_t *cap, size_t need, hipStream_t stream)
+{
+    if (*cap >= need)
+        return PRNGD_OK;
+    if (*buf) {
+        HIP_TRY(hipStreamSynchronize(stream));
+        HIP_TRY(hipEventSynchronize(ws->last));
+        HIP_TRY(hipFree(*buf));
+        *buf = nullptr;
+    }
+    const size_t c = std::max<size_t>(need, 1024);
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, c * sizeof(T)));
+    *buf = static_cast<T *>(p);
+    *cap = c;
     return PRNGD_OK;
 }
 
@@ -493,6 +561,7 @@ struct prngd_handle_s {
     hipEvent_t last_event = nullptr;   // borrowed: last work on this handle
     hipStream_t last_stream = nullptr;
     prngd_plan_s *plan = nullptr;      // live plan the handle is bound to
+    size_t plan_index = 0;             // position in that plan
 };
 
 struct prngd_plan_s {
@@ -500,10 +569,11 @@ struct prngd_plan_s {
     std::vector<prngd_handle_t> handles;
     std::vector<uint32_t> base_parity;
     Workspace ws;
-    Segment *dsegs = nullptr;
-    LaunchArgs args{};
-    const void *kernel = nullptr;
-    uint32_t grid = 0;
+    Segment *dsegs = nullptr;          // look-back segments, then sequential ones
+    uint32_t *tile_seg = nullptr;
+    uint32_t *flip = nullptr;          // device word: parity of the next replay
+    LaunchArgs lb_args{};
+    LaunchArgs seq_args{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t launches = 0;
@@ -530,40 +600,39 @@ uint64_t planned_pairs(const Config &c, uint64_t n, uint32_t slack_mode)
     return n + static_cast<uint64_t>(extra);
 }
 
-int occupancy_of(DeviceInfo *d, const void *kernel)
+int occupancy_of(DeviceInfo *d, const void *kernel, uint32_t threads)
 {
     auto it = d->occupancy.find(kernel);
     if (it != d->occupancy.end())
         return it->second;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlockThreads, 0) != hipSuccess ||
-        nb <= 0)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, int(threads), 0) !=
+            hipSuccess || nb <= 0)
         nb = 1;
     d->occupancy[kernel] = nb;
     return nb;
 }
 
+// Kernels, tile size and generator constants of one launch.
 struct LaunchPlan {
-    const void *kernel;
-    uint32_t grid;
+    const void *kernel;       // look-back kernel
+    const void *seq_kernel;   // segment-sequential kernel
+    uint32_t threads;
     uint64_t T;
+    prngd_tuning_t tune;
 };
 
-prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, uint64_t total_tiles,
-                           LaunchArgs *args, LaunchPlan *lp)
+prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, LaunchPlan *lp)
 {
-    const prngd_tuning_t tune = tuning_for(cfg.fam, cfg.w);
-    lp->kernel = fill_kernel_for(cfg.fam, tune.pairs_per_lane);
-    if (!lp->kernel)
-        return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u pairs per lane",
-                    tune.pairs_per_lane);
-    lp->T = uint64_t(kBlockThreads) * tune.pairs_per_lane;
-    const int occ = occupancy_of(d, lp->kernel);
-    uint64_t per_cu = tune.blocks_per_cu ? std::min<uint64_t>(tune.blocks_per_cu, occ) : occ;
-    uint64_t grid = per_cu * uint64_t(d->cus);
-    grid = std::max<uint64_t>(1, std::min<uint64_t>(grid, total_tiles));
-    lp->grid = uint32_t(grid);
-    args->store_mode = tune.store_mode;
+    lp->tune = tuning_for(cfg.fam, cfg.w);
+    lp->threads = lp->tune.block_threads;
+    lp->kernel = fill_kernel_for(cfg.fam, lp->threads, lp->tune.pairs_per_lane, false);
+    lp->seq_kernel = fill_kernel_for(cfg.fam, lp->threads, lp->tune.pairs_per_lane, true);
+    if (!lp->kernel || !lp->seq_kernel)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u threads x %u pairs per lane",
+                    lp->threads, lp->tune.pairs_per_lane);
+    lp->T = uint64_t(lp->threads) * lp->tune.pairs_per_lane;
+    args->store_mode = lp->tune.store_mode;
     args->w = cfg.w;
     args->a0 = uint32_t(cfg.a0);
     args->a = uint32_t(cfg.a);
@@ -572,9 +641,12 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, uint64_t total_tile
     args->error = d->error_dev;
     args->mrg_thread = nullptr;
     args->mrg_window = nullptr;
+    args->segs = nullptr;
+    args->tile_seg = nullptr;
+    args->flip = nullptr;
     if (cfg.fam == FAM_MRG || cfg.fam == FAM_MIXED) {
         const uint32_t r = cfg.fam == FAM_MRG ? 2u : 1u;
-        prngd_status_t st = mrg_tables_for(d, r, tune.pairs_per_lane, &args->mrg_thread,
+        prngd_status_t st = mrg_tables_for(d, r, lp->tune.pairs_per_lane, &args->mrg_thread,
                                            &args->mrg_window);
         if (st != PRNGD_OK)
             return st;
@@ -582,7 +654,17 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, uint64_t total_tile
     return PRNGD_OK;
 }
 
-// Fill the descriptor of one request; returns tiles allotted.
+// Workgroups of a launch over `units` tiles or segments: all that fit on
+// the device at once (or blocks_per_cu per CU), never more than units.
+uint32_t grid_for(DeviceInfo *d, const LaunchPlan &lp, const void *kernel, uint64_t units)
+{
+    const int occ = occupancy_of(d, kernel, lp.threads);
+    const uint64_t per_cu = lp.tune.blocks_per_cu ? lp.tune.blocks_per_cu : uint64_t(occ);
+    const uint64_t g = std::min<uint64_t>(per_cu * uint64_t(d->cus), units);
+    return uint32_t(std::max<uint64_t>(1, g));
+}
+
+// Fill the descriptor of one request; returns its number of tiles.
 prngd_status_t make_segment(prngd_handle_t h, uint64_t n, double *out, uint64_t T,
                             uint32_t slack_mode, uint64_t tile_begin, Segment *s,
                             uint64_t *ntiles)
@@ -593,9 +675,9 @@ prngd_status_t make_segment(prngd_handle_t h, uint64_t n, double *out, uint64_t 
     if (!out || (reinterpret_cast<uintptr_t>(out) & 7u))
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "out must be a non-null 8-byte aligned pointer");
     const uint64_t planned = planned_pairs(h->cfg, n, slack_mode);
-    const uint64_t tiles = (planned + T - 1) / T + 1;
-    if (tile_begin + tiles > 0xFFFFFFFFull)
-        return fail(PRNGD_ERR_INVALID_ARGUMENT, "launch too large (more than 2^32 tiles)");
+    const uint64_t tiles = std::max<uint64_t>(1, (planned + T - 1) / T);
+    if (tile_begin + tiles > kMaxTiles)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "launch too large (more than 2^31 tiles)");
     s->seed = h->seed;
     s->n = n;
     s->planned = planned;
@@ -619,6 +701,69 @@ bool same_config(const Config &x, const Config &y)
 prngd_status_t current_device(int *dev)
 {
     HIP_TRY(hipGetDevice(dev));
+    return PRNGD_OK;
+}
+
+// A validated request list split for the two kernels: `lb` segments (with
+// tile_begin set, tiles in order) for the look-back kernel, `seq` segments
+// (largest first) for the segment-sequential kernel.
+struct BatchPlan {
+    std::vector<Segment> lb;
+    std::vector<Segment> seq;
+    std::vector<prngd_handle_t> handles;
+    uint64_t lb_tiles = 0;
+};
+
+prngd_status_t build_batch(DeviceInfo *d, const LaunchPlan &lp, const prngd_request_t *reqs,
+                           uint32_t count, BatchPlan *bp)
+{
+    if (!reqs || count == 0)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "empty request list");
+    std::unordered_set<prngd_handle_t> seen;
+    const prngd_handle_t first = reqs[0].h;
+    if (!first)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "request 0 has a NULL handle");
+    std::vector<Segment> all;
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        const prngd_request_t &r = reqs[i];
+        if (!r.h)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "request %u has a NULL handle", i);
+        if (!seen.insert(r.h).second)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle of request %u repeats", i);
+        if (!same_config(r.h->cfg, first->cfg) || r.h->device != first->device)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT,
+                        "request %u: all handles of a batch must share generator, k, min, max",
+                        i);
+        if (r.h->plan)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "request %u: handle bound to a plan", i);
+        if (r.n == 0)
+            continue;
+        Segment s;
+        uint64_t nt = 0;
+        prngd_status_t st = make_segment(r.h, r.n, r.out, lp.T, lp.tune.slack_mode, 0, &s, &nt);
+        if (st != PRNGD_OK)
+            return st;
+        total += nt;
+        all.push_back(s);
+        bp->handles.push_back(r.h);
+    }
+    const uint64_t wg = uint64_t(occupancy_of(d, lp.seq_kernel, lp.threads)) * uint64_t(d->cus);
+    const uint64_t limit = seq_limit(lp.tune, total, wg);
+    for (const Segment &s : all) {
+        if (s.ntiles <= limit) {
+            bp->seq.push_back(s);
+        } else {
+            Segment t = s;
+            if (bp->lb_tiles + t.ntiles > kMaxTiles)
+                return fail(PRNGD_ERR_INVALID_ARGUMENT, "launch too large (more than 2^32 tiles)");
+            t.tile_begin = uint32_t(bp->lb_tiles);
+            bp->lb_tiles += t.ntiles;
+            bp->lb.push_back(t);
+        }
+    }
+    std::stable_sort(bp->seq.begin(), bp->seq.end(),
+                     [](const Segment &x, const Segment &y) { return x.ntiles > y.ntiles; });
     return PRNGD_OK;
 }
 
@@ -690,6 +835,47 @@ prngd_status_t prngd_create(uint64_t seed, prngd_generator_t generator, double k
     return PRNGD_OK;
 }
 
+prngd_status_t prngd_create_many(uint64_t seed, prngd_generator_t generator, double k,
+                                 uint64_t min, uint64_t max, uint32_t first_stream_id,
+                                 uint32_t count, prngd_handle_t *handles)
+{
+    if (!handles)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "handles is NULL");
+    if (count && uint64_t(first_stream_id) + count - 1 > 0xFFFFFFFFull)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "substream ids beyond 2^32 - 1");
+    Config cfg;
+    prngd_status_t st = make_config(generator, k, min, max, &cfg);
+    if (st != PRNGD_OK)
+        return st;
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    int dev = 0;
+    if ((st = current_device(&dev)) != PRNGD_OK)
+        return st;
+    DeviceInfo *d = nullptr;
+    if ((st = device_info(dev, &d)) != PRNGD_OK)
+        return st;
+    for (uint32_t i = 0; i < count; ++i) {
+        std::unique_ptr<prngd_handle_s> h(new prngd_handle_s);
+        h->device = dev;
+        h->gen = generator;
+        h->cfg = cfg;
+        h->seed = seed;
+        h->stream_id = first_stream_id + i;
+        if (cfg.fam == FAM_MRG || cfg.fam == FAM_MIXED)
+            mrg_stream_base(seed, h->stream_id, h->mrg);
+        if ((st = alloc_slot(d, &h->slot)) != PRNGD_OK) {
+            for (uint32_t j = 0; j < i; ++j) {
+                d->free_slots.push_back(handles[j]->slot);
+                delete handles[j];
+                handles[j] = nullptr;
+            }
+            return st;
+        }
+        handles[i] = h.release();
+    }
+    return PRNGD_OK;
+}
+
 prngd_status_t prngd_destroy(prngd_handle_t h)
 {
     if (!h)
@@ -745,9 +931,7 @@ prngd_status_t prngd_get_position(prngd_handle_t h, uint32_t *stream_id, uint64_
     if (h->plan) {
         // position after the plan's launches so far
         const prngd_plan_s *p = h->plan;
-        for (size_t i = 0; i < p->handles.size(); ++i)
-            if (p->handles[i] == h)
-                parity = p->base_parity[i] ^ uint32_t(p->launches & 1u);
+        parity = p->base_parity[h->plan_index] ^ uint32_t(p->launches & 1u);
     }
     uint64_t value = 0;
     HIP_TRY(hipMemcpyAsync(&value, h->slot + parity, sizeof value, hipMemcpyDeviceToHost, s));
@@ -780,27 +964,21 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *strea
         return st;
     LaunchArgs args{};
     LaunchPlan lp{};
-    // the tile size is needed to allot tiles, so plan the kernel first
-    if ((st = plan_launch(d, h->cfg, 1, &args, &lp)) != PRNGD_OK)
+    if ((st = plan_launch(d, h->cfg, &args, &lp)) != PRNGD_OK)
         return st;
     uint64_t ntiles = 0;
-    const prngd_tuning_t tune = tuning_for(h->cfg.fam, h->cfg.w);
-    if ((st = make_segment(h, n, out, lp.T, tune.slack_mode, 0, &args.seg0, &ntiles)) != PRNGD_OK)
+    if ((st = make_segment(h, n, out, lp.T, lp.tune.slack_mode, 0, &args.seg0, &ntiles)) !=
+        PRNGD_OK)
         return st;
-    const int occ = occupancy_of(d, lp.kernel);
-    const uint64_t per_cu = tune.blocks_per_cu ? std::min<uint64_t>(tune.blocks_per_cu, occ) : occ;
-    lp.grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(per_cu * d->cus, ntiles)));
-    args.segs = nullptr;
     args.nseg = 1;
     args.total_tiles = uint32_t(ntiles);
     args.ctl = ws->ctl;
-    args.use_flip = 0;
     if ((st = order_after(h, s)) != PRNGD_OK)
         return st;
     if ((st = ws_prepare(ws, ntiles, s)) != PRNGD_OK)
         return st;
     args.status = ws->status;
-    HIP_TRY(launch_fill(lp.kernel, lp.grid, args, s));
+    HIP_TRY(launch_fill(lp.kernel, grid_for(d, lp, lp.kernel, ntiles), lp.threads, args, s));
     ws->launches++;
     HIP_TRY(hipEventRecord(ws->last, s));
     h->parity ^= 1u;
@@ -808,55 +986,6 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *strea
     h->last_stream = s;
     return PRNGD_OK;
 }
-
-}  // extern "C"
-
-namespace {
-
-// Validate a request list and build its descriptors.
-prngd_status_t build_batch(const prngd_request_t *reqs, uint32_t count, uint64_t T,
-                           uint32_t slack_mode, std::vector<Segment> &segs,
-                           std::vector<prngd_handle_t> &handles, uint64_t *total)
-{
-    if (!reqs || count == 0)
-        return fail(PRNGD_ERR_INVALID_ARGUMENT, "empty request list");
-    std::unordered_set<prngd_handle_t> seen;
-    segs.clear();
-    handles.clear();
-    uint64_t tiles = 0;
-    const prngd_handle_t first = reqs[0].h;
-    if (!first)
-        return fail(PRNGD_ERR_INVALID_ARGUMENT, "request 0 has a NULL handle");
-    for (uint32_t i = 0; i < count; ++i) {
-        const prngd_request_t &r = reqs[i];
-        if (!r.h)
-            return fail(PRNGD_ERR_INVALID_ARGUMENT, "request %u has a NULL handle", i);
-        if (!seen.insert(r.h).second)
-            return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle of request %u repeats", i);
-        if (!same_config(r.h->cfg, first->cfg) || r.h->device != first->device)
-            return fail(PRNGD_ERR_INVALID_ARGUMENT,
-                        "request %u: all handles of a batch must share generator, k, min, max",
-                        i);
-        if (r.h->plan)
-            return fail(PRNGD_ERR_INVALID_ARGUMENT, "request %u: handle bound to a plan", i);
-        if (r.n == 0)
-            continue;
-        Segment s;
-        uint64_t nt = 0;
-        prngd_status_t st = make_segment(r.h, r.n, r.out, T, slack_mode, tiles, &s, &nt);
-        if (st != PRNGD_OK)
-            return st;
-        tiles += nt;
-        segs.push_back(s);
-        handles.push_back(r.h);
-    }
-    *total = tiles;
-    return PRNGD_OK;
-}
-
-}  // namespace
-
-extern "C" {
 
 prngd_status_t prngd_fill_batch(const prngd_request_t *reqs, uint32_t count, void *stream)
 {
@@ -875,15 +1004,12 @@ prngd_status_t prngd_fill_batch(const prngd_request_t *reqs, uint32_t count, voi
     const Config cfg = reqs[0].h->cfg;
     LaunchArgs args{};
     LaunchPlan lp{};
-    if ((st = plan_launch(d, cfg, 1, &args, &lp)) != PRNGD_OK)
+    if ((st = plan_launch(d, cfg, &args, &lp)) != PRNGD_OK)
         return st;
-    const prngd_tuning_t tune = tuning_for(cfg.fam, cfg.w);
-    std::vector<Segment> segs;
-    std::vector<prngd_handle_t> handles;
-    uint64_t total = 0;
-    if ((st = build_batch(reqs, count, lp.T, tune.slack_mode, segs, handles, &total)) != PRNGD_OK)
+    BatchPlan bp;
+    if ((st = build_batch(d, lp, reqs, count, &bp)) != PRNGD_OK)
         return st;
-    if (segs.empty())
+    if (bp.handles.empty())
         return PRNGD_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Workspace *ws = nullptr;
@@ -891,52 +1017,59 @@ prngd_status_t prngd_fill_batch(const prngd_request_t *reqs, uint32_t count, voi
         return st;
     // order after every handle's previous work on other streams
     std::unordered_set<hipEvent_t> waited;
-    for (prngd_handle_t h : handles)
+    for (prngd_handle_t h : bp.handles)
         if (h->last_event && h->last_stream != s && waited.insert(h->last_event).second)
             HIP_TRY(hipStreamWaitEvent(s, h->last_event, 0));
-    if ((st = ws_prepare(ws, total, s)) != PRNGD_OK)
+    const size_t nseg = bp.lb.size() + bp.seq.size();
+    if ((st = ws_prepare(ws, bp.lb_tiles, s)) != PRNGD_OK)
         return st;
-    // descriptors: pinned staging ring of two, then one async copy
-    const size_t bytes = segs.size() * sizeof(Segment);
+    if ((st = ws_grow(ws, &ws->dsegs, &ws->dsegs_cap, nseg, s)) != PRNGD_OK)
+        return st;
+    if ((st = ws_grow(ws, &ws->tile_seg, &ws->tile_seg_cap, std::max<uint64_t>(bp.lb_tiles, 1), s)) !=
+        PRNGD_OK)
+        return st;
+    // descriptors (look-back ones first): pinned staging ring of two, one
+    // async copy, then the tile -> segment map is expanded on the device
     const int slot = ws->hcur;
     ws->hcur ^= 1;
     HIP_TRY(hipEventSynchronize(ws->hsegs_done[slot]));
-    if (ws->hsegs_cap[slot] < segs.size()) {
+    if (ws->hsegs_cap[slot] < nseg) {
         if (ws->hsegs[slot])
             HIP_TRY(hipHostFree(ws->hsegs[slot]));
         void *p = nullptr;
-        const size_t cap = std::max<size_t>(segs.size(), 1024);
+        const size_t cap = std::max<size_t>(nseg, 1024);
         HIP_TRY(hipHostMalloc(&p, cap * sizeof(Segment), hipHostMallocDefault));
         ws->hsegs[slot] = static_cast<Segment *>(p);
         ws->hsegs_cap[slot] = cap;
     }
-    if (ws->dsegs_cap < segs.size()) {
-        if (ws->dsegs) {
-            HIP_TRY(hipStreamSynchronize(s));
-            HIP_TRY(hipFree(ws->dsegs));
-        }
-        void *p = nullptr;
-        const size_t cap = std::max<size_t>(segs.size(), 1024);
-        HIP_TRY(hipMalloc(&p, cap * sizeof(Segment)));
-        ws->dsegs = static_cast<Segment *>(p);
-        ws->dsegs_cap = cap;
-    }
-    std::memcpy(ws->hsegs[slot], segs.data(), bytes);
-    HIP_TRY(hipMemcpyAsync(ws->dsegs, ws->hsegs[slot], bytes, hipMemcpyHostToDevice, s));
+    std::copy(bp.lb.begin(), bp.lb.end(), ws->hsegs[slot]);
+    std::copy(bp.seq.begin(), bp.seq.end(), ws->hsegs[slot] + bp.lb.size());
+    HIP_TRY(hipMemcpyAsync(ws->dsegs, ws->hsegs[slot], nseg * sizeof(Segment),
+                           hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(ws->hsegs_done[slot], s));
-    const int occ = occupancy_of(d, lp.kernel);
-    const uint64_t per_cu = tune.blocks_per_cu ? std::min<uint64_t>(tune.blocks_per_cu, occ) : occ;
-    lp.grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(per_cu * d->cus, total)));
-    args.segs = ws->dsegs;
-    args.nseg = uint32_t(segs.size());
-    args.total_tiles = uint32_t(total);
-    args.status = ws->status;
-    args.ctl = ws->ctl;
-    args.use_flip = 0;
-    HIP_TRY(launch_fill(lp.kernel, lp.grid, args, s));
-    ws->launches++;
+    if (!bp.seq.empty()) {
+        LaunchArgs sa = args;
+        sa.segs = ws->dsegs + bp.lb.size();
+        sa.nseg = uint32_t(bp.seq.size());
+        sa.total_tiles = uint32_t(bp.seq.size());
+        sa.ctl = ws->seq_ctl;
+        HIP_TRY(launch_fill(lp.seq_kernel, grid_for(d, lp, lp.seq_kernel, bp.seq.size()),
+                            lp.threads, sa, s));
+    }
+    if (!bp.lb.empty()) {
+        HIP_TRY(launch_expand_tiles(ws->dsegs, uint32_t(bp.lb.size()), ws->tile_seg, s));
+        args.segs = ws->dsegs;
+        args.tile_seg = ws->tile_seg;
+        args.nseg = uint32_t(bp.lb.size());
+        args.total_tiles = uint32_t(bp.lb_tiles);
+        args.status = ws->status;
+        args.ctl = ws->ctl;
+        HIP_TRY(launch_fill(lp.kernel, grid_for(d, lp, lp.kernel, bp.lb_tiles), lp.threads, args,
+                            s));
+        ws->launches++;
+    }
     HIP_TRY(hipEventRecord(ws->last, s));
-    for (prngd_handle_t h : handles) {
+    for (prngd_handle_t h : bp.handles) {
         h->parity ^= 1u;
         h->last_event = ws->last;
         h->last_stream = s;
@@ -961,57 +1094,105 @@ prngd_status_t prngd_plan_create(const prngd_request_t *reqs, uint32_t count,
     const Config cfg = reqs[0].h->cfg;
     std::unique_ptr<prngd_plan_s> p(new prngd_plan_s);
     p->device = dev;
+    LaunchArgs args{};
     LaunchPlan lp{};
-    if ((st = plan_launch(d, cfg, 1, &p->args, &lp)) != PRNGD_OK)
+    if ((st = plan_launch(d, cfg, &args, &lp)) != PRNGD_OK)
         return st;
-    const prngd_tuning_t tune = tuning_for(cfg.fam, cfg.w);
-    std::vector<Segment> segs;
-    uint64_t total = 0;
-    if ((st = build_batch(reqs, count, lp.T, tune.slack_mode, segs, p->handles, &total)) !=
-        PRNGD_OK)
+    BatchPlan bp;
+    if ((st = build_batch(d, lp, reqs, count, &bp)) != PRNGD_OK)
         return st;
-    if (segs.empty())
+    if (bp.handles.empty())
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "a plan needs at least one request with n > 0");
+    p->handles = bp.handles;
     if ((st = ws_init(&p->ws, dev)) != PRNGD_OK)
         return st;
     // wait for the handles' earlier work before the plan's first use
     for (prngd_handle_t h : p->handles)
         if (h->last_event)
             HIP_TRY(hipEventSynchronize(h->last_event));
-    if ((st = ws_prepare(&p->ws, total, nullptr)) != PRNGD_OK)
+    if ((st = ws_prepare(&p->ws, bp.lb_tiles, nullptr)) != PRNGD_OK) {
+        ws_release(&p->ws);
         return st;
+    }
+    const size_t nseg = bp.lb.size() + bp.seq.size();
+    std::vector<Segment> all(bp.lb);
+    all.insert(all.end(), bp.seq.begin(), bp.seq.end());
+    std::vector<uint32_t> map(std::max<uint64_t>(bp.lb_tiles, 1), 0u);
+    for (size_t i = 0; i < bp.lb.size(); ++i)
+        std::fill(map.begin() + bp.lb[i].tile_begin,
+                  map.begin() + bp.lb[i].tile_begin + bp.lb[i].ntiles, uint32_t(i));
     void *dp = nullptr;
-    HIP_TRY(hipMalloc(&dp, segs.size() * sizeof(Segment)));
+    HIP_TRY(hipMalloc(&dp, nseg * sizeof(Segment)));
     p->dsegs = static_cast<Segment *>(dp);
-    HIP_TRY(hipMemcpy(p->dsegs, segs.data(), segs.size() * sizeof(Segment),
+    HIP_TRY(hipMalloc(&dp, map.size() * sizeof(uint32_t)));
+    p->tile_seg = static_cast<uint32_t *>(dp);
+    HIP_TRY(hipMalloc(&dp, sizeof(uint32_t)));
+    p->flip = static_cast<uint32_t *>(dp);
+    HIP_TRY(hipMemcpy(p->dsegs, all.data(), nseg * sizeof(Segment), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->tile_seg, map.data(), map.size() * sizeof(uint32_t),
                       hipMemcpyHostToDevice));
-    HIP_TRY(hipStreamSynchronize(nullptr));
-    const int occ = occupancy_of(d, lp.kernel);
-    const uint64_t per_cu = tune.blocks_per_cu ? std::min<uint64_t>(tune.blocks_per_cu, occ) : occ;
-    p->grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(per_cu * d->cus, total)));
-    p->kernel = lp.kernel;
-    p->args.segs = p->dsegs;
-    p->args.nseg = uint32_t(segs.size());
-    p->args.total_tiles = uint32_t(total);
-    p->args.status = p->ws.status;
-    p->args.ctl = p->ws.ctl;
-    p->args.use_flip = 1;
+    HIP_TRY(hipMemset(p->flip, 0, sizeof(uint32_t)));
+    HIP_TRY(hipDeviceSynchronize());
+    // graph: [sequential kernel] and [look-back kernel] in parallel, then
+    // the replay-parity toggle after both
     HIP_TRY(hipGraphCreate(&p->graph, 0));
-    hipKernelNodeParams kp{};
-    void *params[] = {&p->args};
-    kp.func = const_cast<void *>(p->kernel);
-    kp.gridDim = dim3(p->grid);
-    kp.blockDim = dim3(kBlockThreads);
-    kp.sharedMemBytes = 0;
-    kp.kernelParams = params;
-    kp.extra = nullptr;
-    hipGraphNode_t node;
-    HIP_TRY(hipGraphAddKernelNode(&node, p->graph, nullptr, 0, &kp));
+    std::vector<hipGraphNode_t> fills;
+    p->seq_args = args;
+    p->seq_args.flip = p->flip;
+    p->lb_args = args;
+    p->lb_args.flip = p->flip;
+    if (!bp.seq.empty()) {
+        p->seq_args.segs = p->dsegs + bp.lb.size();
+        p->seq_args.nseg = uint32_t(bp.seq.size());
+        p->seq_args.total_tiles = uint32_t(bp.seq.size());
+        p->seq_args.ctl = p->ws.seq_ctl;
+        hipKernelNodeParams kp{};
+        void *params[] = {&p->seq_args};
+        kp.func = const_cast<void *>(lp.seq_kernel);
+        kp.gridDim = dim3(grid_for(d, lp, lp.seq_kernel, bp.seq.size()));
+        kp.blockDim = dim3(lp.threads);
+        kp.kernelParams = params;
+        hipGraphNode_t node;
+        HIP_TRY(hipGraphAddKernelNode(&node, p->graph, nullptr, 0, &kp));
+        fills.push_back(node);
+    }
+    if (!bp.lb.empty()) {
+        p->lb_args.segs = p->dsegs;
+        p->lb_args.tile_seg = p->tile_seg;
+        p->lb_args.nseg = uint32_t(bp.lb.size());
+        p->lb_args.total_tiles = uint32_t(bp.lb_tiles);
+        p->lb_args.status = p->ws.status;
+        p->lb_args.ctl = p->ws.ctl;
+        hipKernelNodeParams kp{};
+        void *params[] = {&p->lb_args};
+        kp.func = const_cast<void *>(lp.kernel);
+        kp.gridDim = dim3(grid_for(d, lp, lp.kernel, bp.lb_tiles));
+        kp.blockDim = dim3(lp.threads);
+        kp.kernelParams = params;
+        hipGraphNode_t node;
+        HIP_TRY(hipGraphAddKernelNode(&node, p->graph, nullptr, 0, &kp));
+        fills.push_back(node);
+    }
+    {
+        hipKernelNodeParams kp{};
+        uint32_t *flip = p->flip;
+        void *params[] = {&flip};
+        kp.func = const_cast<void *>(toggle_flip_kernel_ptr());
+        kp.gridDim = dim3(1);
+        kp.blockDim = dim3(1);
+        kp.kernelParams = params;
+        hipGraphNode_t node;
+        HIP_TRY(hipGraphAddKernelNode(&node, p->graph, fills.data(), fills.size(), &kp));
+    }
     HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
-    for (prngd_handle_t h : p->handles) {
+    p->ws.launches = 0;
+    for (size_t i = 0; i < p->handles.size(); ++i) {
+        prngd_handle_t h = p->handles[i];
         p->base_parity.push_back(h->parity);
         h->plan = p.get();
+        h->plan_index = i;
     }
+    p->lb_args.total_tiles = uint32_t(bp.lb_tiles);
     *out_plan = p.release();
     return PRNGD_OK;
 }
@@ -1028,10 +1209,12 @@ prngd_status_t prngd_plan_launch(prngd_plan_t p, void *stream)
     if ((st = check_device_errors(d)) != PRNGD_OK)
         return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (p->ws.launches > 0 && p->ws.launches % kEpochMask == 0)
+    const bool has_lb = p->lb_args.total_tiles > 0;
+    if (has_lb && p->ws.launches > 0 && p->ws.launches % kEpochMask == 0)
         HIP_TRY(launch_zero_words(p->ws.status, p->ws.status_cap, s));
     HIP_TRY(hipGraphLaunch(p->exec, s));
-    p->ws.launches++;
+    if (has_lb)
+        p->ws.launches++;
     p->launches++;
     HIP_TRY(hipEventRecord(p->ws.last, s));
     for (prngd_handle_t h : p->handles) {
@@ -1059,11 +1242,9 @@ prngd_status_t prngd_plan_destroy(prngd_plan_t p)
     if (p->graph)
         (void)hipGraphDestroy(p->graph);
     (void)hipFree(p->dsegs);
-    (void)hipFree(p->ws.status);
-    (void)hipFree(p->ws.ctl);
-    (void)hipEventDestroy(p->ws.last);
-    for (int i = 0; i < 2; ++i)
-        (void)hipEventDestroy(p->ws.hsegs_done[i]);
+    (void)hipFree(p->tile_seg);
+    (void)hipFree(p->flip);
+    ws_release(&p->ws);
     delete p;
     return PRNGD_OK;
 }
@@ -1073,19 +1254,22 @@ prngd_status_t prngd_set_tuning(prngd_generator_t generator, uint32_t w,
 {
     if (generator < PRNGD_PHILOX4X32_10 || generator > PRNGD_ENUMERATE)
         return fail(PRNGD_ERR_UNSUPPORTED, "unknown generator %d", int(generator));
-    const uint32_t fams[] = {FAM_PHILOX, FAM_MRG, FAM_MIXED, FAM_ENUM};
-    const uint32_t fam = fams[generator];
+    const uint32_t fam = kernel_family(generator, w);
     std::lock_guard<std::recursive_mutex> lock(g_mutex);
     if (!tuning) {
         g_tuning.erase(std::make_pair(fam, w));
         return PRNGD_OK;
     }
-    if (tuning->pairs_per_lane && !valid_ppl(fam, tuning->pairs_per_lane))
-        return fail(PRNGD_ERR_INVALID_ARGUMENT, "pairs_per_lane %u not available",
-                    tuning->pairs_per_lane);
-    if (tuning->store_mode > 2 || tuning->slack_mode > 1)
+    prngd_tuning_t t = *tuning;
+    const prngd_tuning_t def = tuning_for(fam, 0xFFFFFFFFu);
+    const uint32_t threads = t.block_threads ? t.block_threads : def.block_threads;
+    const uint32_t ppl = t.pairs_per_lane ? t.pairs_per_lane : def.pairs_per_lane;
+    if (!fill_kernel_for(fam, threads, ppl, false))
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u threads x %u pairs per lane",
+                    threads, ppl);
+    if (t.store_mode > 2 || t.slack_mode > 1)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "bad store_mode or slack_mode");
-    g_tuning[std::make_pair(fam, w)] = *tuning;
+    g_tuning[std::make_pair(fam, w)] = t;
     return PRNGD_OK;
 }
 
@@ -1093,9 +1277,8 @@ prngd_status_t prngd_get_tuning(prngd_generator_t generator, uint32_t w, prngd_t
 {
     if (generator < PRNGD_PHILOX4X32_10 || generator > PRNGD_ENUMERATE || !tuning)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "bad arguments");
-    const uint32_t fams[] = {FAM_PHILOX, FAM_MRG, FAM_MIXED, FAM_ENUM};
     std::lock_guard<std::recursive_mutex> lock(g_mutex);
-    *tuning = tuning_for(fams[generator], w);
+    *tuning = tuning_for(kernel_family(generator, w), w);
     return PRNGD_OK;
 }
 

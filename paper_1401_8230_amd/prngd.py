@@ -47,7 +47,8 @@ class Request(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("pairs_per_lane", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
-                ("store_mode", ctypes.c_uint32), ("slack_mode", ctypes.c_uint32)]
+                ("store_mode", ctypes.c_uint32), ("slack_mode", ctypes.c_uint32),
+                ("block_threads", ctypes.c_uint32), ("seq_max_tiles", ctypes.c_uint32)]
 
 
 # (name, restype, argtypes) of every exported function
@@ -62,6 +63,9 @@ _SIGNATURES = [
     ("prngd_create", ctypes.c_int,
      [ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
       ctypes.POINTER(ctypes.c_void_p)]),
+    ("prngd_create_many", ctypes.c_int,
+     [ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+      ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
     ("prngd_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("prngd_set_position", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p]),
@@ -80,6 +84,11 @@ _SIGNATURES = [
      [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(Tuning)]),
     ("prngd_get_tuning", ctypes.c_int,
      [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(Tuning)]),
+    ("prngd_probe_write", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    ("prngd_probe_philox", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]),
+    ("prngd_probe_philox_store", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
 ]
 
 _lib = None
@@ -162,7 +171,8 @@ class Generator:
     """A PRNGD stream handle: Algorithm 1's PRNGD(k, min, max) with a base
     generator and a seed, positioned at (stream_id, pair counter)."""
 
-    def __init__(self, seed, generator="philox", w=32, k=None, min=None, max=None):
+    def __init__(self, seed, generator="philox", w=32, k=None, min=None, max=None,
+                 _handle=None):
         g = _gen(generator)
         if k is None:
             k = 2.0 ** -w
@@ -170,12 +180,31 @@ class Generator:
             lo, hi = natural_range(g, w)
             min = lo if min is None else min
             max = hi if max is None else max
-        h = ctypes.c_void_p()
-        _check(lib().prngd_create(seed, g, k, min, max, ctypes.byref(h)))
+        if _handle is None:
+            h = ctypes.c_void_p()
+            _check(lib().prngd_create(seed, g, k, min, max, ctypes.byref(h)))
+        else:
+            h = _handle
         self._h = h
         self.generator = g
         self.seed = seed
         self.k = k
+
+    @classmethod
+    def many(cls, seed, count, generator="philox", w=32, first_stream_id=0, k=None,
+             min=None, max=None):
+        """`count` generators on consecutive substreams of one seed, all at
+        pair counter 0, created without any GPU work."""
+        g = _gen(generator)
+        if k is None:
+            k = 2.0 ** -w
+        lo, hi = natural_range(g, w)
+        min = lo if min is None else min
+        max = hi if max is None else max
+        arr = (ctypes.c_void_p * count)()
+        _check(lib().prngd_create_many(seed, g, k, min, max, first_stream_id, count, arr))
+        return [cls(seed, g, w=w, k=k, min=min, max=max, _handle=ctypes.c_void_p(arr[i]))
+                for i in range(count)]
 
     @property
     def handle(self):
@@ -254,8 +283,10 @@ class Plan:
             pass
 
 
-def set_tuning(generator, w, pairs_per_lane=0, blocks_per_cu=0, store_mode=0, slack_mode=0):
-    t = Tuning(pairs_per_lane, blocks_per_cu, store_mode, slack_mode)
+def set_tuning(generator, w, pairs_per_lane=0, blocks_per_cu=0, store_mode=0, slack_mode=0,
+               block_threads=0, seq_max_tiles=0):
+    t = Tuning(pairs_per_lane, blocks_per_cu, store_mode, slack_mode, block_threads,
+               seq_max_tiles)
     _check(lib().prngd_set_tuning(_gen(generator), w, ctypes.byref(t)))
 
 
@@ -267,4 +298,28 @@ def get_tuning(generator, w):
     t = Tuning()
     _check(lib().prngd_get_tuning(_gen(generator), w, ctypes.byref(t)))
     return {"pairs_per_lane": t.pairs_per_lane, "blocks_per_cu": t.blocks_per_cu,
-            "store_mode": t.store_mode, "slack_mode": t.slack_mode}
+            "store_mode": t.store_mode, "slack_mode": t.slack_mode,
+            "block_threads": t.block_threads, "seq_max_tiles": t.seq_max_tiles}
+
+
+# ------------------------------------------------------------------ probes
+def _probe(rc):
+    if rc != 0:
+        raise PrngdError(rc, f"probe failed with code {rc}")
+
+
+def probe_write(out, stream=None):
+    """Coalesced 16-byte stores over all of `out` (float64 CUDA tensor)."""
+    ptr, n = _out_ptr(out, None)
+    _probe(lib().prngd_probe_write(ptr, n, _stream_ptr(stream)))
+
+
+def probe_philox(sink, blocks, stream=None):
+    """`blocks` Philox4x32-10 blocks folded into `sink` (int32 CUDA tensor)."""
+    _probe(lib().prngd_probe_philox(sink.data_ptr(), sink.numel(), blocks, _stream_ptr(stream)))
+
+
+def probe_philox_store(out, stream=None):
+    """Philox pairs mapped and stored to all of `out`, no acceptance test."""
+    ptr, n = _out_ptr(out, None)
+    _probe(lib().prngd_probe_philox_store(ptr, n, _stream_ptr(stream)))

@@ -13,12 +13,17 @@ from paper_1401_8230_amd import prngd
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "prngd.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(prngd_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(prngd_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -33,9 +38,10 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= exported
 
 
-def test_header_is_plain_c():
-    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c", HEADER],
-                   check=True)
+def test_headers_are_plain_c():
+    for h in HEADERS:
+        subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c", h],
+                       check=True)
 
 
 def test_binding_covers_every_declared_symbol():
@@ -117,7 +123,8 @@ def test_null_arguments():
 def test_tuning_round_trip_and_validation():
     prngd.set_tuning("philox", 13, pairs_per_lane=8, blocks_per_cu=3, store_mode=2)
     assert prngd.get_tuning("philox", 13) == {"pairs_per_lane": 8, "blocks_per_cu": 3,
-                                              "store_mode": 2, "slack_mode": 0}
+                                              "store_mode": 2, "slack_mode": 0,
+                                              "block_threads": 256, "seq_max_tiles": 0}
     prngd.reset_tuning("philox", 13)
     assert prngd.get_tuning("philox", 13)["pairs_per_lane"] == 16
     with pytest.raises(prngd.PrngdError):
@@ -126,3 +133,10 @@ def test_tuning_round_trip_and_validation():
         prngd.set_tuning("mrg32k3a", 32, pairs_per_lane=32)
     with pytest.raises(prngd.PrngdError):
         prngd.set_tuning("philox", 13, store_mode=3)
+    with pytest.raises(prngd.PrngdError):
+        prngd.set_tuning("philox", 13, block_threads=128)
+    with pytest.raises(prngd.PrngdError):
+        prngd.set_tuning("mixed", 32, block_threads=512)
+    prngd.set_tuning("philox", 13, block_threads=1024, pairs_per_lane=8)
+    assert prngd.get_tuning("philox", 13)["block_threads"] == 1024
+    prngd.reset_tuning("philox", 13)

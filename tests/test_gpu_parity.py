@@ -251,9 +251,13 @@ def make_handles(reqs, gen, w):
 
 
 @pytest.mark.parametrize("gen,w", [("philox", 32), ("philox", 8), ("mixed", 32), ("mrg32k3a", 32)])
-def test_batch_matches_oracle(gen, w):
+@pytest.mark.parametrize("seq_max_tiles", [0, 1, 3, 1 << 20])
+def test_batch_matches_oracle(gen, w, seq_max_tiles):
+    """Requests split between the segment-sequential kernel and the
+    look-back kernel in every proportion give the oracle's bytes."""
     from paper_1401_8230_amd import workloads
-    note(f"batch {gen} w={w}")
+    note(f"batch {gen} w={w} seq_max_tiles={seq_max_tiles}")
+    prngd.set_tuning(gen, w, seq_max_tiles=seq_max_tiles)
     reqs = workloads.uneven_batch(count=200, lo=1, hi=3e4, rng_seed=w)
     gens = make_handles(reqs, gen, w)
     outs = [torch.empty(r.n, dtype=torch.float64, device=DEV) for r in reqs]
@@ -283,8 +287,10 @@ def test_batch_with_empty_requests_and_errors():
         prngd.fill_batch([(a, ta), (c, tb)])          # mixed configurations
 
 
-def test_plan_replays_advance_handles():
+@pytest.mark.parametrize("seq_max_tiles", [0, 1, 1 << 20])
+def test_plan_replays_advance_handles(seq_max_tiles):
     from paper_1401_8230_amd import workloads
+    prngd.set_tuning("philox", 8, seq_max_tiles=seq_max_tiles)
     reqs = workloads.uneven_batch(count=64, lo=1, hi=5e4, rng_seed=9)
     gens = make_handles(reqs, "philox", 8)
     outs = [torch.empty(r.n, dtype=torch.float64, device=DEV) for r in reqs]
@@ -319,7 +325,7 @@ def test_many_streams_full_size_sampled():
     reqs = workloads.many_streams()
     n = reqs[0].n
     note("many streams: creating handles")
-    gens = make_handles(reqs, "philox", 32)
+    gens = prngd.Generator.many(42, len(reqs), "philox", w=32)
     out = torch.empty(len(reqs) * n, dtype=torch.float64, device=DEV)
     views = [out[i * n:(i + 1) * n] for i in range(len(reqs))]
     plan = prngd.Plan(list(zip(gens, views)))
@@ -379,3 +385,17 @@ def test_single_stream_2_28_sampled(gen, w):
         v = float(out[i])
         cands = [s.map(*s.pair(p)) for p in range(i, i + rejected + 1) if s.accept(s.pair(p)[0])]
         assert v in cands, f"output {i}"
+
+
+@pytest.mark.parametrize("gen,w", [("philox", 32), ("philox", 12), ("mixed", 32)])
+def test_create_many_matches_individual_substreams(gen, w):
+    gens = prngd.Generator.many(99, 5, gen, w=w, first_stream_id=2**32 - 5)
+    for i, g in enumerate(gens):
+        t = torch.empty(3001, dtype=torch.float64, device=DEV)
+        g.fill(t)
+        expect, ectr = oracle_fill(gen, w, 99, 2**32 - 5 + i, 0, 3001)
+        assert_bits_equal(t.cpu().numpy(), expect, f"substream {i}")
+        assert g.get_position() == (2**32 - 5 + i, ectr)
+        g.close()
+    with pytest.raises(prngd.PrngdError):
+        prngd.Generator.many(99, 6, gen, w=w, first_stream_id=2**32 - 5)
