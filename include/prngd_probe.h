@@ -23,6 +23,11 @@ extern "C" {
  * outputs. */
 int prngd_probe_write(double *out, uint64_t n, void *stream);
 
+/* Copy n doubles from src to dst (n even; both 16-byte aligned; the two
+ * ranges must not overlap): 8n bytes read and 8n written, the known
+ * traffic against which HBM byte counters are scaled. */
+int prngd_probe_copy(double *dst, const double *src, uint64_t n, void *stream);
+
 /* Compute `blocks` Philox4x32-10 blocks (a fill of n outputs of the single
  * Philox generator needs n / 2) and fold them into one word per thread of
  * `sink` (sink_words >= grid * 256; the grid shrinks to fit). */

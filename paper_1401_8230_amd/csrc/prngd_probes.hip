@@ -4,6 +4,8 @@
 //   * Philox probe: the same Philox4x32-10 blocks a fill of n outputs
 //     needs, XOR-folded in registers, one word stored per thread (the
 //     integer ALU ceiling of the base generator);
+//   * copy probe: n doubles read and written once (the calibration of the
+//     HBM byte counters);
 //   * Philox+map+store probe: every pair accepted and stored, no
 //     compaction and no cross-block scan (the fill without its ordering
 //     machinery).
@@ -69,6 +71,15 @@ __global__ __launch_bounds__(256) void philox_probe(uint32_t *sink, uint64_t blo
     sink[tid] = acc;
 }
 
+// One 16-byte load and one 16-byte store per thread: a plain copy of known
+// size, the reference by which HBM byte counters are calibrated.
+__global__ __launch_bounds__(256) void copy_probe(double *dst, const double *src, uint64_t n2)
+{
+    const uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
+    if (i < n2)
+        reinterpret_cast<double2v *>(dst)[i] = reinterpret_cast<const double2v *>(src)[i];
+}
+
 // One Philox block per thread over a one-shot grid, like the write probe.
 __global__ __launch_bounds__(256) void philox_store_probe(double *out, uint64_t blocks,
                                                           uint64_t seed, double S)
@@ -112,6 +123,23 @@ int prngd_probe_write(double *out, uint64_t n, void *stream)
         return 1;
     hipLaunchKernelGGL(write_probe, dim3(uint32_t(blocks)), dim3(256), 0,
                        static_cast<hipStream_t>(stream), out, n2, 0.5);
+    return hipGetLastError() == hipSuccess ? 0 : 4;
+}
+
+int prngd_probe_copy(double *dst, const double *src, uint64_t n, void *stream)
+{
+    if (!dst || !src || ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15u) ||
+        (n & 1u))
+        return 1;
+    const uint64_t lo_d = reinterpret_cast<uintptr_t>(dst), lo_s = reinterpret_cast<uintptr_t>(src);
+    if (lo_d < lo_s + 8 * n && lo_s < lo_d + 8 * n)
+        return 1;                                     // overlapping buffers
+    const uint64_t n2 = n / 2;
+    const uint64_t blocks = (n2 + 255) / 256;
+    if (blocks == 0 || blocks > 0xFFFFFFFFull)
+        return 1;
+    hipLaunchKernelGGL(copy_probe, dim3(uint32_t(blocks)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), dst, src, n2);
     return hipGetLastError() == hipSuccess ? 0 : 4;
 }
 

@@ -85,6 +85,8 @@ _SIGNATURES = [
     ("prngd_get_tuning", ctypes.c_int,
      [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(Tuning)]),
     ("prngd_probe_write", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    ("prngd_probe_copy", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     ("prngd_probe_philox", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]),
     ("prngd_probe_philox_store", ctypes.c_int,
@@ -312,6 +314,15 @@ def probe_write(out, stream=None):
     """Coalesced 16-byte stores over all of `out` (float64 CUDA tensor)."""
     ptr, n = _out_ptr(out, None)
     _probe(lib().prngd_probe_write(ptr, n, _stream_ptr(stream)))
+
+
+def probe_copy(dst, src, stream=None):
+    """Copy float64 CUDA tensor `src` into `dst` (same length, disjoint)."""
+    pd, n = _out_ptr(dst, None)
+    ps, ns = _out_ptr(src, None)
+    if n != ns:
+        raise PrngdError(ERR_INVALID_ARGUMENT, "probe_copy: lengths differ")
+    _probe(lib().prngd_probe_copy(pd, ps, n, _stream_ptr(stream)))
 
 
 def probe_philox(sink, blocks, stream=None):
