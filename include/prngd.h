@@ -99,6 +99,15 @@ typedef struct {
                               /* are produced whole by one workgroup; the   */
                               /* rest are split over workgroups joined by   */
                               /* the look-back (0: half a fair share)       */
+    uint32_t path;            /* 0 automatic; 1 ordered (look-back and      */
+                              /* segment-sequential kernels); 2 speculative */
+                              /* (each tile stores at the offset it assumes,*/
+                              /* a repair pass redoes tiles that assumed    */
+                              /* wrong).  Automatic takes the speculative   */
+                              /* fill when a launch expects at most 8       */
+                              /* rejections and has a segment of at least   */
+                              /* 64 tiles.  Philox and the test generator   */
+                              /* only                                       */
 } prngd_tuning_t;
 
 /* Human-readable name of a status code (static storage). */

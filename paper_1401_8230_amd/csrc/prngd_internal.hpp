@@ -61,6 +61,22 @@ struct Control {
 };
 static_assert(sizeof(Control) == 256, "Control layout");
 
+// Per-workspace bookkeeping of the speculative fill, device memory, zero
+// between launches: `count` entries of the rejection list were appended by
+// the fill kernel; the repair kernel's workgroups count themselves out in
+// `done`, and the last one clears the list for the next launch.
+struct SpecControl {
+    uint32_t count;
+    uint32_t pad0[31];
+    uint32_t done;
+    uint32_t pad1[31];
+};
+static_assert(sizeof(SpecControl) == 256, "SpecControl layout");
+
+// Rejection-list entry: (launch-local tile + 1) << 32 | rejected pairs of
+// that tile's window; 0 is an empty slot.
+constexpr uint32_t kHintEntries = 256;    // entries a tile reads for its hint
+
 struct LaunchArgs {
     const Segment *segs;      // nseg descriptors, or null for seg0
     const uint32_t *tile_seg; // launch-local tile -> segment index (segs only)
@@ -76,6 +92,9 @@ struct LaunchArgs {
     uint32_t a0, a;           // x1 range [a0, a]
     uint32_t b0;              // x2 lower bound
     double S;                 // RN((1 - 2^-2w) / D)
+    SpecControl *spec;        // speculative fill: list control,
+    uint64_t *rejlist;        //   rejection list (total_tiles slots),
+    uint32_t *hint;           //   per tile: earlier rejections it assumed
     const uint32_t *mrg_thread;  // [256][18]: A^(r * tid * PPL)
     const uint32_t *mrg_window;  // [8][256][18]: A^(r * T * d * 256^i)
 };
@@ -84,5 +103,6 @@ constexpr uint32_t kMaxTiles = 0xFFFFFFF0u;
 
 // Device error codes (bit flags in the error word).
 constexpr uint32_t kErrLookbackStall = 1;
+constexpr uint32_t kErrSpecList = 2;       // rejection list out of its bounds
 
 }  // namespace prngd

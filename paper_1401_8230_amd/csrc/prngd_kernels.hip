@@ -138,6 +138,16 @@ __device__ __forceinline__ double prngd_map(uint32_t x1, uint32_t x2, const Laun
 }
 
 // ------------------------------------------------------- wave utilities
+// Lane i receives lane i - 1's value (lane 0 receives 0): one DPP
+// wave_shr:1 move per 32-bit half, no LDS round trip.
+__device__ __forceinline__ double wave_shr1(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b)), 0x138, 0xF, 0xF, false));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b >> 32)), 0x138, 0xF, 0xF, false));
+    return __builtin_bit_cast(double, uint64_t(hi) << 32 | lo);
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt(uint32_t lane)
 {
     return (uint64_t(1) << lane) - 1;
@@ -618,8 +628,44 @@ struct SpecTile {
         return FAM == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
     }
 
+    // Accepted pairs of window `win` from window offset lo_off on, without
+    // storing anything.
+    __device__ __forceinline__ static uint32_t count_kept(const LaunchArgs &args,
+                                                          const Segment &seg, uint64_t win,
+                                                          uint32_t lo_off, uint32_t *s_off)
+    {
+        const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+        const uint32_t hm = hmax(args);
+        uint32_t rej = 0;
+#pragma unroll 2
+        for (int j = 0; j < J; ++j) {
+            const uint32_t q = 2u * (uint32_t(j) * B + tid);
+            const HiLo p = words(args, seg, win, j);
+            rej += uint32_t(p.ha >= hm && q >= lo_off) + uint32_t(p.hb >= hm && q + 1 >= lo_off);
+        }
+        uint32_t kept = T - lo_off;
+        if (__syncthreads_or(rej != 0)) {
+            const uint32_t r = wave_incl_scan(rej, lane);
+            if (lane == 63)
+                s_off[wave] = r;
+            __syncthreads();
+            uint32_t total = 0;
+#pragma unroll
+            for (int k = 0; k < NW; ++k)
+                total += s_off[k];
+            kept -= total;
+            __syncthreads();
+        }
+        return kept;
+    }
+
     // Produce window `win` (from window offset lo_off on) at segment offset
-    // excl; returns the window's number of accepted pairs.
+    // excl; returns the window's number of accepted pairs.  With kSpec the
+    // pairs are stored as they are generated (a window that turns out not
+    // to be clean leaves stale values on up to T positions past its own
+    // outputs); without it the window is always produced exactly and
+    // writes nothing but its own outputs.
+    template <bool kSpec = true>
     __device__ __forceinline__ uint32_t run(const LaunchArgs &args, const Segment &seg,
                                             uint64_t win, uint32_t lo_off, uint64_t excl,
                                             uint64_t *next_counter, uint32_t *s_off)
@@ -629,11 +675,15 @@ struct SpecTile {
         double *o = seg.out + excl;
         const uint64_t left = n - excl;       // outputs still wanted, >= 1
         const bool aligned = args.store_mode != 1 && (reinterpret_cast<uintptr_t>(o) & 15u) == 0;
+        // outputs 8 bytes off a 16-byte boundary: lane i stores its first
+        // output with the second one of lane i - 1 (lanes 0 and 63 store
+        // one output alone), so the stores stay 16 bytes wide
+        const bool shifted = args.store_mode != 1 && !aligned;
         const uint32_t hm = hmax(args);
         const double tw = two_w(args);
         uint32_t acc = 0;
         bool dirty;
-        if (lo_off == 0 && left > T) {
+        if (kSpec && lo_off == 0 && left > T) {
             // a full window that does not hold output n - 1: no bounds, no
             // counter; one running max of hi finds any rejection
             uint32_t mx = 0;
@@ -646,6 +696,14 @@ struct SpecTile {
                 const double zb = map_hi_lo(p.hb, p.lb, tw, args.S);
                 if (aligned) {
                     store_two(o + q, za, zb, args.store_mode);
+                } else if (shifted) {
+                    const double prev = wave_shr1(zb);
+                    if (lane == 0)
+                        store_one(o + q, za, args.store_mode);
+                    else
+                        store_two(o + q - 1, prev, za, args.store_mode);
+                    if (lane == 63)
+                        store_one(o + q + 1, zb, args.store_mode);
                 } else {
                     store_one(o + q, za, args.store_mode);
                     store_one(o + q + 1, zb, args.store_mode);
@@ -667,7 +725,7 @@ struct SpecTile {
                 const bool oka = p.ha < hm && q >= lo_off;
                 const bool okb = p.hb < hm && q + 1 >= lo_off;
                 acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
-                if (lo_off == 0) {
+                if (kSpec && lo_off == 0) {
                     const double za = map_hi_lo(p.ha, p.la, tw, args.S);
                     const double zb = map_hi_lo(p.hb, p.lb, tw, args.S);
                     if (aligned && q + 1 < left) {
@@ -682,7 +740,7 @@ struct SpecTile {
                         *next_counter = win * T + left;
                 }
             }
-            dirty = __syncthreads_or(lo_off != 0 || acc != kAll);
+            dirty = __syncthreads_or(!kSpec || lo_off != 0 || acc != kAll);
             if (!dirty)
                 return T;
         }
@@ -1076,6 +1134,248 @@ __global__ __launch_bounds__(64 * NW) void seq_philox_kernel(LaunchArgs args)
     sequential_spec_loop<NW, PPL, FAM>(args, s_off, &s_state, s_next);
 }
 
+// ======================================================================
+// Speculative fill for configurations whose rejections are rare (w = 32:
+// one pair in 2^31).  One workgroup per tile, no tickets and no waits:
+// tile t of a segment assumes that the segment's earlier tiles rejected
+// exactly the pairs it has heard of, and stores its window at once at the
+// offset that gives.  Tiles whose window rejects pairs append
+// (tile, count) to a rejection list, which later tiles read as their
+// hint; each tile records the hint it used.  A repair launch that follows
+// in stream order recomputes every tile's true offset from the complete
+// list and produces again exactly the tiles that (a) assumed too few
+// earlier rejections, (b) may hold stale values written there by an
+// earlier tile, or (c) hold the segment's last output (so that the next
+// pair counter is the true one).  With no rejection in the launch the
+// repair launch reads one word and exits.
+// ======================================================================
+template <int NW, int PPL, uint32_t FAM>
+__global__ __launch_bounds__(64 * NW) void spec_philox_kernel(LaunchArgs args)
+{
+    using Tile = SpecTile<NW, PPL, FAM>;
+    constexpr uint32_t T = Tile::T;
+    __shared__ uint32_t s_off[Tile::E + 1];
+    __shared__ uint32_t s_hint;
+    const uint32_t g = blockIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    Segment seg;
+    uint32_t t;
+    lookup(args, g, &seg, &t);
+    const uint32_t par = seg.parity ^ read_flip(args);
+    const uint64_t c0 = load_start(seg, par);
+    uint64_t *next_counter = seg.counter + (par ^ 1u);
+    if (tid < 64) {
+        uint32_t used = 0;
+        if (t > 0) {
+            const uint32_t cnt = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                &args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (cnt != 0) {
+                const uint32_t lim = cnt < kHintEntries ? cnt : kHintEntries;
+                for (uint32_t i = lane; i < lim; i += 64) {
+                    const uint64_t e = __hip_atomic_load(&args.rejlist[i], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t et = uint32_t(e >> 32);    // tile + 1; 0 = not written yet
+                    if (et > seg.tile_begin && et <= g)
+                        used += uint32_t(e);
+                }
+                used = wave_incl_scan(used, lane);
+            }
+        }
+        if (lane == 63)
+            s_hint = used;
+    }
+    __syncthreads();
+    const uint32_t used = __builtin_amdgcn_readfirstlane(s_hint);
+    if (tid == 0)
+        args.hint[g] = used;
+    const uint64_t w0 = c0 / T;
+    const uint32_t lo0 = uint32_t(c0 - w0 * T);
+    const uint64_t win = w0 + t;
+    const uint32_t lo_off = t == 0 ? lo0 : 0u;
+    const uint64_t excl = (t == 0 ? 0 : uint64_t(t) * T - lo0) - used;
+    uint32_t kept;
+    if (excl < seg.n)
+        kept = Tile().run(args, seg, win, lo_off, excl, next_counter, s_off);
+    else
+        kept = Tile::count_kept(args, seg, win, lo_off, s_off);
+    const uint32_t rej = (T - lo_off) - kept;
+    if (rej != 0 && tid == 0) {
+        const uint32_t slot = __hip_atomic_fetch_add(&args.spec->count, 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        if (slot < args.total_tiles)
+            __hip_atomic_store(&args.rejlist[slot], (uint64_t(g) + 1u) << 32 | rej,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            __hip_atomic_fetch_or(args.error, kErrSpecList, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    // the segment's last tile takes every further window until n outputs
+    if (t == seg.ntiles - 1) {
+        uint64_t running = excl + kept;
+        for (uint64_t w2 = win + 1; running < seg.n; ++w2)
+            running += Tile().run(args, seg, w2, 0u, running, next_counter, s_off);
+    }
+}
+
+// What the repair needs to know of one tile of a dirty segment, from the
+// complete rejection list: earlier rejections in its segment (P), its own
+// rejections, and whether any earlier tile of the segment rejected pairs.
+struct TileFacts {
+    uint32_t P;
+    uint32_t rej;
+    bool after_dirty;
+};
+
+__device__ __forceinline__ TileFacts tile_facts(const uint64_t *list, uint32_t cnt,
+                                                uint32_t tile_begin, uint32_t g)
+{
+    TileFacts f{0u, 0u, false};
+    for (uint32_t i = 0; i < cnt; ++i) {
+        const uint64_t e = list[i];
+        const uint32_t et = uint32_t(e >> 32);
+        if (et > tile_begin && et <= g) {
+            f.P += uint32_t(e);
+            f.after_dirty = true;
+        } else if (et == g + 1) {
+            f.rej = uint32_t(e);
+        }
+    }
+    return f;
+}
+
+constexpr uint32_t kRepairCache = 1024;    // list entries kept in LDS
+
+// Whether tile g (of segment `seg`, tile index t, start position c0) has
+// to be produced again, and at which true offset.
+template <uint32_t T>
+__device__ __forceinline__ bool needs_redo(const LaunchArgs &args, const uint64_t *list,
+                                           uint32_t cnt, const Segment &seg, uint32_t t,
+                                           uint64_t c0, uint32_t g, uint64_t *true_off)
+{
+    const TileFacts f = tile_facts(list, cnt, seg.tile_begin, g);
+    if (!f.after_dirty)
+        return false;                 // up to the segment's first dirty tile all is exact
+    const uint32_t lo0 = uint32_t(c0 % T);
+    const uint64_t off = uint64_t(t) * T - lo0 - f.P;    // t >= 1 here
+    if (off >= seg.n)
+        return false;                 // every output of the tile lies past n
+    *true_off = off;
+    if (args.hint[g] != f.P)
+        return true;                  // (a) assumed too few earlier rejections
+    const uint64_t kept = uint64_t(T) - f.rej;
+    if (off + kept >= seg.n || t == seg.ntiles - 1)
+        return true;                  // (c) holds output n - 1
+    // (b) an earlier tile v wrote T positions from its assumed offset,
+    // which lies P(v) - hint(v) past its true one, and kept only the first
+    // kept(v) of them: stale values reach P(v) - hint(v) + rej(v) past
+    // its true end.  Earlier tiles' reach is bounded by P + T.
+    uint64_t gap = 0;                 // outputs between v's true end and this tile
+    for (uint32_t v = g - 1;; --v) {
+        const TileFacts fv = tile_facts(list, cnt, seg.tile_begin, v);
+        const uint64_t reach = uint64_t(fv.P - args.hint[v]) + fv.rej;
+        if (reach > gap)
+            return true;
+        if (!fv.after_dirty || v == seg.tile_begin)
+            break;                    // v is the first dirty tile or earlier
+        const uint32_t tv = v - seg.tile_begin;
+        gap += uint64_t(T) - (tv == 0 ? lo0 : 0u) - fv.rej;
+        if (gap >= uint64_t(f.P) + T)
+            break;
+    }
+    return false;
+}
+
+template <int NW, int PPL, uint32_t FAM>
+__global__ __launch_bounds__(64 * NW) void spec_repair_kernel(LaunchArgs args)
+{
+    using Tile = SpecTile<NW, PPL, FAM>;
+    constexpr uint32_t T = Tile::T;
+    constexpr uint32_t B = 64 * NW;
+    __shared__ uint32_t s_off[Tile::E + 1];
+    __shared__ uint64_t s_list[kRepairCache];
+    __shared__ uint32_t s_queue[B];
+    __shared__ uint64_t s_qoff[B];
+    __shared__ uint32_t s_nq;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t cnt0 =
+        __hip_atomic_load(&args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cnt0 == 0)
+        return;
+    const uint32_t cnt = cnt0 < args.total_tiles ? cnt0 : args.total_tiles;
+    const uint64_t *list = args.rejlist;
+    if (cnt <= kRepairCache) {
+        for (uint32_t i = tid; i < cnt; i += B)
+            s_list[i] = __hip_atomic_load(&args.rejlist[i], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        list = s_list;
+    }
+    const uint32_t flip = read_flip(args);
+    // pass p: thread tid checks tile (p B + tid) G + blockIdx, so that a run
+    // of consecutive tiles to redo is spread over all workgroups
+    const uint64_t G = gridDim.x;
+    for (uint64_t p = 0; p * B * G + blockIdx.x < args.total_tiles; ++p) {
+        if (tid == 0)
+            s_nq = 0;
+        __syncthreads();
+        const uint64_t g64 = (p * B + tid) * G + blockIdx.x;
+        if (g64 < args.total_tiles) {
+            const uint32_t g = uint32_t(g64);
+            Segment seg;
+            uint32_t t;
+            if (args.segs == nullptr) {
+                seg = args.seg0;
+                t = g;
+            } else {
+                seg = args.segs[args.tile_seg[g]];
+                t = g - seg.tile_begin;
+            }
+            const uint64_t c0 = seg.counter[seg.parity ^ flip];
+            uint64_t off = 0;
+            if (t > 0 && needs_redo<T>(args, list, cnt, seg, t, c0, g, &off)) {
+                const uint32_t k = atomicAdd(&s_nq, 1u);
+                s_queue[k] = g;
+                s_qoff[k] = off;
+            }
+        }
+        __syncthreads();
+        const uint32_t nq = s_nq;
+        for (uint32_t k = 0; k < nq; ++k) {
+            const uint32_t g = __builtin_amdgcn_readfirstlane(s_queue[k]);
+            const uint64_t q = s_qoff[k];
+            const uint64_t off = uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(q))) |
+                                 uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(q >> 32))) << 32;
+            Segment seg;
+            uint32_t t;
+            lookup(args, g, &seg, &t);
+            const uint32_t par = seg.parity ^ flip;
+            const uint64_t c0 = load_start(seg, par);
+            uint64_t *next_counter = seg.counter + (par ^ 1u);
+            const uint64_t win = c0 / T + t;
+            uint64_t running = off + Tile().template run<false>(args, seg, win, 0u, off,
+                                                                 next_counter, s_off);
+            if (t == seg.ntiles - 1)
+                for (uint64_t w2 = win + 1; running < seg.n; ++w2)
+                    running += Tile().run(args, seg, w2, 0u, running, next_counter, s_off);
+        }
+        __syncthreads();
+    }
+    // the last workgroup out clears the list for the next launch
+    __shared__ bool s_last;
+    __syncthreads();
+    if (tid == 0)
+        s_last = __hip_atomic_fetch_add(&args.spec->done, 1u, __ATOMIC_ACQ_REL,
+                                        __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    __syncthreads();
+    if (s_last) {
+        for (uint32_t i = tid; i < cnt; i += B)
+            args.rejlist[i] = 0;
+        if (tid == 0) {
+            __hip_atomic_store(&args.spec->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&args.spec->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 template <int PPL, uint32_t FAM>
 __global__ __launch_bounds__(kMrgBlockThreads) void seq_mrg_kernel(LaunchArgs args)
 {
@@ -1144,6 +1444,55 @@ static const void *mrg_family(uint32_t fam, bool seq)
                           : reinterpret_cast<const void *>(&fill_mrg_kernel<PPL, FAM_MIXED>);
 }
 
+template <int NW, int PPL>
+static const void *spec_family(uint32_t fam, bool repair)
+{
+    switch (fam) {
+    case FAM_ENUM:
+        return repair ? reinterpret_cast<const void *>(&spec_repair_kernel<NW, PPL, FAM_ENUM>)
+                      : reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM_ENUM>);
+    case FAM_PHILOX32:
+        return repair ? reinterpret_cast<const void *>(&spec_repair_kernel<NW, PPL, FAM_PHILOX32>)
+                      : reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM_PHILOX32>);
+    default:
+        return repair ? reinterpret_cast<const void *>(&spec_repair_kernel<NW, PPL, FAM_PHILOX>)
+                      : reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM_PHILOX>);
+    }
+}
+
+// The speculative fill kernel (or its repair kernel) for (family, threads
+// per workgroup, pairs per lane); null for shapes or families without one.
+const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair)
+{
+    if (fam != FAM_PHILOX && fam != FAM_ENUM && fam != FAM_PHILOX32)
+        return nullptr;
+    if (threads == 256) {
+        switch (ppl) {
+        case 2: return spec_family<4, 2>(fam, repair);
+        case 4: return spec_family<4, 4>(fam, repair);
+        case 8: return spec_family<4, 8>(fam, repair);
+        case 16: return spec_family<4, 16>(fam, repair);
+        case 32: return spec_family<4, 32>(fam, repair);
+        default: return nullptr;
+        }
+    }
+    if (threads == 512) {
+        switch (ppl) {
+        case 8: return spec_family<8, 8>(fam, repair);
+        case 16: return spec_family<8, 16>(fam, repair);
+        default: return nullptr;
+        }
+    }
+    if (threads == 1024) {
+        switch (ppl) {
+        case 8: return spec_family<16, 8>(fam, repair);
+        case 16: return spec_family<16, 16>(fam, repair);
+        default: return nullptr;
+        }
+    }
+    return nullptr;
+}
+
 // The kernel for (family, threads per workgroup, pairs per lane), either
 // the look-back kernel or the segment-sequential one (seq), or null if
 // that shape is not instantiated.
@@ -1152,6 +1501,7 @@ const void *fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool s
     if (fam == FAM_PHILOX || fam == FAM_ENUM || fam == FAM_PHILOX32) {
         if (threads == 256) {
             switch (ppl) {
+            case 2: return philox_family<4, 2>(fam, seq);
             case 4: return philox_family<4, 4>(fam, seq);
             case 8: return philox_family<4, 8>(fam, seq);
             case 16: return philox_family<4, 16>(fam, seq);

@@ -20,6 +20,7 @@
 
 namespace prngd {
 const void *fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool seq);
+const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair);
 hipError_t launch_toggle_flip(uint32_t *flip, hipStream_t stream);
 const void *toggle_flip_kernel_ptr();
 hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads,
@@ -440,6 +441,11 @@ struct Workspace {
     Control *seq_ctl = nullptr;           // segment-sequential kernel
     uint64_t *status = nullptr;
     size_t status_cap = 0;
+    // speculative fill: list control, rejection list, per-tile hints
+    SpecControl *spec = nullptr;
+    uint64_t *rejlist = nullptr;
+    uint32_t *hint = nullptr;
+    size_t spec_cap = 0;
     uint64_t launches = 0;
     hipEvent_t last = nullptr;            // recorded after every launch
     // batch descriptors and the tile -> segment map
@@ -465,6 +471,9 @@ prngd_status_t ws_init(Workspace *ws, int dev)
     init[0].epoch = 1;
     init[1].epoch = 1;
     HIP_TRY(hipMemcpy(ws->ctl, init, sizeof init, hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&p, sizeof(SpecControl)));
+    ws->spec = static_cast<SpecControl *>(p);
+    HIP_TRY(hipMemset(ws->spec, 0, sizeof(SpecControl)));
     HIP_TRY(hipEventCreateWithFlags(&ws->last, hipEventDisableTiming));
     for (int i = 0; i < 2; ++i)
         HIP_TRY(hipEventCreateWithFlags(&ws->hsegs_done[i], hipEventDisableTiming));
@@ -475,6 +484,9 @@ void ws_release(Workspace *ws)
 {
     (void)hipFree(ws->status);
     (void)hipFree(ws->ctl);
+    (void)hipFree(ws->spec);
+    (void)hipFree(ws->rejlist);
+    (void)hipFree(ws->hint);
     (void)hipFree(ws->dsegs);
     (void)hipFree(ws->tile_seg);
     for (int i = 0; i < 2; ++i) {
@@ -505,6 +517,32 @@ prngd_status_t ws_prepare(Workspace *ws, size_t tiles, hipStream_t stream)
     }
     if (ws->launches > 0 && ws->launches % kEpochMask == 0)
         HIP_TRY(launch_zero_words(ws->status, ws->status_cap, stream));
+    return PRNGD_OK;
+}
+
+// Make room for the speculative fill's rejection list and hints of `tiles`
+// tiles.  A new list starts empty (all slots zero); afterwards every
+// repair launch leaves it empty again.
+prngd_status_t ws_prepare_spec(Workspace *ws, size_t tiles, hipStream_t stream)
+{
+    if (tiles <= ws->spec_cap)
+        return PRNGD_OK;
+    const size_t cap = std::max<size_t>(tiles, 1 << 16);
+    if (ws->rejlist) {
+        HIP_TRY(hipStreamSynchronize(stream));
+        HIP_TRY(hipEventSynchronize(ws->last));
+        HIP_TRY(hipFree(ws->rejlist));
+        HIP_TRY(hipFree(ws->hint));
+        ws->rejlist = nullptr;
+        ws->hint = nullptr;
+    }
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, cap * sizeof(uint64_t)));
+    ws->rejlist = static_cast<uint64_t *>(p);
+    HIP_TRY(hipMalloc(&p, cap * sizeof(uint32_t)));
+    ws->hint = static_cast<uint32_t *>(p);
+    ws->spec_cap = cap;
+    HIP_TRY(launch_zero_words(ws->rejlist, cap, stream));
     return PRNGD_OK;
 }
 
@@ -577,6 +615,7 @@ struct prngd_plan_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t launches = 0;
+    bool spec = false;                 // speculative fill (no status words)
 };
 
 namespace {
@@ -617,6 +656,9 @@ int occupancy_of(DeviceInfo *d, const void *kernel, uint32_t threads)
 struct LaunchPlan {
     const void *kernel;       // look-back kernel
     const void *seq_kernel;   // segment-sequential kernel
+    const void *spec_kernel;  // speculative fill and its repair, if used
+    const void *repair_kernel;
+    bool spec;
     uint32_t threads;
     uint64_t T;
     prngd_tuning_t tune;
@@ -632,6 +674,9 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u threads x %u pairs per lane",
                     lp->threads, lp->tune.pairs_per_lane);
     lp->T = uint64_t(lp->threads) * lp->tune.pairs_per_lane;
+    lp->spec_kernel = spec_kernel_for(cfg.fam, lp->threads, lp->tune.pairs_per_lane, false);
+    lp->repair_kernel = spec_kernel_for(cfg.fam, lp->threads, lp->tune.pairs_per_lane, true);
+    lp->spec = false;                  // decided per launch by choose_path
     args->store_mode = lp->tune.store_mode;
     args->w = cfg.w;
     args->a0 = uint32_t(cfg.a0);
@@ -644,6 +689,9 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     args->segs = nullptr;
     args->tile_seg = nullptr;
     args->flip = nullptr;
+    args->spec = nullptr;
+    args->rejlist = nullptr;
+    args->hint = nullptr;
     if (cfg.fam == FAM_MRG || cfg.fam == FAM_MIXED) {
         const uint32_t r = cfg.fam == FAM_MRG ? 2u : 1u;
         prngd_status_t st = mrg_tables_for(d, r, lp->tune.pairs_per_lane, &args->mrg_thread,
@@ -654,6 +702,25 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     return PRNGD_OK;
 }
 
+// Whether a launch of `pairs` planned pairs whose longest segment has
+// `max_tiles` tiles takes the speculative fill.  Automatic choice:
+// speculation pays when the whole launch expects at most a few rejections
+// (x1 uniform on [a0, a] rejects 2 / (a - a0 + 1) of the pairs), so that
+// the repair pass has next to nothing to redo, and when some segment is
+// long enough that ordering its tiles across workgroups would cost.
+void choose_path(LaunchPlan *lp, const Config &c, uint64_t pairs, uint64_t max_tiles)
+{
+    lp->spec = false;
+    if (!lp->spec_kernel || !lp->repair_kernel || lp->tune.path == 1)
+        return;
+    if (lp->tune.path == 2) {
+        lp->spec = true;
+        return;
+    }
+    const double rho = 2.0 / double(c.a - c.a0 + 1);
+    lp->spec = double(pairs) * rho <= 8.0 && max_tiles >= 64;
+}
+
 // Workgroups of a launch over `units` tiles or segments: all that fit on
 // the device at once (or blocks_per_cu per CU), never more than units.
 uint32_t grid_for(DeviceInfo *d, const LaunchPlan &lp, const void *kernel, uint64_t units)
@@ -662,6 +729,27 @@ uint32_t grid_for(DeviceInfo *d, const LaunchPlan &lp, const void *kernel, uint6
     const uint64_t per_cu = lp.tune.blocks_per_cu ? lp.tune.blocks_per_cu : uint64_t(occ);
     const uint64_t g = std::min<uint64_t>(per_cu * uint64_t(d->cus), units);
     return uint32_t(std::max<uint64_t>(1, g));
+}
+
+// Workgroups of a repair launch over `tiles` tiles: each takes a block of
+// as many tiles as it has threads per pass.
+uint32_t repair_grid(DeviceInfo *d, const LaunchPlan &lp, uint64_t tiles)
+{
+    const uint64_t blocks = (tiles + lp.threads - 1) / lp.threads;
+    return uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(blocks, 2 * uint64_t(d->cus))));
+}
+
+// Enqueue the speculative fill of `tiles` tiles and its repair.
+prngd_status_t launch_spec(DeviceInfo *d, const LaunchPlan &lp, Workspace *ws, LaunchArgs args,
+                           uint64_t tiles, hipStream_t s)
+{
+    args.spec = ws->spec;
+    args.rejlist = ws->rejlist;
+    args.hint = ws->hint;
+    args.total_tiles = uint32_t(tiles);
+    HIP_TRY(launch_fill(lp.spec_kernel, uint32_t(tiles), lp.threads, args, s));
+    HIP_TRY(launch_fill(lp.repair_kernel, repair_grid(d, lp, tiles), lp.threads, args, s));
+    return PRNGD_OK;
 }
 
 // Fill the descriptor of one request; returns its number of tiles.
@@ -714,7 +802,7 @@ struct BatchPlan {
     uint64_t lb_tiles = 0;
 };
 
-prngd_status_t build_batch(DeviceInfo *d, const LaunchPlan &lp, const prngd_request_t *reqs,
+prngd_status_t build_batch(DeviceInfo *d, LaunchPlan &lp, const prngd_request_t *reqs,
                            uint32_t count, BatchPlan *bp)
 {
     if (!reqs || count == 0)
@@ -724,7 +812,7 @@ prngd_status_t build_batch(DeviceInfo *d, const LaunchPlan &lp, const prngd_requ
     if (!first)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "request 0 has a NULL handle");
     std::vector<Segment> all;
-    uint64_t total = 0;
+    uint64_t total = 0, pairs = 0, max_tiles = 0;
     for (uint32_t i = 0; i < count; ++i) {
         const prngd_request_t &r = reqs[i];
         if (!r.h)
@@ -745,11 +833,15 @@ prngd_status_t build_batch(DeviceInfo *d, const LaunchPlan &lp, const prngd_requ
         if (st != PRNGD_OK)
             return st;
         total += nt;
+        pairs += s.planned;
+        max_tiles = std::max<uint64_t>(max_tiles, nt);
         all.push_back(s);
         bp->handles.push_back(r.h);
     }
+    choose_path(&lp, first->cfg, pairs, max_tiles);
     const uint64_t wg = uint64_t(occupancy_of(d, lp.seq_kernel, lp.threads)) * uint64_t(d->cus);
-    const uint64_t limit = seq_limit(lp.tune, total, wg);
+    // the speculative fill takes every segment tile by tile
+    const uint64_t limit = lp.spec ? 0 : seq_limit(lp.tune, total, wg);
     for (const Segment &s : all) {
         if (s.ntiles <= limit) {
             bp->seq.push_back(s);
@@ -973,13 +1065,21 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *strea
     args.nseg = 1;
     args.total_tiles = uint32_t(ntiles);
     args.ctl = ws->ctl;
+    choose_path(&lp, h->cfg, args.seg0.planned, ntiles);
     if ((st = order_after(h, s)) != PRNGD_OK)
         return st;
-    if ((st = ws_prepare(ws, ntiles, s)) != PRNGD_OK)
-        return st;
-    args.status = ws->status;
-    HIP_TRY(launch_fill(lp.kernel, grid_for(d, lp, lp.kernel, ntiles), lp.threads, args, s));
-    ws->launches++;
+    if (lp.spec) {
+        if ((st = ws_prepare_spec(ws, ntiles, s)) != PRNGD_OK)
+            return st;
+        if ((st = launch_spec(d, lp, ws, args, ntiles, s)) != PRNGD_OK)
+            return st;
+    } else {
+        if ((st = ws_prepare(ws, ntiles, s)) != PRNGD_OK)
+            return st;
+        args.status = ws->status;
+        HIP_TRY(launch_fill(lp.kernel, grid_for(d, lp, lp.kernel, ntiles), lp.threads, args, s));
+        ws->launches++;
+    }
     HIP_TRY(hipEventRecord(ws->last, s));
     h->parity ^= 1u;
     h->last_event = ws->last;
@@ -1021,7 +1121,8 @@ prngd_status_t prngd_fill_batch(const prngd_request_t *reqs, uint32_t count, voi
         if (h->last_event && h->last_stream != s && waited.insert(h->last_event).second)
             HIP_TRY(hipStreamWaitEvent(s, h->last_event, 0));
     const size_t nseg = bp.lb.size() + bp.seq.size();
-    if ((st = ws_prepare(ws, bp.lb_tiles, s)) != PRNGD_OK)
+    if ((st = lp.spec ? ws_prepare_spec(ws, bp.lb_tiles, s) : ws_prepare(ws, bp.lb_tiles, s)) !=
+        PRNGD_OK)
         return st;
     if ((st = ws_grow(ws, &ws->dsegs, &ws->dsegs_cap, nseg, s)) != PRNGD_OK)
         return st;
@@ -1062,11 +1163,16 @@ prngd_status_t prngd_fill_batch(const prngd_request_t *reqs, uint32_t count, voi
         args.tile_seg = ws->tile_seg;
         args.nseg = uint32_t(bp.lb.size());
         args.total_tiles = uint32_t(bp.lb_tiles);
-        args.status = ws->status;
-        args.ctl = ws->ctl;
-        HIP_TRY(launch_fill(lp.kernel, grid_for(d, lp, lp.kernel, bp.lb_tiles), lp.threads, args,
-                            s));
-        ws->launches++;
+        if (lp.spec) {
+            if ((st = launch_spec(d, lp, ws, args, bp.lb_tiles, s)) != PRNGD_OK)
+                return st;
+        } else {
+            args.status = ws->status;
+            args.ctl = ws->ctl;
+            HIP_TRY(launch_fill(lp.kernel, grid_for(d, lp, lp.kernel, bp.lb_tiles), lp.threads,
+                                args, s));
+            ws->launches++;
+        }
     }
     HIP_TRY(hipEventRecord(ws->last, s));
     for (prngd_handle_t h : bp.handles) {
@@ -1110,7 +1216,8 @@ prngd_status_t prngd_plan_create(const prngd_request_t *reqs, uint32_t count,
     for (prngd_handle_t h : p->handles)
         if (h->last_event)
             HIP_TRY(hipEventSynchronize(h->last_event));
-    if ((st = ws_prepare(&p->ws, bp.lb_tiles, nullptr)) != PRNGD_OK) {
+    if ((st = lp.spec ? ws_prepare_spec(&p->ws, bp.lb_tiles, nullptr)
+                      : ws_prepare(&p->ws, bp.lb_tiles, nullptr)) != PRNGD_OK) {
         ws_release(&p->ws);
         return st;
     }
@@ -1156,7 +1263,29 @@ prngd_status_t prngd_plan_create(const prngd_request_t *reqs, uint32_t count,
         HIP_TRY(hipGraphAddKernelNode(&node, p->graph, nullptr, 0, &kp));
         fills.push_back(node);
     }
-    if (!bp.lb.empty()) {
+    if (!bp.lb.empty() && lp.spec) {
+        // speculative fill, then its repair
+        p->spec = true;
+        p->lb_args.segs = p->dsegs;
+        p->lb_args.tile_seg = p->tile_seg;
+        p->lb_args.nseg = uint32_t(bp.lb.size());
+        p->lb_args.total_tiles = uint32_t(bp.lb_tiles);
+        p->lb_args.spec = p->ws.spec;
+        p->lb_args.rejlist = p->ws.rejlist;
+        p->lb_args.hint = p->ws.hint;
+        hipKernelNodeParams kp{};
+        void *params[] = {&p->lb_args};
+        kp.func = const_cast<void *>(lp.spec_kernel);
+        kp.gridDim = dim3(uint32_t(bp.lb_tiles));
+        kp.blockDim = dim3(lp.threads);
+        kp.kernelParams = params;
+        hipGraphNode_t node, rnode;
+        HIP_TRY(hipGraphAddKernelNode(&node, p->graph, nullptr, 0, &kp));
+        kp.func = const_cast<void *>(lp.repair_kernel);
+        kp.gridDim = dim3(repair_grid(d, lp, bp.lb_tiles));
+        HIP_TRY(hipGraphAddKernelNode(&rnode, p->graph, &node, 1, &kp));
+        fills.push_back(rnode);
+    } else if (!bp.lb.empty()) {
         p->lb_args.segs = p->dsegs;
         p->lb_args.tile_seg = p->tile_seg;
         p->lb_args.nseg = uint32_t(bp.lb.size());
@@ -1209,7 +1338,7 @@ prngd_status_t prngd_plan_launch(prngd_plan_t p, void *stream)
     if ((st = check_device_errors(d)) != PRNGD_OK)
         return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const bool has_lb = p->lb_args.total_tiles > 0;
+    const bool has_lb = p->lb_args.total_tiles > 0 && !p->spec;
     if (has_lb && p->ws.launches > 0 && p->ws.launches % kEpochMask == 0)
         HIP_TRY(launch_zero_words(p->ws.status, p->ws.status_cap, s));
     HIP_TRY(hipGraphLaunch(p->exec, s));
@@ -1267,8 +1396,11 @@ prngd_status_t prngd_set_tuning(prngd_generator_t generator, uint32_t w,
     if (!fill_kernel_for(fam, threads, ppl, false))
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u threads x %u pairs per lane",
                     threads, ppl);
-    if (t.store_mode > 2 || t.slack_mode > 1)
-        return fail(PRNGD_ERR_INVALID_ARGUMENT, "bad store_mode or slack_mode");
+    if (t.store_mode > 2 || t.slack_mode > 1 || t.path > 2)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "bad store_mode, slack_mode or path");
+    if (t.path == 2 && !spec_kernel_for(fam, threads, ppl, false))
+        return fail(PRNGD_ERR_INVALID_ARGUMENT,
+                    "no speculative fill for this generator and launch shape");
     g_tuning[std::make_pair(fam, w)] = t;
     return PRNGD_OK;
 }

@@ -48,7 +48,8 @@ class Request(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("pairs_per_lane", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
                 ("store_mode", ctypes.c_uint32), ("slack_mode", ctypes.c_uint32),
-                ("block_threads", ctypes.c_uint32), ("seq_max_tiles", ctypes.c_uint32)]
+                ("block_threads", ctypes.c_uint32), ("seq_max_tiles", ctypes.c_uint32),
+                ("path", ctypes.c_uint32)]
 
 
 # (name, restype, argtypes) of every exported function
@@ -285,10 +286,16 @@ class Plan:
             pass
 
 
+PATHS = {"auto": 0, "ordered": 1, "speculative": 2}
+
+
 def set_tuning(generator, w, pairs_per_lane=0, blocks_per_cu=0, store_mode=0, slack_mode=0,
-               block_threads=0, seq_max_tiles=0):
+               block_threads=0, seq_max_tiles=0, path=0):
+    """Launch shape for (generator, w); `path` is 0/"auto", 1/"ordered" or
+    2/"speculative"."""
+    path = PATHS.get(path, path)
     t = Tuning(pairs_per_lane, blocks_per_cu, store_mode, slack_mode, block_threads,
-               seq_max_tiles)
+               seq_max_tiles, path)
     _check(lib().prngd_set_tuning(_gen(generator), w, ctypes.byref(t)))
 
 
@@ -301,7 +308,8 @@ def get_tuning(generator, w):
     _check(lib().prngd_get_tuning(_gen(generator), w, ctypes.byref(t)))
     return {"pairs_per_lane": t.pairs_per_lane, "blocks_per_cu": t.blocks_per_cu,
             "store_mode": t.store_mode, "slack_mode": t.slack_mode,
-            "block_threads": t.block_threads, "seq_max_tiles": t.seq_max_tiles}
+            "block_threads": t.block_threads, "seq_max_tiles": t.seq_max_tiles,
+            "path": t.path}
 
 
 # ------------------------------------------------------------------ probes

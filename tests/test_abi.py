@@ -124,7 +124,8 @@ def test_tuning_round_trip_and_validation():
     prngd.set_tuning("philox", 13, pairs_per_lane=8, blocks_per_cu=3, store_mode=2)
     assert prngd.get_tuning("philox", 13) == {"pairs_per_lane": 8, "blocks_per_cu": 3,
                                               "store_mode": 2, "slack_mode": 0,
-                                              "block_threads": 256, "seq_max_tiles": 0}
+                                              "block_threads": 256, "seq_max_tiles": 0,
+                                              "path": 0}
     prngd.reset_tuning("philox", 13)
     assert prngd.get_tuning("philox", 13)["pairs_per_lane"] == 16
     with pytest.raises(prngd.PrngdError):
@@ -139,4 +140,10 @@ def test_tuning_round_trip_and_validation():
         prngd.set_tuning("mixed", 32, block_threads=512)
     prngd.set_tuning("philox", 13, block_threads=1024, pairs_per_lane=8)
     assert prngd.get_tuning("philox", 13)["block_threads"] == 1024
+    prngd.set_tuning("philox", 13, path="speculative")
+    assert prngd.get_tuning("philox", 13)["path"] == 2
+    with pytest.raises(prngd.PrngdError):
+        prngd.set_tuning("philox", 13, path=3)
+    with pytest.raises(prngd.PrngdError):
+        prngd.set_tuning("mixed", 32, path="speculative")   # no speculative MRG fill
     prngd.reset_tuning("philox", 13)

@@ -211,9 +211,12 @@ def test_checkpoint_resume():
     assert g.get_position() == g2.get_position()
 
 
-def test_repeated_high_rejection_fills():
-    # many launches in a row: stale status words of earlier launches must
-    # never be taken for the current one
+@pytest.mark.parametrize("path", ["ordered", "speculative"])
+def test_repeated_high_rejection_fills(path):
+    # many launches in a row: stale status words (ordered path) or rejection
+    # list entries (speculative path) of earlier launches must never be
+    # taken for the current one
+    prngd.set_tuning("philox", 3, path=path)
     rng = np.random.default_rng(2)
     g = prngd.Generator(5, "philox", w=3)
     ref = O.PRNGD(O.GEN_PHILOX, 3, seed=5)
@@ -312,6 +315,73 @@ def test_plan_replays_advance_handles(seq_max_tiles):
     gens[3].fill(t)
     assert_bits_equal(t.cpu().numpy(), refs[3].fill(777), "after plan")
     for g in gens:
+        g.close()
+
+
+# ------------------------------------------------ the speculative fill
+
+@pytest.mark.parametrize("gen,w", [("philox", 2), ("philox", 3), ("philox", 8), ("philox", 12),
+                                   ("enumerate", 6), ("philox", 32)])
+@pytest.mark.parametrize("ppl", [4, 16])
+def test_speculative_fill_at_any_rejection_rate(gen, w, ppl):
+    """Speculation forced where most windows reject pairs: most tiles store
+    at a wrong offset first, and the repair pass must still leave exactly
+    the oracle's bytes and counter."""
+    prngd.set_tuning(gen, w, path="speculative", pairs_per_lane=ppl)
+    for counter, n in [(0, 1), (7, 4097), (3, 100003), (4095, 300001)]:
+        parity(gen, w, seed=19, counter=counter, n=n)
+
+
+def test_speculative_fill_with_a_long_rejection_list():
+    # more dirty tiles than the repair caches in LDS
+    prngd.set_tuning("philox", 3, path="speculative", pairs_per_lane=4)
+    parity("philox", 3, seed=23, counter=11, n=1 << 22)
+
+
+@pytest.mark.parametrize("gen,w", [("philox", 3), ("philox", 8), ("philox", 32)])
+def test_speculative_batches_and_plans(gen, w):
+    from paper_1401_8230_amd import workloads
+    prngd.set_tuning(gen, w, path="speculative")
+    reqs = workloads.uneven_batch(count=200, lo=1, hi=3e4, rng_seed=w + 100)
+    note(f"speculative batch {gen} w={w}")
+    gens = make_handles(reqs, gen, w)
+    outs = [torch.empty(r.n, dtype=torch.float64, device=DEV) for r in reqs]
+    prngd.fill_batch(list(zip(gens, outs)))
+    torch.cuda.synchronize()
+    refs = [O.PRNGD(OGEN[gen], w, seed=r.seed, stream=r.stream_id, counter=r.counter)
+            for r in reqs]
+    for i, (r, o) in enumerate(zip(reqs, outs)):
+        assert_bits_equal(o.cpu().numpy(), refs[i].fill(r.n), f"request {i}")
+        assert gens[i].get_position() == (r.stream_id, refs[i].counter), f"request {i}"
+    plan = prngd.Plan(list(zip(gens, outs)))
+    for rep in range(3):
+        note(f"speculative plan replay {rep}")
+        plan.launch()
+        torch.cuda.synchronize()
+        for i, (r, o) in enumerate(zip(reqs, outs)):
+            assert_bits_equal(o.cpu().numpy(), refs[i].fill(r.n), f"replay {rep} request {i}")
+    plan.close()
+    for i, g in enumerate(gens):
+        assert g.get_position() == (reqs[i].stream_id, refs[i].counter)
+        g.close()
+
+
+@pytest.mark.parametrize("w", [24, 32])
+def test_ordered_path_at_rare_rejections(w):
+    # the look-back and segment-sequential kernels stay correct where the
+    # speculative fill is the default
+    from paper_1401_8230_amd import workloads
+    prngd.set_tuning("philox", w, path="ordered")
+    parity("philox", w, seed=42, counter=3, n=1 << 20)
+    reqs = workloads.uneven_batch(count=100, lo=1, hi=3e4, rng_seed=w)
+    gens = make_handles(reqs, "philox", w)
+    outs = [torch.empty(r.n, dtype=torch.float64, device=DEV) for r in reqs]
+    prngd.fill_batch(list(zip(gens, outs)))
+    torch.cuda.synchronize()
+    for i, (r, g, o) in enumerate(zip(reqs, gens, outs)):
+        expect, ectr = oracle_fill("philox", w, r.seed, r.stream_id, r.counter, r.n)
+        assert_bits_equal(o.cpu().numpy(), expect, f"request {i}")
+        assert g.get_position() == (r.stream_id, ectr), f"request {i}"
         g.close()
 
 
