@@ -1,15 +1,25 @@
 """Benchmark of the PRNGD fill on one MI355X.
 
-Default workload: 2^16 independent Philox4x32-10 substreams of seed 42
+Headline workload: 2^16 independent Philox4x32-10 substreams of seed 42
 (substream id in counter word 3), w = 32, 2^14 FP64 outputs each -- 2^30
 outputs, 8 GiB written per step -- filled by one resident batch (the
-request descriptors live in device memory, the persistent fill kernel is
-replayed from a HIP graph).  A step is one such launch; every handle
-advances, so every step produces new numbers.
+request descriptors live in device memory, the fill is replayed from a
+HIP graph).  A step is one such launch; every handle advances, so every
+step produces new numbers.
 
 Prints one JSON line: accepted FP64 uniforms per second, the roofline of
-the fill kernel (HBM write bandwidth; 8 algorithmic bytes per output) and
-the CPU oracle's rate on a bounded sample of the same workload.
+the fill kernel (HBM write bandwidth; 8 algorithmic bytes per output), the
+CPU oracle's rate on a bounded sample of the same workload, and, unless
+--headline-only, two more measurements on the same GPU:
+
+* batched_vs_plain: 4096 requests with log-uniform sizes in [1e3, 1e7],
+  each with its own seed, substream and start position, as one autotuned
+  resident batch versus 4096 plain prngd_fill calls (and versus plain
+  calls that each wait for their result), with identical output bytes;
+* serving: a Poisson trace of fill requests (2e4 per second, sizes
+  log-uniform in [1e2, 1e8], 1024 clients with device-resident positions)
+  served by the continuous-batching loop under a 64 GB HBM budget, against
+  the same trace served one plain fill at a time: throughput, p50, p99.
 """
 import argparse
 import hashlib
@@ -27,6 +37,10 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1401_8230_amd", "csrc", "prngd_kernels.hi
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_many_streams.json")
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -37,6 +51,10 @@ def parse():
     ap.add_argument("--seed", type=int, default=42)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-streams", type=int, default=16384)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the batched-vs-plain and serving measurements")
+    ap.add_argument("--uneven-steps", type=int, default=5)
+    ap.add_argument("--serving-requests", type=int, default=20000)
     ap.add_argument("--calibrate", action="store_true",
                     help="after the timed steps, copy half of the output buffer onto the "
                          "other half once (the known-size kernel that scales HBM counters)")
@@ -76,46 +94,40 @@ def cpu_baseline(streams, n_each, seed):
                       f"each ({total} outputs, {dt:.1f} s, one thread)"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding of the fill is described in DESIGN.md", file=sys.stderr)
-        sys.exit(2)
+def timed(fn, steps, stream):
+    """Seconds per call of fn over `steps` calls, HIP events on `stream`."""
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1e3 / steps
+
+
+def run_many_streams(args, result):
     import torch
     from paper_1401_8230_amd import prngd
-
-    torch.cuda.set_device(0)
     n = args.outputs_per_stream
     S = args.streams
-    print(f"[bench] creating {S} handles", file=sys.stderr, flush=True)
+    log(f"many streams: creating {S} handles")
     gens = prngd.Generator.many(args.seed, S, "philox", w=32)
     out = torch.empty(S * n, dtype=torch.float64, device="cuda:0")
     views = [out[i * n:(i + 1) * n] for i in range(S)]
     plan = prngd.Plan(list(zip(gens, views)))
     stream = torch.cuda.current_stream()
-    print("[bench] warmup", file=sys.stderr, flush=True)
+    log("many streams: warmup")
     for _ in range(args.warmup):
         plan.launch(stream)
     torch.cuda.synchronize()
-
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record(stream)
-    for _ in range(args.steps):
-        plan.launch(stream)
-    stop.record(stream)
-    torch.cuda.synchronize()
+    step_s = timed(lambda: plan.launch(stream), args.steps, stream)
     wall = time.perf_counter() - t0
-    gpu_s = start.elapsed_time(stop) / 1e3
-    print(f"[bench] timed {args.steps} steps", file=sys.stderr, flush=True)
-
+    log(f"many streams: timed {args.steps} steps, {step_s * 1e3:.3f} ms per step")
     outputs = S * n
-    step_s = gpu_s / args.steps
-    value = outputs * args.steps / gpu_s
-    achieved_gbs = outputs * BYTES_PER_OUTPUT / step_s / 1e9
     lo, hi = float(out.min()), float(out.max())
     if not (0.0 <= lo and hi < 1.0):
         raise SystemExit(f"outputs out of [0, 1): {lo} {hi}")
@@ -123,31 +135,23 @@ def main():
         half = outputs // 2
         prngd.probe_copy(out[half:2 * half], out[:half], stream)
         torch.cuda.synchronize()
-        print(f"[bench] calibration copy of {half * 8} bytes", file=sys.stderr, flush=True)
+        log(f"calibration copy of {half * 8} bytes")
     plan.close()
-
-    traffic = measured_traffic()
-    result = {
-        "metric": "accepted FP64 uniforms/s",
-        "value": value,
-        "unit": "accepted FP64 uniforms/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+    for g in gens:
+        g.close()
+    del out, views
+    achieved_gbs = outputs * BYTES_PER_OUTPUT / step_s / 1e9
+    result.update({
+        "value": outputs / step_s,
         "ms_per_step": step_s * 1e3,
         "wall_ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
         "config": {
             "workload": f"{S} Philox4x32-10 substreams of seed {args.seed}, w=32, "
                         f"{n} FP64 outputs each, one resident batch per step",
             "streams": S,
             "outputs_per_stream": n,
             "outputs_per_step": outputs,
-            "launch": "persistent fill kernel replayed from a HIP graph",
+            "launch": "resident batch replayed from a HIP graph",
         },
         "roofline": {
             "bound": "hbm",
@@ -155,14 +159,142 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": traffic,
+            "traffic": measured_traffic(),
         },
-    }
-    if not args.no_cpu_baseline:
-        print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(min(args.cpu_sample_streams, S), n, args.seed)
+    })
+
+
+def run_uneven(args):
+    """4096 uneven requests: autotuned resident batch vs plain fills."""
+    import torch
+    from paper_1401_8230_amd import autotune, prngd, workloads
+    reqs = workloads.uneven_batch()
+    sizes = [r.n for r in reqs]
+    total = sum(sizes)
+    log(f"uneven batch: {len(reqs)} requests, {total} outputs ({total * 8 / 1e9:.1f} GB)")
+    arena = torch.empty(total, dtype=torch.float64, device="cuda:0")
+    outs, off = [], 0
+    for n in sizes:
+        outs.append(arena[off:off + n])
+        off += n
+    tune = autotune.autotune_batch(sizes, outs, "philox", 32, retune=True)
+    log(f"uneven batch: autotuned {tune['tuning']} ({tune['seconds'] * 1e3:.3f} ms)")
+    gens = [prngd.Generator(r.seed, "philox", w=32) for r in reqs]
+    for g, r in zip(gens, reqs):
+        g.set_position(r.stream_id, r.counter)
+    stream = torch.cuda.current_stream()
+
+    def checksums():
+        v = arena.view(torch.int64)
+        out, o = [], 0
+        for n in sizes:
+            out.append(v[o:o + n].sum())
+            o += n
+        return torch.stack(out).cpu()
+
+    # bit-identity: one batched launch and one round of plain fills from the
+    # same start positions
+    plan = prngd.Plan(list(zip(gens, outs)))
+    plan.launch(stream)
+    torch.cuda.synchronize()
+    batched_sums = checksums()
+    plan.close()
+    for g, r in zip(gens, reqs):
+        g.set_position(r.stream_id, r.counter)
+    for g, o in zip(gens, outs):
+        g.fill(o, stream=stream)
+    torch.cuda.synchronize()
+    plain_sums = checksums()
+    identical = bool(torch.equal(batched_sums, plain_sums))
+    log(f"uneven batch: batched and plain outputs identical: {identical}")
+
+    plan = prngd.Plan(list(zip(gens, outs)))
+    plan.launch(stream)
+    batched_s = timed(lambda: plan.launch(stream), args.uneven_steps, stream)
+    plan.close()
+    log(f"uneven batch: batched {batched_s * 1e3:.3f} ms per step")
+
+    def plain_round():
+        for g, o in zip(gens, outs):
+            g.fill(o, stream=stream)
+    plain_round()
+    plain_s = timed(plain_round, args.uneven_steps, stream)
+    log(f"uneven batch: plain {plain_s * 1e3:.3f} ms per step")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g, o in zip(gens, outs):
+        g.fill(o, stream=stream)
+        stream.synchronize()
+    sync_s = time.perf_counter() - t0
+    log(f"uneven batch: plain with a wait per request {sync_s * 1e3:.3f} ms per step")
     for g in gens:
         g.close()
+    del arena, outs
+    gbs = total * BYTES_PER_OUTPUT / batched_s / 1e9
+    return {
+        "workload": f"{len(reqs)} requests, sizes log-uniform in [1e3, 1e7], own seed, "
+                    f"substream and start position each",
+        "outputs_per_step": total,
+        "batched": {"value": total / batched_s, "ms_per_step": batched_s * 1e3,
+                    "hbm_frac": gbs / HBM_PEAK_GBS, "tuning": tune["tuning"]},
+        "plain": {"value": total / plain_s, "ms_per_step": plain_s * 1e3},
+        "plain_wait_each": {"value": total / sync_s, "ms_per_step": sync_s * 1e3},
+        "speedup_vs_plain": plain_s / batched_s,
+        "speedup_vs_plain_wait_each": sync_s / batched_s,
+        "outputs_identical": identical,
+        "unit": "accepted FP64 uniforms/s",
+    }
+
+
+def run_serving(args):
+    from paper_1401_8230_amd import serving, workloads
+    trace = workloads.poisson_trace(count=args.serving_requests + 1000)
+    log(f"serving: {len(trace)} requests (first 1000 warm up)")
+    batched = serving.run_trace(trace, mode="batched", warmup=1000, log=log)
+    log(f"serving: batched p50 {batched['p50_ms']:.3f} ms p99 {batched['p99_ms']:.3f} ms")
+    plain = serving.run_trace(trace, mode="plain", warmup=1000, log=log)
+    log(f"serving: plain p50 {plain['p50_ms']:.3f} ms p99 {plain['p99_ms']:.3f} ms")
+    return {
+        "workload": "Poisson arrivals at 2e4 requests/s, sizes log-uniform in [1e2, 1e8], "
+                    "1024 clients, HBM budget 64 GB",
+        "batched": batched,
+        "plain": plain,
+        "throughput_ratio": batched["value"] / plain["value"],
+        "p99_ratio": plain["p99_ms"] / batched["p99_ms"],
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding of the fill is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    result = {
+        "metric": "accepted FP64 uniforms/s",
+        "value": None,
+        "unit": "accepted FP64 uniforms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+    }
+    run_many_streams(args, result)
+    if not args.headline_only:
+        result["batched_vs_plain"] = run_uneven(args)
+        result["serving"] = run_serving(args)
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        result["cpu_baseline"] = cpu_baseline(
+            min(args.cpu_sample_streams, args.streams), args.outputs_per_stream, args.seed)
     print(json.dumps(result), flush=True)
 
 

@@ -1149,21 +1149,13 @@ __global__ __launch_bounds__(64 * NW) void seq_philox_kernel(LaunchArgs args)
 // pair counter is the true one).  With no rejection in the launch the
 // repair launch reads one word and exits.
 // ======================================================================
-template <int NW, int PPL, uint32_t FAM>
-__global__ __launch_bounds__(64 * NW) void spec_philox_kernel(LaunchArgs args)
+// The hint of tile g (tile t of its segment): the rejections the segment's
+// earlier tiles have published so far.  Read by wave 0, broadcast through
+// LDS, and recorded for the repair pass.
+__device__ __forceinline__ uint32_t read_hint(const LaunchArgs &args, const Segment &seg,
+                                              uint32_t t, uint32_t g, uint32_t *s_hint)
 {
-    using Tile = SpecTile<NW, PPL, FAM>;
-    constexpr uint32_t T = Tile::T;
-    __shared__ uint32_t s_off[Tile::E + 1];
-    __shared__ uint32_t s_hint;
-    const uint32_t g = blockIdx.x;
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
-    Segment seg;
-    uint32_t t;
-    lookup(args, g, &seg, &t);
-    const uint32_t par = seg.parity ^ read_flip(args);
-    const uint64_t c0 = load_start(seg, par);
-    uint64_t *next_counter = seg.counter + (par ^ 1u);
     if (tid < 64) {
         uint32_t used = 0;
         if (t > 0) {
@@ -1182,12 +1174,46 @@ __global__ __launch_bounds__(64 * NW) void spec_philox_kernel(LaunchArgs args)
             }
         }
         if (lane == 63)
-            s_hint = used;
+            *s_hint = used;
     }
     __syncthreads();
-    const uint32_t used = __builtin_amdgcn_readfirstlane(s_hint);
+    const uint32_t used = __builtin_amdgcn_readfirstlane(*s_hint);
     if (tid == 0)
         args.hint[g] = used;
+    return used;
+}
+
+// Appends tile g's rejections to the launch's list (thread 0).
+__device__ __forceinline__ void publish_rejections(const LaunchArgs &args, uint32_t g,
+                                                   uint32_t rej)
+{
+    if (rej == 0 || threadIdx.x != 0)
+        return;
+    const uint32_t slot = __hip_atomic_fetch_add(&args.spec->count, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (slot < args.total_tiles)
+        __hip_atomic_store(&args.rejlist[slot], (uint64_t(g) + 1u) << 32 | rej,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        __hip_atomic_fetch_or(args.error, kErrSpecList, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <int NW, int PPL, uint32_t FAM>
+__global__ __launch_bounds__(64 * NW) void spec_philox_kernel(LaunchArgs args)
+{
+    using Tile = SpecTile<NW, PPL, FAM>;
+    constexpr uint32_t T = Tile::T;
+    __shared__ uint32_t s_off[Tile::E + 1];
+    __shared__ uint32_t s_hint;
+    const uint32_t g = blockIdx.x;
+    Segment seg;
+    uint32_t t;
+    lookup(args, g, &seg, &t);
+    const uint32_t par = seg.parity ^ read_flip(args);
+    const uint64_t c0 = load_start(seg, par);
+    uint64_t *next_counter = seg.counter + (par ^ 1u);
+    const uint32_t used = read_hint(args, seg, t, g, &s_hint);
     const uint64_t w0 = c0 / T;
     const uint32_t lo0 = uint32_t(c0 - w0 * T);
     const uint64_t win = w0 + t;
@@ -1198,22 +1224,53 @@ __global__ __launch_bounds__(64 * NW) void spec_philox_kernel(LaunchArgs args)
         kept = Tile().run(args, seg, win, lo_off, excl, next_counter, s_off);
     else
         kept = Tile::count_kept(args, seg, win, lo_off, s_off);
-    const uint32_t rej = (T - lo_off) - kept;
-    if (rej != 0 && tid == 0) {
-        const uint32_t slot = __hip_atomic_fetch_add(&args.spec->count, 1u, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-        if (slot < args.total_tiles)
-            __hip_atomic_store(&args.rejlist[slot], (uint64_t(g) + 1u) << 32 | rej,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else
-            __hip_atomic_fetch_or(args.error, kErrSpecList, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_SYSTEM);
-    }
+    publish_rejections(args, g, (T - lo_off) - kept);
     // the segment's last tile takes every further window until n outputs
     if (t == seg.ntiles - 1) {
         uint64_t running = excl + kept;
         for (uint64_t w2 = win + 1; running < seg.n; ++w2)
             running += Tile().run(args, seg, w2, 0u, running, next_counter, s_off);
+    }
+}
+
+// The speculative fill for MRG32k3a and the mixed generator: the tile is
+// generated into registers and compacted through LDS as in the look-back
+// kernel, then stored at the offset the hint gives.  It writes nothing but
+// its own outputs (at a shifted place if the hint was short).
+template <int PPL, uint32_t FAM>
+__global__ __launch_bounds__(kMrgBlockThreads) void spec_mrg_kernel(LaunchArgs args)
+{
+    using Tile = MrgTile<PPL, FAM>;
+    constexpr uint32_t T = Tile::T;
+    __shared__ double s_vals[Tile::T + Tile::T / 16];
+    __shared__ uint32_t s_wave[kMrgBlockThreads / 64];
+    __shared__ uint32_t s_hint;
+    const uint32_t g = blockIdx.x;
+    Segment seg;
+    uint32_t t;
+    lookup(args, g, &seg, &t);
+    const uint32_t par = seg.parity ^ read_flip(args);
+    const uint64_t c0 = load_start(seg, par);
+    uint64_t *next_counter = seg.counter + (par ^ 1u);
+    const uint32_t used = read_hint(args, seg, t, g, &s_hint);
+    const uint64_t w0 = c0 / T;
+    const uint32_t lo0 = uint32_t(c0 - w0 * T);
+    const uint64_t win = w0 + t;
+    const uint32_t lo_off = t == 0 ? lo0 : 0u;
+    const uint64_t excl = (t == 0 ? 0 : uint64_t(t) * T - lo0) - used;
+    Tile tile;
+    const uint32_t kept = tile.generate(args, seg, win, lo_off, s_wave);
+    if (excl < seg.n)
+        tile.store(args, seg, win, excl, kept, next_counter, s_vals);
+    publish_rejections(args, g, (T - lo_off) - kept);
+    if (t == seg.ntiles - 1) {
+        uint64_t running = excl + kept;
+        for (uint64_t w2 = win + 1; running < seg.n; ++w2) {
+            Tile t2;
+            const uint32_t k2 = t2.generate(args, seg, w2, 0u, s_wave);
+            t2.store(args, seg, w2, running, k2, next_counter, s_vals);
+            running += k2;
+        }
     }
 }
 
@@ -1285,13 +1342,60 @@ __device__ __forceinline__ bool needs_redo(const LaunchArgs &args, const uint64_
     return false;
 }
 
+// How the repair pass produces one tile again, per generator family: the
+// tile's first window exactly (nothing written but its own outputs), then,
+// for a segment's last tile, every further window until n outputs exist.
 template <int NW, int PPL, uint32_t FAM>
-__global__ __launch_bounds__(64 * NW) void spec_repair_kernel(LaunchArgs args)
-{
+struct PhiloxRedo {
     using Tile = SpecTile<NW, PPL, FAM>;
-    constexpr uint32_t T = Tile::T;
-    constexpr uint32_t B = 64 * NW;
-    __shared__ uint32_t s_off[Tile::E + 1];
+    static constexpr uint32_t T = Tile::T;
+    static constexpr uint32_t B = Tile::B;
+    struct Scratch {
+        uint32_t off[Tile::E + 1];
+    };
+    __device__ __forceinline__ static void produce(const LaunchArgs &args, const Segment &seg,
+                                                   uint64_t win, uint64_t off, bool last,
+                                                   uint64_t *next_counter, Scratch &sh)
+    {
+        uint64_t running =
+            off + Tile().template run<false>(args, seg, win, 0u, off, next_counter, sh.off);
+        if (last)
+            for (uint64_t w2 = win + 1; running < seg.n; ++w2)
+                running += Tile().run(args, seg, w2, 0u, running, next_counter, sh.off);
+    }
+};
+
+template <int PPL, uint32_t FAM>
+struct MrgRedo {
+    using Tile = MrgTile<PPL, FAM>;
+    static constexpr uint32_t T = Tile::T;
+    static constexpr uint32_t B = Tile::B;
+    struct Scratch {
+        double vals[Tile::T + Tile::T / 16];
+        uint32_t wave[kMrgBlockThreads / 64];
+    };
+    __device__ __forceinline__ static void produce(const LaunchArgs &args, const Segment &seg,
+                                                   uint64_t win, uint64_t off, bool last,
+                                                   uint64_t *next_counter, Scratch &sh)
+    {
+        uint64_t running = off;
+        for (uint64_t w2 = win;; ++w2) {
+            Tile tile;
+            const uint32_t kept = tile.generate(args, seg, w2, 0u, sh.wave);
+            tile.store(args, seg, w2, running, kept, next_counter, sh.vals);
+            running += kept;
+            if (!last || running >= seg.n)
+                break;
+        }
+    }
+};
+
+template <class F>
+__global__ __launch_bounds__(F::B) void spec_repair_kernel(LaunchArgs args)
+{
+    constexpr uint32_t T = F::T;
+    constexpr uint32_t B = F::B;
+    __shared__ typename F::Scratch sh;
     __shared__ uint64_t s_list[kRepairCache];
     __shared__ uint32_t s_queue[B];
     __shared__ uint64_t s_qoff[B];
@@ -1349,13 +1453,8 @@ __global__ __launch_bounds__(64 * NW) void spec_repair_kernel(LaunchArgs args)
             lookup(args, g, &seg, &t);
             const uint32_t par = seg.parity ^ flip;
             const uint64_t c0 = load_start(seg, par);
-            uint64_t *next_counter = seg.counter + (par ^ 1u);
-            const uint64_t win = c0 / T + t;
-            uint64_t running = off + Tile().template run<false>(args, seg, win, 0u, off,
-                                                                 next_counter, s_off);
-            if (t == seg.ntiles - 1)
-                for (uint64_t w2 = win + 1; running < seg.n; ++w2)
-                    running += Tile().run(args, seg, w2, 0u, running, next_counter, s_off);
+            F::produce(args, seg, c0 / T + t, off, t == seg.ntiles - 1, seg.counter + (par ^ 1u),
+                       sh);
         }
         __syncthreads();
     }
@@ -1444,28 +1543,51 @@ static const void *mrg_family(uint32_t fam, bool seq)
                           : reinterpret_cast<const void *>(&fill_mrg_kernel<PPL, FAM_MIXED>);
 }
 
+template <int NW, int PPL, uint32_t FAM>
+static const void *spec_pair(bool repair)
+{
+    return repair ? reinterpret_cast<const void *>(&spec_repair_kernel<PhiloxRedo<NW, PPL, FAM>>)
+                  : reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM>);
+}
+
 template <int NW, int PPL>
 static const void *spec_family(uint32_t fam, bool repair)
 {
     switch (fam) {
-    case FAM_ENUM:
-        return repair ? reinterpret_cast<const void *>(&spec_repair_kernel<NW, PPL, FAM_ENUM>)
-                      : reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM_ENUM>);
-    case FAM_PHILOX32:
-        return repair ? reinterpret_cast<const void *>(&spec_repair_kernel<NW, PPL, FAM_PHILOX32>)
-                      : reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM_PHILOX32>);
-    default:
-        return repair ? reinterpret_cast<const void *>(&spec_repair_kernel<NW, PPL, FAM_PHILOX>)
-                      : reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM_PHILOX>);
+    case FAM_ENUM: return spec_pair<NW, PPL, FAM_ENUM>(repair);
+    case FAM_PHILOX32: return spec_pair<NW, PPL, FAM_PHILOX32>(repair);
+    default: return spec_pair<NW, PPL, FAM_PHILOX>(repair);
     }
 }
 
+template <int PPL, uint32_t FAM>
+static const void *spec_mrg_pair(bool repair)
+{
+    return repair ? reinterpret_cast<const void *>(&spec_repair_kernel<MrgRedo<PPL, FAM>>)
+                  : reinterpret_cast<const void *>(&spec_mrg_kernel<PPL, FAM>);
+}
+
+template <int PPL>
+static const void *spec_mrg_family(uint32_t fam, bool repair)
+{
+    return fam == FAM_MRG ? spec_mrg_pair<PPL, FAM_MRG>(repair)
+                          : spec_mrg_pair<PPL, FAM_MIXED>(repair);
+}
+
 // The speculative fill kernel (or its repair kernel) for (family, threads
-// per workgroup, pairs per lane); null for shapes or families without one.
+// per workgroup, pairs per lane); null for shapes without one.
 const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair)
 {
-    if (fam != FAM_PHILOX && fam != FAM_ENUM && fam != FAM_PHILOX32)
-        return nullptr;
+    if (fam == FAM_MRG || fam == FAM_MIXED) {
+        if (threads != kMrgBlockThreads)
+            return nullptr;
+        switch (ppl) {
+        case 4: return spec_mrg_family<4>(fam, repair);
+        case 8: return spec_mrg_family<8>(fam, repair);
+        case 16: return spec_mrg_family<16>(fam, repair);
+        default: return nullptr;
+        }
+    }
     if (threads == 256) {
         switch (ppl) {
         case 2: return spec_family<4, 2>(fam, repair);

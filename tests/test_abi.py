@@ -144,6 +144,7 @@ def test_tuning_round_trip_and_validation():
     assert prngd.get_tuning("philox", 13)["path"] == 2
     with pytest.raises(prngd.PrngdError):
         prngd.set_tuning("philox", 13, path=3)
-    with pytest.raises(prngd.PrngdError):
-        prngd.set_tuning("mixed", 32, path="speculative")   # no speculative MRG fill
+    prngd.set_tuning("mixed", 32, path="speculative")
+    assert prngd.get_tuning("mixed", 32)["path"] == 2
+    prngd.reset_tuning("mixed", 32)
     prngd.reset_tuning("philox", 13)

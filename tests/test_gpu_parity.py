@@ -321,7 +321,8 @@ def test_plan_replays_advance_handles(seq_max_tiles):
 # ------------------------------------------------ the speculative fill
 
 @pytest.mark.parametrize("gen,w", [("philox", 2), ("philox", 3), ("philox", 8), ("philox", 12),
-                                   ("enumerate", 6), ("philox", 32)])
+                                   ("enumerate", 6), ("philox", 32), ("mixed", 32),
+                                   ("mrg32k3a", 32)])
 @pytest.mark.parametrize("ppl", [4, 16])
 def test_speculative_fill_at_any_rejection_rate(gen, w, ppl):
     """Speculation forced where most windows reject pairs: most tiles store
@@ -338,7 +339,7 @@ def test_speculative_fill_with_a_long_rejection_list():
     parity("philox", 3, seed=23, counter=11, n=1 << 22)
 
 
-@pytest.mark.parametrize("gen,w", [("philox", 3), ("philox", 8), ("philox", 32)])
+@pytest.mark.parametrize("gen,w", [("philox", 3), ("philox", 8), ("philox", 32), ("mixed", 32)])
 def test_speculative_batches_and_plans(gen, w):
     from paper_1401_8230_amd import workloads
     prngd.set_tuning(gen, w, path="speculative")
