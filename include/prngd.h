@@ -101,13 +101,16 @@ typedef struct {
                               /* the look-back (0: half a fair share)       */
     uint32_t path;            /* 0 automatic; 1 ordered (look-back and      */
                               /* segment-sequential kernels); 2 speculative */
-                              /* (each tile stores at the offset it assumes,*/
-                              /* a repair pass redoes tiles that assumed    */
-                              /* wrong).  Automatic takes the speculative   */
-                              /* fill when a launch expects at most 8       */
-                              /* rejections and has a segment of at least   */
-                              /* 64 tiles.  Philox and the test generator   */
-                              /* only                                       */
+                              /* (each tile stores at the offset it assumes */
+                              /* from the rejections published so far, a    */
+                              /* repair pass redoes tiles that assumed      */
+                              /* wrong); 3 speculative, holding the window  */
+                              /* in registers until its offset is read.     */
+                              /* Automatic takes 2 when a launch expects at */
+                              /* most 2 rejections, 3 when at most 128, and */
+                              /* 1 otherwise or when no segment reaches 64  */
+                              /* tiles.  MRG32k3a and mixed have form 3     */
+                              /* only (2 means 3 for them)                  */
 } prngd_tuning_t;
 
 /* Human-readable name of a status code (static storage). */

@@ -40,8 +40,9 @@ def candidates(generator, w):
         return out
     for threads, ppl in _philox_shapes():
         for store_mode in (0, 2):
-            out.append({"block_threads": threads, "pairs_per_lane": ppl,
-                        "store_mode": store_mode, "path": 2})
+            for path in (2, 3):
+                out.append({"block_threads": threads, "pairs_per_lane": ppl,
+                            "store_mode": store_mode, "path": path})
             for seq in (0, 1 << 20):
                 out.append({"block_threads": threads, "pairs_per_lane": ppl,
                             "store_mode": store_mode, "path": 1, "seq_max_tiles": seq})

@@ -502,11 +502,21 @@ struct PhiloxTile {
             const bool aligned = args.store_mode != 1 &&
                                  (reinterpret_cast<uintptr_t>(o) & 15u) == 0;
             if (excl + T < n) {
+                const uint32_t lane = tid & 63u;
 #pragma unroll
                 for (int j = 0; j < J; ++j) {
                     const uint32_t q = 2u * (uint32_t(j) * B + tid);
                     if (aligned) {
                         store_two(o + q, v[2 * j], v[2 * j + 1], args.store_mode);
+                    } else if (args.store_mode != 1) {
+                        // 8 bytes off: pair with lane - 1's second output
+                        const double prev = wave_shr1(v[2 * j + 1]);
+                        if (lane == 0)
+                            store_one(o + q, v[2 * j], args.store_mode);
+                        else
+                            store_two(o + q - 1, prev, v[2 * j], args.store_mode);
+                        if (lane == 63)
+                            store_one(o + q + 1, v[2 * j + 1], args.store_mode);
                     } else {
                         store_one(o + q, v[2 * j], args.store_mode);
                         store_one(o + q + 1, v[2 * j + 1], args.store_mode);
@@ -1149,29 +1159,42 @@ __global__ __launch_bounds__(64 * NW) void seq_philox_kernel(LaunchArgs args)
 // pair counter is the true one).  With no rejection in the launch the
 // repair launch reads one word and exits.
 // ======================================================================
-// The hint of tile g (tile t of its segment): the rejections the segment's
-// earlier tiles have published so far.  Read by wave 0, broadcast through
-// LDS, and recorded for the repair pass.
-__device__ __forceinline__ uint32_t read_hint(const LaunchArgs &args, const Segment &seg,
-                                              uint32_t t, uint32_t g, uint32_t *s_hint)
+// Start of a speculative tile: its segment, its index t in the segment,
+// its segment's start position, and its hint -- the rejections the
+// segment's earlier tiles have published so far (read by wave 0,
+// broadcast through LDS, recorded for the repair pass).  The list length,
+// the replay parity and both halves of the position slot are independent
+// loads, issued together; SINGLE launches take the segment from the
+// kernel arguments.
+struct TileStart {
+    Segment seg;
+    uint32_t t;
+    uint32_t par;
+    uint64_t c0;
+    uint32_t used;
+};
+
+// The hint of tile g: the rejections its segment's earlier tiles have
+// published by now (wave 0 reads the list, LDS broadcasts, thread 0
+// records it for the repair pass).
+__device__ __forceinline__ uint32_t read_hint(const LaunchArgs &args, const TileStart &ts,
+                                              uint32_t g, uint32_t *s_hint)
 {
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     if (tid < 64) {
         uint32_t used = 0;
-        if (t > 0) {
-            const uint32_t cnt = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                &args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            if (cnt != 0) {
-                const uint32_t lim = cnt < kHintEntries ? cnt : kHintEntries;
-                for (uint32_t i = lane; i < lim; i += 64) {
-                    const uint64_t e = __hip_atomic_load(&args.rejlist[i], __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-                    const uint32_t et = uint32_t(e >> 32);    // tile + 1; 0 = not written yet
-                    if (et > seg.tile_begin && et <= g)
-                        used += uint32_t(e);
-                }
-                used = wave_incl_scan(used, lane);
+        const uint32_t cnt = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (ts.t > 0 && cnt != 0) {
+            const uint32_t lim = cnt < kHintEntries ? cnt : kHintEntries;
+            for (uint32_t i = lane; i < lim; i += 64) {
+                const uint64_t e = __hip_atomic_load(&args.rejlist[i], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t et = uint32_t(e >> 32);        // tile + 1; 0 = not written yet
+                if (et > ts.seg.tile_begin && et <= g)
+                    used += uint32_t(e);
             }
+            used = wave_incl_scan(used, lane);
         }
         if (lane == 63)
             *s_hint = used;
@@ -1181,6 +1204,70 @@ __device__ __forceinline__ uint32_t read_hint(const LaunchArgs &args, const Segm
     if (tid == 0)
         args.hint[g] = used;
     return used;
+}
+
+// A tile's segment, index and start position, without its hint.
+template <bool SINGLE>
+__device__ __forceinline__ TileStart tile_start(const LaunchArgs &args, uint32_t g)
+{
+    const uint32_t flip = ((constant_u32 *)args.flip)[0];
+    TileStart ts;
+    if (SINGLE) {
+        ts.seg = args.seg0;
+        ts.t = g;
+    } else {
+        lookup(args, g, &ts.seg, &ts.t);
+    }
+    const uint64_t c_a = ((constant_u64 *)ts.seg.counter)[0];
+    const uint64_t c_b = ((constant_u64 *)ts.seg.counter)[1];
+    ts.par = (ts.seg.parity ^ flip) & 1u;
+    ts.c0 = ts.par ? c_b : c_a;
+    ts.used = 0;
+    return ts;
+}
+
+template <bool SINGLE>
+__device__ __forceinline__ TileStart spec_prologue(const LaunchArgs &args, uint32_t g,
+                                                   uint32_t *s_hint)
+{
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    uint32_t cnt = 0;
+    if (tid < 64)
+        cnt = __hip_atomic_load(&args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t flip = ((constant_u32 *)args.flip)[0];
+    TileStart ts;
+    if (SINGLE) {
+        ts.seg = args.seg0;
+        ts.t = g;
+    } else {
+        lookup(args, g, &ts.seg, &ts.t);
+    }
+    const uint64_t c_a = ((constant_u64 *)ts.seg.counter)[0];
+    const uint64_t c_b = ((constant_u64 *)ts.seg.counter)[1];
+    ts.par = (ts.seg.parity ^ flip) & 1u;
+    ts.c0 = ts.par ? c_b : c_a;
+    if (tid < 64) {
+        uint32_t used = 0;
+        cnt = __builtin_amdgcn_readfirstlane(cnt);
+        if (ts.t > 0 && cnt != 0) {
+            const uint32_t lim = cnt < kHintEntries ? cnt : kHintEntries;
+            for (uint32_t i = lane; i < lim; i += 64) {
+                const uint64_t e = __hip_atomic_load(&args.rejlist[i], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t et = uint32_t(e >> 32);        // tile + 1; 0 = not written yet
+                if (et > ts.seg.tile_begin && et <= g)
+                    used += uint32_t(e);
+            }
+            used = wave_incl_scan(used, lane);
+        }
+        if (lane == 63)
+            *s_hint = used;
+    }
+    __syncthreads();
+    ts.used = __builtin_amdgcn_readfirstlane(*s_hint);
+    if (tid == 0)
+        args.hint[g] = ts.used;
+    return ts;
 }
 
 // Appends tile g's rejections to the launch's list (thread 0).
@@ -1199,7 +1286,7 @@ __device__ __forceinline__ void publish_rejections(const LaunchArgs &args, uint3
                               __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-template <int NW, int PPL, uint32_t FAM>
+template <int NW, int PPL, uint32_t FAM, bool SINGLE>
 __global__ __launch_bounds__(64 * NW) void spec_philox_kernel(LaunchArgs args)
 {
     using Tile = SpecTile<NW, PPL, FAM>;
@@ -1207,13 +1294,11 @@ __global__ __launch_bounds__(64 * NW) void spec_philox_kernel(LaunchArgs args)
     __shared__ uint32_t s_off[Tile::E + 1];
     __shared__ uint32_t s_hint;
     const uint32_t g = blockIdx.x;
-    Segment seg;
-    uint32_t t;
-    lookup(args, g, &seg, &t);
-    const uint32_t par = seg.parity ^ read_flip(args);
-    const uint64_t c0 = load_start(seg, par);
-    uint64_t *next_counter = seg.counter + (par ^ 1u);
-    const uint32_t used = read_hint(args, seg, t, g, &s_hint);
+    const TileStart ts = spec_prologue<SINGLE>(args, g, &s_hint);
+    const Segment &seg = ts.seg;
+    const uint32_t t = ts.t, used = ts.used;
+    const uint64_t c0 = ts.c0;
+    uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
     const uint64_t w0 = c0 / T;
     const uint32_t lo0 = uint32_t(c0 - w0 * T);
     const uint64_t win = w0 + t;
@@ -1233,11 +1318,52 @@ __global__ __launch_bounds__(64 * NW) void spec_philox_kernel(LaunchArgs args)
     }
 }
 
-// The speculative fill for MRG32k3a and the mixed generator: the tile is
-// generated into registers and compacted through LDS as in the look-back
-// kernel, then stored at the offset the hint gives.  It writes nothing but
-// its own outputs (at a shifted place if the hint was short).
-template <int PPL, uint32_t FAM>
+// The speculative fill in its holding form: the tile's window is generated
+// into registers first (rejections published at once), and only then is the
+// hint read and the window stored at the offset it gives.  A tile thus
+// hears of every rejection published while it was generating, which keeps
+// the repair pass short where rejections are not rare.  It writes nothing
+// but its own outputs.
+template <int NW, int PPL, uint32_t FAM, bool SINGLE>
+__global__ __launch_bounds__(64 * NW) void spec_hold_kernel(LaunchArgs args)
+{
+    using Tile = PhiloxTile<NW, PPL, FAM>;
+    constexpr uint32_t T = Tile::T;
+    __shared__ uint32_t s_off[Tile::E + 1];
+    __shared__ uint32_t s_hint;
+    const uint32_t g = blockIdx.x;
+    const TileStart ts = tile_start<SINGLE>(args, g);
+    const Segment &seg = ts.seg;
+    const uint32_t t = ts.t;
+    uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
+    const uint64_t w0 = ts.c0 / T;
+    const uint32_t lo0 = uint32_t(ts.c0 - w0 * T);
+    const uint64_t win = w0 + t;
+    const uint32_t lo_off = t == 0 ? lo0 : 0u;
+    Tile tile;
+    const uint32_t kept = tile.generate(args, seg, win, lo_off, s_off);
+    publish_rejections(args, g, (T - lo_off) - kept);
+    const uint32_t used = read_hint(args, ts, g, &s_hint);
+    const uint64_t excl = (t == 0 ? 0 : uint64_t(t) * T - lo0) - used;
+    if (excl < seg.n)
+        tile.store(args, seg, win, excl, next_counter, s_off);
+    if (t == seg.ntiles - 1) {
+        uint64_t running = excl + kept;
+        for (uint64_t w2 = win + 1; running < seg.n; ++w2) {
+            __syncthreads();
+            const uint32_t k2 = tile.generate(args, seg, w2, 0u, s_off);
+            tile.store(args, seg, w2, running, next_counter, s_off);
+            running += k2;
+        }
+    }
+}
+
+// The speculative fill for MRG32k3a and the mixed generator, in holding
+// form: the tile is generated into registers and compacted through LDS as
+// in the look-back kernel, its rejections are published, and then it is
+// stored at the offset the hint gives.  It writes nothing but its own
+// outputs (at a shifted place if the hint was short).
+template <int PPL, uint32_t FAM, bool SINGLE>
 __global__ __launch_bounds__(kMrgBlockThreads) void spec_mrg_kernel(LaunchArgs args)
 {
     using Tile = MrgTile<PPL, FAM>;
@@ -1246,23 +1372,21 @@ __global__ __launch_bounds__(kMrgBlockThreads) void spec_mrg_kernel(LaunchArgs a
     __shared__ uint32_t s_wave[kMrgBlockThreads / 64];
     __shared__ uint32_t s_hint;
     const uint32_t g = blockIdx.x;
-    Segment seg;
-    uint32_t t;
-    lookup(args, g, &seg, &t);
-    const uint32_t par = seg.parity ^ read_flip(args);
-    const uint64_t c0 = load_start(seg, par);
-    uint64_t *next_counter = seg.counter + (par ^ 1u);
-    const uint32_t used = read_hint(args, seg, t, g, &s_hint);
-    const uint64_t w0 = c0 / T;
-    const uint32_t lo0 = uint32_t(c0 - w0 * T);
+    const TileStart ts = tile_start<SINGLE>(args, g);
+    const Segment &seg = ts.seg;
+    const uint32_t t = ts.t;
+    uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
+    const uint64_t w0 = ts.c0 / T;
+    const uint32_t lo0 = uint32_t(ts.c0 - w0 * T);
     const uint64_t win = w0 + t;
     const uint32_t lo_off = t == 0 ? lo0 : 0u;
-    const uint64_t excl = (t == 0 ? 0 : uint64_t(t) * T - lo0) - used;
     Tile tile;
     const uint32_t kept = tile.generate(args, seg, win, lo_off, s_wave);
+    publish_rejections(args, g, (T - lo_off) - kept);
+    const uint32_t used = read_hint(args, ts, g, &s_hint);
+    const uint64_t excl = (t == 0 ? 0 : uint64_t(t) * T - lo0) - used;
     if (excl < seg.n)
         tile.store(args, seg, win, excl, kept, next_counter, s_vals);
-    publish_rejections(args, g, (T - lo_off) - kept);
     if (t == seg.ntiles - 1) {
         uint64_t running = excl + kept;
         for (uint64_t w2 = win + 1; running < seg.n; ++w2) {
@@ -1544,71 +1668,81 @@ static const void *mrg_family(uint32_t fam, bool seq)
 }
 
 template <int NW, int PPL, uint32_t FAM>
-static const void *spec_pair(bool repair)
+static const void *spec_pair(bool repair, bool single, bool hold)
 {
-    return repair ? reinterpret_cast<const void *>(&spec_repair_kernel<PhiloxRedo<NW, PPL, FAM>>)
-                  : reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM>);
+    if (repair)
+        return reinterpret_cast<const void *>(&spec_repair_kernel<PhiloxRedo<NW, PPL, FAM>>);
+    if (hold)
+        return single ? reinterpret_cast<const void *>(&spec_hold_kernel<NW, PPL, FAM, true>)
+                      : reinterpret_cast<const void *>(&spec_hold_kernel<NW, PPL, FAM, false>);
+    return single ? reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM, true>)
+                  : reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM, false>);
 }
 
 template <int NW, int PPL>
-static const void *spec_family(uint32_t fam, bool repair)
+static const void *spec_family(uint32_t fam, bool repair, bool single, bool hold)
 {
     switch (fam) {
-    case FAM_ENUM: return spec_pair<NW, PPL, FAM_ENUM>(repair);
-    case FAM_PHILOX32: return spec_pair<NW, PPL, FAM_PHILOX32>(repair);
-    default: return spec_pair<NW, PPL, FAM_PHILOX>(repair);
+    case FAM_ENUM: return spec_pair<NW, PPL, FAM_ENUM>(repair, single, hold);
+    case FAM_PHILOX32: return spec_pair<NW, PPL, FAM_PHILOX32>(repair, single, hold);
+    default: return spec_pair<NW, PPL, FAM_PHILOX>(repair, single, hold);
     }
 }
 
 template <int PPL, uint32_t FAM>
-static const void *spec_mrg_pair(bool repair)
+static const void *spec_mrg_pair(bool repair, bool single)
 {
-    return repair ? reinterpret_cast<const void *>(&spec_repair_kernel<MrgRedo<PPL, FAM>>)
-                  : reinterpret_cast<const void *>(&spec_mrg_kernel<PPL, FAM>);
+    if (repair)
+        return reinterpret_cast<const void *>(&spec_repair_kernel<MrgRedo<PPL, FAM>>);
+    return single ? reinterpret_cast<const void *>(&spec_mrg_kernel<PPL, FAM, true>)
+                  : reinterpret_cast<const void *>(&spec_mrg_kernel<PPL, FAM, false>);
 }
 
 template <int PPL>
-static const void *spec_mrg_family(uint32_t fam, bool repair)
+static const void *spec_mrg_family(uint32_t fam, bool repair, bool single)
 {
-    return fam == FAM_MRG ? spec_mrg_pair<PPL, FAM_MRG>(repair)
-                          : spec_mrg_pair<PPL, FAM_MIXED>(repair);
+    return fam == FAM_MRG ? spec_mrg_pair<PPL, FAM_MRG>(repair, single)
+                          : spec_mrg_pair<PPL, FAM_MIXED>(repair, single);
 }
 
-// The speculative fill kernel (or its repair kernel) for (family, threads
-// per workgroup, pairs per lane); null for shapes without one.
-const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair)
+// The speculative fill kernel (single-segment or batched form) or its
+// repair kernel for (family, threads per workgroup, pairs per lane); null
+// for shapes without one.
+const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair,
+                            bool single, bool hold)
 {
     if (fam == FAM_MRG || fam == FAM_MIXED) {
-        if (threads != kMrgBlockThreads)
+        // the MRG fill always holds its window before storing
+        if (threads != kMrgBlockThreads || (!hold && !repair))
             return nullptr;
         switch (ppl) {
-        case 4: return spec_mrg_family<4>(fam, repair);
-        case 8: return spec_mrg_family<8>(fam, repair);
-        case 16: return spec_mrg_family<16>(fam, repair);
+        case 4: return spec_mrg_family<4>(fam, repair, single);
+        case 8: return spec_mrg_family<8>(fam, repair, single);
+        case 16: return spec_mrg_family<16>(fam, repair, single);
         default: return nullptr;
         }
     }
     if (threads == 256) {
         switch (ppl) {
-        case 2: return spec_family<4, 2>(fam, repair);
-        case 4: return spec_family<4, 4>(fam, repair);
-        case 8: return spec_family<4, 8>(fam, repair);
-        case 16: return spec_family<4, 16>(fam, repair);
-        case 32: return spec_family<4, 32>(fam, repair);
+        case 2: return spec_family<4, 2>(fam, repair, single, hold);
+        case 4: return spec_family<4, 4>(fam, repair, single, hold);
+        case 8: return spec_family<4, 8>(fam, repair, single, hold);
+        case 16: return spec_family<4, 16>(fam, repair, single, hold);
+        case 32: return spec_family<4, 32>(fam, repair, single, hold);
         default: return nullptr;
         }
     }
     if (threads == 512) {
         switch (ppl) {
-        case 8: return spec_family<8, 8>(fam, repair);
-        case 16: return spec_family<8, 16>(fam, repair);
+        case 8: return spec_family<8, 8>(fam, repair, single, hold);
+        case 16: return spec_family<8, 16>(fam, repair, single, hold);
         default: return nullptr;
         }
     }
     if (threads == 1024) {
         switch (ppl) {
-        case 8: return spec_family<16, 8>(fam, repair);
-        case 16: return spec_family<16, 16>(fam, repair);
+        case 8: return spec_family<16, 8>(fam, repair, single, hold);
+        case 16: return spec_family<16, 16>(fam, repair, single, hold);
         default: return nullptr;
         }
     }

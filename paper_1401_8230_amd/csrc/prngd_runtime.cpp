@@ -20,7 +20,8 @@
 
 namespace prngd {
 const void *fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool seq);
-const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair);
+const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair,
+                            bool single, bool hold);
 hipError_t launch_toggle_flip(uint32_t *flip, hipStream_t stream);
 const void *toggle_flip_kernel_ptr();
 hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads,
@@ -312,6 +313,8 @@ struct DeviceInfo {
     int cus = 0;
     uint32_t *error_host = nullptr;      // mapped pinned word
     uint32_t *error_dev = nullptr;
+    uint32_t *zero_word = nullptr;       // device word that stays 0 (replay parity of
+                                         // launches outside plans)
     std::vector<uint64_t *> slot_chunks;
     std::vector<uint64_t *> clean_slots;   // zero since their chunk was cleared
     std::vector<uint64_t *> free_slots;    // returned by destroyed handles
@@ -337,6 +340,9 @@ prngd_status_t device_info(int dev, DeviceInfo **out)
     void *dp = nullptr;
     HIP_TRY(hipHostGetDevicePointer(&dp, p, 0));
     d.error_dev = static_cast<uint32_t *>(dp);
+    HIP_TRY(hipMalloc(&dp, 256));
+    HIP_TRY(hipMemset(dp, 0, 256));
+    d.zero_word = static_cast<uint32_t *>(dp);
     *out = &g_devices.emplace(dev, std::move(d)).first->second;
     return PRNGD_OK;
 }
@@ -656,8 +662,11 @@ int occupancy_of(DeviceInfo *d, const void *kernel, uint32_t threads)
 struct LaunchPlan {
     const void *kernel;       // look-back kernel
     const void *seq_kernel;   // segment-sequential kernel
-    const void *spec_kernel;  // speculative fill and its repair, if used
+    const void *spec_kernels[2][2];  // [holding form][single segment]
+    const void *spec_kernel;  // the chosen speculative fill (batches, single
+    const void *spec_single_kernel;  // fills) and its repair
     const void *repair_kernel;
+    uint32_t *zero_word;
     bool spec;
     uint32_t threads;
     uint64_t T;
@@ -674,8 +683,17 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u threads x %u pairs per lane",
                     lp->threads, lp->tune.pairs_per_lane);
     lp->T = uint64_t(lp->threads) * lp->tune.pairs_per_lane;
-    lp->spec_kernel = spec_kernel_for(cfg.fam, lp->threads, lp->tune.pairs_per_lane, false);
-    lp->repair_kernel = spec_kernel_for(cfg.fam, lp->threads, lp->tune.pairs_per_lane, true);
+    for (int hold = 0; hold < 2; ++hold) {
+        lp->spec_kernels[hold][0] = spec_kernel_for(cfg.fam, lp->threads,
+                                                    lp->tune.pairs_per_lane, false, false, hold);
+        lp->spec_kernels[hold][1] = spec_kernel_for(cfg.fam, lp->threads,
+                                                    lp->tune.pairs_per_lane, false, true, hold);
+    }
+    lp->repair_kernel = spec_kernel_for(cfg.fam, lp->threads, lp->tune.pairs_per_lane, true,
+                                        false, false);
+    lp->spec_kernel = nullptr;
+    lp->spec_single_kernel = nullptr;
+    lp->zero_word = d->zero_word;
     lp->spec = false;                  // decided per launch by choose_path
     args->store_mode = lp->tune.store_mode;
     args->w = cfg.w;
@@ -711,14 +729,27 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
 void choose_path(LaunchPlan *lp, const Config &c, uint64_t pairs, uint64_t max_tiles)
 {
     lp->spec = false;
-    if (!lp->spec_kernel || !lp->repair_kernel || lp->tune.path == 1)
+    if (!lp->repair_kernel || lp->tune.path == 1)
         return;
-    if (lp->tune.path == 2) {
-        lp->spec = true;
-        return;
-    }
     const double rho = 2.0 / double(c.a - c.a0 + 1);
-    lp->spec = double(pairs) * rho <= 8.0 && max_tiles >= 64;
+    const double expected = double(pairs) * rho;
+    int hold = -1;
+    if (lp->tune.path == 2)
+        hold = 0;
+    else if (lp->tune.path == 3)
+        hold = 1;
+    else if (max_tiles >= 64 && expected <= 2.0)
+        hold = 0;
+    else if (max_tiles >= 64 && expected <= 128.0)
+        hold = 1;
+    if (hold < 0)
+        return;
+    // MRG32k3a and mixed have the holding form only
+    if (!lp->spec_kernels[hold][0])
+        hold = 1;
+    lp->spec_kernel = lp->spec_kernels[hold][0];
+    lp->spec_single_kernel = lp->spec_kernels[hold][1];
+    lp->spec = lp->spec_kernel && lp->spec_single_kernel;
 }
 
 // Workgroups of a launch over `units` tiles or segments: all that fit on
@@ -747,7 +778,10 @@ prngd_status_t launch_spec(DeviceInfo *d, const LaunchPlan &lp, Workspace *ws, L
     args.rejlist = ws->rejlist;
     args.hint = ws->hint;
     args.total_tiles = uint32_t(tiles);
-    HIP_TRY(launch_fill(lp.spec_kernel, uint32_t(tiles), lp.threads, args, s));
+    if (!args.flip)
+        args.flip = lp.zero_word;
+    HIP_TRY(launch_fill(args.segs ? lp.spec_kernel : lp.spec_single_kernel, uint32_t(tiles),
+                        lp.threads, args, s));
     HIP_TRY(launch_fill(lp.repair_kernel, repair_grid(d, lp, tiles), lp.threads, args, s));
     return PRNGD_OK;
 }
@@ -1396,9 +1430,9 @@ prngd_status_t prngd_set_tuning(prngd_generator_t generator, uint32_t w,
     if (!fill_kernel_for(fam, threads, ppl, false))
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u threads x %u pairs per lane",
                     threads, ppl);
-    if (t.store_mode > 2 || t.slack_mode > 1 || t.path > 2)
+    if (t.store_mode > 2 || t.slack_mode > 1 || t.path > 3)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "bad store_mode, slack_mode or path");
-    if (t.path == 2 && !spec_kernel_for(fam, threads, ppl, false))
+    if (t.path >= 2 && !spec_kernel_for(fam, threads, ppl, false, false, true))
         return fail(PRNGD_ERR_INVALID_ARGUMENT,
                     "no speculative fill for this generator and launch shape");
     g_tuning[std::make_pair(fam, w)] = t;

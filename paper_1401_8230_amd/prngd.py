@@ -286,13 +286,13 @@ class Plan:
             pass
 
 
-PATHS = {"auto": 0, "ordered": 1, "speculative": 2}
+PATHS = {"auto": 0, "ordered": 1, "speculative": 2, "speculative-hold": 3}
 
 
 def set_tuning(generator, w, pairs_per_lane=0, blocks_per_cu=0, store_mode=0, slack_mode=0,
                block_threads=0, seq_max_tiles=0, path=0):
-    """Launch shape for (generator, w); `path` is 0/"auto", 1/"ordered" or
-    2/"speculative"."""
+    """Launch shape for (generator, w); `path` is 0/"auto", 1/"ordered",
+    2/"speculative" or 3/"speculative-hold"."""
     path = PATHS.get(path, path)
     t = Tuning(pairs_per_lane, blocks_per_cu, store_mode, slack_mode, block_threads,
                seq_max_tiles, path)

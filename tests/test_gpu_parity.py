@@ -211,7 +211,7 @@ def test_checkpoint_resume():
     assert g.get_position() == g2.get_position()
 
 
-@pytest.mark.parametrize("path", ["ordered", "speculative"])
+@pytest.mark.parametrize("path", ["ordered", "speculative", "speculative-hold"])
 def test_repeated_high_rejection_fills(path):
     # many launches in a row: stale status words (ordered path) or rejection
     # list entries (speculative path) of earlier launches must never be
@@ -324,25 +324,30 @@ def test_plan_replays_advance_handles(seq_max_tiles):
                                    ("enumerate", 6), ("philox", 32), ("mixed", 32),
                                    ("mrg32k3a", 32)])
 @pytest.mark.parametrize("ppl", [4, 16])
-def test_speculative_fill_at_any_rejection_rate(gen, w, ppl):
+@pytest.mark.parametrize("path", ["speculative", "speculative-hold"])
+def test_speculative_fill_at_any_rejection_rate(gen, w, ppl, path):
     """Speculation forced where most windows reject pairs: most tiles store
     at a wrong offset first, and the repair pass must still leave exactly
     the oracle's bytes and counter."""
-    prngd.set_tuning(gen, w, path="speculative", pairs_per_lane=ppl)
+    prngd.set_tuning(gen, w, path=path, pairs_per_lane=ppl)
     for counter, n in [(0, 1), (7, 4097), (3, 100003), (4095, 300001)]:
         parity(gen, w, seed=19, counter=counter, n=n)
 
 
-def test_speculative_fill_with_a_long_rejection_list():
+@pytest.mark.parametrize("path", ["speculative", "speculative-hold"])
+def test_speculative_fill_with_a_long_rejection_list(path):
     # more dirty tiles than the repair caches in LDS
-    prngd.set_tuning("philox", 3, path="speculative", pairs_per_lane=4)
+    prngd.set_tuning("philox", 3, path=path, pairs_per_lane=4)
     parity("philox", 3, seed=23, counter=11, n=1 << 22)
 
 
-@pytest.mark.parametrize("gen,w", [("philox", 3), ("philox", 8), ("philox", 32), ("mixed", 32)])
-def test_speculative_batches_and_plans(gen, w):
+@pytest.mark.parametrize("gen,w,path", [("philox", 3, "speculative"), ("philox", 8, "speculative"),
+                                        ("philox", 32, "speculative"), ("mixed", 32, "speculative"),
+                                        ("philox", 3, "speculative-hold"),
+                                        ("philox", 24, "speculative-hold")])
+def test_speculative_batches_and_plans(gen, w, path):
     from paper_1401_8230_amd import workloads
-    prngd.set_tuning(gen, w, path="speculative")
+    prngd.set_tuning(gen, w, path=path)
     reqs = workloads.uneven_batch(count=200, lo=1, hi=3e4, rng_seed=w + 100)
     note(f"speculative batch {gen} w={w}")
     gens = make_handles(reqs, gen, w)

@@ -117,7 +117,7 @@ def test_autotune_candidates_are_valid_launch_shapes(gen, w):
     cands = autotune.candidates(gen, w)
     assert len(cands) >= 6
     paths = {c.get("path", 0) for c in cands}
-    assert paths == {1, 2}
+    assert {1, 2} <= paths
     try:
         for c in cands:
             prngd.set_tuning(gen, w, **c)             # validated on the host
