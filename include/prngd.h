@@ -105,12 +105,14 @@ typedef struct {
                               /* from the rejections published so far, a    */
                               /* repair pass redoes tiles that assumed      */
                               /* wrong); 3 speculative, holding the window  */
-                              /* in registers until its offset is read.     */
-                              /* Automatic takes 2 when a launch expects at */
-                              /* most 2 rejections, 3 when at most 128, and */
-                              /* 1 otherwise or when no segment reaches 64  */
-                              /* tiles.  MRG32k3a and mixed have form 3     */
-                              /* only (2 means 3 for them)                  */
+                              /* in registers until its offset is read;     */
+                              /* 4 speculative in 128-pair chunks, one per  */
+                              /* wave, for single fills (batches take 2).   */
+                              /* Automatic: ordered unless some request has */
+                              /* at least 2^18 pairs; then 3 when the launch*/
+                              /* expects at most 2 rejections, 4 (single    */
+                              /* fills) up to 1024, 3 (batches) up to 128.  */
+                              /* MRG32k3a and mixed have form 3 only        */
 } prngd_tuning_t;
 
 /* Human-readable name of a status code (static storage). */

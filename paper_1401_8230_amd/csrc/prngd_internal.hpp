@@ -95,6 +95,9 @@ struct LaunchArgs {
     SpecControl *spec;        // speculative fill: list control,
     uint64_t *rejlist;        //   rejection list (total_tiles slots),
     uint32_t *hint;           //   per tile: earlier rejections it assumed
+    uint64_t *hint64;         // wave-granular form: per chunk, written only
+                              //   when nonzero, (epoch << 24) | rejections
+    uint64_t epoch;           // launch number of the workspace (from 1)
     const uint32_t *mrg_thread;  // [256][18]: A^(r * tid * PPL)
     const uint32_t *mrg_window;  // [8][256][18]: A^(r * T * d * 256^i)
 };

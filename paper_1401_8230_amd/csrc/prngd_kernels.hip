@@ -1606,6 +1606,269 @@ __global__ __launch_bounds__(kMrgBlockThreads) void seq_mrg_kernel(LaunchArgs ar
     sequential_loop<MrgTile<PPL, FAM>>(args, sh);
 }
 
+// ======================================================================
+// Wave-granular speculative fill of a single segment.  A chunk is C = 128
+// consecutive pairs, one Philox block per lane; a workgroup of a one-shot
+// grid covers 4 CPW consecutive chunks, so workgroups retire in order and
+// the region being written at any moment stays narrow.  A chunk knows its
+// rejections from one ballot before it stores anything: a clean chunk is
+// stored in 16-byte pieces at the offset its hint gives, a chunk with
+// rejections ranks its kept pairs by ballot and popcount.  No barrier, no
+// LDS.  Each wave reads the rejection list once, at its start; a chunk
+// records its hint only when it is nonzero, tagged with the launch epoch.
+// ======================================================================
+constexpr uint32_t kChunk = 128;
+constexpr uint32_t kChunksPerWave = 2;
+
+template <uint32_t FAM>
+struct WaveChunk {
+    using HiLo = typename SpecTile<4, 4, FAM>::HiLo;
+
+    __device__ __forceinline__ static HiLo words(const LaunchArgs &args, const Segment &seg,
+                                                 uint64_t win, uint32_t lane)
+    {
+        uint32_t x1a, x2a, x1b, x2b;
+        if (FAM == FAM_ENUM) {
+            const uint64_t q = win * kChunk + 2u * lane;
+            const uint64_t mask = (uint64_t(1) << args.w) - 1;
+            x1a = uint32_t((q >> args.w) & mask);
+            x2a = uint32_t(q & mask);
+            x1b = uint32_t(((q + 1) >> args.w) & mask);
+            x2b = uint32_t((q + 1) & mask);
+        } else {
+            const uint64_t blk = win * (kChunk / 2) + lane;
+            const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u, seg.stream_id,
+                                           uint32_t(seg.seed), uint32_t(seg.seed >> 32));
+            if (FAM == FAM_PHILOX32) {
+                x1a = r.v0; x2a = r.v1; x1b = r.v2; x2b = r.v3;
+            } else {
+                const uint32_t shift = 32u - args.w;
+                x1a = r.v0 >> shift; x2a = r.v1 >> shift;
+                x1b = r.v2 >> shift; x2b = r.v3 >> shift;
+            }
+        }
+        if (FAM == FAM_PHILOX32)
+            return {x1a - 1u, x2a, x1b - 1u, x2b};
+        return {x1a - args.a0 - 1u, x2a - args.b0, x1b - args.a0 - 1u, x2b - args.b0};
+    }
+
+    // Produce chunk window `win` (from window offset lo_off on) at segment
+    // offset excl (outputs at or past n are dropped); returns the chunk's
+    // kept pairs.  Writes nothing but its own outputs.
+    __device__ __forceinline__ static uint32_t run(const LaunchArgs &args, const Segment &seg,
+                                                   uint64_t win, uint32_t lo_off, uint64_t excl,
+                                                   uint64_t *next_counter, bool store)
+    {
+        const uint32_t lane = threadIdx.x & 63u;
+        const uint32_t hm = FAM == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
+        const double tw = FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+        const HiLo p = words(args, seg, win, lane);
+        const uint32_t q = 2u * lane;
+        const bool oka = p.ha < hm && q >= lo_off;
+        const bool okb = p.hb < hm && q + 1 >= lo_off;
+        const uint64_t ka = __ballot(oka), kb = __ballot(okb);
+        const uint32_t kept = uint32_t(__popcll(ka) + __popcll(kb));
+        if (!store)
+            return kept;
+        const double za = map_hi_lo(p.ha, p.la, tw, args.S);
+        const double zb = map_hi_lo(p.hb, p.lb, tw, args.S);
+        const uint64_t left = seg.n - excl;            // >= 1
+        double *o = seg.out + excl;
+        if (kept == kChunk && left > kChunk) {
+            if (args.store_mode != 1 && (reinterpret_cast<uintptr_t>(o) & 15u) == 0) {
+                store_two(o + q, za, zb, args.store_mode);
+            } else if (args.store_mode != 1) {
+                const double prev = wave_shr1(zb);
+                if (lane == 0)
+                    store_one(o + q, za, args.store_mode);
+                else
+                    store_two(o + q - 1, prev, za, args.store_mode);
+                if (lane == 63)
+                    store_one(o + q + 1, zb, args.store_mode);
+            } else {
+                store_one(o + q, za, args.store_mode);
+                store_one(o + q + 1, zb, args.store_mode);
+            }
+            return kept;
+        }
+        const uint64_t lt = lanemask_lt(lane);
+        const uint32_t pos_a = uint32_t(__popcll(ka & lt) + __popcll(kb & lt));
+        const uint32_t pos_b = pos_a + (oka ? 1u : 0u);
+        if (oka && pos_a < left)
+            store_one(o + pos_a, za, args.store_mode);
+        if (okb && pos_b < left)
+            store_one(o + pos_b, zb, args.store_mode);
+        if (oka && pos_a + 1 == left)
+            *next_counter = win * kChunk + q + 1;
+        if (okb && pos_b + 1 == left)
+            *next_counter = win * kChunk + q + 2;
+        return kept;
+    }
+};
+
+__device__ __forceinline__ uint32_t chunk_hint(const LaunchArgs &args, uint32_t g)
+{
+    const uint64_t r = args.hint64[g];
+    return (r >> 24) == args.epoch ? uint32_t(r & 0xFFFFFFu) : 0u;
+}
+
+template <uint32_t FAM, uint32_t CPW>
+__global__ __launch_bounds__(256) void spec_wave_kernel(LaunchArgs args)
+{
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t total = args.total_tiles;
+    const TileStart ts = tile_start<true>(args, 0);
+    const Segment &seg = ts.seg;
+    uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
+    const uint64_t w0 = ts.c0 / kChunk;
+    const uint32_t lo0 = uint32_t(ts.c0 - w0 * kChunk);
+    // the wave's hint source: the list as this wave sees it at its start
+    const uint32_t cnt = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(&args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    uint64_t entry = 0;
+    if (cnt != 0 && lane < cnt)
+        entry = __hip_atomic_load(&args.rejlist[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the workgroup covers 4 CPW consecutive chunks; wave w takes every
+    // fourth of them
+#pragma unroll
+    for (uint32_t i = 0; i < CPW; ++i) {
+        const uint32_t k = (blockIdx.x * CPW + i) * 4u + wave;
+        if (k >= total)
+            break;
+        uint32_t used = 0;
+        if (k > 0) {
+            const uint32_t et = uint32_t(entry >> 32);     // chunk + 1; 0 = none
+            const uint32_t mine = et != 0 && et <= k ? uint32_t(entry) : 0u;
+            if (__ballot(mine != 0)) {
+                used = mine;
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1)
+                    used += __shfl_xor(used, d, 64);
+                if (lane == 0)
+                    args.hint64[k] = (args.epoch << 24) | used;
+            }
+        }
+        const uint64_t win = w0 + k;
+        const uint32_t lo_off = k == 0 ? lo0 : 0u;
+        const uint64_t excl = (k == 0 ? 0 : uint64_t(k) * kChunk - lo0) - used;
+        const uint32_t kept =
+            WaveChunk<FAM>::run(args, seg, win, lo_off, excl, next_counter, excl < seg.n);
+        const uint32_t rej = (kChunk - lo_off) - kept;
+        if (rej != 0 && lane == 0) {
+            const uint32_t slot = __hip_atomic_fetch_add(&args.spec->count, 1u, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            if (slot < total)
+                __hip_atomic_store(&args.rejlist[slot], (uint64_t(k) + 1u) << 32 | rej,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                __hip_atomic_fetch_or(args.error, kErrSpecList, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        if (k == total - 1) {
+            uint64_t running = excl + kept;
+            for (uint64_t w2 = win + 1; running < seg.n; ++w2)
+                running += WaveChunk<FAM>::run(args, seg, w2, 0u, running, next_counter, true);
+        }
+    }
+}
+
+// Whether chunk g (of the single segment) has to be produced again, and
+// at which true offset: the rules of needs_redo with chunk hints.
+__device__ __forceinline__ bool chunk_needs_redo(const LaunchArgs &args, const uint64_t *list,
+                                                 uint32_t cnt, uint32_t g, uint32_t lo0,
+                                                 uint64_t *true_off)
+{
+    const Segment &seg = args.seg0;
+    const TileFacts f = tile_facts(list, cnt, 0u, g);
+    if (!f.after_dirty)
+        return false;
+    const uint64_t off = uint64_t(g) * kChunk - lo0 - f.P;   // g >= 1 here
+    if (off >= seg.n)
+        return false;
+    *true_off = off;
+    if (chunk_hint(args, g) != f.P)
+        return true;
+    if (off + (kChunk - f.rej) >= seg.n || g == args.total_tiles - 1)
+        return true;
+    uint64_t gap = 0;
+    for (uint32_t v = g - 1;; --v) {
+        const TileFacts fv = tile_facts(list, cnt, 0u, v);
+        const uint64_t reach = uint64_t(fv.P - chunk_hint(args, v)) + fv.rej;
+        if (reach > gap)
+            return true;
+        if (!fv.after_dirty || v == 0)
+            break;
+        gap += uint64_t(kChunk) - (v == 0 ? lo0 : 0u) - fv.rej;
+        if (gap >= uint64_t(f.P) + kChunk)
+            break;
+    }
+    return false;
+}
+
+template <uint32_t FAM>
+__global__ __launch_bounds__(256) void spec_wave_repair_kernel(LaunchArgs args)
+{
+    __shared__ uint64_t s_list[kRepairCache];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t cnt0 =
+        __hip_atomic_load(&args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cnt0 == 0)
+        return;
+    const uint32_t total = args.total_tiles;
+    const uint32_t cnt = cnt0 < total ? cnt0 : total;
+    const uint64_t *list = args.rejlist;
+    if (cnt <= kRepairCache) {
+        for (uint32_t i = tid; i < cnt; i += 256)
+            s_list[i] = __hip_atomic_load(&args.rejlist[i], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        list = s_list;
+    }
+    __syncthreads();
+    const Segment &seg = args.seg0;
+    const uint32_t flip = read_flip(args);
+    const uint32_t par = (seg.parity ^ flip) & 1u;
+    const uint64_t c0 = load_start(seg, par);
+    uint64_t *next_counter = seg.counter + (par ^ 1u);
+    const uint64_t w0 = c0 / kChunk;
+    const uint32_t lo0 = uint32_t(c0 - w0 * kChunk);
+    // each wave checks 64 chunks per pass, one per lane, spread over waves
+    const uint64_t wid = blockIdx.x * 4u + (tid >> 6);
+    const uint64_t W = uint64_t(gridDim.x) * 4u;
+    for (uint64_t p = 0; (p * 64) * W + wid < total; ++p) {
+        const uint64_t g64 = (p * 64 + lane) * W + wid;
+        uint64_t off = 0;
+        const bool redo = g64 < total && g64 > 0 &&
+                          chunk_needs_redo(args, list, cnt, uint32_t(g64), lo0, &off);
+        uint64_t todo = __ballot(redo);
+        while (todo) {
+            const uint32_t l = uint32_t(__builtin_ctzll(todo));
+            todo &= todo - 1;
+            const uint32_t g = uint32_t(__shfl(uint32_t(g64), l, 64));
+            const uint64_t o = uint64_t(uint32_t(__shfl(uint32_t(off), l, 64))) |
+                               uint64_t(uint32_t(__shfl(uint32_t(off >> 32), l, 64))) << 32;
+            uint64_t running = o + WaveChunk<FAM>::run(args, seg, w0 + g, 0u, o, next_counter,
+                                                       true);
+            if (g == total - 1)
+                for (uint64_t w2 = w0 + g + 1; running < seg.n; ++w2)
+                    running += WaveChunk<FAM>::run(args, seg, w2, 0u, running, next_counter, true);
+        }
+    }
+    __shared__ bool s_last;
+    __syncthreads();
+    if (tid == 0)
+        s_last = __hip_atomic_fetch_add(&args.spec->done, 1u, __ATOMIC_ACQ_REL,
+                                        __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    __syncthreads();
+    if (s_last) {
+        for (uint32_t i = tid; i < cnt; i += 256)
+            args.rejlist[i] = 0;
+        if (tid == 0) {
+            __hip_atomic_store(&args.spec->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&args.spec->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 // Toggles a resident plan's replay parity after all of a replay's fills.
 __global__ void toggle_flip_kernel(uint32_t *flip)
 {
@@ -1703,6 +1966,27 @@ static const void *spec_mrg_family(uint32_t fam, bool repair, bool single)
 {
     return fam == FAM_MRG ? spec_mrg_pair<PPL, FAM_MRG>(repair, single)
                           : spec_mrg_pair<PPL, FAM_MIXED>(repair, single);
+}
+
+// The wave-granular speculative fill of a single segment (or its repair)
+// for a Philox-family generator; null for other families.
+const void *spec_wave_kernel_for(uint32_t fam, bool repair)
+{
+    switch (fam) {
+    case FAM_PHILOX32:
+        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<FAM_PHILOX32>)
+                      : reinterpret_cast<const void *>(
+                            &spec_wave_kernel<FAM_PHILOX32, kChunksPerWave>);
+    case FAM_PHILOX:
+        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<FAM_PHILOX>)
+                      : reinterpret_cast<const void *>(
+                            &spec_wave_kernel<FAM_PHILOX, kChunksPerWave>);
+    case FAM_ENUM:
+        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<FAM_ENUM>)
+                      : reinterpret_cast<const void *>(&spec_wave_kernel<FAM_ENUM, kChunksPerWave>);
+    default:
+        return nullptr;
+    }
 }
 
 // The speculative fill kernel (single-segment or batched form) or its

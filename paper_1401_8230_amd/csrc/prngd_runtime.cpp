@@ -22,6 +22,7 @@ namespace prngd {
 const void *fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool seq);
 const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair,
                             bool single, bool hold);
+const void *spec_wave_kernel_for(uint32_t fam, bool repair);
 hipError_t launch_toggle_flip(uint32_t *flip, hipStream_t stream);
 const void *toggle_flip_kernel_ptr();
 hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads,
@@ -423,7 +424,7 @@ prngd_tuning_t tuning_for(uint32_t fam, uint32_t w)
     if (t.block_threads == 0)
         t.block_threads = philox_family(fam) ? 256 : kMrgBlockThreads;
     if (t.pairs_per_lane == 0)
-        t.pairs_per_lane = philox_family(fam) ? 16 : 8;
+        t.pairs_per_lane = 16;
     return t;
 }
 
@@ -452,6 +453,9 @@ struct Workspace {
     uint64_t *rejlist = nullptr;
     uint32_t *hint = nullptr;
     size_t spec_cap = 0;
+    uint64_t *hint64 = nullptr;           // wave-granular form: per chunk
+    size_t hint64_cap = 0;
+    uint64_t spec_epoch = 0;
     uint64_t launches = 0;
     hipEvent_t last = nullptr;            // recorded after every launch
     // batch descriptors and the tile -> segment map
@@ -493,6 +497,7 @@ void ws_release(Workspace *ws)
     (void)hipFree(ws->spec);
     (void)hipFree(ws->rejlist);
     (void)hipFree(ws->hint);
+    (void)hipFree(ws->hint64);
     (void)hipFree(ws->dsegs);
     (void)hipFree(ws->tile_seg);
     for (int i = 0; i < 2; ++i) {
@@ -549,6 +554,27 @@ prngd_status_t ws_prepare_spec(Workspace *ws, size_t tiles, hipStream_t stream)
     ws->hint = static_cast<uint32_t *>(p);
     ws->spec_cap = cap;
     HIP_TRY(launch_zero_words(ws->rejlist, cap, stream));
+    return PRNGD_OK;
+}
+
+// Room for the wave-granular form's per-chunk hints (never cleared: a
+// record counts only while it carries the current launch epoch).
+prngd_status_t ws_prepare_hint64(Workspace *ws, size_t chunks, hipStream_t stream)
+{
+    if (chunks <= ws->hint64_cap)
+        return PRNGD_OK;
+    const size_t cap = std::max<size_t>(chunks, 1 << 16);
+    if (ws->hint64) {
+        HIP_TRY(hipStreamSynchronize(stream));
+        HIP_TRY(hipEventSynchronize(ws->last));
+        HIP_TRY(hipFree(ws->hint64));
+        ws->hint64 = nullptr;
+    }
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, cap * sizeof(uint64_t)));
+    ws->hint64 = static_cast<uint64_t *>(p);
+    ws->hint64_cap = cap;
+    HIP_TRY(launch_zero_words(ws->hint64, cap, stream));
     return PRNGD_OK;
 }
 
@@ -666,6 +692,9 @@ struct LaunchPlan {
     const void *spec_kernel;  // the chosen speculative fill (batches, single
     const void *spec_single_kernel;  // fills) and its repair
     const void *repair_kernel;
+    const void *wave_kernel;  // wave-granular single-segment form, if any
+    const void *wave_repair_kernel;
+    bool wave;                // single fills take the wave-granular form
     uint32_t *zero_word;
     bool spec;
     uint32_t threads;
@@ -693,6 +722,9 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
                                         false, false);
     lp->spec_kernel = nullptr;
     lp->spec_single_kernel = nullptr;
+    lp->wave_kernel = spec_wave_kernel_for(cfg.fam, false);
+    lp->wave_repair_kernel = spec_wave_kernel_for(cfg.fam, true);
+    lp->wave = false;
     lp->zero_word = d->zero_word;
     lp->spec = false;                  // decided per launch by choose_path
     args->store_mode = lp->tune.store_mode;
@@ -721,27 +753,41 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
 }
 
 // Whether a launch of `pairs` planned pairs whose longest segment has
-// `max_tiles` tiles takes the speculative fill.  Automatic choice:
-// speculation pays when the whole launch expects at most a few rejections
-// (x1 uniform on [a0, a] rejects 2 / (a - a0 + 1) of the pairs), so that
-// the repair pass has next to nothing to redo, and when some segment is
-// long enough that ordering its tiles across workgroups would cost.
-void choose_path(LaunchPlan *lp, const Config &c, uint64_t pairs, uint64_t max_tiles)
+// `longest` planned pairs takes a speculative fill, and which form.  Automatic
+// choice (x1 uniform on [a0, a] rejects 2 / (a - a0 + 1) of the pairs):
+// speculation pays when some segment is long enough that ordering its
+// tiles across workgroups would cost, and the launch expects few enough
+// rejections that the repair pass has little to redo.  Measured on
+// MI355X: up to 2 expected rejections the holding form is fastest; with
+// more (up to 1024) a single fill is fastest in 128-pair chunks, a batch
+// in the holding form (up to 128); beyond that the ordered kernels win.
+void choose_path(LaunchPlan *lp, const Config &c, uint64_t pairs, uint64_t longest,
+                 bool single)
 {
     lp->spec = false;
+    lp->wave = false;
     if (!lp->repair_kernel || lp->tune.path == 1)
         return;
     const double rho = 2.0 / double(c.a - c.a0 + 1);
     const double expected = double(pairs) * rho;
+    const bool wave_ok = single && lp->wave_kernel && lp->wave_repair_kernel;
     int hold = -1;
-    if (lp->tune.path == 2)
+    if (lp->tune.path == 4) {
+        lp->wave = wave_ok;
         hold = 0;
-    else if (lp->tune.path == 3)
-        hold = 1;
-    else if (max_tiles >= 64 && expected <= 2.0)
+    } else if (lp->tune.path == 2) {
         hold = 0;
-    else if (max_tiles >= 64 && expected <= 128.0)
+    } else if (lp->tune.path == 3) {
         hold = 1;
+    } else if (longest >= (uint64_t(64) << 12)) {
+        if (expected <= 2.0)
+            hold = 1;
+        else if (wave_ok && expected <= 1024.0) {
+            lp->wave = true;
+            hold = 1;
+        } else if (expected <= 128.0)
+            hold = 1;
+    }
     if (hold < 0)
         return;
     // MRG32k3a and mixed have the holding form only
@@ -783,6 +829,39 @@ prngd_status_t launch_spec(DeviceInfo *d, const LaunchPlan &lp, Workspace *ws, L
     HIP_TRY(launch_fill(args.segs ? lp.spec_kernel : lp.spec_single_kernel, uint32_t(tiles),
                         lp.threads, args, s));
     HIP_TRY(launch_fill(lp.repair_kernel, repair_grid(d, lp, tiles), lp.threads, args, s));
+    return PRNGD_OK;
+}
+
+// Enqueue the wave-granular speculative fill of one segment (args.seg0)
+// and its repair.
+prngd_status_t launch_spec_wave(DeviceInfo *d, const LaunchPlan &lp, Workspace *ws,
+                                LaunchArgs args, hipStream_t s)
+{
+    const uint64_t chunks = std::max<uint64_t>(1, (args.seg0.planned + 127) / 128);
+    if (chunks > kMaxTiles)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "fill too large for the wave-granular form");
+    prngd_status_t st;
+    if ((st = ws_prepare_spec(ws, chunks, s)) != PRNGD_OK)
+        return st;
+    if ((st = ws_prepare_hint64(ws, chunks, s)) != PRNGD_OK)
+        return st;
+    args.spec = ws->spec;
+    args.rejlist = ws->rejlist;
+    args.hint = ws->hint;
+    args.hint64 = ws->hint64;
+    args.epoch = ++ws->spec_epoch;
+    args.total_tiles = uint32_t(chunks);
+    if (!args.flip)
+        args.flip = lp.zero_word;
+    // one-shot grid: a workgroup covers 4 waves x 2 chunks
+    const uint64_t per_wg = 4 * 2;
+    const uint64_t grid = (chunks + per_wg - 1) / per_wg;
+    if (grid > 0xFFFFFFFFull)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "fill too large for the wave-granular form");
+    HIP_TRY(launch_fill(lp.wave_kernel, uint32_t(grid), 256, args, s));
+    const uint32_t rgrid = uint32_t(
+        std::max<uint64_t>(1, std::min<uint64_t>((chunks + 255) / 256, 2 * uint64_t(d->cus))));
+    HIP_TRY(launch_fill(lp.wave_repair_kernel, rgrid, 256, args, s));
     return PRNGD_OK;
 }
 
@@ -846,7 +925,7 @@ prngd_status_t build_batch(DeviceInfo *d, LaunchPlan &lp, const prngd_request_t 
     if (!first)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "request 0 has a NULL handle");
     std::vector<Segment> all;
-    uint64_t total = 0, pairs = 0, max_tiles = 0;
+    uint64_t total = 0, pairs = 0, max_seg_pairs = 0;
     for (uint32_t i = 0; i < count; ++i) {
         const prngd_request_t &r = reqs[i];
         if (!r.h)
@@ -868,11 +947,11 @@ prngd_status_t build_batch(DeviceInfo *d, LaunchPlan &lp, const prngd_request_t 
             return st;
         total += nt;
         pairs += s.planned;
-        max_tiles = std::max<uint64_t>(max_tiles, nt);
+        max_seg_pairs = std::max<uint64_t>(max_seg_pairs, s.planned);
         all.push_back(s);
         bp->handles.push_back(r.h);
     }
-    choose_path(&lp, first->cfg, pairs, max_tiles);
+    choose_path(&lp, first->cfg, pairs, max_seg_pairs, false);
     const uint64_t wg = uint64_t(occupancy_of(d, lp.seq_kernel, lp.threads)) * uint64_t(d->cus);
     // the speculative fill takes every segment tile by tile
     const uint64_t limit = lp.spec ? 0 : seq_limit(lp.tune, total, wg);
@@ -1099,10 +1178,13 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *strea
     args.nseg = 1;
     args.total_tiles = uint32_t(ntiles);
     args.ctl = ws->ctl;
-    choose_path(&lp, h->cfg, args.seg0.planned, ntiles);
+    choose_path(&lp, h->cfg, args.seg0.planned, args.seg0.planned, true);
     if ((st = order_after(h, s)) != PRNGD_OK)
         return st;
-    if (lp.spec) {
+    if (lp.spec && lp.wave) {
+        if ((st = launch_spec_wave(d, lp, ws, args, s)) != PRNGD_OK)
+            return st;
+    } else if (lp.spec) {
         if ((st = ws_prepare_spec(ws, ntiles, s)) != PRNGD_OK)
             return st;
         if ((st = launch_spec(d, lp, ws, args, ntiles, s)) != PRNGD_OK)
@@ -1430,7 +1512,7 @@ prngd_status_t prngd_set_tuning(prngd_generator_t generator, uint32_t w,
     if (!fill_kernel_for(fam, threads, ppl, false))
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u threads x %u pairs per lane",
                     threads, ppl);
-    if (t.store_mode > 2 || t.slack_mode > 1 || t.path > 3)
+    if (t.store_mode > 2 || t.slack_mode > 1 || t.path > 4)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "bad store_mode, slack_mode or path");
     if (t.path >= 2 && !spec_kernel_for(fam, threads, ppl, false, false, true))
         return fail(PRNGD_ERR_INVALID_ARGUMENT,

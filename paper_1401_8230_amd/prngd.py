@@ -286,7 +286,8 @@ class Plan:
             pass
 
 
-PATHS = {"auto": 0, "ordered": 1, "speculative": 2, "speculative-hold": 3}
+PATHS = {"auto": 0, "ordered": 1, "speculative": 2, "speculative-hold": 3,
+         "speculative-wave": 4}
 
 
 def set_tuning(generator, w, pairs_per_lane=0, blocks_per_cu=0, store_mode=0, slack_mode=0,

@@ -211,7 +211,8 @@ def test_checkpoint_resume():
     assert g.get_position() == g2.get_position()
 
 
-@pytest.mark.parametrize("path", ["ordered", "speculative", "speculative-hold"])
+@pytest.mark.parametrize("path", ["ordered", "speculative", "speculative-hold",
+                                  "speculative-wave"])
 def test_repeated_high_rejection_fills(path):
     # many launches in a row: stale status words (ordered path) or rejection
     # list entries (speculative path) of earlier launches must never be
@@ -324,7 +325,7 @@ def test_plan_replays_advance_handles(seq_max_tiles):
                                    ("enumerate", 6), ("philox", 32), ("mixed", 32),
                                    ("mrg32k3a", 32)])
 @pytest.mark.parametrize("ppl", [4, 16])
-@pytest.mark.parametrize("path", ["speculative", "speculative-hold"])
+@pytest.mark.parametrize("path", ["speculative", "speculative-hold", "speculative-wave"])
 def test_speculative_fill_at_any_rejection_rate(gen, w, ppl, path):
     """Speculation forced where most windows reject pairs: most tiles store
     at a wrong offset first, and the repair pass must still leave exactly
@@ -334,7 +335,7 @@ def test_speculative_fill_at_any_rejection_rate(gen, w, ppl, path):
         parity(gen, w, seed=19, counter=counter, n=n)
 
 
-@pytest.mark.parametrize("path", ["speculative", "speculative-hold"])
+@pytest.mark.parametrize("path", ["speculative", "speculative-hold", "speculative-wave"])
 def test_speculative_fill_with_a_long_rejection_list(path):
     # more dirty tiles than the repair caches in LDS
     prngd.set_tuning("philox", 3, path=path, pairs_per_lane=4)
