@@ -19,7 +19,9 @@ CPU oracle's rate on a bounded sample of the same workload, and, unless
 * serving: a Poisson trace of fill requests (2e4 per second, sizes
   log-uniform in [1e2, 1e8], 1024 clients with device-resident positions)
   served by the continuous-batching loop under a 64 GB HBM budget, against
-  the same trace served one plain fill at a time: throughput, p50, p99.
+  the same trace served one plain fill at a time: throughput, p50, p99;
+  and both loops at saturation (arrivals far faster than service), with
+  the trace's sizes and with small requests.
 """
 import argparse
 import hashlib
@@ -49,6 +51,10 @@ def parse():
     ap.add_argument("--streams", type=int, default=1 << 16)
     ap.add_argument("--outputs-per-stream", type=int, default=1 << 14)
     ap.add_argument("--seed", type=int, default=42)
+    ap.add_argument("--workload", choices=["many_streams", "single"], default="many_streams",
+                    help="timed step: the resident many-streams batch (default), or one "
+                         "prngd_fill of --single-outputs outputs of one Philox stream")
+    ap.add_argument("--single-outputs", type=int, default=1 << 30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-streams", type=int, default=16384)
     ap.add_argument("--headline-only", action="store_true",
@@ -92,6 +98,15 @@ def cpu_baseline(streams, n_each, seed):
             "kind": "oracle",
             "sample": f"substreams 0..{streams - 1} of the same workload, {n_each} outputs "
                       f"each ({total} outputs, {dt:.1f} s, one thread)"}
+
+
+def cpu_baseline_single(n, seed):
+    import oracle as O
+    t0 = time.perf_counter()
+    O.PRNGD(O.GEN_PHILOX, 32, seed=seed, stream=0).fill(n)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "accepted FP64 uniforms/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {n} outputs of the same stream ({dt:.1f} s, one thread)"}
 
 
 def timed(fn, steps, stream):
@@ -161,6 +176,41 @@ def run_many_streams(args, result):
             "frac": achieved_gbs / HBM_PEAK_GBS,
             "traffic": measured_traffic(),
         },
+    })
+
+
+def run_single(args, result):
+    """One Philox4x32-10 stream (seed, substream 0), w = 32: each step is one
+    prngd_fill of --single-outputs outputs, continuing the stream."""
+    import torch
+    from paper_1401_8230_amd import prngd
+    n = args.single_outputs
+    g = prngd.Generator(args.seed, "philox", w=32)
+    out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        g.fill(out, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_s = timed(lambda: g.fill(out, stream=stream), args.steps, stream)
+    wall = time.perf_counter() - t0
+    log(f"single stream: {n} outputs, {step_s * 1e3:.3f} ms per fill")
+    if args.calibrate:
+        half = n // 2
+        prngd.probe_copy(out[half:2 * half], out[:half], stream)
+        torch.cuda.synchronize()
+    g.close()
+    del out
+    achieved_gbs = n * BYTES_PER_OUTPUT / step_s / 1e9
+    result.update({
+        "value": n / step_s,
+        "ms_per_step": step_s * 1e3,
+        "wall_ms_per_step": wall / args.steps * 1e3,
+        "config": {"workload": f"one Philox4x32-10 stream of seed {args.seed}, w=32, "
+                               f"{n} FP64 outputs per fill", "outputs_per_step": n,
+                   "launch": "prngd_fill (speculative fill and its repair pass)"},
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None},
     })
 
 
@@ -255,6 +305,18 @@ def run_serving(args):
     log(f"serving: batched p50 {batched['p50_ms']:.3f} ms p99 {batched['p99_ms']:.3f} ms")
     plain = serving.run_trace(trace, mode="plain", warmup=1000, log=log)
     log(f"serving: plain p50 {plain['p50_ms']:.3f} ms p99 {plain['p99_ms']:.3f} ms")
+    # the same loops at saturation: arrivals far faster than either can
+    # serve, once with the trace's sizes and once with small requests
+    sat = {}
+    for name, lo, hi, count in (("sizes_1e2_1e8", 1e2, 1e8, 4000),
+                                ("sizes_1e2_1e4", 1e2, 1e4, 20000)):
+        tr = workloads.poisson_trace(count=count, rate=1e8, lo=lo, hi=hi, rng_seed=7)
+        b = serving.run_trace(tr, mode="batched")
+        p = serving.run_trace(tr, mode="plain")
+        log(f"serving at saturation ({name}): batched {b['value']:.3e}/s, "
+            f"plain {p['value']:.3e}/s")
+        sat[name] = {"requests": count, "batched": b, "plain": p,
+                     "throughput_ratio": b["value"] / p["value"]}
     return {
         "workload": "Poisson arrivals at 2e4 requests/s, sizes log-uniform in [1e2, 1e8], "
                     "1024 clients, HBM budget 64 GB",
@@ -262,6 +324,7 @@ def run_serving(args):
         "plain": plain,
         "throughput_ratio": batched["value"] / plain["value"],
         "p99_ratio": plain["p99_ms"] / batched["p99_ms"],
+        "saturated": sat,
     }
 
 
@@ -287,14 +350,21 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
     }
-    run_many_streams(args, result)
+    if args.workload == "single":
+        run_single(args, result)
+    else:
+        run_many_streams(args, result)
     if not args.headline_only:
         result["batched_vs_plain"] = run_uneven(args)
         result["serving"] = run_serving(args)
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        result["cpu_baseline"] = cpu_baseline(
-            min(args.cpu_sample_streams, args.streams), args.outputs_per_stream, args.seed)
+        if args.workload == "single":
+            result["cpu_baseline"] = cpu_baseline_single(min(args.single_outputs, 1 << 28),
+                                                         args.seed)
+        else:
+            result["cpu_baseline"] = cpu_baseline(
+                min(args.cpu_sample_streams, args.streams), args.outputs_per_stream, args.seed)
     print(json.dumps(result), flush=True)
 
 

@@ -1210,6 +1210,12 @@ prngd_status_t prngd_fill_batch(const prngd_request_t *reqs, uint32_t count, voi
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "empty request list");
     if (!reqs[0].h)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "request 0 has a NULL handle");
+    // one request: the single-fill path (no descriptor upload)
+    if (count == 1) {
+        if (reqs[0].h->plan)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "request 0: handle bound to a plan");
+        return prngd_fill(reqs[0].h, reqs[0].n, reqs[0].out, stream);
+    }
     const int dev = reqs[0].h->device;
     DeviceInfo *d = nullptr;
     prngd_status_t st = device_info(dev, &d);
