@@ -281,6 +281,7 @@ def run_uneven(args):
     for g in gens:
         g.close()
     del arena, outs
+    prngd.reset_tuning("philox", 32)          # the tuned shape is this batch's
     gbs = total * BYTES_PER_OUTPUT / batched_s / 1e9
     return {
         "workload": f"{len(reqs)} requests, sizes log-uniform in [1e3, 1e7], own seed, "

@@ -456,6 +456,10 @@ struct Workspace {
     uint64_t *hint64 = nullptr;           // wave-granular form: per chunk
     size_t hint64_cap = 0;
     uint64_t spec_epoch = 0;
+    // buffers replaced by larger ones: kept until the workspace is released,
+    // so that growing never waits for work in flight (freeing would)
+    std::vector<void *> retired_dev;
+    std::vector<void *> retired_host;
     uint64_t launches = 0;
     hipEvent_t last = nullptr;            // recorded after every launch
     // batch descriptors and the tile -> segment map
@@ -492,6 +496,10 @@ prngd_status_t ws_init(Workspace *ws, int dev)
 
 void ws_release(Workspace *ws)
 {
+    for (void *p : ws->retired_dev)
+        (void)hipFree(p);
+    for (void *p : ws->retired_host)
+        (void)hipHostFree(p);
     (void)hipFree(ws->status);
     (void)hipFree(ws->ctl);
     (void)hipFree(ws->spec);
@@ -513,11 +521,9 @@ void ws_release(Workspace *ws)
 prngd_status_t ws_prepare(Workspace *ws, size_t tiles, hipStream_t stream)
 {
     if (tiles > ws->status_cap) {
-        const size_t cap = std::max<size_t>(tiles, 1 << 16);
+        const size_t cap = std::max<size_t>({tiles, size_t(1) << 16, 2 * ws->status_cap});
         if (ws->status) {
-            HIP_TRY(hipStreamSynchronize(stream));
-            HIP_TRY(hipEventSynchronize(ws->last));
-            HIP_TRY(hipFree(ws->status));
+            ws->retired_dev.push_back(ws->status);
             ws->status = nullptr;
         }
         void *p = nullptr;
@@ -538,12 +544,10 @@ prngd_status_t ws_prepare_spec(Workspace *ws, size_t tiles, hipStream_t stream)
 {
     if (tiles <= ws->spec_cap)
         return PRNGD_OK;
-    const size_t cap = std::max<size_t>(tiles, 1 << 16);
+    const size_t cap = std::max<size_t>({tiles, size_t(1) << 20, 2 * ws->spec_cap});
     if (ws->rejlist) {
-        HIP_TRY(hipStreamSynchronize(stream));
-        HIP_TRY(hipEventSynchronize(ws->last));
-        HIP_TRY(hipFree(ws->rejlist));
-        HIP_TRY(hipFree(ws->hint));
+        ws->retired_dev.push_back(ws->rejlist);
+        ws->retired_dev.push_back(ws->hint);
         ws->rejlist = nullptr;
         ws->hint = nullptr;
     }
@@ -563,11 +567,9 @@ prngd_status_t ws_prepare_hint64(Workspace *ws, size_t chunks, hipStream_t strea
 {
     if (chunks <= ws->hint64_cap)
         return PRNGD_OK;
-    const size_t cap = std::max<size_t>(chunks, 1 << 16);
+    const size_t cap = std::max<size_t>({chunks, size_t(1) << 20, 2 * ws->hint64_cap});
     if (ws->hint64) {
-        HIP_TRY(hipStreamSynchronize(stream));
-        HIP_TRY(hipEventSynchronize(ws->last));
-        HIP_TRY(hipFree(ws->hint64));
+        ws->retired_dev.push_back(ws->hint64);
         ws->hint64 = nullptr;
     }
     void *p = nullptr;
@@ -585,13 +587,12 @@ prngd_status_t ws_grow(Workspace *ws, T **buf, size_t *cap, size_t need, hipStre
 {
     if (*cap >= need)
         return PRNGD_OK;
+    (void)stream;
     if (*buf) {
-        HIP_TRY(hipStreamSynchronize(stream));
-        HIP_TRY(hipEventSynchronize(ws->last));
-        HIP_TRY(hipFree(*buf));
+        ws->retired_dev.push_back(*buf);
         *buf = nullptr;
     }
-    const size_t c = std::max<size_t>(need, 1024);
+    const size_t c = std::max<size_t>({need, size_t(1024), 2 * *cap});
     void *p = nullptr;
     HIP_TRY(hipMalloc(&p, c * sizeof(T)));
     *buf = static_cast<T *>(p);
@@ -1258,9 +1259,9 @@ prngd_status_t prngd_fill_batch(const prngd_request_t *reqs, uint32_t count, voi
     HIP_TRY(hipEventSynchronize(ws->hsegs_done[slot]));
     if (ws->hsegs_cap[slot] < nseg) {
         if (ws->hsegs[slot])
-            HIP_TRY(hipHostFree(ws->hsegs[slot]));
+            ws->retired_host.push_back(ws->hsegs[slot]);
         void *p = nullptr;
-        const size_t cap = std::max<size_t>(nseg, 1024);
+        const size_t cap = std::max<size_t>({nseg, size_t(1024), 2 * ws->hsegs_cap[slot]});
         HIP_TRY(hipHostMalloc(&p, cap * sizeof(Segment), hipHostMallocDefault));
         ws->hsegs[slot] = static_cast<Segment *>(p);
         ws->hsegs_cap[slot] = cap;

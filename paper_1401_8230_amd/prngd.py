@@ -45,6 +45,11 @@ class Request(ctypes.Structure):
     _fields_ = [("h", ctypes.c_void_p), ("n", ctypes.c_uint64), ("out", ctypes.c_void_p)]
 
 
+def _request_dtype():
+    import numpy as np
+    return np.dtype([("h", np.uint64), ("n", np.uint64), ("out", np.uint64)])
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("pairs_per_lane", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
                 ("store_mode", ctypes.c_uint32), ("slack_mode", ctypes.c_uint32),
@@ -259,6 +264,33 @@ def fill_batch(pairs, stream=None):
     """pairs: [(Generator, tensor) or (Generator, tensor, n), ...]; one launch."""
     reqs = _requests(pairs)
     _check(lib().prngd_fill_batch(reqs, len(pairs), _stream_ptr(stream)))
+
+
+_REQUEST_DTYPE = None
+
+
+def fill_batch_raw(handles, ns, ptrs, stream):
+    """The same as fill_batch, from plain integers: handle addresses (the
+    `.handle.value` of each Generator), output counts and device addresses
+    of 8-byte aligned float64 buffers the caller keeps alive; `stream` is a
+    hipStream_t address.  For request loops where per-request marshalling
+    matters."""
+    import numpy as np
+    global _REQUEST_DTYPE
+    if _REQUEST_DTYPE is None:
+        _REQUEST_DTYPE = _request_dtype()
+        assert _REQUEST_DTYPE.itemsize == ctypes.sizeof(Request)
+    count = len(handles)
+    arr = np.empty(count, dtype=_REQUEST_DTYPE)
+    arr["h"] = handles
+    arr["n"] = ns
+    arr["out"] = ptrs
+    _check(lib().prngd_fill_batch(arr.ctypes.data_as(ctypes.POINTER(Request)), count, stream))
+
+
+def fill_raw(handle, n, ptr, stream):
+    """prngd_fill from plain integers (see fill_batch_raw)."""
+    _check(lib().prngd_fill(ctypes.c_void_p(handle), n, ctypes.c_void_p(ptr), stream))
 
 
 class Plan:

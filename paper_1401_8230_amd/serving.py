@@ -21,6 +21,7 @@ Latency of a request = the host time its completion was observed minus its
 scheduled arrival time.
 """
 import bisect
+import gc
 import time
 from collections import deque
 
@@ -34,6 +35,7 @@ class Arena:
     def __init__(self, elements, device="cuda:0"):
         import torch
         self.buf = torch.empty(int(elements), dtype=torch.float64, device=device)
+        self.base = self.buf.data_ptr()
         self.size = int(elements)
         self.free = [(0, self.size)]          # sorted (offset, length)
         self.used = 0
@@ -64,6 +66,9 @@ class Arena:
     def view(self, off, n):
         return self.buf[off:off + n]
 
+    def address(self, off):
+        return self.base + 8 * off
+
 
 class Request:
     __slots__ = ("rid", "client", "n", "arrival", "done", "off", "out")
@@ -86,8 +91,11 @@ class Server:
                  streams=4, max_batch=512, keep_outputs=False):
         import torch
         self.gens = prngd.Generator.many(seed, clients, generator, w=w)
+        self.hids = [g.handle.value for g in self.gens]
         self.arena = Arena(int(budget_bytes) // 8)
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
+        self.sptrs = [st.cuda_stream for st in self.streams]
+        self.events = [torch.cuda.Event() for _ in range(streams)]
         self.stream_busy = [None] * streams           # in-flight batch per stream
         self.queues = {}                              # client -> deque of requests
         self.order = deque()                          # clients with queued work, FIFO
@@ -95,6 +103,26 @@ class Server:
         self.max_batch = max_batch
         self.keep = keep_outputs
         self.finished = []
+        self.queued = 0                               # requests not yet launched
+        self._warm_streams(generator, w)
+
+    def _warm_streams(self, generator, w):
+        """One small and one full-size batch on every stream, on scratch
+        handles, so that each stream's workspace exists and is large enough
+        before requests arrive."""
+        import torch
+        scratch = prngd.Generator.many(0x5EED, self.max_batch, generator, w=w)
+        try:
+            n_big = min(10**8, self.arena.size // 4)
+            for s in self.streams:
+                prngd.fill_batch([(scratch[0], self.arena.view(0, n_big)),
+                                  (scratch[1], self.arena.view(n_big, n_big))], stream=s)
+                prngd.fill_batch([(g, self.arena.view(i * 64, 64))
+                                  for i, g in enumerate(scratch)], stream=s)
+            torch.cuda.synchronize()
+        finally:
+            for g in scratch:
+                g.close()
 
     def submit(self, req):
         if req.n * 8 > self.arena.size * 8:
@@ -105,6 +133,7 @@ class Server:
         if not q:
             self.order.append(req.client)
         q.append(req)
+        self.queued += 1
 
     def _retire(self, now_fn):
         for i, b in enumerate(self.stream_busy):
@@ -114,9 +143,7 @@ class Server:
             for r in b[1]:
                 r.done = t
                 if self.keep:
-                    r.out = r.out.cpu().numpy()
-                else:
-                    r.out = None
+                    r.out = self.arena.view(r.off, r.n).cpu().numpy()
                 self.arena.release(r.off, r.n)
                 self.busy.discard(r.client)
                 self.finished.append(r)
@@ -140,8 +167,8 @@ class Server:
                 skipped.append(c)               # waits for memory; keeps its place
                 continue
             q.popleft()
+            self.queued -= 1
             r.off = off
-            r.out = self.arena.view(off, r.n)
             self.busy.add(c)
             batch.append(r)
         self.order.extendleft(reversed(skipped))
@@ -150,7 +177,6 @@ class Server:
     def step(self, now_fn):
         """Retire finished batches, then launch one new batch if a stream is
         free.  Returns True if anything happened."""
-        import torch
         before = len(self.finished)
         self._retire(now_fn)
         progressed = len(self.finished) != before
@@ -161,15 +187,15 @@ class Server:
         batch = self._admit()
         if not batch:
             return progressed
-        s = self.streams[slot]
-        prngd.fill_batch([(self.gens[r.client], r.out, r.n) for r in batch], stream=s)
-        ev = torch.cuda.Event()
-        ev.record(s)
+        prngd.fill_batch_raw([self.hids[r.client] for r in batch], [r.n for r in batch],
+                             [self.arena.address(r.off) for r in batch], self.sptrs[slot])
+        ev = self.events[slot]
+        ev.record(self.streams[slot])
         self.stream_busy[slot] = (ev, batch)
         return True
 
     def idle(self):
-        return all(b is None for b in self.stream_busy) and not any(self.queues.values())
+        return self.queued == 0 and all(b is None for b in self.stream_busy)
 
     def close(self):
         import torch
@@ -187,8 +213,11 @@ class PlainServer:
                  keep_outputs=False):
         import torch
         self.gens = prngd.Generator.many(seed, clients, generator, w=w)
+        self.hids = [g.handle.value for g in self.gens]
         self.arena = Arena(int(budget_bytes) // 8)
         self.stream = torch.cuda.Stream()
+        self.sptr = self.stream.cuda_stream
+        self.pool = []                           # retired events, reused
         self.waiting = deque()
         self.running = deque()                   # (event, request), in order
         self.keep = keep_outputs
@@ -201,10 +230,12 @@ class PlainServer:
         import torch
         progressed = False
         while self.running and self.running[0][0].query():
-            _, r = self.running.popleft()
+            ev, r = self.running.popleft()
             r.done = now_fn()
-            r.out = r.out.cpu().numpy() if self.keep else None
+            if self.keep:
+                r.out = self.arena.view(r.off, r.n).cpu().numpy()
             self.arena.release(r.off, r.n)
+            self.pool.append(ev)
             self.finished.append(r)
             progressed = True
         while self.waiting:
@@ -214,9 +245,8 @@ class PlainServer:
                 break                            # first come, first served
             self.waiting.popleft()
             r.off = off
-            r.out = self.arena.view(off, r.n)
-            self.gens[r.client].fill(r.out, stream=self.stream)
-            ev = torch.cuda.Event()
+            prngd.fill_raw(self.hids[r.client], r.n, self.arena.address(off), self.sptr)
+            ev = self.pool.pop() if self.pool else torch.cuda.Event()
             ev.record(self.stream)
             self.running.append((ev, r))
             progressed = True
@@ -243,6 +273,22 @@ def percentile(values, q):
     return v[lo] + (v[hi] - v[lo]) * (k - lo)
 
 
+def preload_kernels(generator="philox", w=32, sizes=(100, 10**4, 10**6, 3 * 10**7)):
+    """Run every fill form a request loop may pick once, on scratch handles,
+    so that no kernel is loaded for the first time while requests wait."""
+    import torch
+    gens = prngd.Generator.many(0x5EED, 2, generator, w=w)
+    try:
+        buf = torch.empty(2 * max(sizes), dtype=torch.float64, device="cuda:0")
+        for n in sizes:
+            gens[0].fill(buf[:n])
+            prngd.fill_batch([(gens[0], buf[:n]), (gens[1], buf[n:2 * n])])
+        torch.cuda.synchronize()
+    finally:
+        for g in gens:
+            g.close()
+
+
 def run_trace(trace, mode="batched", warmup=0, clients=1024, budget_bytes=64e9, streams=4,
               keep_outputs=False, log=None, server=None):
     """Replay `trace` (workloads.Arrival items) in real time.  Returns
@@ -258,19 +304,28 @@ def run_trace(trace, mode="batched", warmup=0, clients=1024, budget_bytes=64e9, 
             server = PlainServer(clients=clients, budget_bytes=budget_bytes,
                                  keep_outputs=keep_outputs)
     reqs = [Request(i, a.client, a.n, a.t) for i, a in enumerate(trace)]
+    preload_kernels()
     torch.cuda.synchronize()
+    # a full garbage collection in the middle of the loop would stall it
+    gc_was_enabled = gc.isenabled()
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
 
     def now():
         return time.perf_counter() - t0
 
     i = 0
-    while i < len(reqs) or not server.idle():
-        t = now()
-        while i < len(reqs) and reqs[i].arrival <= t:
-            server.submit(reqs[i])
-            i += 1
-        server.step(now)
+    try:
+        while i < len(reqs) or not server.idle():
+            t = now()
+            while i < len(reqs) and reqs[i].arrival <= t:
+                server.submit(reqs[i])
+                i += 1
+            server.step(now)
+    finally:
+        if gc_was_enabled:
+            gc.enable()
     measured = [r for r in reqs[warmup:]]
     lat = [(r.done - r.arrival) * 1e3 for r in measured]
     first = min(r.arrival for r in measured)
