@@ -18,6 +18,10 @@ GEN_MRG32K3A = 1
 GEN_MIXED = 2
 GEN_ENUMERATE = 3
 
+MAP_EQ5 = 0          # Eq. (5): [0, 1)
+MAP_EQ4 = 1          # Eq. (4), Algorithm 1's Z: (0, 1)
+MAP_ONE_MINUS = 2    # 1 - Eq. (5): (0, 1]
+
 M1 = 4294967087
 M2 = 4294944443
 
@@ -35,6 +39,9 @@ class Stream(ctypes.Structure):
         ("b", ctypes.c_uint64),
         ("D", ctypes.c_uint64),
         ("S", ctypes.c_double),
+        ("map", ctypes.c_int),
+        ("D4", ctypes.c_uint64),
+        ("S4", ctypes.c_double),
         ("mrg", ctypes.c_uint32 * 6),
     ]
 
@@ -75,6 +82,9 @@ def lib():
         L.orc_fill.argtypes = [sp, ctypes.c_uint64, dp, u64p]
         L.orc_scale.argtypes = [ctypes.c_int, ctypes.c_uint64]
         L.orc_scale.restype = ctypes.c_double
+        L.orc_recip.argtypes = [ctypes.c_uint64]
+        L.orc_recip.restype = ctypes.c_double
+        L.orc_set_map.argtypes = [sp, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -143,10 +153,14 @@ def scale(w, D):
     return lib().orc_scale(w, D)
 
 
+def recip(D):
+    return lib().orc_recip(D)
+
+
 class PRNGD:
     """One oracle stream (sequential, single-threaded)."""
 
-    def __init__(self, generator, w, seed=0, stream=0, counter=0, ranges=None):
+    def __init__(self, generator, w, seed=0, stream=0, counter=0, ranges=None, map=MAP_EQ5):
         self.s = Stream()
         if ranges is not None:
             a0, a, b0, b = ranges
@@ -156,6 +170,8 @@ class PRNGD:
                                 counter)
         if rc != 0:
             raise ValueError("invalid oracle stream parameters")
+        if lib().orc_set_map(ctypes.byref(self.s), map) != 0:
+            raise ValueError("unknown map")
 
     @property
     def counter(self):
@@ -172,6 +188,14 @@ class PRNGD:
     @property
     def S(self):
         return float(self.s.S)
+
+    @property
+    def D4(self):
+        return int(self.s.D4)
+
+    @property
+    def S4(self):
+        return float(self.s.S4)
 
     @property
     def ranges(self):

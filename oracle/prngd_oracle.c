@@ -215,6 +215,34 @@ double orc_scale(int w, uint64_t D)
     return 0.0;
 }
 
+/* Exact RN(1 / D) for D >= 2: q = floor(2^s / D) with exactly 53 bits,
+ * rounded half to even, times 2^-s. */
+double orc_recip(uint64_t D)
+{
+    if (D < 2)
+        return D == 1 ? 1.0 : 0.0;
+    for (int s = 126; s >= 53; s--) {
+        u128 n2 = (u128)1 << s;
+        u128 q = n2 / D, r = n2 % D;
+        if (q >= ((u128)1 << 53))
+            continue;
+        if (q < ((u128)1 << 52))
+            return 0.0;                /* cannot happen: s decreases by one */
+        if (2 * r > (u128)D || (2 * r == (u128)D && (q & 1u)))
+            q += 1;
+        return ldexp((double)(uint64_t)q, -s);
+    }
+    return 0.0;
+}
+
+int orc_set_map(orc_stream *s, int map)
+{
+    if (map != ORC_MAP_EQ5 && map != ORC_MAP_EQ4 && map != ORC_MAP_ONE_MINUS)
+        return -1;
+    s->map = map;
+    return 0;
+}
+
 static int finish_init(orc_stream *s)
 {
     if (s->w < 1 || s->w > 32 || s->a < s->a0 || s->b < s->b0)
@@ -229,6 +257,11 @@ static int finish_init(orc_stream *s)
         return -1;
     s->D = (s->a - s->a0 - 2) * two_w + (s->b - s->b0);
     s->S = orc_scale(s->w, s->D);
+    /* Eq. (4) multiplied through by 2^w: z' = (x1 2^w + x2 - a0 2^w - b) /
+     * ((a - a0) 2^w - (b - b0)), with the division folded into RN(1/D4) */
+    s->D4 = (s->a - s->a0) * two_w - (s->b - s->b0);
+    s->S4 = orc_recip(s->D4);
+    s->map = ORC_MAP_EQ5;
     return 0;
 }
 
@@ -346,10 +379,20 @@ int orc_accept(const orc_stream *s, uint64_t x1)
  * reaches 1.0 (possible only for w > 26, where 1 - k^2 is not a double). */
 double orc_map(const orc_stream *s, uint64_t x1, uint64_t x2)
 {
+    if (s->map == ORC_MAP_EQ4) {
+        /* numerator of Eq. (4) in integer units; positive for accepted x1 */
+        uint64_t N4 = ((x1 - s->a0) << s->w) + x2 - s->b;
+        double z = (double)N4 * s->S4;
+        if (z >= 1.0)
+            z = 0x1.fffffffffffffp-1;
+        return z;
+    }
     uint64_t N = ((x1 - s->a0 - 1) << s->w) + (x2 - s->b0);
     double z = (double)N * s->S;
     if (z >= 1.0)
         z = 0x1.fffffffffffffp-1;
+    if (s->map == ORC_MAP_ONE_MINUS)
+        z = 1.0 - z;
     return z;
 }
 

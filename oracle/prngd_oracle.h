@@ -46,6 +46,13 @@ enum {
     ORC_GEN_ENUMERATE = 3  /* pair p = ((p >> w) mod 2^w, p mod 2^w), tests    */
 };
 
+/* How an accepted pair becomes an output (Section 2). */
+enum {
+    ORC_MAP_EQ5       = 0, /* Eq. (5): z' in [0, 1), the default              */
+    ORC_MAP_EQ4       = 1, /* Eq. (4), Algorithm 1's Z: z' in (0, 1)          */
+    ORC_MAP_ONE_MINUS = 2  /* 1 - z' of Eq. (5): no zero, in (0, 1]           */
+};
+
 /* One PRNGD stream: which generator, the ranges of x1 and x2 (integer
  * units), and the position (pairs consumed so far, rejected ones included). */
 typedef struct {
@@ -58,6 +65,9 @@ typedef struct {
     uint64_t b0, b;    /* x2 in [b0, b]                                */
     uint64_t D;        /* (a - a0 - 2) * 2^w + (b - b0)                */
     double   S;        /* RN((1 - 2^-2w) / D)                          */
+    int      map;      /* ORC_MAP_*                                     */
+    uint64_t D4;       /* Eq. (4) in integer units: (a - a0) 2^w - (b - b0) */
+    double   S4;       /* RN(1 / D4)                                    */
     uint32_t mrg[6];   /* MRG32k3a state at stream position 0          */
 } orc_stream;
 
@@ -98,6 +108,10 @@ void orc_fill(orc_stream *s, uint64_t n, double *out,
               uint64_t *accepted_index);
 /* Exact RN((2^2w - 1) / (D * 2^2w)), the folded constant of Eq. (5). */
 double orc_scale(int w, uint64_t D);
+/* Exact RN(1 / D), the folded constant of Eq. (4). */
+double orc_recip(uint64_t D);
+/* Choose the map of the stream's outputs; 0 on success, -1 if unknown. */
+int orc_set_map(orc_stream *s, int map);
 
 #ifdef __cplusplus
 }

@@ -314,3 +314,90 @@ def test_uniformity_chi2_and_ks_2_24_samples(gen, w, seed):
     assert stats.chisquare(counts_low).pvalue > 1e-4
     ks = stats.kstest(z, "uniform")
     assert ks.pvalue > 1e-4
+
+
+# ------------------------------------------------------ map variants
+# Eq. (4) -- Algorithm 1's Z -- maps the accepted region onto the open
+# interval (0, 1); the last part of Section 2 suggests 1 - z' where zero
+# must not occur.  Both are pinned against the paper's own formulas in
+# exact rationals, not against the oracle's integer rewriting.
+
+def algorithm1_z(w, a0, a, x1, x2):
+    """Algorithm 1's Z for a single generator on [min, max] = [a0, a] k,
+    R1 = x1 k, R2 = x2 k, in exact rationals."""
+    k = Fraction(1, 2**w)
+    R1, R2, mn, mx = Fraction(x1) * k, Fraction(x2) * k, Fraction(a0) * k, Fraction(a) * k
+    return (R1 + k * R2 - (mn + k * mx)) / ((mx - mn) * (1 - k))
+
+
+def eq4_z(w, a0, a, b0, b, x1, x2):
+    """Eq. (4) in the paper's scale, exact rationals."""
+    k = Fraction(1, 2**w)
+    X1, X2, A0, A, B0, B = (Fraction(v) * k for v in (x1, x2, a0, a, b0, b))
+    return (X1 + k * X2 - (A0 + k * B)) / (A - A0 - k * (B - B0))
+
+
+def test_algorithm1_z_is_eq4_for_a_single_generator():
+    rng = random.Random(41)
+    for w in (3, 8, 16, 24, 32):
+        a0, a = 0, 2**w - 1
+        for _ in range(50):
+            x1, x2 = rng.randrange(a0 + 1, a), rng.randrange(a0, a + 1)
+            assert algorithm1_z(w, a0, a, x1, x2) == eq4_z(w, a0, a, a0, a, x1, x2)
+
+
+@pytest.mark.parametrize("w,a0,a,b0,b", RANGES)
+def test_eq4_map_within_rounding_bound(w, a0, a, b0, b):
+    s = O.PRNGD(None, w, ranges=(a0, a, b0, b), map=O.MAP_EQ4)
+    assert s.S4 == float(1 / Fraction(s.D4))         # the folded constant, correctly rounded
+    rng = random.Random(w * 77 + a)
+    bound = 2 if 2 * w <= 53 else 3
+    near = 0
+    trials = 400
+    for _ in range(trials):
+        x1 = rng.randrange(a0 + 1, a)
+        x2 = rng.randrange(b0, b + 1)
+        z = s.map(x1, x2)
+        ex = eq4_z(w, a0, a, b0, b, x1, x2)
+        assert 0 < ex < 1 and 0.0 < z < 1.0
+        if z == ONE_MINUS_ULP and ex >= Fraction(ONE_MINUS_ULP):
+            near += 1
+            continue
+        assert abs(Fraction(z) - ex) <= bound * Fraction(ulp(z)), (x1, x2)
+        near += abs(z - float(ex)) <= ulp(float(ex))
+    assert near >= 0.99 * trials
+
+
+def test_eq4_exhaustive_w8_open_interval_increasing():
+    s = O.PRNGD(O.GEN_ENUMERATE, 8, map=O.MAP_EQ4)
+    out, idx = s.fill((256 - 2) * 256, with_index=True)
+    assert np.all(np.diff(out) > 0)                  # distinct, in pair order
+    assert out[0] > 0.0 and out[-1] < 1.0            # open at both ends
+    # Algorithm 1's Z at the end points: (N + 1) / (D + 2) for the full range
+    assert abs(Fraction(out[0]) - Fraction(1, s.D + 2)) <= Fraction(ulp(out[0]))
+    assert abs(Fraction(out[-1]) - Fraction(s.D + 1, s.D + 2)) <= Fraction(ulp(out[-1]))
+
+
+def test_eq4_top_clamps_at_w32():
+    s = O.PRNGD(O.GEN_PHILOX, 32, map=O.MAP_EQ4)
+    assert s.map(1, 0) > 0.0
+    assert s.map(2**32 - 2, 2**32 - 1) == ONE_MINUS_ULP   # (D + 1) / (D + 2) rounds to 1
+
+
+def test_one_minus_map_has_no_zero_and_reaches_one():
+    s5 = O.PRNGD(O.GEN_ENUMERATE, 8)
+    s1 = O.PRNGD(O.GEN_ENUMERATE, 8, map=O.MAP_ONE_MINUS)
+    n = (256 - 2) * 256
+    z5, z1 = s5.fill(n), s1.fill(n)
+    assert np.all(z1 > 0.0) and np.all(z1 <= 1.0)
+    assert z1[0] == 1.0                               # z' = 0 becomes 1
+    assert np.all(np.diff(z1) < 0)                    # order reversed, values distinct
+    # 1 - z' is a single rounding of the exact difference, and exact for
+    # z' >= 1/2 (the difference of two doubles within a factor 2)
+    for a, b in zip(z5[::97], z1[::97]):
+        exact = 1 - Fraction(a)
+        assert abs(Fraction(b) - exact) <= Fraction(ulp(b)) / 2
+        if a >= 0.5:
+            assert Fraction(b) == exact
+    top = O.PRNGD(O.GEN_PHILOX, 32, map=O.MAP_ONE_MINUS).map(2**32 - 2, 2**32 - 1)
+    assert top == 2.0**-53                            # the clamped 1 - 2^-53 turned over
