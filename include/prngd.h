@@ -76,6 +76,22 @@ typedef enum {
     PRNGD_ENUMERATE = 3
 } prngd_generator_t;
 
+/* How an accepted pair becomes an output (Section 2 of the paper):
+ *   PRNGD_MAP_EQ5       Eq. (5), the default: z' = RN(RN(N) * S) in [0, 1),
+ *                       forced to 1 - 2^-53 if it rounds to 1 (see above).
+ *   PRNGD_MAP_EQ4       Eq. (4), Algorithm 1's Z: the accepted region onto
+ *                       the open interval (0, 1).  In integer units
+ *                       N4 = (x1 - a0) 2^w + x2 - b = N + 2^w - (b - b0),
+ *                       D4 = (a - a0) 2^w - (b - b0), S4 = RN(1 / D4),
+ *                       z' = RN(RN(N4) * S4), forced below 1 the same way.
+ *   PRNGD_MAP_ONE_MINUS 1 - z' of Eq. (5), one rounding: no zero, (0, 1]
+ *                       (the paper's remedy where zero must not occur). */
+typedef enum {
+    PRNGD_MAP_EQ5 = 0,
+    PRNGD_MAP_EQ4 = 1,
+    PRNGD_MAP_ONE_MINUS = 2
+} prngd_map_t;
+
 typedef struct prngd_handle_s *prngd_handle_t;
 typedef struct prngd_plan_s *prngd_plan_t;
 
@@ -138,6 +154,17 @@ prngd_status_t prngd_describe(prngd_generator_t generator, double k,
                               double *S);
 
 /*
+ * The constants of one map for (generator, k, min, max), host only: the
+ * offset added to N (2^w - (b - b0) for Eq. (4), else 0), the denominator
+ * (D, or D4 for Eq. (4)) and the folded constant S.  Any output pointer
+ * may be NULL.  Errors: as prngd_describe; PRNGD_ERR_INVALID_ARGUMENT for
+ * an unknown map.
+ */
+prngd_status_t prngd_describe_map(prngd_generator_t generator, double k,
+                                  uint64_t min, uint64_t max, prngd_map_t map,
+                                  uint64_t *n_offset, uint64_t *D, double *S);
+
+/*
  * Create a PRNGD stream handle on the current HIP device: Algorithm 1's
  * PRNGD(k, min, max) with a base generator and a seed.  Stream id 0, pair
  * counter 0.  The library allocates the handle and its device state (two
@@ -162,6 +189,14 @@ prngd_status_t prngd_create_many(uint64_t seed, prngd_generator_t generator,
                                  double k, uint64_t min, uint64_t max,
                                  uint32_t first_stream_id, uint32_t count,
                                  prngd_handle_t *handles);
+
+/* Choose the map of the handle's later outputs (PRNGD_MAP_EQ5 after
+ * prngd_create).  Host only; fills already enqueued are not affected.
+ * Handles of one batch must share their map.  Errors:
+ * PRNGD_ERR_INVALID_ARGUMENT (NULL handle, unknown map, handle bound to a
+ * live plan). */
+prngd_status_t prngd_set_map(prngd_handle_t h, prngd_map_t map);
+prngd_status_t prngd_get_map(prngd_handle_t h, prngd_map_t *map);
 
 /* Wait for the handle's outstanding work, then free it.  NULL is a no-op. */
 prngd_status_t prngd_destroy(prngd_handle_t h);
@@ -202,7 +237,7 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out,
  * exactly what prngd_fill(reqs[i].h, reqs[i].n, reqs[i].out) would give,
  * bit for bit, and each handle advances as it would.  `reqs` is read
  * before the call returns.  All handles must be distinct and share the
- * generator, k, min and max; requests with n = 0 are skipped.
+ * generator, k, min, max and map; requests with n = 0 are skipped.
  * Errors: PRNGD_ERR_INVALID_ARGUMENT (count = 0 with reqs NULL, a NULL or
  * repeated handle, mixed configurations, bad out), PRNGD_ERR_HIP.
  */

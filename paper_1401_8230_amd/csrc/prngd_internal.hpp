@@ -91,7 +91,9 @@ struct LaunchArgs {
     uint32_t w;
     uint32_t a0, a;           // x1 range [a0, a]
     uint32_t b0;              // x2 lower bound
-    double S;                 // RN((1 - 2^-2w) / D)
+    double S;                 // RN((1 - 2^-2w) / D), or RN(1 / D4) for Eq. (4)
+    double nadd;              // added to N: 0, or 2^w - (b - b0) for Eq. (4)
+    double osign, ooff;       // output = osign * z + ooff: (1, 0), or (-1, 1) for 1 - z
     SpecControl *spec;        // speculative fill: list control,
     uint64_t *rejlist;        //   rejection list (total_tiles slots),
     uint32_t *hint;           //   per tile: earlier rejections it assumed

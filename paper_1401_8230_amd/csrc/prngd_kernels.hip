@@ -121,20 +121,25 @@ struct Mrg {
 // rounds once, exactly like converting the 64-bit integer N -- multiplied
 // by the folded constant S with one rounding, and forced below 1: the
 // largest double below 1 is the only value between a product that rounded
-// up to 1.0 and every product that did not.
+// up to 1.0 and every product that did not.  Eq. (4) (Algorithm 1's Z) is
+// the same with N + 2^w - (b - b0) (lo + nadd stays exact: both are below
+// 2^34) and S = RN(1 / D4); the no-zero form returns 1 - z, one rounding
+// of the exact difference (fma(-1, z, 1)).  For Eq. (5) nadd = 0 and the
+// last step is fma(1, z, 0) = z, so the default output is unchanged.
 constexpr double kBelowOne = 0x1.fffffffffffffp-1;
 
-__device__ __forceinline__ double map_hi_lo(uint32_t hi, uint32_t lo, double two_w, double S)
+__device__ __forceinline__ double map_hi_lo(uint32_t hi, uint32_t lo, double two_w,
+                                            const LaunchArgs &a)
 {
-    const double N = __builtin_fma(double(hi), two_w, double(lo));
-    const double z = N * S;
-    return z < kBelowOne ? z : kBelowOne;
+    const double N = __builtin_fma(double(hi), two_w, double(lo) + a.nadd);
+    const double z = N * a.S;
+    return __builtin_fma(a.osign, z < kBelowOne ? z : kBelowOne, a.ooff);
 }
 
 __device__ __forceinline__ double prngd_map(uint32_t x1, uint32_t x2, const LaunchArgs &a,
                                             double two_w)
 {
-    return map_hi_lo(x1 - a.a0 - 1u, x2 - a.b0, two_w, a.S);
+    return map_hi_lo(x1 - a.a0 - 1u, x2 - a.b0, two_w, a);
 }
 
 // ------------------------------------------------------- wave utilities
@@ -427,8 +432,8 @@ struct PhiloxTile {
                                                seg.stream_id, k0, k1);
                 const bool oka = r.v0 + 1u >= 2u;
                 const bool okb = r.v2 + 1u >= 2u;
-                v[2 * j] = map_hi_lo(r.v0 - 1u, r.v1, 4294967296.0, args.S);
-                v[2 * j + 1] = map_hi_lo(r.v2 - 1u, r.v3, 4294967296.0, args.S);
+                v[2 * j] = map_hi_lo(r.v0 - 1u, r.v1, 4294967296.0, args);
+                v[2 * j + 1] = map_hi_lo(r.v2 - 1u, r.v3, 4294967296.0, args);
                 acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
             }
         } else {
@@ -702,8 +707,8 @@ struct SpecTile {
                 const uint32_t q = 2u * (uint32_t(j) * B + tid);
                 const HiLo p = words(args, seg, win, j);
                 mx = max(mx, max(p.ha, p.hb));
-                const double za = map_hi_lo(p.ha, p.la, tw, args.S);
-                const double zb = map_hi_lo(p.hb, p.lb, tw, args.S);
+                const double za = map_hi_lo(p.ha, p.la, tw, args);
+                const double zb = map_hi_lo(p.hb, p.lb, tw, args);
                 if (aligned) {
                     store_two(o + q, za, zb, args.store_mode);
                 } else if (shifted) {
@@ -736,8 +741,8 @@ struct SpecTile {
                 const bool okb = p.hb < hm && q + 1 >= lo_off;
                 acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
                 if (kSpec && lo_off == 0) {
-                    const double za = map_hi_lo(p.ha, p.la, tw, args.S);
-                    const double zb = map_hi_lo(p.hb, p.lb, tw, args.S);
+                    const double za = map_hi_lo(p.ha, p.la, tw, args);
+                    const double zb = map_hi_lo(p.hb, p.lb, tw, args);
                     if (aligned && q + 1 < left) {
                         store_two(o + q, za, zb, args.store_mode);
                     } else {
@@ -777,8 +782,8 @@ struct SpecTile {
             const uint32_t pos_b = pos_a + (oka ? 1u : 0u);
             if (oka || okb) {
                 const HiLo p = words(args, seg, win, j);
-                const double za = map_hi_lo(p.ha, p.la, tw, args.S);
-                const double zb = map_hi_lo(p.hb, p.lb, tw, args.S);
+                const double za = map_hi_lo(p.ha, p.la, tw, args);
+                const double zb = map_hi_lo(p.hb, p.lb, tw, args);
                 if (oka && pos_a < left)
                     store_one(o + pos_a, za, args.store_mode);
                 if (okb && pos_b < left)
@@ -1670,8 +1675,8 @@ struct WaveChunk {
         const uint32_t kept = uint32_t(__popcll(ka) + __popcll(kb));
         if (!store)
             return kept;
-        const double za = map_hi_lo(p.ha, p.la, tw, args.S);
-        const double zb = map_hi_lo(p.hb, p.lb, tw, args.S);
+        const double za = map_hi_lo(p.ha, p.la, tw, args);
+        const double zb = map_hi_lo(p.hb, p.lb, tw, args);
         const uint64_t left = seg.n - excl;            // >= 1
         double *o = seg.out + excl;
         if (kept == kChunk && left > kChunk) {

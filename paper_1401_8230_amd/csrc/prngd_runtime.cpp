@@ -75,6 +75,14 @@ struct Config {
     uint64_t a0, a, b0, b;
     uint64_t D;
     double S;
+    uint32_t map;     // prngd_map_t
+    uint64_t D4;      // Eq. (4) denominator in integer units: (a - a0) 2^w - (b - b0)
+    double S4;        // RN(1 / D4)
+};
+
+// The map constants a launch passes to the kernels.
+struct MapConsts {
+    double S, nadd, osign, ooff;
 };
 
 // RN((1 - 2^-2w) / D): long division of (2^2w - 1) by D to 64 significant
@@ -100,6 +108,35 @@ double folded_constant(uint32_t w, uint64_t D)
     if (dropped > 0x400u || (dropped == 0x400u && (sticky || (keep & 1u))))
         ++keep;
     return std::ldexp(static_cast<double>(keep), 11 - frac - int(2 * w));
+}
+
+// RN(1 / D) for D >= 2: 2^(62 + L) / D with L the bit length of D has 63
+// or 64 significant bits; rounded half-to-even to 53 with the remainder as
+// sticky bit.
+double folded_recip(uint64_t D)
+{
+    const int L = 64 - __builtin_clzll(D);
+    const int sh = 62 + L;
+    const unsigned __int128 num = static_cast<unsigned __int128>(1) << sh;
+    const uint64_t q = static_cast<uint64_t>(num / D);
+    const bool sticky = (num % D) != 0;
+    const int bits = 64 - __builtin_clzll(q);
+    const int drop = bits - 53;
+    uint64_t keep = q >> drop;
+    const uint64_t dropped = q & ((uint64_t(1) << drop) - 1);
+    const uint64_t half = uint64_t(1) << (drop - 1);
+    if (dropped > half || (dropped == half && (sticky || (keep & 1u))))
+        ++keep;
+    return std::ldexp(static_cast<double>(keep), drop - sh);
+}
+
+MapConsts map_consts(const Config &c)
+{
+    if (c.map == PRNGD_MAP_EQ4)
+        return {c.S4, double((uint64_t(1) << c.w) - (c.b - c.b0)), 1.0, 0.0};
+    if (c.map == PRNGD_MAP_ONE_MINUS)
+        return {c.S, 0.0, -1.0, 1.0};
+    return {c.S, 0.0, 1.0, 0.0};
 }
 
 // The kernel family that serves a generator at resolution 2^-w.
@@ -150,6 +187,9 @@ prngd_status_t make_config(prngd_generator_t gen, double k, uint64_t min, uint64
                     (unsigned long long)c->a0, (unsigned long long)c->a);
     c->D = (c->a - c->a0 - 2) * (uint64_t(1) << w) + (c->b - c->b0);
     c->S = folded_constant(c->w, c->D);
+    c->D4 = (c->a - c->a0) * (uint64_t(1) << w) - (c->b - c->b0);
+    c->S4 = folded_recip(c->D4);
+    c->map = PRNGD_MAP_EQ5;
     c->fam = kernel_family(gen, c->w);
     return PRNGD_OK;
 }
@@ -733,7 +773,11 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     args->a0 = uint32_t(cfg.a0);
     args->a = uint32_t(cfg.a);
     args->b0 = uint32_t(cfg.b0);
-    args->S = cfg.S;
+    const MapConsts mc = map_consts(cfg);
+    args->S = mc.S;
+    args->nadd = mc.nadd;
+    args->osign = mc.osign;
+    args->ooff = mc.ooff;
     args->error = d->error_dev;
     args->mrg_thread = nullptr;
     args->mrg_window = nullptr;
@@ -897,7 +941,7 @@ prngd_status_t make_segment(prngd_handle_t h, uint64_t n, double *out, uint64_t 
 bool same_config(const Config &x, const Config &y)
 {
     return x.fam == y.fam && x.w == y.w && x.a0 == y.a0 && x.a == y.a && x.b0 == y.b0 &&
-           x.b == y.b;
+           x.b == y.b && x.map == y.map;
 }
 
 prngd_status_t current_device(int *dev)
@@ -1008,6 +1052,47 @@ prngd_status_t prngd_describe(prngd_generator_t generator, double k, uint64_t mi
     if (b) *b = c.b;
     if (D) *D = c.D;
     if (S) *S = c.S;
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_describe_map(prngd_generator_t generator, double k, uint64_t min,
+                                  uint64_t max, prngd_map_t map, uint64_t *n_offset,
+                                  uint64_t *D, double *S)
+{
+    Config c;
+    prngd_status_t st = make_config(generator, k, min, max, &c);
+    if (st != PRNGD_OK)
+        return st;
+    if (map != PRNGD_MAP_EQ5 && map != PRNGD_MAP_EQ4 && map != PRNGD_MAP_ONE_MINUS)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "unknown map %d", int(map));
+    c.map = uint32_t(map);
+    if (n_offset)
+        *n_offset = map == PRNGD_MAP_EQ4 ? (uint64_t(1) << c.w) - (c.b - c.b0) : 0;
+    if (D)
+        *D = map == PRNGD_MAP_EQ4 ? c.D4 : c.D;
+    if (S)
+        *S = map == PRNGD_MAP_EQ4 ? c.S4 : c.S;
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_set_map(prngd_handle_t h, prngd_map_t map)
+{
+    if (!h)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "NULL handle");
+    if (map != PRNGD_MAP_EQ5 && map != PRNGD_MAP_EQ4 && map != PRNGD_MAP_ONE_MINUS)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "unknown map %d", int(map));
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    if (h->plan)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle is bound to a live plan");
+    h->cfg.map = uint32_t(map);
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_get_map(prngd_handle_t h, prngd_map_t *map)
+{
+    if (!h || !map)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "NULL argument");
+    *map = static_cast<prngd_map_t>(h->cfg.map);
     return PRNGD_OK;
 }
 

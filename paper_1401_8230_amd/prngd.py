@@ -16,6 +16,11 @@ MRG32K3A = 1
 PHILOX_X1_MRG32K3A_X2 = 2
 ENUMERATE = 3
 
+MAP_EQ5 = 0
+MAP_EQ4 = 1
+MAP_ONE_MINUS = 2
+MAPS = {"eq5": MAP_EQ5, "eq4": MAP_EQ4, "one_minus": MAP_ONE_MINUS}
+
 GENERATORS = {
     "philox": PHILOX4X32_10,
     "philox4x32_10": PHILOX4X32_10,
@@ -90,6 +95,12 @@ _SIGNATURES = [
      [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(Tuning)]),
     ("prngd_get_tuning", ctypes.c_int,
      [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(Tuning)]),
+    ("prngd_describe_map", ctypes.c_int,
+     [ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+      ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+      ctypes.POINTER(ctypes.c_double)]),
+    ("prngd_set_map", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("prngd_get_map", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
     ("prngd_probe_write", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     ("prngd_probe_copy", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
@@ -167,6 +178,20 @@ def describe(generator, k, min, max):
     return {"w": w.value, "b0": b0.value, "b": b.value, "D": D.value, "S": S.value}
 
 
+def _map(m):
+    return MAPS[m] if isinstance(m, str) else int(m)
+
+
+def describe_map(generator, k, min, max, map):
+    """(offset added to N, denominator, folded constant) of a map, host only."""
+    off = ctypes.c_uint64()
+    D = ctypes.c_uint64()
+    S = ctypes.c_double()
+    _check(lib().prngd_describe_map(_gen(generator), k, min, max, _map(map), ctypes.byref(off),
+                                    ctypes.byref(D), ctypes.byref(S)))
+    return {"n_offset": off.value, "D": D.value, "S": S.value}
+
+
 def natural_range(generator, w):
     """(min, max) that prngd_create expects for a generator at resolution 2^-w."""
     g = _gen(generator)
@@ -180,7 +205,7 @@ class Generator:
     generator and a seed, positioned at (stream_id, pair counter)."""
 
     def __init__(self, seed, generator="philox", w=32, k=None, min=None, max=None,
-                 _handle=None):
+                 _handle=None, map=None):
         g = _gen(generator)
         if k is None:
             k = 2.0 ** -w
@@ -197,6 +222,17 @@ class Generator:
         self.generator = g
         self.seed = seed
         self.k = k
+        if map is not None:
+            self.set_map(map)
+
+    def set_map(self, map):
+        """Map of later outputs: "eq5" (default), "eq4" or "one_minus"."""
+        _check(lib().prngd_set_map(self.handle, _map(map)))
+
+    def get_map(self):
+        m = ctypes.c_int()
+        _check(lib().prngd_get_map(self.handle, ctypes.byref(m)))
+        return m.value
 
     @classmethod
     def many(cls, seed, count, generator="philox", w=32, first_stream_id=0, k=None,

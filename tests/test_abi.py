@@ -152,3 +152,29 @@ def test_tuning_round_trip_and_validation():
     assert prngd.get_tuning("mixed", 32)["path"] == 2
     prngd.reset_tuning("mixed", 32)
     prngd.reset_tuning("philox", 13)
+
+
+@pytest.mark.parametrize("gen,w,a0,a,b0,b", CASES)
+def test_describe_map_constants_are_exact(gen, w, a0, a, b0, b):
+    e4 = prngd.describe_map(gen, 2.0**-w, a0, a, "eq4")
+    assert e4["n_offset"] == 2**w - (b - b0)
+    D4 = (a - a0) * 2**w - (b - b0)
+    assert e4["D"] == D4 and e4["S"] == float(Fraction(1, D4))
+    e5 = prngd.describe_map(gen, 2.0**-w, a0, a, "eq5")
+    om = prngd.describe_map(gen, 2.0**-w, a0, a, "one_minus")
+    assert e5 == om == {"n_offset": 0, "D": (a - a0 - 2) * 2**w + (b - b0),
+                        "S": prngd.describe(gen, 2.0**-w, a0, a)["S"]}
+
+
+@pytest.mark.gpu
+def test_map_selection_on_handles():
+    g = prngd.Generator(1, "philox", w=32)
+    assert g.get_map() == prngd.MAP_EQ5
+    g.set_map("eq4")
+    assert g.get_map() == prngd.MAP_EQ4
+    with pytest.raises(prngd.PrngdError):
+        g.set_map(7)
+    h = prngd.Generator(1, "philox", w=32, map="one_minus")
+    assert h.get_map() == prngd.MAP_ONE_MINUS
+    with pytest.raises(prngd.PrngdError):
+        prngd.describe_map("philox", 2.0**-8, 0, 255, 9)

@@ -74,8 +74,11 @@ def gpu_fill(gen, w, seed, stream_id, counter, n, misalign=False):
     return res, pos
 
 
-def oracle_fill(gen, w, seed, stream_id, counter, n):
-    s = O.PRNGD(OGEN[gen], w, seed=seed, stream=stream_id, counter=counter)
+OMAP = {"eq5": O.MAP_EQ5, "eq4": O.MAP_EQ4, "one_minus": O.MAP_ONE_MINUS}
+
+
+def oracle_fill(gen, w, seed, stream_id, counter, n, map="eq5"):
+    s = O.PRNGD(OGEN[gen], w, seed=seed, stream=stream_id, counter=counter, map=OMAP[map])
     out = s.fill(n)
     return out, s.counter
 
@@ -476,3 +479,52 @@ def test_create_many_matches_individual_substreams(gen, w):
         g.close()
     with pytest.raises(prngd.PrngdError):
         prngd.Generator.many(99, 6, gen, w=w, first_stream_id=2**32 - 5)
+
+
+# ------------------------------------------------------------ map variants
+
+@pytest.mark.parametrize("map", ["eq4", "one_minus"])
+@pytest.mark.parametrize("gen,w", [("philox", 32), ("philox", 8), ("philox", 24), ("mixed", 32),
+                                   ("mrg32k3a", 32), ("enumerate", 8)])
+@pytest.mark.parametrize("path", ["ordered", "speculative-hold", "speculative-wave"])
+def test_map_variants_match_oracle(map, gen, w, path):
+    prngd.set_tuning(gen, w, path=path)
+    for counter, n in [(0, 70001), (3, 4097)]:
+        note(f"map {map} {gen} w={w} {path} counter={counter} n={n}")
+        g = prngd.Generator(42, gen, w=w, map=map)
+        if counter:
+            g.set_position(0, counter)
+        buf, out = guarded(n)
+        g.fill(out)
+        torch.cuda.synchronize()
+        check_guards(buf, n)
+        expect, ectr = oracle_fill(gen, w, 42, 0, counter, n, map=map)
+        assert_bits_equal(out.cpu().numpy(), expect, f"{map} {gen} w={w}")
+        assert g.get_position()[1] == ectr
+        g.close()
+
+
+def test_map_variants_in_batches_and_plans():
+    from paper_1401_8230_amd import workloads
+    reqs = workloads.uneven_batch(count=40, lo=1, hi=3e4, rng_seed=5)
+    for map in ("eq4", "one_minus"):
+        gens = make_handles(reqs, "philox", 32)
+        for g in gens:
+            g.set_map(map)
+        outs = [torch.empty(r.n, dtype=torch.float64, device=DEV) for r in reqs]
+        prngd.fill_batch(list(zip(gens, outs)))
+        plan = prngd.Plan(list(zip(gens, outs)))
+        plan.launch()
+        torch.cuda.synchronize()
+        plan.close()
+        for i, (r, o) in enumerate(zip(reqs, outs)):
+            s = O.PRNGD(O.GEN_PHILOX, 32, seed=r.seed, stream=r.stream_id, counter=r.counter,
+                        map=OMAP[map])
+            s.fill(r.n)
+            assert_bits_equal(o.cpu().numpy(), s.fill(r.n), f"{map} request {i}")
+        # a batch mixing maps is refused
+        gens[1].set_map("eq5")
+        with pytest.raises(prngd.PrngdError):
+            prngd.fill_batch(list(zip(gens[:2], outs[:2])))
+        for g in gens:
+            g.close()
