@@ -22,6 +22,9 @@ MAP_EQ5 = 0          # Eq. (5): [0, 1)
 MAP_EQ4 = 1          # Eq. (4), Algorithm 1's Z: (0, 1)
 MAP_ONE_MINUS = 2    # 1 - Eq. (5): (0, 1]
 
+CONSUME_PAIR = 0     # a rejected x1 consumes the whole pair
+CONSUME_SINGLE = 1   # Algorithm 1: a rejected r1 consumes one word
+
 M1 = 4294967087
 M2 = 4294944443
 
@@ -42,6 +45,7 @@ class Stream(ctypes.Structure):
         ("map", ctypes.c_int),
         ("D4", ctypes.c_uint64),
         ("S4", ctypes.c_double),
+        ("consume", ctypes.c_int),
         ("mrg", ctypes.c_uint32 * 6),
     ]
 
@@ -85,6 +89,9 @@ def lib():
         L.orc_recip.argtypes = [ctypes.c_uint64]
         L.orc_recip.restype = ctypes.c_double
         L.orc_set_map.argtypes = [sp, ctypes.c_int]
+        L.orc_set_consume.argtypes = [sp, ctypes.c_int]
+        L.orc_word.argtypes = [sp, ctypes.c_uint64]
+        L.orc_word.restype = ctypes.c_uint64
         _lib = L
     return _lib
 
@@ -160,7 +167,8 @@ def recip(D):
 class PRNGD:
     """One oracle stream (sequential, single-threaded)."""
 
-    def __init__(self, generator, w, seed=0, stream=0, counter=0, ranges=None, map=MAP_EQ5):
+    def __init__(self, generator, w, seed=0, stream=0, counter=0, ranges=None, map=MAP_EQ5,
+                 consume=CONSUME_PAIR):
         self.s = Stream()
         if ranges is not None:
             a0, a, b0, b = ranges
@@ -172,6 +180,8 @@ class PRNGD:
             raise ValueError("invalid oracle stream parameters")
         if lib().orc_set_map(ctypes.byref(self.s), map) != 0:
             raise ValueError("unknown map")
+        if lib().orc_set_consume(ctypes.byref(self.s), consume) != 0:
+            raise ValueError("unknown consumption mode, or not a single-generator stream")
 
     @property
     def counter(self):
@@ -206,6 +216,9 @@ class PRNGD:
         x2 = ctypes.c_uint64()
         lib().orc_pair(ctypes.byref(self.s), p, ctypes.byref(x1), ctypes.byref(x2))
         return int(x1.value), int(x2.value)
+
+    def word(self, j):
+        return int(lib().orc_word(ctypes.byref(self.s), j))
 
     def accept(self, x1):
         return bool(lib().orc_accept(ctypes.byref(self.s), x1))

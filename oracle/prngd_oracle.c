@@ -235,6 +235,77 @@ double orc_recip(uint64_t D)
     return 0.0;
 }
 
+int orc_set_consume(orc_stream *s, int consume)
+{
+    if (consume != ORC_CONSUME_PAIR && consume != ORC_CONSUME_SINGLE)
+        return -1;
+    if (consume == ORC_CONSUME_SINGLE && s->generator != ORC_GEN_PHILOX &&
+        s->generator != ORC_GEN_MRG32K3A && s->generator != ORC_GEN_ENUMERATE)
+        return -1;
+    s->consume = consume;
+    return 0;
+}
+
+uint64_t orc_word(const orc_stream *s, uint64_t j)
+{
+    uint64_t x1, x2;
+    uint32_t st[6], o;
+    switch (s->generator) {
+    case ORC_GEN_PHILOX:
+        return philox_word(s->seed, s->stream, j) >> (32 - s->w);
+    case ORC_GEN_MRG32K3A:
+        memcpy(st, s->mrg, sizeof st);
+        {
+            uint64_t e[1] = { j };
+            orc_mrg_jump(st, e, 1);
+        }
+        orc_mrg_outputs(st, 1, &o);
+        return o;
+    default:
+        orc_pair(s, j / 2, &x1, &x2);
+        return j % 2 ? x2 : x1;
+    }
+}
+
+/* Algorithm 1 word by word: draw r1 until it is accepted, then r2 is the
+ * next word.  The counter is the next word index. */
+static void fill_single(orc_stream *s, uint64_t n, double *out, uint64_t *accepted_index)
+{
+    uint64_t c = s->counter, made = 0;
+    uint32_t st[6];
+    int mrg = s->generator == ORC_GEN_MRG32K3A;
+    if (mrg) {
+        memcpy(st, s->mrg, sizeof st);
+        uint64_t e[1] = { c };
+        orc_mrg_jump(st, e, 1);
+    }
+    while (made < n) {
+        uint64_t r1, r2;
+        uint32_t o;
+        if (mrg) {
+            orc_mrg_outputs(st, 1, &o);
+            r1 = o;
+        } else {
+            r1 = orc_word(s, c);
+        }
+        c++;
+        if (!orc_accept(s, r1))
+            continue;
+        if (mrg) {
+            orc_mrg_outputs(st, 1, &o);
+            r2 = o;
+        } else {
+            r2 = orc_word(s, c);
+        }
+        c++;
+        out[made] = orc_map(s, r1, r2);
+        if (accepted_index)
+            accepted_index[made] = c - 2;
+        made++;
+    }
+    s->counter = c;
+}
+
 int orc_set_map(orc_stream *s, int map)
 {
     if (map != ORC_MAP_EQ5 && map != ORC_MAP_EQ4 && map != ORC_MAP_ONE_MINUS)
@@ -262,6 +333,7 @@ static int finish_init(orc_stream *s)
     s->D4 = (s->a - s->a0) * two_w - (s->b - s->b0);
     s->S4 = orc_recip(s->D4);
     s->map = ORC_MAP_EQ5;
+    s->consume = ORC_CONSUME_PAIR;
     return 0;
 }
 
@@ -401,6 +473,10 @@ double orc_map(const orc_stream *s, uint64_t x1, uint64_t x2)
 void orc_fill(orc_stream *s, uint64_t n, double *out,
               uint64_t *accepted_index)
 {
+    if (s->consume == ORC_CONSUME_SINGLE) {
+        fill_single(s, n, out, accepted_index);
+        return;
+    }
     int mrg = s->generator == ORC_GEN_MRG32K3A || s->generator == ORC_GEN_MIXED;
     uint32_t st[6];
     int shift = 32 - s->w;

@@ -53,6 +53,13 @@ enum {
     ORC_MAP_ONE_MINUS = 2  /* 1 - z' of Eq. (5): no zero, in (0, 1]           */
 };
 
+/* What a rejected x1 consumes. */
+enum {
+    ORC_CONSUME_PAIR   = 0, /* the whole pair (the text of Section 2)        */
+    ORC_CONSUME_SINGLE = 1  /* one word (Algorithm 1: only r1 is redrawn);
+                               single-generator streams only               */
+};
+
 /* One PRNGD stream: which generator, the ranges of x1 and x2 (integer
  * units), and the position (pairs consumed so far, rejected ones included). */
 typedef struct {
@@ -60,7 +67,7 @@ typedef struct {
     int      w;        /* resolution k = 2^-w                          */
     uint64_t seed;
     uint32_t stream;
-    uint64_t counter;  /* pairs consumed                               */
+    uint64_t counter;  /* pairs consumed (words, when consume = single) */
     uint64_t a0, a;    /* x1 in [a0, a]                                */
     uint64_t b0, b;    /* x2 in [b0, b]                                */
     uint64_t D;        /* (a - a0 - 2) * 2^w + (b - b0)                */
@@ -68,6 +75,7 @@ typedef struct {
     int      map;      /* ORC_MAP_*                                     */
     uint64_t D4;       /* Eq. (4) in integer units: (a - a0) 2^w - (b - b0) */
     double   S4;       /* RN(1 / D4)                                    */
+    int      consume;  /* ORC_CONSUME_*                                 */
     uint32_t mrg[6];   /* MRG32k3a state at stream position 0          */
 } orc_stream;
 
@@ -112,6 +120,12 @@ double orc_scale(int w, uint64_t D);
 double orc_recip(uint64_t D);
 /* Choose the map of the stream's outputs; 0 on success, -1 if unknown. */
 int orc_set_map(orc_stream *s, int map);
+/* Choose what a rejection consumes; 0 on success, -1 if unknown or if the
+ * stream combines two generators.  The counter then counts words. */
+int orc_set_consume(orc_stream *s, int consume);
+/* Word j of a single-generator stream: Philox word j >> (32 - w); MRG32k3a
+ * output j; ENUMERATE: x1 of pair j / 2 for even j, x2 for odd j. */
+uint64_t orc_word(const orc_stream *s, uint64_t j);
 
 #ifdef __cplusplus
 }

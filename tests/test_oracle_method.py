@@ -401,3 +401,85 @@ def test_one_minus_map_has_no_zero_and_reaches_one():
             assert Fraction(b) == exact
     top = O.PRNGD(O.GEN_PHILOX, 32, map=O.MAP_ONE_MINUS).map(2**32 - 2, 2**32 - 1)
     assert top == 2.0**-53                            # the clamped 1 - 2^-53 turned over
+
+
+# ------------------------------------ Algorithm 1's single-word consumption
+
+def algorithm1_literal(words, w, mn, mx, count):
+    """Algorithm 1 as printed, with PRNG() returning words * k in order:
+    the exact Z of each output and the number of PRNG() calls.  Its
+    comparisons are made in exact rationals and, as printed, in double
+    precision; both must decide alike."""
+    k = Fraction(1, 2**w)
+    Rmin, Rmax = mn + k * (mx - mn), mx - k * (mx - mn)
+    rmin_dp = float(mn) + float(k) * (float(mx) - float(mn))
+    rmax_dp = float(mx) - float(k) * (float(mx) - float(mn))
+    it = iter(words)
+    calls, out = 0, []
+    for _ in range(count):
+        R1 = Fraction(-1)
+        while R1 < Rmin or R1 > Rmax:
+            R1 = Fraction(next(it)) * k
+            calls += 1
+            assert (R1 < Rmin or R1 > Rmax) == (float(R1) < rmin_dp or float(R1) > rmax_dp)
+        R2 = Fraction(next(it)) * k
+        calls += 1
+        out.append((R1 + k * R2 - (mn + k * mx)) / ((mx - mn) * (1 - k)))
+    return out, calls
+
+
+def _philox_w_words(seed, stream, count, w):
+    return [int(u) >> (32 - w) for u in O.philox_words(seed, stream, 0, count)]
+
+
+@pytest.mark.parametrize("w,seed", [(3, 1), (5, 2), (8, 3), (12, 4), (16, 5)])
+def test_single_consumption_is_algorithm1_as_printed(w, seed):
+    n = 3000
+    words = _philox_w_words(seed, 0, 4 * n + 64, w)
+    k = Fraction(1, 2**w)
+    Z, calls = algorithm1_literal(words, w, Fraction(0), (2**w - 1) * k, n)
+    s = O.PRNGD(O.GEN_PHILOX, w, seed=seed, map=O.MAP_EQ4, consume=O.CONSUME_SINGLE)
+    out = s.fill(n)
+    assert s.counter == calls                        # the same words consumed
+    bound = 2 if 2 * w <= 53 else 3
+    for z, ex in zip(out, Z):
+        assert 0.0 < z < 1.0
+        assert abs(Fraction(z) - ex) <= bound * Fraction(ulp(z))
+
+
+def test_single_consumption_mrg32k3a_is_algorithm1_as_printed():
+    n = 2000
+    state = O.mrg_stream_base(7, 0)
+    outs, _ = O.mrg_outputs(state, 2 * n + 16)
+    words = [int(v) for v in outs]
+    k = Fraction(1, 2**32)
+    Z, calls = algorithm1_literal(words, 32, Fraction(1) * k, Fraction(O.M1) * k, n)
+    s = O.PRNGD(O.GEN_MRG32K3A, 32, seed=7, map=O.MAP_EQ4, consume=O.CONSUME_SINGLE)
+    out = s.fill(n)
+    assert s.counter == calls == 2 * n               # no rejection this early
+    for z, ex in zip(out, Z):
+        assert abs(Fraction(z) - ex) <= 3 * Fraction(ulp(z))
+
+
+def test_single_and_pair_consumption_agree_until_the_first_rejection():
+    w = 8
+    pair = O.PRNGD(O.GEN_PHILOX, w, seed=9)
+    single = O.PRNGD(O.GEN_PHILOX, w, seed=9, consume=O.CONSUME_SINGLE)
+    zp, idx = pair.fill(400, with_index=True)
+    zs = single.fill(400)
+    # the first rejected pair index is the first gap in the accepted indices
+    gaps = np.flatnonzero(np.diff(idx.astype(np.int64)) != 1)
+    first = int(gaps[0]) + 1 if idx[0] == 0 else 0
+    assert first > 0
+    np.testing.assert_array_equal(zp[:first], zs[:first])
+    # after it, single consumption is realigned by one word: the next output
+    # pairs the word after the rejected x1 with the one after it
+    rej_word = 2 * (int(idx[first - 1]) + 1)
+    x1, x2 = single.word(rej_word + 1), single.word(rej_word + 2)
+    if pair.accept(x1):
+        assert zs[first] == pair.map(x1, x2)
+
+
+def test_single_consumption_refuses_two_generators():
+    with pytest.raises(ValueError):
+        O.PRNGD(O.GEN_MIXED, 32, consume=O.CONSUME_SINGLE)
