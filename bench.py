@@ -55,6 +55,10 @@ def parse():
                     help="timed step: the resident many-streams batch (default), or one "
                          "prngd_fill of --single-outputs outputs of one Philox stream")
     ap.add_argument("--single-outputs", type=int, default=1 << 30)
+    ap.add_argument("--consume", choices=["pair", "single"], default="pair",
+                    help="what a rejected x1 consumes (single: Algorithm 1's loop)")
+    ap.add_argument("--map", choices=["eq5", "eq4", "one_minus"], default="eq5",
+                    help="output map: Eq. (5), Eq. (4) / Algorithm 1's Z, or 1 - z")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-streams", type=int, default=16384)
     ap.add_argument("--headline-only", action="store_true",
@@ -130,6 +134,11 @@ def run_many_streams(args, result):
     S = args.streams
     log(f"many streams: creating {S} handles")
     gens = prngd.Generator.many(args.seed, S, "philox", w=32)
+    for g in gens:
+        if args.consume != "pair":
+            g.set_consume(args.consume)
+        if args.map != "eq5":
+            g.set_map(args.map)
     out = torch.empty(S * n, dtype=torch.float64, device="cuda:0")
     views = [out[i * n:(i + 1) * n] for i in range(S)]
     plan = prngd.Plan(list(zip(gens, views)))
@@ -162,7 +171,9 @@ def run_many_streams(args, result):
         "wall_ms_per_step": wall / args.steps * 1e3,
         "config": {
             "workload": f"{S} Philox4x32-10 substreams of seed {args.seed}, w=32, "
-                        f"{n} FP64 outputs each, one resident batch per step",
+                        f"{n} FP64 outputs each, one resident batch per step"
+                        + ("" if args.consume == "pair" and args.map == "eq5" else
+                           f", consume={args.consume}, map={args.map}"),
             "streams": S,
             "outputs_per_stream": n,
             "outputs_per_step": outputs,
@@ -185,7 +196,8 @@ def run_single(args, result):
     import torch
     from paper_1401_8230_amd import prngd
     n = args.single_outputs
-    g = prngd.Generator(args.seed, "philox", w=32)
+    g = prngd.Generator(args.seed, "philox", w=32, map=args.map,
+                        consume=None if args.consume == "pair" else args.consume)
     out = torch.empty(n, dtype=torch.float64, device="cuda:0")
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):

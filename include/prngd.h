@@ -92,6 +92,20 @@ typedef enum {
     PRNGD_MAP_ONE_MINUS = 2
 } prngd_map_t;
 
+/* What a rejected x1 consumes:
+ *   PRNGD_CONSUME_PAIR   the whole pair (the default; Section 2's text, "take
+ *                        next pair"); the position counts pairs.
+ *   PRNGD_CONSUME_SINGLE one word, as in Algorithm 1, whose loop redraws
+ *                        only r1; r2 is the word right after the accepted
+ *                        r1, and the position counts words.  Philox and the
+ *                        test generator only (word 2p, 2p+1 = pair p's x1,
+ *                        x2 for ENUMERATE); PRNGD_ERR_UNSUPPORTED otherwise.
+ *                        Each request is produced by one workgroup. */
+typedef enum {
+    PRNGD_CONSUME_PAIR = 0,
+    PRNGD_CONSUME_SINGLE = 1
+} prngd_consume_t;
+
 typedef struct prngd_handle_s *prngd_handle_t;
 typedef struct prngd_plan_s *prngd_plan_t;
 
@@ -198,6 +212,14 @@ prngd_status_t prngd_create_many(uint64_t seed, prngd_generator_t generator,
 prngd_status_t prngd_set_map(prngd_handle_t h, prngd_map_t map);
 prngd_status_t prngd_get_map(prngd_handle_t h, prngd_map_t *map);
 
+/* Choose what a rejection consumes for the handle's later fills
+ * (PRNGD_CONSUME_PAIR after prngd_create).  The position is not converted:
+ * it counts pairs in one mode and words in the other.  Handles of one
+ * batch must share it.  Errors: PRNGD_ERR_INVALID_ARGUMENT (NULL handle,
+ * unknown mode, handle bound to a live plan), PRNGD_ERR_UNSUPPORTED. */
+prngd_status_t prngd_set_consume(prngd_handle_t h, prngd_consume_t consume);
+prngd_status_t prngd_get_consume(prngd_handle_t h, prngd_consume_t *consume);
+
 /* Wait for the handle's outstanding work, then free it.  NULL is a no-op. */
 prngd_status_t prngd_destroy(prngd_handle_t h);
 
@@ -237,7 +259,8 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out,
  * exactly what prngd_fill(reqs[i].h, reqs[i].n, reqs[i].out) would give,
  * bit for bit, and each handle advances as it would.  `reqs` is read
  * before the call returns.  All handles must be distinct and share the
- * generator, k, min, max and map; requests with n = 0 are skipped.
+ * generator, k, min, max, map and consumption; requests with n = 0 are
+ * skipped.
  * Errors: PRNGD_ERR_INVALID_ARGUMENT (count = 0 with reqs NULL, a NULL or
  * repeated handle, mixed configurations, bad out), PRNGD_ERR_HIP.
  */

@@ -1874,6 +1874,252 @@ __global__ __launch_bounds__(256) void spec_wave_repair_kernel(LaunchArgs args)
     }
 }
 
+// ======================================================================
+// Algorithm 1's single-word consumption (Philox family): a rejected r1
+// consumes one word and r2 is the word right after the accepted r1.  The
+// pair boundaries then move by one word at every rejected r1, so a segment
+// is produced by one workgroup, window by window, carrying the automaton
+// state: E (the next word is an r1 candidate) or P (the next word is the
+// r2 of the pending r1, the previous window's last word).  A window of
+// T = 64 NW 16 consecutive words is generated in registers (4 Philox blocks
+// per thread, word q = 4 (j B + tid) + l).  A window with no word equal to
+// a0 or a cannot reject: its roles alternate from the incoming state, and
+// each thread stores its two outputs per block (pairs (4m, 4m+1),
+// (4m+2, 4m+3) from state E; (4m-1, 4m), (4m+1, 4m+2) from state P, the
+// word 4m-1 coming from the previous thread), outputs at or past n dropped.
+// Any other window -- a candidate rejection, the clipped first window -- is
+// walked exactly by wave 0, 64 words at a time, the states before each
+// word obtained by a wave scan of the words' transition maps.
+// ======================================================================
+template <int NW, uint32_t FAM>
+struct SingleWords {
+    static constexpr int B = 64 * NW;
+    static constexpr int J = 4;                     // Philox blocks per thread
+    static constexpr uint32_t T = uint32_t(B) * 4u * J;   // words per window
+
+    // the four words of thread-block (j, tid) of window `win`
+    __device__ __forceinline__ static void words(const LaunchArgs &args, const Segment &seg,
+                                                 uint64_t win, int j, uint32_t u[4])
+    {
+        const uint32_t tid = threadIdx.x;
+        const uint64_t blk = win * (T / 4) + uint32_t(j) * B + tid;
+        if (FAM == FAM_ENUM) {
+            const uint64_t mask = (uint64_t(1) << args.w) - 1;
+            const uint64_t p0 = 2 * blk, p1 = 2 * blk + 1;   // pairs 2b, 2b + 1
+            u[0] = uint32_t((p0 >> args.w) & mask);
+            u[1] = uint32_t(p0 & mask);
+            u[2] = uint32_t((p1 >> args.w) & mask);
+            u[3] = uint32_t(p1 & mask);
+        } else {
+            const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u, seg.stream_id,
+                                           uint32_t(seg.seed), uint32_t(seg.seed >> 32));
+            const uint32_t sh = FAM == FAM_PHILOX32 ? 0u : 32u - args.w;
+            u[0] = r.v0 >> sh;
+            u[1] = r.v1 >> sh;
+            u[2] = r.v2 >> sh;
+            u[3] = r.v3 >> sh;
+        }
+    }
+};
+
+// Transition map of one word on {E = 0, P = 1}, two bits: bit 0 = image of
+// E, bit 1 = image of P.  An accepted r1 candidate moves E to P, a
+// rejected one keeps E; an r2 moves P to E.  Words outside the fill: the
+// identity (bits 0b10).
+__device__ __forceinline__ uint32_t word_map(bool in_fill, bool bad)
+{
+    return !in_fill ? 0x2u : (bad ? 0x0u : 0x1u);
+}
+
+__device__ __forceinline__ uint32_t map_apply(uint32_t m, uint32_t s)
+{
+    return (m >> s) & 1u;
+}
+
+// g after f
+__device__ __forceinline__ uint32_t map_then(uint32_t f, uint32_t g)
+{
+    return map_apply(g, f & 1u) | (map_apply(g, (f >> 1) & 1u) << 1);
+}
+
+struct SingleState {
+    uint64_t running;     // outputs made so far in the segment
+    uint32_t st;          // E = 0, P = 1
+    uint32_t pending;     // the accepted r1 when st = P
+};
+
+template <int NW, uint32_t FAM>
+__global__ __launch_bounds__(64 * NW) void seq_single_kernel(LaunchArgs args)
+{
+    using W = SingleWords<NW, FAM>;
+    constexpr uint32_t T = W::T;
+    constexpr int B = W::B, J = W::J;
+    __shared__ uint32_t s_words[T];
+    __shared__ uint32_t s_last[J][NW];          // word 3 of lane 63, per (j, wave)
+    __shared__ SingleState s_state;
+    __shared__ LaunchState s_launch;
+    __shared__ uint32_t s_next;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const double two_w = FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+    const LaunchState st0 = read_launch_state(args, &s_launch);
+    if (tid == 0)
+        s_next = finish_ticket(args, st0, issue_ticket(args));
+    __syncthreads();
+    for (;;) {
+        const uint32_t si = __builtin_amdgcn_readfirstlane(s_next);
+        if (si == ~0u)
+            break;
+        uint64_t pending_ticket = 0;
+        if (tid == 0)
+            pending_ticket = issue_ticket(args);
+        const Segment seg = load_segment(args.segs, si);
+        const uint32_t par = seg.parity ^ st0.flip;
+        const uint64_t c0 = load_start(seg, par);
+        uint64_t *next_counter = seg.counter + (par ^ 1u);
+        const uint64_t n = seg.n;
+        uint64_t win = c0 / T;
+        uint32_t lo = uint32_t(c0 - win * T);
+        SingleState ss{0, 0, 0};
+        while (ss.running < n) {
+            uint32_t u[J][4];
+            bool bad = false;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                W::words(args, seg, win, j, u[j]);
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    const uint32_t q = 4u * (uint32_t(j) * B + tid) + l;
+                    bad |= q >= lo && (u[j][l] == args.a0 || u[j][l] == args.a);
+                }
+            }
+            const bool exact = __syncthreads_or(bad) || lo != 0;
+            if (!exact) {
+                // outputs 2m and 2m + 1 of the window (m = j B + tid); the
+                // window may hold output n - 1 (the r2 word of output k is
+                // word 2k + 1 from state E, word 2k from state P)
+                double *o = seg.out + ss.running;
+                const uint64_t left = n - ss.running;
+                const bool aligned = ((reinterpret_cast<uintptr_t>(o) & 15u) == 0);
+                const bool whole = left > T / 2;
+                const uint32_t r2_of_0 = ss.st == 0 ? 1u : 0u;
+                if (ss.st == 0) {
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        const uint32_t m = uint32_t(j) * B + tid;
+                        const double za = prngd_map(u[j][0], u[j][1], args, two_w);
+                        const double zb = prngd_map(u[j][2], u[j][3], args, two_w);
+                        if (aligned && (whole || 2 * m + 1 < left)) {
+                            store_two(o + 2 * m, za, zb, args.store_mode);
+                        } else {
+                            if (2 * m < left)
+                                store_one(o + 2 * m, za, args.store_mode);
+                            if (2 * m + 1 < left)
+                                store_one(o + 2 * m + 1, zb, args.store_mode);
+                        }
+                        if (!whole && (2 * m + 1 == left || 2 * m + 2 == left))
+                            *next_counter = win * T + 2 * (left - 1) + r2_of_0 + 1;
+                    }
+                } else {
+                    // word 4m - 1 is word 3 of the previous thread-block
+                    if (lane == 63) {
+#pragma unroll
+                        for (int j = 0; j < J; ++j)
+                            s_last[j][wave] = u[j][3];
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        const uint32_t m = uint32_t(j) * B + tid;
+                        uint32_t prev = uint32_t(__shfl_up(int(u[j][3]), 1u, 64));
+                        if (lane == 0) {
+                            if (wave > 0)
+                                prev = s_last[j][wave - 1];
+                            else if (j > 0)
+                                prev = s_last[j - 1][NW - 1];
+                            else
+                                prev = ss.pending;
+                        }
+                        const double za = prngd_map(prev, u[j][0], args, two_w);
+                        const double zb = prngd_map(u[j][1], u[j][2], args, two_w);
+                        if (aligned && (whole || 2 * m + 1 < left)) {
+                            store_two(o + 2 * m, za, zb, args.store_mode);
+                        } else {
+                            if (2 * m < left)
+                                store_one(o + 2 * m, za, args.store_mode);
+                            if (2 * m + 1 < left)
+                                store_one(o + 2 * m + 1, zb, args.store_mode);
+                        }
+                        if (!whole && (2 * m + 1 == left || 2 * m + 2 == left))
+                            *next_counter = win * T + 2 * (left - 1) + r2_of_0 + 1;
+                    }
+                    // the window's last word is the next pending r1
+                    ss.pending = s_last[J - 1][NW - 1];
+                    __syncthreads();
+                }
+                ss.running += T / 2;
+            } else {
+                // exact walk by wave 0 over the words in order
+#pragma unroll
+                for (int j = 0; j < J; ++j)
+#pragma unroll
+                    for (int l = 0; l < 4; ++l)
+                        s_words[4u * (uint32_t(j) * B + tid) + l] = u[j][l];
+                __syncthreads();
+                if (wave == 0) {
+                    uint32_t state = ss.st, prev_word = ss.pending;
+                    uint64_t running = ss.running;
+                    for (uint32_t base = 0; base < T && running < n; base += 64) {
+                        const uint32_t q = base + lane;
+                        const uint32_t x = s_words[q];
+                        const bool in_fill = q >= lo;
+                        const bool isbad = x == args.a0 || x == args.a;
+                        // inclusive scan of the maps, lane order
+                        uint32_t mp = word_map(in_fill, isbad);
+#pragma unroll
+                        for (int d = 1; d < 64; d <<= 1) {
+                            const uint32_t other = uint32_t(__shfl_up(int(mp), uint32_t(d), 64));
+                            if (lane >= uint32_t(d))
+                                mp = map_then(other, mp);
+                        }
+                        const uint32_t after = map_apply(mp, state);
+                        uint32_t before = uint32_t(__shfl_up(int(after), 1u, 64));
+                        if (lane == 0)
+                            before = state;
+                        const bool r2 = in_fill && before == 1u;
+                        uint32_t x1 = uint32_t(__shfl_up(int(x), 1u, 64));
+                        if (lane == 0)
+                            x1 = prev_word;
+                        const uint64_t ball = __ballot(r2);
+                        const uint64_t pos = running + uint64_t(__popcll(ball & lanemask_lt(lane)));
+                        if (r2 && pos < n) {
+                            store_one(seg.out + pos, prngd_map(x1, x, args, two_w),
+                                      args.store_mode == 1 ? 0u : args.store_mode);
+                            if (pos == n - 1)
+                                *next_counter = win * T + q + 1;
+                        }
+                        running += uint64_t(__popcll(ball));
+                        state = uint32_t(__shfl(int(after), 63, 64));
+                        prev_word = uint32_t(__shfl(int(x), 63, 64));
+                    }
+                    if (lane == 0) {
+                        s_state.running = running;
+                        s_state.st = state;
+                        s_state.pending = prev_word;
+                    }
+                }
+                __syncthreads();
+                ss = s_state;
+                __syncthreads();
+            }
+            ++win;
+            lo = 0;
+        }
+        if (tid == 0)
+            s_next = finish_ticket(args, st0, pending_ticket);
+        __syncthreads();
+    }
+}
+
 // Toggles a resident plan's replay parity after all of a replay's fills.
 __global__ void toggle_flip_kernel(uint32_t *flip)
 {
@@ -2036,6 +2282,18 @@ const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool r
         }
     }
     return nullptr;
+}
+
+// The single-word-consumption kernel for a Philox-family generator (256
+// threads), or null.
+const void *single_kernel_for(uint32_t fam)
+{
+    switch (fam) {
+    case FAM_PHILOX: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_PHILOX>);
+    case FAM_PHILOX32: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_PHILOX32>);
+    case FAM_ENUM: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_ENUM>);
+    default: return nullptr;
+    }
 }
 
 // The kernel for (family, threads per workgroup, pairs per lane), either

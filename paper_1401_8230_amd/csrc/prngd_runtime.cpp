@@ -23,6 +23,7 @@ const void *fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool s
 const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair,
                             bool single, bool hold);
 const void *spec_wave_kernel_for(uint32_t fam, bool repair);
+const void *single_kernel_for(uint32_t fam);
 hipError_t launch_toggle_flip(uint32_t *flip, hipStream_t stream);
 const void *toggle_flip_kernel_ptr();
 hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads,
@@ -76,6 +77,7 @@ struct Config {
     uint64_t D;
     double S;
     uint32_t map;     // prngd_map_t
+    uint32_t consume; // prngd_consume_t
     uint64_t D4;      // Eq. (4) denominator in integer units: (a - a0) 2^w - (b - b0)
     double S4;        // RN(1 / D4)
 };
@@ -190,6 +192,7 @@ prngd_status_t make_config(prngd_generator_t gen, double k, uint64_t min, uint64
     c->D4 = (c->a - c->a0) * (uint64_t(1) << w) - (c->b - c->b0);
     c->S4 = folded_recip(c->D4);
     c->map = PRNGD_MAP_EQ5;
+    c->consume = PRNGD_CONSUME_PAIR;
     c->fam = kernel_family(gen, c->w);
     return PRNGD_OK;
 }
@@ -752,6 +755,16 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     if (!lp->kernel || !lp->seq_kernel)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u threads x %u pairs per lane",
                     lp->threads, lp->tune.pairs_per_lane);
+    if (cfg.consume == PRNGD_CONSUME_SINGLE) {
+        // one workgroup of 256 threads per segment, windows in order
+        const void *k = single_kernel_for(cfg.fam);
+        if (!k)
+            return fail(PRNGD_ERR_UNSUPPORTED, "single-word consumption needs a Philox-family "
+                                               "generator on the GPU");
+        lp->threads = 256;
+        lp->seq_kernel = k;
+        lp->kernel = k;
+    }
     lp->T = uint64_t(lp->threads) * lp->tune.pairs_per_lane;
     for (int hold = 0; hold < 2; ++hold) {
         lp->spec_kernels[hold][0] = spec_kernel_for(cfg.fam, lp->threads,
@@ -811,7 +824,7 @@ void choose_path(LaunchPlan *lp, const Config &c, uint64_t pairs, uint64_t longe
 {
     lp->spec = false;
     lp->wave = false;
-    if (!lp->repair_kernel || lp->tune.path == 1)
+    if (!lp->repair_kernel || lp->tune.path == 1 || c.consume == PRNGD_CONSUME_SINGLE)
         return;
     const double rho = 2.0 / double(c.a - c.a0 + 1);
     const double expected = double(pairs) * rho;
@@ -941,7 +954,7 @@ prngd_status_t make_segment(prngd_handle_t h, uint64_t n, double *out, uint64_t 
 bool same_config(const Config &x, const Config &y)
 {
     return x.fam == y.fam && x.w == y.w && x.a0 == y.a0 && x.a == y.a && x.b0 == y.b0 &&
-           x.b == y.b && x.map == y.map;
+           x.b == y.b && x.map == y.map && x.consume == y.consume;
 }
 
 prngd_status_t current_device(int *dev)
@@ -998,8 +1011,11 @@ prngd_status_t build_batch(DeviceInfo *d, LaunchPlan &lp, const prngd_request_t 
     }
     choose_path(&lp, first->cfg, pairs, max_seg_pairs, false);
     const uint64_t wg = uint64_t(occupancy_of(d, lp.seq_kernel, lp.threads)) * uint64_t(d->cus);
-    // the speculative fill takes every segment tile by tile
-    const uint64_t limit = lp.spec ? 0 : seq_limit(lp.tune, total, wg);
+    // the speculative fill takes every segment tile by tile; single-word
+    // consumption every segment whole
+    const uint64_t limit = first->cfg.consume == PRNGD_CONSUME_SINGLE
+                               ? ~uint64_t(0)
+                               : lp.spec ? 0 : seq_limit(lp.tune, total, wg);
     for (const Segment &s : all) {
         if (s.ntiles <= limit) {
             bp->seq.push_back(s);
@@ -1085,6 +1101,30 @@ prngd_status_t prngd_set_map(prngd_handle_t h, prngd_map_t map)
     if (h->plan)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle is bound to a live plan");
     h->cfg.map = uint32_t(map);
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_set_consume(prngd_handle_t h, prngd_consume_t consume)
+{
+    if (!h)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "NULL handle");
+    if (consume != PRNGD_CONSUME_PAIR && consume != PRNGD_CONSUME_SINGLE)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "unknown consumption mode %d", int(consume));
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    if (h->plan)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle is bound to a live plan");
+    if (consume == PRNGD_CONSUME_SINGLE && !single_kernel_for(h->cfg.fam))
+        return fail(PRNGD_ERR_UNSUPPORTED,
+                    "single-word consumption needs a Philox-family generator on the GPU");
+    h->cfg.consume = uint32_t(consume);
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_get_consume(prngd_handle_t h, prngd_consume_t *consume)
+{
+    if (!h || !consume)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "NULL argument");
+    *consume = static_cast<prngd_consume_t>(h->cfg.consume);
     return PRNGD_OK;
 }
 
@@ -1234,6 +1274,9 @@ prngd_status_t prngd_get_position(prngd_handle_t h, uint32_t *stream_id, uint64_
     return PRNGD_OK;
 }
 
+static prngd_status_t fill_batch_impl(const prngd_request_t *reqs, uint32_t count,
+                                      void *stream);
+
 prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *stream)
 {
     if (!h)
@@ -1243,6 +1286,11 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *strea
     if (n == 0)
         return PRNGD_OK;
     std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    if (h->cfg.consume == PRNGD_CONSUME_SINGLE) {
+        // a one-segment batch: the segment-sequential single-word kernel
+        const prngd_request_t r{h, n, out};
+        return fill_batch_impl(&r, 1, stream);
+    }
     DeviceInfo *d = nullptr;
     prngd_status_t st = device_info(h->device, &d);
     if (st != PRNGD_OK)
@@ -1297,11 +1345,17 @@ prngd_status_t prngd_fill_batch(const prngd_request_t *reqs, uint32_t count, voi
     if (!reqs[0].h)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "request 0 has a NULL handle");
     // one request: the single-fill path (no descriptor upload)
-    if (count == 1) {
+    if (count == 1 && reqs[0].h->cfg.consume == PRNGD_CONSUME_PAIR) {
         if (reqs[0].h->plan)
             return fail(PRNGD_ERR_INVALID_ARGUMENT, "request 0: handle bound to a plan");
         return prngd_fill(reqs[0].h, reqs[0].n, reqs[0].out, stream);
     }
+    return fill_batch_impl(reqs, count, stream);
+}
+
+static prngd_status_t fill_batch_impl(const prngd_request_t *reqs, uint32_t count, void *stream)
+{
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
     const int dev = reqs[0].h->device;
     DeviceInfo *d = nullptr;
     prngd_status_t st = device_info(dev, &d);

@@ -21,6 +21,10 @@ MAP_EQ4 = 1
 MAP_ONE_MINUS = 2
 MAPS = {"eq5": MAP_EQ5, "eq4": MAP_EQ4, "one_minus": MAP_ONE_MINUS}
 
+CONSUME_PAIR = 0
+CONSUME_SINGLE = 1
+CONSUMES = {"pair": CONSUME_PAIR, "single": CONSUME_SINGLE}
+
 GENERATORS = {
     "philox": PHILOX4X32_10,
     "philox4x32_10": PHILOX4X32_10,
@@ -100,6 +104,8 @@ _SIGNATURES = [
       ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
       ctypes.POINTER(ctypes.c_double)]),
     ("prngd_set_map", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("prngd_set_consume", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("prngd_get_consume", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
     ("prngd_get_map", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
     ("prngd_probe_write", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     ("prngd_probe_copy", ctypes.c_int,
@@ -205,7 +211,7 @@ class Generator:
     generator and a seed, positioned at (stream_id, pair counter)."""
 
     def __init__(self, seed, generator="philox", w=32, k=None, min=None, max=None,
-                 _handle=None, map=None):
+                 _handle=None, map=None, consume=None):
         g = _gen(generator)
         if k is None:
             k = 2.0 ** -w
@@ -224,6 +230,19 @@ class Generator:
         self.k = k
         if map is not None:
             self.set_map(map)
+        if consume is not None:
+            self.set_consume(consume)
+
+    def set_consume(self, consume):
+        """"pair" (default) or "single" (Algorithm 1: a rejected r1 consumes
+        one word; the position then counts words)."""
+        c = CONSUMES[consume] if isinstance(consume, str) else int(consume)
+        _check(lib().prngd_set_consume(self.handle, c))
+
+    def get_consume(self):
+        c = ctypes.c_int()
+        _check(lib().prngd_get_consume(self.handle, ctypes.byref(c)))
+        return c.value
 
     def set_map(self, map):
         """Map of later outputs: "eq5" (default), "eq4" or "one_minus"."""

@@ -528,3 +528,74 @@ def test_map_variants_in_batches_and_plans():
             prngd.fill_batch(list(zip(gens[:2], outs[:2])))
         for g in gens:
             g.close()
+
+
+# ------------------------------------ Algorithm 1's single-word consumption
+
+def single_fill(gen, w, seed, counter, n, map="eq5", misalign=False):
+    g = prngd.Generator(seed, gen, w=w, consume="single", map=map)
+    if counter:
+        g.set_position(0, counter)
+    buf, out = guarded(n, misalign)
+    g.fill(out)
+    torch.cuda.synchronize()
+    check_guards(buf, n, misalign)
+    pos = g.get_position()[1]
+    g.close()
+    s = O.PRNGD(OGEN[gen], w, seed=seed, counter=counter, map=OMAP[map],
+                consume=O.CONSUME_SINGLE)
+    expect = s.fill(n)
+    return out.cpu().numpy(), expect, pos, s.counter
+
+
+@pytest.mark.parametrize("gen,w", [("philox", 3), ("philox", 8), ("philox", 12), ("philox", 16),
+                                   ("philox", 24), ("philox", 32), ("enumerate", 8)])
+@pytest.mark.parametrize("counter,n", [(0, 1), (0, 2048), (0, 2049), (1, 5000), (4095, 6001),
+                                       (7, 100003)])
+def test_single_consumption_matches_oracle(gen, w, counter, n):
+    note(f"single {gen} w={w} counter={counter} n={n}")
+    got, expect, pos, ectr = single_fill(gen, w, 17, counter, n)
+    assert_bits_equal(got, expect, f"single {gen} w={w}")
+    assert pos == ectr
+
+
+@pytest.mark.parametrize("w", [8, 32])
+def test_algorithm1_literally_on_the_gpu(w):
+    # Algorithm 1 as printed = single-word consumption + Eq. (4)'s map
+    got, expect, pos, ectr = single_fill("philox", w, 5, 3, 300001, map="eq4", misalign=True)
+    assert_bits_equal(got, expect, f"Algorithm 1 w={w}")
+    assert pos == ectr
+
+
+def test_single_consumption_batches_plans_and_errors():
+    from paper_1401_8230_amd import workloads
+    reqs = workloads.uneven_batch(count=60, lo=1, hi=5e4, rng_seed=21)
+    gens = make_handles(reqs, "philox", 8)
+    for g in gens:
+        g.set_consume("single")
+    outs = [torch.empty(r.n, dtype=torch.float64, device=DEV) for r in reqs]
+    refs = [O.PRNGD(O.GEN_PHILOX, 8, seed=r.seed, stream=r.stream_id, counter=r.counter,
+                    consume=O.CONSUME_SINGLE) for r in reqs]
+    prngd.fill_batch(list(zip(gens, outs)))
+    torch.cuda.synchronize()
+    for i, (r, o) in enumerate(zip(reqs, outs)):
+        assert_bits_equal(o.cpu().numpy(), refs[i].fill(r.n), f"request {i}")
+        assert gens[i].get_position() == (r.stream_id, refs[i].counter)
+    plan = prngd.Plan(list(zip(gens, outs)))
+    for rep in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        for i, (r, o) in enumerate(zip(reqs, outs)):
+            assert_bits_equal(o.cpu().numpy(), refs[i].fill(r.n), f"replay {rep} request {i}")
+    plan.close()
+    # pair and single handles do not mix in one batch
+    gens[0].set_consume("pair")
+    with pytest.raises(prngd.PrngdError):
+        prngd.fill_batch(list(zip(gens[:2], outs[:2])))
+    for g in gens:
+        g.close()
+    m = prngd.Generator(1, "mrg32k3a", w=32)
+    with pytest.raises(prngd.PrngdError) as e:
+        m.set_consume("single")
+    assert e.value.status == prngd.ERR_UNSUPPORTED
+    m.close()
