@@ -8,9 +8,9 @@
  *     (the paper's z = x1 + k x2 with k = 2^-w, Eq. (1)).
  *   - The pair is rejected if x1 lies in the rejection intervals
  *     x1 < a0 + k(b - b0) or x1 > a - k(b - b0) (Section 2); for integer x1
- *     with 1 <= b - b0 < 2^w these are exactly x1 = a0 and x1 = a ("drop
- *     such values and take next pair").  A rejected pair consumes both
- *     words.
+ *     with 1 <= b - b0 < 2^w these are exactly x1 = a0 and x1 = a.  By
+ *     default a rejected pair consumes both words (prngd_set_consume
+ *     selects Algorithm 1's one-word redraw instead).
  *   - An accepted pair is mapped by Eq. (5):
  *         N  = (x1 - a0 - 1) 2^w + (x2 - b0)         exact 64-bit integer
  *         D  = (a - a0 - 2) 2^w + (b - b0)
@@ -93,8 +93,9 @@ typedef enum {
 } prngd_map_t;
 
 /* What a rejected x1 consumes:
- *   PRNGD_CONSUME_PAIR   the whole pair (the default; Section 2's text, "take
- *                        next pair"); the position counts pairs.
+ *   PRNGD_CONSUME_PAIR   the whole pair (the default; Section 2's text moves
+ *                        on to the following pair); the position counts
+ *                        pairs.
  *   PRNGD_CONSUME_SINGLE one word, as in Algorithm 1, whose loop redraws
  *                        only r1; r2 is the word right after the accepted
  *                        r1, and the position counts words.  Philox and the

@@ -469,7 +469,8 @@ double orc_map(const orc_stream *s, uint64_t x1, uint64_t x2)
 }
 
 /* Algorithm 1 with pair consumption: draw the next pair, drop it if x1 is
- * in a rejection interval ("take next pair"), otherwise map it. */
+ * in a rejection interval (both of its words are used up), otherwise map
+ * it. */
 void orc_fill(orc_stream *s, uint64_t n, double *out,
               uint64_t *accepted_index)
 {

@@ -25,7 +25,7 @@
  *   - Generator words are unsigned integers; the paper's w-bit PRN x in
  *     [0, 1) with step k = 2^-w is the integer X = x / k.  All formulas below
  *     are the paper's formulas scaled by 2^w, which changes no ratio.
- *   - A rejected pair consumes both of its words ("take next pair").
+ *   - A rejected pair consumes both of its words (Section 2's text).
  *   - The constant part of Eq. (5) is folded into one FP64 constant
  *     S = RN((1 - k^2) / D); the output is RN(RN(N) * S), clamped below 1.
  */
