@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 BYTES_PER_OUTPUT = 8           # one FP64 written per accepted pair
 KERNEL_SRC = os.path.join(ROOT, "paper_1401_8230_amd", "csrc", "prngd_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_many_streams.json")
+TRAFFIC_FILE_SINGLE = os.path.join(ROOT, "profiles", "traffic_single_stream.json")
 
 
 def log(msg):
@@ -76,11 +77,11 @@ def kernel_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(path=TRAFFIC_FILE):
     """HBM bytes per launch from rocprofv3 counter runs, if they were taken
     on the current kernel source; otherwise None."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -185,7 +186,9 @@ def run_many_streams(args, result):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": measured_traffic(),
+            # the counters were taken on the default form (pair consumption, Eq. (5))
+            "traffic": measured_traffic() if args.consume == "pair" and args.map == "eq5"
+            else None,
         },
     })
 
@@ -214,15 +217,21 @@ def run_single(args, result):
     g.close()
     del out
     achieved_gbs = n * BYTES_PER_OUTPUT / step_s / 1e9
+    # the counters were taken on the default form (pair consumption, Eq. (5))
+    default_form = args.consume == "pair" and args.map == "eq5"
     result.update({
         "value": n / step_s,
         "ms_per_step": step_s * 1e3,
         "wall_ms_per_step": wall / args.steps * 1e3,
         "config": {"workload": f"one Philox4x32-10 stream of seed {args.seed}, w=32, "
-                               f"{n} FP64 outputs per fill", "outputs_per_step": n,
+                               f"{n} FP64 outputs per fill"
+                               + ("" if default_form else
+                                  f", consume={args.consume}, map={args.map}"),
+                   "outputs_per_step": n,
                    "launch": "prngd_fill (speculative fill and its repair pass)"},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(TRAFFIC_FILE_SINGLE) if default_form else None},
     })
 
 

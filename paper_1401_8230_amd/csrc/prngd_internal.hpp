@@ -95,8 +95,10 @@ struct LaunchArgs {
     double nadd;              // added to N: 0, or 2^w - (b - b0) for Eq. (4)
     double osign, ooff;       // output = osign * z + ooff: (1, 0), or (-1, 1) for 1 - z
     SpecControl *spec;        // speculative fill: list control,
-    uint64_t *rejlist;        //   rejection list (total_tiles slots),
+    uint64_t *rejlist;        //   rejection list (total_tiles slots; list_cap
+                              //   slots in the one-word form's candidate list),
     uint32_t *hint;           //   per tile: earlier rejections it assumed
+    uint32_t list_cap;        // slots of rejlist
     uint64_t *hint64;         // wave-granular form: per chunk, written only
                               //   when nonzero, (epoch << 24) | rejections
     uint64_t epoch;           // launch number of the workspace (from 1)

@@ -1945,21 +1945,207 @@ __device__ __forceinline__ uint32_t map_then(uint32_t f, uint32_t g)
 struct SingleState {
     uint64_t running;     // outputs made so far in the segment
     uint32_t st;          // E = 0, P = 1
-    uint32_t pending;     // the accepted r1 when st = P
+    uint32_t pending;     // the accepted r1 when st = P (needed by thread 0 only)
 };
+
+template <int NW, uint32_t FAM>
+struct SingleScratch {
+    uint32_t words[SingleWords<NW, FAM>::T];
+    uint32_t last[SingleWords<NW, FAM>::J][NW];   // word 3 of lane 63, per (j, wave)
+    SingleState state;
+};
+
+// Word q (absolute index) of a single-generator stream.
+template <uint32_t FAM>
+__device__ __forceinline__ uint32_t single_word_at(const LaunchArgs &args, const Segment &seg,
+                                                   uint64_t q)
+{
+    if (FAM == FAM_ENUM) {
+        const uint64_t mask = (uint64_t(1) << args.w) - 1;
+        const uint64_t p = q >> 1;
+        return uint32_t((q & 1u) ? (p & mask) : ((p >> args.w) & mask));
+    }
+    const uint64_t blk = q >> 2;
+    const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u, seg.stream_id,
+                                   uint32_t(seg.seed), uint32_t(seg.seed >> 32));
+    const uint32_t l = uint32_t(q & 3u);
+    const uint32_t v = l == 0 ? r.v0 : l == 1 ? r.v1 : l == 2 ? r.v2 : r.v3;
+    return FAM == FAM_PHILOX32 ? v : v >> (32u - args.w);
+}
+
+// The words of window `win` into u; returns whether this thread holds a
+// word of the fill (q >= lo) equal to a0 or a.
+template <int NW, uint32_t FAM>
+__device__ __forceinline__ bool single_generate(const LaunchArgs &args, const Segment &seg,
+                                                uint64_t win, uint32_t lo,
+                                                uint32_t (&u)[SingleWords<NW, FAM>::J][4])
+{
+    using W = SingleWords<NW, FAM>;
+    const uint32_t tid = threadIdx.x;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < W::J; ++j) {
+        W::words(args, seg, win, j, u[j]);
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const uint32_t q = 4u * (uint32_t(j) * W::B + tid) + l;
+            bad |= q >= lo && (u[j][l] == args.a0 || u[j][l] == args.a);
+        }
+    }
+    return bad;
+}
+
+// Produces the outputs whose r2 word lies in window `win` (words q >= lo of
+// it belong to the fill), from the incoming state ss, which must be the
+// same in every thread; stores only outputs below n, and the thread that
+// stores output n - 1 writes the next word position.  Leaves ss as the
+// state after the window.  `bad` is this thread's flag from
+// single_generate.
+template <int NW, uint32_t FAM>
+__device__ __forceinline__ void single_window_store(const LaunchArgs &args, const Segment &seg,
+                                                    uint64_t win, uint32_t lo,
+                                                    const uint32_t (&u)[SingleWords<NW, FAM>::J][4],
+                                                    bool bad, SingleState &ss,
+                                                    uint64_t *next_counter,
+                                                    SingleScratch<NW, FAM> &sm, double two_w)
+{
+    using W = SingleWords<NW, FAM>;
+    constexpr uint32_t T = W::T;
+    constexpr int B = W::B, J = W::J;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint64_t n = seg.n;
+    const bool exact = __syncthreads_or(bad) || lo != 0;
+    if (ss.running >= n)
+        return;
+    if (!exact) {
+        // outputs 2m and 2m + 1 of the window (m = j B + tid); the window
+        // may hold output n - 1 (the r2 word of output k is word 2k + 1 from
+        // state E, word 2k from state P)
+        double *o = seg.out + ss.running;
+        const uint64_t left = n - ss.running;
+        const bool aligned = ((reinterpret_cast<uintptr_t>(o) & 15u) == 0);
+        const bool whole = left > T / 2;
+        const uint32_t r2_of_0 = ss.st == 0 ? 1u : 0u;
+        if (ss.st == 0) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const uint32_t m = uint32_t(j) * B + tid;
+                const double za = prngd_map(u[j][0], u[j][1], args, two_w);
+                const double zb = prngd_map(u[j][2], u[j][3], args, two_w);
+                if (aligned && (whole || 2 * m + 1 < left)) {
+                    store_two(o + 2 * m, za, zb, args.store_mode);
+                } else {
+                    if (2 * m < left)
+                        store_one(o + 2 * m, za, args.store_mode);
+                    if (2 * m + 1 < left)
+                        store_one(o + 2 * m + 1, zb, args.store_mode);
+                }
+                if (!whole && (2 * m + 1 == left || 2 * m + 2 == left))
+                    *next_counter = win * T + 2 * (left - 1) + r2_of_0 + 1;
+            }
+        } else {
+            // word 4m - 1 is word 3 of the previous thread-block
+            if (lane == 63) {
+#pragma unroll
+                for (int j = 0; j < J; ++j)
+                    sm.last[j][wave] = u[j][3];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const uint32_t m = uint32_t(j) * B + tid;
+                uint32_t prev = uint32_t(__shfl_up(int(u[j][3]), 1u, 64));
+                if (lane == 0) {
+                    if (wave > 0)
+                        prev = sm.last[j][wave - 1];
+                    else if (j > 0)
+                        prev = sm.last[j - 1][NW - 1];
+                    else
+                        prev = ss.pending;
+                }
+                const double za = prngd_map(prev, u[j][0], args, two_w);
+                const double zb = prngd_map(u[j][1], u[j][2], args, two_w);
+                if (aligned && (whole || 2 * m + 1 < left)) {
+                    store_two(o + 2 * m, za, zb, args.store_mode);
+                } else {
+                    if (2 * m < left)
+                        store_one(o + 2 * m, za, args.store_mode);
+                    if (2 * m + 1 < left)
+                        store_one(o + 2 * m + 1, zb, args.store_mode);
+                }
+                if (!whole && (2 * m + 1 == left || 2 * m + 2 == left))
+                    *next_counter = win * T + 2 * (left - 1) + r2_of_0 + 1;
+            }
+            // the window's last word is the next pending r1
+            ss.pending = sm.last[J - 1][NW - 1];
+            __syncthreads();
+        }
+        ss.running += T / 2;
+        return;
+    }
+    // exact walk by wave 0 over the words in order
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+            sm.words[4u * (uint32_t(j) * B + tid) + l] = u[j][l];
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t state = ss.st, prev_word = ss.pending;
+        uint64_t running = ss.running;
+        for (uint32_t base = 0; base < T && running < n; base += 64) {
+            const uint32_t q = base + lane;
+            const uint32_t x = sm.words[q];
+            const bool in_fill = q >= lo;
+            const bool isbad = x == args.a0 || x == args.a;
+            // inclusive scan of the maps, lane order
+            uint32_t mp = word_map(in_fill, isbad);
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t other = uint32_t(__shfl_up(int(mp), uint32_t(d), 64));
+                if (lane >= uint32_t(d))
+                    mp = map_then(other, mp);
+            }
+            const uint32_t after = map_apply(mp, state);
+            uint32_t before = uint32_t(__shfl_up(int(after), 1u, 64));
+            if (lane == 0)
+                before = state;
+            const bool r2 = in_fill && before == 1u;
+            uint32_t x1 = uint32_t(__shfl_up(int(x), 1u, 64));
+            if (lane == 0)
+                x1 = prev_word;
+            const uint64_t ball = __ballot(r2);
+            const uint64_t pos = running + uint64_t(__popcll(ball & lanemask_lt(lane)));
+            if (r2 && pos < n) {
+                store_one(seg.out + pos, prngd_map(x1, x, args, two_w),
+                          args.store_mode == 1 ? 0u : args.store_mode);
+                if (pos == n - 1)
+                    *next_counter = win * T + q + 1;
+            }
+            running += uint64_t(__popcll(ball));
+            state = uint32_t(__shfl(int(after), 63, 64));
+            prev_word = uint32_t(__shfl(int(x), 63, 64));
+        }
+        if (lane == 0) {
+            sm.state.running = running;
+            sm.state.st = state;
+            sm.state.pending = prev_word;
+        }
+    }
+    __syncthreads();
+    ss = sm.state;
+    __syncthreads();
+}
 
 template <int NW, uint32_t FAM>
 __global__ __launch_bounds__(64 * NW) void seq_single_kernel(LaunchArgs args)
 {
     using W = SingleWords<NW, FAM>;
     constexpr uint32_t T = W::T;
-    constexpr int B = W::B, J = W::J;
-    __shared__ uint32_t s_words[T];
-    __shared__ uint32_t s_last[J][NW];          // word 3 of lane 63, per (j, wave)
-    __shared__ SingleState s_state;
+    __shared__ SingleScratch<NW, FAM> sm;
     __shared__ LaunchState s_launch;
     __shared__ uint32_t s_next;
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t tid = threadIdx.x;
     const double two_w = FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
     const LaunchState st0 = read_launch_state(args, &s_launch);
     if (tid == 0)
@@ -1976,147 +2162,370 @@ __global__ __launch_bounds__(64 * NW) void seq_single_kernel(LaunchArgs args)
         const uint32_t par = seg.parity ^ st0.flip;
         const uint64_t c0 = load_start(seg, par);
         uint64_t *next_counter = seg.counter + (par ^ 1u);
-        const uint64_t n = seg.n;
         uint64_t win = c0 / T;
         uint32_t lo = uint32_t(c0 - win * T);
         SingleState ss{0, 0, 0};
-        while (ss.running < n) {
-            uint32_t u[J][4];
-            bool bad = false;
-#pragma unroll
-            for (int j = 0; j < J; ++j) {
-                W::words(args, seg, win, j, u[j]);
-#pragma unroll
-                for (int l = 0; l < 4; ++l) {
-                    const uint32_t q = 4u * (uint32_t(j) * B + tid) + l;
-                    bad |= q >= lo && (u[j][l] == args.a0 || u[j][l] == args.a);
-                }
-            }
-            const bool exact = __syncthreads_or(bad) || lo != 0;
-            if (!exact) {
-                // outputs 2m and 2m + 1 of the window (m = j B + tid); the
-                // window may hold output n - 1 (the r2 word of output k is
-                // word 2k + 1 from state E, word 2k from state P)
-                double *o = seg.out + ss.running;
-                const uint64_t left = n - ss.running;
-                const bool aligned = ((reinterpret_cast<uintptr_t>(o) & 15u) == 0);
-                const bool whole = left > T / 2;
-                const uint32_t r2_of_0 = ss.st == 0 ? 1u : 0u;
-                if (ss.st == 0) {
-#pragma unroll
-                    for (int j = 0; j < J; ++j) {
-                        const uint32_t m = uint32_t(j) * B + tid;
-                        const double za = prngd_map(u[j][0], u[j][1], args, two_w);
-                        const double zb = prngd_map(u[j][2], u[j][3], args, two_w);
-                        if (aligned && (whole || 2 * m + 1 < left)) {
-                            store_two(o + 2 * m, za, zb, args.store_mode);
-                        } else {
-                            if (2 * m < left)
-                                store_one(o + 2 * m, za, args.store_mode);
-                            if (2 * m + 1 < left)
-                                store_one(o + 2 * m + 1, zb, args.store_mode);
-                        }
-                        if (!whole && (2 * m + 1 == left || 2 * m + 2 == left))
-                            *next_counter = win * T + 2 * (left - 1) + r2_of_0 + 1;
-                    }
-                } else {
-                    // word 4m - 1 is word 3 of the previous thread-block
-                    if (lane == 63) {
-#pragma unroll
-                        for (int j = 0; j < J; ++j)
-                            s_last[j][wave] = u[j][3];
-                    }
-                    __syncthreads();
-#pragma unroll
-                    for (int j = 0; j < J; ++j) {
-                        const uint32_t m = uint32_t(j) * B + tid;
-                        uint32_t prev = uint32_t(__shfl_up(int(u[j][3]), 1u, 64));
-                        if (lane == 0) {
-                            if (wave > 0)
-                                prev = s_last[j][wave - 1];
-                            else if (j > 0)
-                                prev = s_last[j - 1][NW - 1];
-                            else
-                                prev = ss.pending;
-                        }
-                        const double za = prngd_map(prev, u[j][0], args, two_w);
-                        const double zb = prngd_map(u[j][1], u[j][2], args, two_w);
-                        if (aligned && (whole || 2 * m + 1 < left)) {
-                            store_two(o + 2 * m, za, zb, args.store_mode);
-                        } else {
-                            if (2 * m < left)
-                                store_one(o + 2 * m, za, args.store_mode);
-                            if (2 * m + 1 < left)
-                                store_one(o + 2 * m + 1, zb, args.store_mode);
-                        }
-                        if (!whole && (2 * m + 1 == left || 2 * m + 2 == left))
-                            *next_counter = win * T + 2 * (left - 1) + r2_of_0 + 1;
-                    }
-                    // the window's last word is the next pending r1
-                    ss.pending = s_last[J - 1][NW - 1];
-                    __syncthreads();
-                }
-                ss.running += T / 2;
-            } else {
-                // exact walk by wave 0 over the words in order
-#pragma unroll
-                for (int j = 0; j < J; ++j)
-#pragma unroll
-                    for (int l = 0; l < 4; ++l)
-                        s_words[4u * (uint32_t(j) * B + tid) + l] = u[j][l];
-                __syncthreads();
-                if (wave == 0) {
-                    uint32_t state = ss.st, prev_word = ss.pending;
-                    uint64_t running = ss.running;
-                    for (uint32_t base = 0; base < T && running < n; base += 64) {
-                        const uint32_t q = base + lane;
-                        const uint32_t x = s_words[q];
-                        const bool in_fill = q >= lo;
-                        const bool isbad = x == args.a0 || x == args.a;
-                        // inclusive scan of the maps, lane order
-                        uint32_t mp = word_map(in_fill, isbad);
-#pragma unroll
-                        for (int d = 1; d < 64; d <<= 1) {
-                            const uint32_t other = uint32_t(__shfl_up(int(mp), uint32_t(d), 64));
-                            if (lane >= uint32_t(d))
-                                mp = map_then(other, mp);
-                        }
-                        const uint32_t after = map_apply(mp, state);
-                        uint32_t before = uint32_t(__shfl_up(int(after), 1u, 64));
-                        if (lane == 0)
-                            before = state;
-                        const bool r2 = in_fill && before == 1u;
-                        uint32_t x1 = uint32_t(__shfl_up(int(x), 1u, 64));
-                        if (lane == 0)
-                            x1 = prev_word;
-                        const uint64_t ball = __ballot(r2);
-                        const uint64_t pos = running + uint64_t(__popcll(ball & lanemask_lt(lane)));
-                        if (r2 && pos < n) {
-                            store_one(seg.out + pos, prngd_map(x1, x, args, two_w),
-                                      args.store_mode == 1 ? 0u : args.store_mode);
-                            if (pos == n - 1)
-                                *next_counter = win * T + q + 1;
-                        }
-                        running += uint64_t(__popcll(ball));
-                        state = uint32_t(__shfl(int(after), 63, 64));
-                        prev_word = uint32_t(__shfl(int(x), 63, 64));
-                    }
-                    if (lane == 0) {
-                        s_state.running = running;
-                        s_state.st = state;
-                        s_state.pending = prev_word;
-                    }
-                }
-                __syncthreads();
-                ss = s_state;
-                __syncthreads();
-            }
+        while (ss.running < seg.n) {
+            uint32_t u[W::J][4];
+            const bool bad = single_generate<NW, FAM>(args, seg, win, lo, u);
+            single_window_store<NW, FAM>(args, seg, win, lo, u, bad, ss, next_counter, sm, two_w);
             ++win;
             lo = 0;
         }
         if (tid == 0)
             s_next = finish_ticket(args, st0, pending_ticket);
         __syncthreads();
+    }
+}
+
+// ======================================================================
+// One-word consumption of one long segment across workgroups.  Word r of
+// the fill (r = 0 at the start position) is a *candidate* when it equals a0
+// or a.  After any candidate the next word is an r1 candidate (a rejected
+// r1 keeps state E; an r2, even one equal to a0 or a, returns to E), so the
+// i-th candidate is a rejected r1 exactly when r_i - r_{i-1} is odd
+// (r_{-1} = -1), and with h the rejected r1 before word r, the state at r is
+// E iff r - h is even and floor((r - h) / 2) outputs are complete.  Every
+// quantity a window needs thus follows from the candidates before it.
+//
+// spec_words_kernel: a one-shot grid, tile t = window w0 + t of T words.
+// The tile generates its words, appends each of its candidates to the
+// launch's list ((t + 1) << 32 | word in window), then reads the list and
+// takes the rejected r1 among the earlier tiles' candidates it can see (its
+// hint h), and produces its window from state (r0 - h) mod 2 at output
+// floor((r0 - h) / 2).  Dropping candidates from a set never raises its
+// count of rejected r1 (two gaps merge into one whose parity is their sum's),
+// so a hint never exceeds the truth and a tile never writes below its true
+// offset.  The segment's last tile produces every further window itself.
+//
+// spec_words_repair_kernel, in stream order: from the complete list it
+// computes every tile's true h and produces again the tiles that (a) took a
+// smaller h, (b) may hold values a wrong earlier tile wrote past its true
+// end (a tile with hint h' < h and c candidates writes at most
+// (h - h' + c + 2) / 2 outputs past it), or (c) hold output n - 1, or are the
+// last tile, behind a wrong one.  With more candidates than it caches, one
+// workgroup produces the segment again from its first dirty window on.
+// ======================================================================
+__device__ __forceinline__ void publish_word(const LaunchArgs &args, uint32_t t, uint32_t q)
+{
+    const uint32_t slot =
+        __hip_atomic_fetch_add(&args.spec->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (slot < args.list_cap)
+        __hip_atomic_store(&args.rejlist[slot], (uint64_t(t) + 1u) << 32 | q, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    else
+        __hip_atomic_fetch_or(args.error, kErrSpecList, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// The hint of tile t: rejected r1 among the candidates of tiles before t
+// visible in the list now (at most kHintEntries list slots are read).
+// Every thread takes part; thread 0 records the hint for the repair pass.
+template <uint32_t T>
+__device__ __forceinline__ uint32_t read_word_hint(const LaunchArgs &args, uint32_t t, uint32_t lo0,
+                                                   int64_t *s_vis, uint32_t *s_nv, uint32_t *s_h)
+{
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    if (tid < 64) {
+        uint32_t nv = 0;
+        const uint32_t cnt = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (t > 0 && cnt != 0) {
+            const uint32_t lim = cnt < kHintEntries ? cnt : kHintEntries;
+            for (uint32_t base = 0; base < lim; base += 64) {
+                const uint32_t i = base + lane;
+                uint64_t e = 0;
+                if (i < lim)
+                    e = __hip_atomic_load(&args.rejlist[i], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t et = uint32_t(e >> 32);        // tile + 1; 0 = not written yet
+                const bool vis = et != 0 && et <= t;
+                const uint64_t m = __ballot(vis);
+                if (vis)
+                    s_vis[nv + uint32_t(__popcll(m & lanemask_lt(lane)))] =
+                        int64_t(uint64_t(et - 1u) * T + uint32_t(e & 0xFFFFFFFFu)) - int64_t(lo0);
+                nv += uint32_t(__popcll(m));
+            }
+        }
+        if (lane == 0) {
+            *s_nv = nv;
+            *s_h = 0;
+        }
+    }
+    __syncthreads();
+    const uint32_t nv = __builtin_amdgcn_readfirstlane(*s_nv);
+    if (nv != 0) {
+        uint32_t skips = 0;
+        for (uint32_t i = tid; i < nv; i += blockDim.x) {
+            const int64_t r = s_vis[i];
+            int64_t pred = -1;
+            for (uint32_t k = 0; k < nv; ++k) {
+                const int64_t rk = s_vis[k];
+                if (rk < r && rk > pred)
+                    pred = rk;
+            }
+            skips += uint32_t((r - pred) & 1);
+        }
+        if (skips)
+            atomicAdd(s_h, skips);
+        __syncthreads();
+    }
+    const uint32_t h = __builtin_amdgcn_readfirstlane(*s_h);
+    if (tid == 0)
+        args.hint[t] = h;
+    return h;
+}
+
+// Incoming state of tile t >= 1 of a fill that starts lo0 words into its
+// first window, with h rejected r1 before it.
+template <uint32_t FAM, uint32_t T>
+__device__ __forceinline__ SingleState single_entry(const LaunchArgs &args, const Segment &seg,
+                                                    uint64_t win, uint32_t t, uint32_t lo0,
+                                                    uint32_t h)
+{
+    const uint64_t done = uint64_t(t) * T - lo0 - h;   // words used by complete or pending outputs
+    SingleState ss;
+    ss.running = done >> 1;
+    ss.st = uint32_t(done & 1u);
+    ss.pending = 0;
+    if (ss.st && threadIdx.x == 0)
+        ss.pending = single_word_at<FAM>(args, seg, win * T - 1u);
+    return ss;
+}
+
+template <int NW, uint32_t FAM>
+__global__ __launch_bounds__(64 * NW) void spec_words_kernel(LaunchArgs args)
+{
+    using W = SingleWords<NW, FAM>;
+    constexpr uint32_t T = W::T;
+    constexpr int B = W::B, J = W::J;
+    __shared__ SingleScratch<NW, FAM> sm;
+    __shared__ int64_t s_vis[kHintEntries];
+    __shared__ uint32_t s_nv, s_h;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t t = blockIdx.x;
+    const double two_w = FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+    const TileStart ts = tile_start<true>(args, t);
+    const Segment &seg = ts.seg;
+    uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
+    const uint64_t w0 = ts.c0 / T;
+    const uint32_t lo0 = uint32_t(ts.c0 - w0 * T);
+    const uint64_t win = w0 + t;
+    const uint32_t lo = t == 0 ? lo0 : 0u;
+    uint32_t u[J][4];
+    const bool bad = single_generate<NW, FAM>(args, seg, win, lo, u);
+    if (bad) {
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const uint32_t q = 4u * (uint32_t(j) * B + tid) + l;
+                if (q >= lo && (u[j][l] == args.a0 || u[j][l] == args.a))
+                    publish_word(args, t, q);
+            }
+    }
+    const uint32_t h = read_word_hint<T>(args, t, lo0, s_vis, &s_nv, &s_h);
+    SingleState ss{0, 0, 0};
+    if (t > 0)
+        ss = single_entry<FAM, T>(args, seg, win, t, lo0, h);
+    single_window_store<NW, FAM>(args, seg, win, lo, u, bad, ss, next_counter, sm, two_w);
+    if (t == seg.ntiles - 1) {
+        for (uint64_t w2 = win + 1; ss.running < seg.n; ++w2) {
+            uint32_t v[J][4];
+            const bool b2 = single_generate<NW, FAM>(args, seg, w2, 0u, v);
+            single_window_store<NW, FAM>(args, seg, w2, 0u, v, b2, ss, next_counter, sm, two_w);
+        }
+    }
+}
+
+// What the repair knows of tile g from the complete candidate list.
+struct WordFacts {
+    uint32_t h;           // rejected r1 before the tile
+    uint32_t c;           // candidates in the tile
+    uint32_t k;           // rejected r1 in the tile
+    bool after_dirty;     // some earlier tile has a candidate
+};
+
+__device__ __forceinline__ WordFacts word_facts(const uint32_t *s_t, const uint8_t *s_skip,
+                                                uint32_t cnt, uint32_t g)
+{
+    WordFacts f{0u, 0u, 0u, false};
+    for (uint32_t i = 0; i < cnt; ++i) {
+        const uint32_t ti = s_t[i];
+        if (ti < g) {
+            f.h += s_skip[i];
+            f.after_dirty = true;
+        } else if (ti == g) {
+            f.c += 1u;
+            f.k += s_skip[i];
+        }
+    }
+    return f;
+}
+
+template <uint32_t T>
+__device__ __forceinline__ bool words_need_redo(const LaunchArgs &args, const uint32_t *s_t,
+                                                const uint8_t *s_skip, uint32_t cnt,
+                                                const Segment &seg, uint32_t lo0, uint32_t g,
+                                                uint32_t *true_h)
+{
+    const WordFacts f = word_facts(s_t, s_skip, cnt, g);
+    if (!f.after_dirty)
+        return false;                 // up to the first dirty tile all is exact (g >= 1 here)
+    const uint64_t r0 = uint64_t(g) * T - lo0;
+    const uint64_t off = (r0 - f.h) >> 1;
+    if (off >= seg.n)
+        return false;                 // every output of the tile lies past n
+    *true_h = f.h;
+    if (args.hint[g] != f.h)
+        return true;                  // (a)
+    const uint64_t off_end = (r0 + T - f.h - f.k) >> 1;
+    if (off_end >= seg.n || g == seg.ntiles - 1)
+        return true;                  // (c)
+    // (b) walk back over earlier tiles while their stale writes could reach
+    uint64_t gap = 0;
+    const uint64_t bound = (uint64_t(cnt) + 2u) / 2u;
+    for (uint32_t v = g - 1;; --v) {
+        const WordFacts fv = word_facts(s_t, s_skip, cnt, v);
+        const uint32_t hv = args.hint[v];
+        const uint64_t reach = hv == fv.h ? 0u : (uint64_t(fv.h - hv) + fv.c + 2u) / 2u;
+        if (reach > gap)
+            return true;
+        if (!fv.after_dirty)
+            break;                    // v and all before it wrote exactly (v >= 1 past here)
+        const uint64_t rv = uint64_t(v) * T - lo0;
+        gap += ((rv + T - fv.h - fv.k) >> 1) - ((rv - fv.h) >> 1);
+        if (gap >= bound)
+            break;
+    }
+    return false;
+}
+
+template <int NW, uint32_t FAM>
+__global__ __launch_bounds__(64 * NW) void spec_words_repair_kernel(LaunchArgs args)
+{
+    using W = SingleWords<NW, FAM>;
+    constexpr uint32_t T = W::T;
+    constexpr int B = W::B, J = W::J;
+    __shared__ SingleScratch<NW, FAM> sm;
+    __shared__ int64_t s_r[kRepairCache];
+    __shared__ uint32_t s_t[kRepairCache];
+    __shared__ uint8_t s_skip[kRepairCache];
+    __shared__ uint32_t s_queue[B];
+    __shared__ uint32_t s_qh[B];
+    __shared__ uint32_t s_nq, s_first;
+    __shared__ bool s_last;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t cnt0 = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(&args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (cnt0 == 0)
+        return;
+    const uint32_t cnt = cnt0 < args.list_cap ? cnt0 : args.list_cap;
+    const double two_w = FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+    const Segment seg = args.seg0;
+    const uint32_t par = (seg.parity ^ read_flip(args)) & 1u;
+    const uint64_t c0 = load_start(seg, par);
+    uint64_t *next_counter = seg.counter + (par ^ 1u);
+    const uint64_t w0 = c0 / T;
+    const uint32_t lo0 = uint32_t(c0 - w0 * T);
+    if (cnt <= kRepairCache) {
+        for (uint32_t i = tid; i < cnt; i += B) {
+            const uint64_t e = __hip_atomic_load(&args.rejlist[i], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t ti = uint32_t(e >> 32) - 1u;
+            s_t[i] = ti;
+            s_r[i] = int64_t(uint64_t(ti) * T + uint32_t(e & 0xFFFFFFFFu)) - int64_t(lo0);
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < cnt; i += B) {
+            const int64_t r = s_r[i];
+            int64_t pred = -1;
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const int64_t rk = s_r[k];
+                if (rk < r && rk > pred)
+                    pred = rk;
+            }
+            s_skip[i] = uint8_t((r - pred) & 1);
+        }
+        __syncthreads();
+        // pass p: thread tid checks tile (p B + tid) G + blockIdx, so that a
+        // run of consecutive tiles to redo is spread over all workgroups
+        const uint64_t G = gridDim.x;
+        for (uint64_t p = 0; p * B * G + blockIdx.x < seg.ntiles; ++p) {
+            if (tid == 0)
+                s_nq = 0;
+            __syncthreads();
+            const uint64_t g64 = (p * B + tid) * G + blockIdx.x;
+            uint32_t h = 0;
+            if (g64 < seg.ntiles && g64 > 0 &&
+                words_need_redo<T>(args, s_t, s_skip, cnt, seg, lo0, uint32_t(g64), &h)) {
+                const uint32_t k = atomicAdd(&s_nq, 1u);
+                s_queue[k] = uint32_t(g64);
+                s_qh[k] = h;
+            }
+            __syncthreads();
+            const uint32_t nq = __builtin_amdgcn_readfirstlane(s_nq);
+            for (uint32_t k = 0; k < nq; ++k) {
+                const uint32_t g = __builtin_amdgcn_readfirstlane(s_queue[k]);
+                const uint32_t hg = __builtin_amdgcn_readfirstlane(s_qh[k]);
+                const uint64_t win = w0 + g;
+                SingleState ss = single_entry<FAM, T>(args, seg, win, g, lo0, hg);
+                uint32_t u[J][4];
+                const bool bad = single_generate<NW, FAM>(args, seg, win, 0u, u);
+                single_window_store<NW, FAM>(args, seg, win, 0u, u, bad, ss, next_counter, sm,
+                                             two_w);
+                if (g == seg.ntiles - 1) {
+                    for (uint64_t w2 = win + 1; ss.running < seg.n; ++w2) {
+                        const bool b2 = single_generate<NW, FAM>(args, seg, w2, 0u, u);
+                        single_window_store<NW, FAM>(args, seg, w2, 0u, u, b2, ss, next_counter,
+                                                     sm, two_w);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    } else if (blockIdx.x == 0) {
+        // too many candidates to cache: produce the segment again, in
+        // order, from the first window that holds one
+        if (tid == 0)
+            s_first = ~0u;
+        __syncthreads();
+        uint32_t first = ~0u;
+        for (uint32_t i = tid; i < cnt; i += B) {
+            const uint64_t e = __hip_atomic_load(&args.rejlist[i], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t ti = uint32_t(e >> 32) - 1u;
+            first = ti < first ? ti : first;
+        }
+        atomicMin(&s_first, first);
+        __syncthreads();
+        const uint32_t f = __builtin_amdgcn_readfirstlane(s_first);
+        uint64_t win = w0 + f;
+        uint32_t lo = f == 0 ? lo0 : 0u;
+        SingleState ss{0, 0, 0};
+        if (f > 0)
+            ss = single_entry<FAM, T>(args, seg, win, f, lo0, 0u);
+        while (ss.running < seg.n) {
+            uint32_t u[J][4];
+            const bool bad = single_generate<NW, FAM>(args, seg, win, lo, u);
+            single_window_store<NW, FAM>(args, seg, win, lo, u, bad, ss, next_counter, sm, two_w);
+            ++win;
+            lo = 0;
+        }
+    }
+    // the last workgroup out clears the list for the next launch
+    __syncthreads();
+    if (tid == 0)
+        s_last = __hip_atomic_fetch_add(&args.spec->done, 1u, __ATOMIC_ACQ_REL,
+                                        __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    __syncthreads();
+    if (s_last) {
+        for (uint32_t i = tid; i < cnt; i += B)
+            args.rejlist[i] = 0;
+        if (tid == 0) {
+            __hip_atomic_store(&args.spec->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&args.spec->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -2292,6 +2701,24 @@ const void *single_kernel_for(uint32_t fam)
     case FAM_PHILOX: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_PHILOX>);
     case FAM_PHILOX32: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_PHILOX32>);
     case FAM_ENUM: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_ENUM>);
+    default: return nullptr;
+    }
+}
+
+// The one-word-consumption speculative fill of one segment across
+// workgroups (256 threads), or its repair pass; null for other families.
+const void *spec_words_kernel_for(uint32_t fam, bool repair)
+{
+    switch (fam) {
+    case FAM_PHILOX:
+        return repair ? reinterpret_cast<const void *>(&spec_words_repair_kernel<4, FAM_PHILOX>)
+                      : reinterpret_cast<const void *>(&spec_words_kernel<4, FAM_PHILOX>);
+    case FAM_PHILOX32:
+        return repair ? reinterpret_cast<const void *>(&spec_words_repair_kernel<4, FAM_PHILOX32>)
+                      : reinterpret_cast<const void *>(&spec_words_kernel<4, FAM_PHILOX32>);
+    case FAM_ENUM:
+        return repair ? reinterpret_cast<const void *>(&spec_words_repair_kernel<4, FAM_ENUM>)
+                      : reinterpret_cast<const void *>(&spec_words_kernel<4, FAM_ENUM>);
     default: return nullptr;
     }
 }

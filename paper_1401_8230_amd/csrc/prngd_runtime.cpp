@@ -24,6 +24,7 @@ const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool r
                             bool single, bool hold);
 const void *spec_wave_kernel_for(uint32_t fam, bool repair);
 const void *single_kernel_for(uint32_t fam);
+const void *spec_words_kernel_for(uint32_t fam, bool repair);
 hipError_t launch_toggle_flip(uint32_t *flip, hipStream_t stream);
 const void *toggle_flip_kernel_ptr();
 hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads,
@@ -738,6 +739,8 @@ struct LaunchPlan {
     const void *repair_kernel;
     const void *wave_kernel;  // wave-granular single-segment form, if any
     const void *wave_repair_kernel;
+    const void *words_kernel;         // one-word consumption across workgroups
+    const void *words_repair_kernel;
     bool wave;                // single fills take the wave-granular form
     uint32_t *zero_word;
     bool spec;
@@ -778,6 +781,8 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     lp->spec_single_kernel = nullptr;
     lp->wave_kernel = spec_wave_kernel_for(cfg.fam, false);
     lp->wave_repair_kernel = spec_wave_kernel_for(cfg.fam, true);
+    lp->words_kernel = spec_words_kernel_for(cfg.fam, false);
+    lp->words_repair_kernel = spec_words_kernel_for(cfg.fam, true);
     lp->wave = false;
     lp->zero_word = d->zero_word;
     lp->spec = false;                  // decided per launch by choose_path
@@ -881,12 +886,57 @@ prngd_status_t launch_spec(DeviceInfo *d, const LaunchPlan &lp, Workspace *ws, L
     args.spec = ws->spec;
     args.rejlist = ws->rejlist;
     args.hint = ws->hint;
+    args.list_cap = uint32_t(std::min<size_t>(ws->spec_cap, 0xFFFFFFFFu));
     args.total_tiles = uint32_t(tiles);
     if (!args.flip)
         args.flip = lp.zero_word;
     HIP_TRY(launch_fill(args.segs ? lp.spec_kernel : lp.spec_single_kernel, uint32_t(tiles),
                         lp.threads, args, s));
     HIP_TRY(launch_fill(lp.repair_kernel, repair_grid(d, lp, tiles), lp.threads, args, s));
+    return PRNGD_OK;
+}
+
+// Words per window of the one-word-consumption kernels.
+constexpr uint64_t kWordsT = 4096;
+
+// Whether a one-word-consumption fill of n outputs takes the speculative
+// form across workgroups: automatically from 2^15 outputs while the fill
+// expects at most 64 words equal to a0 or a (about 4 n / (a - a0 + 1)),
+// when a speculative path is forced while it expects at most 256; the
+// segment-sequential kernel otherwise.
+bool words_spec_wanted(const LaunchPlan &lp, const Config &c, uint64_t n)
+{
+    if (!lp.words_kernel || !lp.words_repair_kernel || lp.tune.path == 1)
+        return false;
+    const double expected = 4.0 * double(n) / double(c.a - c.a0 + 1);
+    if (lp.tune.path >= 2)
+        return expected <= 256.0;
+    return n >= (uint64_t(1) << 15) && expected <= 64.0;
+}
+
+// Enqueue the one-word-consumption speculative fill of args.seg0 and its
+// repair: one workgroup per window of kWordsT words, one more window than
+// the planned words need wherever the start lies in its window.
+prngd_status_t launch_spec_words(DeviceInfo *d, const LaunchPlan &lp, Workspace *ws,
+                                 LaunchArgs args, hipStream_t s)
+{
+    const uint64_t words = 2 * args.seg0.planned;
+    const uint64_t tiles = (words + kWordsT - 1) / kWordsT + 1;
+    if (tiles > kMaxTiles)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "fill too large for the one-word form");
+    prngd_status_t st;
+    if ((st = ws_prepare_spec(ws, tiles, s)) != PRNGD_OK)
+        return st;
+    args.spec = ws->spec;
+    args.rejlist = ws->rejlist;
+    args.hint = ws->hint;
+    args.list_cap = uint32_t(std::min<size_t>(ws->spec_cap, 0xFFFFFFFFu));
+    args.total_tiles = uint32_t(tiles);
+    args.seg0.ntiles = uint32_t(tiles);
+    if (!args.flip)
+        args.flip = lp.zero_word;
+    HIP_TRY(launch_fill(lp.words_kernel, uint32_t(tiles), 256, args, s));
+    HIP_TRY(launch_fill(lp.words_repair_kernel, repair_grid(d, lp, tiles), 256, args, s));
     return PRNGD_OK;
 }
 
@@ -1286,24 +1336,25 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *strea
     if (n == 0)
         return PRNGD_OK;
     std::lock_guard<std::recursive_mutex> lock(g_mutex);
-    if (h->cfg.consume == PRNGD_CONSUME_SINGLE) {
-        // a one-segment batch: the segment-sequential single-word kernel
-        const prngd_request_t r{h, n, out};
-        return fill_batch_impl(&r, 1, stream);
-    }
     DeviceInfo *d = nullptr;
     prngd_status_t st = device_info(h->device, &d);
     if (st != PRNGD_OK)
         return st;
     if ((st = check_device_errors(d)) != PRNGD_OK)
         return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    Workspace *ws = nullptr;
-    if ((st = stream_workspace(h->device, s, &ws)) != PRNGD_OK)
-        return st;
     LaunchArgs args{};
     LaunchPlan lp{};
     if ((st = plan_launch(d, h->cfg, &args, &lp)) != PRNGD_OK)
+        return st;
+    const bool words = h->cfg.consume == PRNGD_CONSUME_SINGLE;
+    if (words && !words_spec_wanted(lp, h->cfg, n)) {
+        // a one-segment batch: the segment-sequential one-word kernel
+        const prngd_request_t r{h, n, out};
+        return fill_batch_impl(&r, 1, stream);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    if ((st = stream_workspace(h->device, s, &ws)) != PRNGD_OK)
         return st;
     uint64_t ntiles = 0;
     if ((st = make_segment(h, n, out, lp.T, lp.tune.slack_mode, 0, &args.seg0, &ntiles)) !=
@@ -1315,7 +1366,10 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *strea
     choose_path(&lp, h->cfg, args.seg0.planned, args.seg0.planned, true);
     if ((st = order_after(h, s)) != PRNGD_OK)
         return st;
-    if (lp.spec && lp.wave) {
+    if (words) {
+        if ((st = launch_spec_words(d, lp, ws, args, s)) != PRNGD_OK)
+            return st;
+    } else if (lp.spec && lp.wave) {
         if ((st = launch_spec_wave(d, lp, ws, args, s)) != PRNGD_OK)
             return st;
     } else if (lp.spec) {

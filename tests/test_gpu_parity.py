@@ -599,3 +599,42 @@ def test_single_consumption_batches_plans_and_errors():
         m.set_consume("single")
     assert e.value.status == prngd.ERR_UNSUPPORTED
     m.close()
+
+
+# One-word consumption of one long request across workgroups: the speculative
+# form (forced, so that small w puts hundreds of candidates into one launch)
+# and the automatic choice; the repair's cached rules and, with more
+# candidates than it caches (the test generator from position 0 at w = 16,
+# whose x1 words are 0 for 2^16 pairs in a row), its in-order re-production.
+@pytest.mark.parametrize("gen,w,n,forced", [
+    ("philox", 8, 16000, True), ("philox", 12, 250001, True), ("philox", 16, 2**20 + 3, True),
+    ("philox", 16, 2**20 + 3, False), ("philox", 32, 2**22 + 1, False),
+    ("enumerate", 16, 2**16, False), ("enumerate", 16, 2**17 + 9, True)])
+@pytest.mark.parametrize("counter", [0, 1, 4095, 3 * 4096 + 2, 2**40 + 7])
+def test_single_consumption_across_workgroups(gen, w, n, forced, counter):
+    if gen == "enumerate" and counter == 2**40 + 7:
+        counter = 2**33 + 5          # inside the test generator's period
+    note(f"single across workgroups {gen} w={w} n={n} forced={forced} counter={counter}")
+    if forced:
+        prngd.set_tuning(gen, w, path=3)
+    got, expect, pos, ectr = single_fill(gen, w, 23, counter, n, misalign=counter == 1)
+    assert_bits_equal(got, expect, f"single {gen} w={w} n={n} counter={counter}")
+    assert pos == ectr
+
+
+@pytest.mark.parametrize("w,forced", [(10, True), (32, False)])
+def test_single_consumption_across_workgroups_repeated(w, forced):
+    # consecutive fills of one handle continue its word position on the device
+    if forced:
+        prngd.set_tuning("philox", w, path=3)
+    g = prngd.Generator(31, "philox", w=w, consume="single")
+    ref = O.PRNGD(O.GEN_PHILOX, w, seed=31, consume=O.CONSUME_SINGLE)
+    for i, n in enumerate([40000, 1, 65537, 2**16, 50001]):
+        note(f"repeated single fill {i} w={w} n={n}")
+        buf, out = guarded(n)
+        g.fill(out)
+        torch.cuda.synchronize()
+        check_guards(buf, n)
+        assert_bits_equal(out.cpu().numpy(), ref.fill(n), f"fill {i}")
+        assert g.get_position()[1] == ref.counter
+    g.close()
