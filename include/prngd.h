@@ -98,10 +98,18 @@ typedef enum {
  *                        pairs.
  *   PRNGD_CONSUME_SINGLE one word, as in Algorithm 1, whose loop redraws
  *                        only r1; r2 is the word right after the accepted
- *                        r1, and the position counts words.  Philox and the
- *                        test generator only (word 2p, 2p+1 = pair p's x1,
- *                        x2 for ENUMERATE); PRNGD_ERR_UNSUPPORTED otherwise.
- *                        Each request is produced by one workgroup. */
+ *                        r1, and the position counts words.  Streams of
+ *                        one generator only: Philox (word j as above),
+ *                        MRG32k3a (word j = output j) and the test generator
+ *                        (words 2p, 2p + 1 = pair p's x1, x2);
+ *                        PRNGD_ERR_UNSUPPORTED for the mixed generator.
+ *                        A batch produces each request in one workgroup; a
+ *                        single prngd_fill of at least 2^15 outputs that
+ *                        expects at most 64 words equal to a0 or a (256 when
+ *                        a speculative path is forced by prngd_set_tuning)
+ *                        spreads its windows of 4096 words over
+ *                        workgroups and repairs them in a second kernel on
+ *                        the same stream. */
 typedef enum {
     PRNGD_CONSUME_PAIR = 0,
     PRNGD_CONSUME_SINGLE = 1

@@ -18,7 +18,7 @@
 //   5. coalesced stores; the thread that writes output n - 1 stores the
 //      handle's next pair counter.
 // The segment's last tile continues window by window until n outputs
-// exist ("take next pair" past every rejection).
+// exist (every rejection moves the end of the segment one pair further).
 #include <hip/hip_runtime.h>
 
 #include "prngd_internal.hpp"
@@ -1955,11 +1955,43 @@ struct SingleScratch {
     SingleState state;
 };
 
+// MRG32k3a state at output 16 block16 of window `win` (kSingleWindowWords
+// outputs per window) of a stream whose base state is seg.mrg: the window
+// tables jump by the base-256 digits of the window index, the thread table
+// by the 16-output block (tables built for two outputs per pair, 8 pairs
+// per thread, 256 threads).
+constexpr uint32_t kSingleWindowWords = 4096;
+
+__device__ __forceinline__ Mrg mrg_at_window(const LaunchArgs &args, const Segment &seg,
+                                             uint64_t win, uint32_t block16)
+{
+    Mrg g;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        g.s[i] = seg.mrg[i];
+    uint64_t m = win;
+    for (int d = 0; d < kMrgDigits && m != 0; ++d, m >>= 8) {
+        const uint32_t digit = uint32_t(m & 255u);
+        if (digit)
+            g.apply(args.mrg_window + (size_t(d) * 256 + digit) * kMrgMatWords);
+    }
+    g.apply(args.mrg_thread + size_t(block16) * kMrgMatWords);
+    return g;
+}
+
 // Word q (absolute index) of a single-generator stream.
 template <uint32_t FAM>
 __device__ __forceinline__ uint32_t single_word_at(const LaunchArgs &args, const Segment &seg,
                                                    uint64_t q)
 {
+    if (FAM == FAM_MRG) {
+        const uint32_t off = uint32_t(q % kSingleWindowWords);
+        Mrg g = mrg_at_window(args, seg, q / kSingleWindowWords, off / 16u);
+        uint32_t x = 0;
+        for (uint32_t k = 0; k <= off % 16u; ++k)
+            x = g.next();
+        return x;
+    }
     if (FAM == FAM_ENUM) {
         const uint64_t mask = (uint64_t(1) << args.w) - 1;
         const uint64_t p = q >> 1;
@@ -1974,18 +2006,44 @@ __device__ __forceinline__ uint32_t single_word_at(const LaunchArgs &args, const
 }
 
 // The words of window `win` into u; returns whether this thread holds a
-// word of the fill (q >= lo) equal to a0 or a.
+// word of the fill (q >= lo) equal to a0 or a.  MRG32k3a words are stepped
+// 16 consecutive ones per thread from one jump and regrouped through
+// s_stage (T words of LDS); every thread must call it.
 template <int NW, uint32_t FAM>
 __device__ __forceinline__ bool single_generate(const LaunchArgs &args, const Segment &seg,
                                                 uint64_t win, uint32_t lo,
-                                                uint32_t (&u)[SingleWords<NW, FAM>::J][4])
+                                                uint32_t (&u)[SingleWords<NW, FAM>::J][4],
+                                                uint32_t *s_stage)
 {
     using W = SingleWords<NW, FAM>;
     const uint32_t tid = threadIdx.x;
+    if (FAM == FAM_MRG) {
+        static_assert(FAM != FAM_MRG || (W::T == kSingleWindowWords && W::B == 256),
+                      "the MRG32k3a tables assume 256 threads and 4096-word windows");
+        Mrg g = mrg_at_window(args, seg, win, tid);
+        uint32_t x[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            x[k] = g.next();
+#pragma unroll
+        for (int k = 0; k < 16; k += 4)
+            *reinterpret_cast<uint4 *>(s_stage + 16u * tid + k) =
+                make_uint4(x[k], x[k + 1], x[k + 2], x[k + 3]);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < W::J; ++j) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(s_stage + 4u * (uint32_t(j) * W::B + tid));
+            u[j][0] = v.x;
+            u[j][1] = v.y;
+            u[j][2] = v.z;
+            u[j][3] = v.w;
+        }
+    }
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < W::J; ++j) {
-        W::words(args, seg, win, j, u[j]);
+        if (FAM != FAM_MRG)
+            W::words(args, seg, win, j, u[j]);
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
             const uint32_t q = 4u * (uint32_t(j) * W::B + tid) + l;
@@ -2167,7 +2225,7 @@ __global__ __launch_bounds__(64 * NW) void seq_single_kernel(LaunchArgs args)
         SingleState ss{0, 0, 0};
         while (ss.running < seg.n) {
             uint32_t u[W::J][4];
-            const bool bad = single_generate<NW, FAM>(args, seg, win, lo, u);
+            const bool bad = single_generate<NW, FAM>(args, seg, win, lo, u, sm.words);
             single_window_store<NW, FAM>(args, seg, win, lo, u, bad, ss, next_counter, sm, two_w);
             ++win;
             lo = 0;
@@ -2313,7 +2371,7 @@ __global__ __launch_bounds__(64 * NW) void spec_words_kernel(LaunchArgs args)
     const uint64_t win = w0 + t;
     const uint32_t lo = t == 0 ? lo0 : 0u;
     uint32_t u[J][4];
-    const bool bad = single_generate<NW, FAM>(args, seg, win, lo, u);
+    const bool bad = single_generate<NW, FAM>(args, seg, win, lo, u, sm.words);
     if (bad) {
 #pragma unroll
         for (int j = 0; j < J; ++j)
@@ -2332,7 +2390,7 @@ __global__ __launch_bounds__(64 * NW) void spec_words_kernel(LaunchArgs args)
     if (t == seg.ntiles - 1) {
         for (uint64_t w2 = win + 1; ss.running < seg.n; ++w2) {
             uint32_t v[J][4];
-            const bool b2 = single_generate<NW, FAM>(args, seg, w2, 0u, v);
+            const bool b2 = single_generate<NW, FAM>(args, seg, w2, 0u, v, sm.words);
             single_window_store<NW, FAM>(args, seg, w2, 0u, v, b2, ss, next_counter, sm, two_w);
         }
     }
@@ -2471,12 +2529,12 @@ __global__ __launch_bounds__(64 * NW) void spec_words_repair_kernel(LaunchArgs a
                 const uint64_t win = w0 + g;
                 SingleState ss = single_entry<FAM, T>(args, seg, win, g, lo0, hg);
                 uint32_t u[J][4];
-                const bool bad = single_generate<NW, FAM>(args, seg, win, 0u, u);
+                const bool bad = single_generate<NW, FAM>(args, seg, win, 0u, u, sm.words);
                 single_window_store<NW, FAM>(args, seg, win, 0u, u, bad, ss, next_counter, sm,
                                              two_w);
                 if (g == seg.ntiles - 1) {
                     for (uint64_t w2 = win + 1; ss.running < seg.n; ++w2) {
-                        const bool b2 = single_generate<NW, FAM>(args, seg, w2, 0u, u);
+                        const bool b2 = single_generate<NW, FAM>(args, seg, w2, 0u, u, sm.words);
                         single_window_store<NW, FAM>(args, seg, w2, 0u, u, b2, ss, next_counter,
                                                      sm, two_w);
                     }
@@ -2507,7 +2565,7 @@ __global__ __launch_bounds__(64 * NW) void spec_words_repair_kernel(LaunchArgs a
             ss = single_entry<FAM, T>(args, seg, win, f, lo0, 0u);
         while (ss.running < seg.n) {
             uint32_t u[J][4];
-            const bool bad = single_generate<NW, FAM>(args, seg, win, lo, u);
+            const bool bad = single_generate<NW, FAM>(args, seg, win, lo, u, sm.words);
             single_window_store<NW, FAM>(args, seg, win, lo, u, bad, ss, next_counter, sm, two_w);
             ++win;
             lo = 0;
@@ -2701,6 +2759,7 @@ const void *single_kernel_for(uint32_t fam)
     case FAM_PHILOX: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_PHILOX>);
     case FAM_PHILOX32: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_PHILOX32>);
     case FAM_ENUM: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_ENUM>);
+    case FAM_MRG: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_MRG>);
     default: return nullptr;
     }
 }
@@ -2719,6 +2778,9 @@ const void *spec_words_kernel_for(uint32_t fam, bool repair)
     case FAM_ENUM:
         return repair ? reinterpret_cast<const void *>(&spec_words_repair_kernel<4, FAM_ENUM>)
                       : reinterpret_cast<const void *>(&spec_words_kernel<4, FAM_ENUM>);
+    case FAM_MRG:
+        return repair ? reinterpret_cast<const void *>(&spec_words_repair_kernel<4, FAM_MRG>)
+                      : reinterpret_cast<const void *>(&spec_words_kernel<4, FAM_MRG>);
     default: return nullptr;
     }
 }

@@ -762,8 +762,8 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
         // one workgroup of 256 threads per segment, windows in order
         const void *k = single_kernel_for(cfg.fam);
         if (!k)
-            return fail(PRNGD_ERR_UNSUPPORTED, "single-word consumption needs a Philox-family "
-                                               "generator on the GPU");
+            return fail(PRNGD_ERR_UNSUPPORTED, "single-word consumption needs a single-generator "
+                                               "stream (Philox, MRG32k3a or the test generator)");
         lp->threads = 256;
         lp->seq_kernel = k;
         lp->kernel = k;
@@ -807,8 +807,9 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     args->hint = nullptr;
     if (cfg.fam == FAM_MRG || cfg.fam == FAM_MIXED) {
         const uint32_t r = cfg.fam == FAM_MRG ? 2u : 1u;
-        prngd_status_t st = mrg_tables_for(d, r, lp->tune.pairs_per_lane, &args->mrg_thread,
-                                           &args->mrg_window);
+        // one-word consumption steps 16 outputs per thread (8 pairs of 2)
+        const uint32_t ppl = cfg.consume == PRNGD_CONSUME_SINGLE ? 8u : lp->tune.pairs_per_lane;
+        prngd_status_t st = mrg_tables_for(d, r, ppl, &args->mrg_thread, &args->mrg_window);
         if (st != PRNGD_OK)
             return st;
     }
@@ -1165,7 +1166,8 @@ prngd_status_t prngd_set_consume(prngd_handle_t h, prngd_consume_t consume)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle is bound to a live plan");
     if (consume == PRNGD_CONSUME_SINGLE && !single_kernel_for(h->cfg.fam))
         return fail(PRNGD_ERR_UNSUPPORTED,
-                    "single-word consumption needs a Philox-family generator on the GPU");
+                    "single-word consumption needs a single-generator stream (Philox, MRG32k3a "
+                    "or the test generator)");
     h->cfg.consume = uint32_t(consume);
     return PRNGD_OK;
 }

@@ -549,7 +549,8 @@ def single_fill(gen, w, seed, counter, n, map="eq5", misalign=False):
 
 
 @pytest.mark.parametrize("gen,w", [("philox", 3), ("philox", 8), ("philox", 12), ("philox", 16),
-                                   ("philox", 24), ("philox", 32), ("enumerate", 8)])
+                                   ("philox", 24), ("philox", 32), ("enumerate", 8),
+                                   ("mrg32k3a", 32)])
 @pytest.mark.parametrize("counter,n", [(0, 1), (0, 2048), (0, 2049), (1, 5000), (4095, 6001),
                                        (7, 100003)])
 def test_single_consumption_matches_oracle(gen, w, counter, n):
@@ -594,7 +595,7 @@ def test_single_consumption_batches_plans_and_errors():
         prngd.fill_batch(list(zip(gens[:2], outs[:2])))
     for g in gens:
         g.close()
-    m = prngd.Generator(1, "mrg32k3a", w=32)
+    m = prngd.Generator(1, "mixed", w=32)
     with pytest.raises(prngd.PrngdError) as e:
         m.set_consume("single")
     assert e.value.status == prngd.ERR_UNSUPPORTED
@@ -609,7 +610,8 @@ def test_single_consumption_batches_plans_and_errors():
 @pytest.mark.parametrize("gen,w,n,forced", [
     ("philox", 8, 16000, True), ("philox", 12, 250001, True), ("philox", 16, 2**20 + 3, True),
     ("philox", 16, 2**20 + 3, False), ("philox", 32, 2**22 + 1, False),
-    ("enumerate", 16, 2**16, False), ("enumerate", 16, 2**17 + 9, True)])
+    ("enumerate", 16, 2**16, False), ("enumerate", 16, 2**17 + 9, True),
+    ("mrg32k3a", 32, 2**21 + 5, False)])
 @pytest.mark.parametrize("counter", [0, 1, 4095, 3 * 4096 + 2, 2**40 + 7])
 def test_single_consumption_across_workgroups(gen, w, n, forced, counter):
     if gen == "enumerate" and counter == 2**40 + 7:
