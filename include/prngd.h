@@ -128,7 +128,9 @@ typedef struct {
 /* Launch shape of the fill kernels.  None of these change the output
  * bytes; they only change speed.  Zero fields mean "library default". */
 typedef struct {
-    uint32_t pairs_per_lane;  /* pairs per thread per tile: 4, 8, 16, 32    */
+    uint32_t pairs_per_lane;  /* pairs per thread per tile: 2, 4, 8, 16, 32 */
+                              /* (0: 8 for a single Philox fill that takes  */
+                              /* path 2 or 3, 16 otherwise)                 */
     uint32_t blocks_per_cu;   /* workgroups per CU (0: all that fit)        */
     uint32_t store_mode;      /* 0 default, 1 plain 8-byte, 2 nontemporal   */
     uint32_t slack_mode;      /* 0 plan rejections ahead, 1 plan none (the  */

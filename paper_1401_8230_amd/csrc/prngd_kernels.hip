@@ -388,9 +388,49 @@ __device__ __forceinline__ void store_two(double *p, double v0, double v1, uint3
         *g = v;
 }
 
+// LDS index of staged value i: one spare slot per 16 doubles against bank
+// conflicts.
+__device__ __forceinline__ uint32_t pad_index(uint32_t i)
+{
+    return i + (i >> 4);
+}
+
+// Stores outputs [e0, e0 + cnt) of `out` that lie below n -- output e0 + i
+// staged at s_vals[pad_index(i)] -- in 16-byte stores laid on the absolute
+// 4 KB grid of addresses, so that each pass of a 256-thread workgroup
+// writes one whole aligned 4 KB block (on MI355X plain streaming stores
+// that straddle 128-byte lines ran up to 1.5x slower, and ones that
+// straddle 4 KB blocks up to 1.13x).  Every thread of the B-thread
+// workgroup calls it; store_mode 1 splits the 16-byte stores.
+template <int B>
+__device__ __forceinline__ void store_staged(double *out, uint64_t e0, uint32_t cnt, uint64_t n,
+                                             const double *s_vals, uint32_t mode)
+{
+    const uint64_t a0 = reinterpret_cast<uintptr_t>(out + e0) >> 3;   // 8-byte slot of output e0
+    const uint32_t r = uint32_t(a0 & 511u);        // slots of its 4 KB block before it
+    const uint32_t slots = (cnt + r + 1u) >> 1;    // 16-byte slots from that block's start
+    const uint32_t end = n <= e0 ? 0u : (n - e0 < cnt ? uint32_t(n - e0) : cnt);
+    const uint32_t m1 = mode == 1 ? 0u : mode;
+    for (uint32_t k = threadIdx.x; k < slots; k += B) {
+        const int64_t i = int64_t(2u * k) - int64_t(r);   // range index of the slot's first output
+        const bool in0 = i >= 0 && i < int64_t(end);
+        const bool in1 = i + 1 >= 0 && i + 1 < int64_t(end);
+        if (in0 && in1 && mode != 1) {
+            store_two(out + (e0 + uint64_t(i)), s_vals[pad_index(uint32_t(i))],
+                      s_vals[pad_index(uint32_t(i + 1))], m1);
+        } else {
+            if (in0)
+                store_one(out + (e0 + uint64_t(i)), s_vals[pad_index(uint32_t(i))], m1);
+            if (in1)
+                store_one(out + (e0 + uint64_t(i + 1)), s_vals[pad_index(uint32_t(i + 1))], m1);
+        }
+    }
+}
+
 // ======================================================================
-// Philox / enumerate family.  Thread tid of the B-thread workgroup takes
-// Philox block  win * T / 2 + j * B + tid  for j < PPL / 2, i.e. the two
+// Philox / enumerate family.  A window is T consecutive pairs from an even
+// pair wb (a Philox block boundary); thread tid of the B-thread workgroup
+// takes Philox block  wb / 2 + j * B + tid  for j < PPL / 2, i.e. the two
 // consecutive pairs at window offsets q = 2 (j B + tid) and q + 1; for a
 // fixed j a wave covers 128 consecutive pairs, so its outputs are
 // contiguous in memory.
@@ -413,17 +453,77 @@ struct PhiloxTile {
     uint32_t acc;                              // bit i: pair i of this thread kept
     bool clean;                                // every pair of the window kept
 
-    // Generate window `win` from window offset lo_off on and return the
-    // window's number of accepted pairs; for a window that is not clean the
-    // exclusive offset of every (j, wave) group is left in s_off.
+    // LDS words the caller provides as s_off.
+    static constexpr int kOffWords = 2 * E + 2;
+
+    // Generate the window of T pairs from pair wb, from window offset lo_off
+    // on, and return its number of accepted pairs; for a window that is not
+    // clean the exclusive offset of every (j, wave) group is left in s_off
+    // (kOffWords words).  A window may start on the second pair of a Philox
+    // block (odd wb): each thread then takes its block's second pair and the
+    // first pair of the block after it, which is the next lane's block (lane
+    // 63 reads it from LDS, and one extra block follows the window).
     __device__ __forceinline__ uint32_t generate(const LaunchArgs &args, const Segment &seg,
-                                                 uint64_t win, uint32_t lo_off, uint32_t *s_off)
+                                                 uint64_t wb, uint32_t lo_off, uint32_t *s_off)
     {
         const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-        const uint64_t blk0 = win * (T / 2);
+        const uint64_t blk0 = (wb >> 1);
         const uint32_t k0 = uint32_t(seg.seed), k1 = uint32_t(seg.seed >> 32);
         acc = 0;
-        if (FAM == FAM_PHILOX32) {
+        if (FAM != FAM_ENUM && (wb & 1u)) {
+            uint32_t a1[J], a2[J], b1[J], b2[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const uint64_t blk = blk0 + uint32_t(j) * B + tid;
+                const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u,
+                                               seg.stream_id, k0, k1);
+                a1[j] = r.v2;
+                a2[j] = r.v3;
+                b1[j] = r.v0;       // this block's first pair goes to the lane before
+                b2[j] = r.v1;
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    s_off[2 * (j * NW + wave)] = b1[j];
+                    s_off[2 * (j * NW + wave) + 1] = b2[j];
+                }
+            }
+            if (tid == 0) {
+                const uint64_t blk = blk0 + uint64_t(J) * B;
+                const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u,
+                                               seg.stream_id, k0, k1);
+                s_off[2 * E] = r.v0;
+                s_off[2 * E + 1] = r.v1;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                uint32_t n1 = uint32_t(__shfl_down(int(b1[j]), 1u, 64));
+                uint32_t n2 = uint32_t(__shfl_down(int(b2[j]), 1u, 64));
+                if (lane == 63) {
+                    const uint32_t e = wave + 1 < uint32_t(NW) ? uint32_t(j) * NW + wave + 1
+                                                               : uint32_t(j + 1) * NW;
+                    n1 = s_off[2 * e];
+                    n2 = s_off[2 * e + 1];
+                }
+                b1[j] = n1;
+                b2[j] = n2;
+            }
+            // s_off is rewritten only after the barrier of the clean test below
+            const uint32_t shift = FAM == FAM_PHILOX32 ? 0u : 32u - args.w;
+            const double two_w = FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const uint32_t x1a = a1[j] >> shift, x2a = a2[j] >> shift;
+                const uint32_t x1b = b1[j] >> shift, x2b = b2[j] >> shift;
+                const bool oka = x1a != args.a0 && x1a != args.a;
+                const bool okb = x1b != args.a0 && x1b != args.a;
+                v[2 * j] = prngd_map(x1a, x2a, args, two_w);
+                v[2 * j + 1] = prngd_map(x1b, x2b, args, two_w);
+                acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
+            }
+        } else if (FAM == FAM_PHILOX32) {
             // x in [0, 2^32 - 1]: keep x1 unless x1 + 1 wraps to 0 or is 1
 #pragma unroll
             for (int j = 0; j < J; ++j) {
@@ -451,7 +551,7 @@ struct PhiloxTile {
                     x1b = r.v2 >> shift;
                     x2b = r.v3 >> shift;
                 } else {
-                    const uint64_t p = win * T + 2u * (uint32_t(j) * B + tid);
+                    const uint64_t p = wb + 2u * (uint32_t(j) * B + tid);
                     const uint64_t mask = (uint64_t(1) << args.w) - 1;
                     x1a = uint32_t((p >> args.w) & mask);
                     x2a = uint32_t(p & mask);
@@ -494,9 +594,9 @@ struct PhiloxTile {
         return s_off[E];
     }
 
-    // Store the kept outputs of window `win` at segment offset `excl`.
+    // Store the kept outputs of window `wb` at segment offset `excl`.
     __device__ __forceinline__ void store(const LaunchArgs &args, const Segment &seg,
-                                          uint64_t win, uint64_t excl, uint64_t *next_counter,
+                                          uint64_t wb, uint64_t excl, uint64_t *next_counter,
                                           const uint32_t *s_off)
     {
         const uint32_t tid = threadIdx.x;
@@ -542,7 +642,7 @@ struct PhiloxTile {
                             store_one(o + q + 1, v[2 * j + 1], args.store_mode);
                     }
                     if (q + 1 == left || q + 2 == left)
-                        *next_counter = win * T + left;
+                        *next_counter = wb + left;
                 }
             }
             return;
@@ -570,7 +670,7 @@ struct PhiloxTile {
             const bool last_a = oka && pos_a == n - 1;
             const bool last_b = okb && pos_b == n - 1;
             if (last_a || last_b)
-                *next_counter = win * T + 2u * (uint32_t(j) * B + tid) + (last_a ? 1u : 2u);
+                *next_counter = wb + 2u * (uint32_t(j) * B + tid) + (last_a ? 1u : 2u);
         }
     }
 };
@@ -604,22 +704,29 @@ struct SpecTile {
     };
 
     __device__ __forceinline__ static HiLo words(const LaunchArgs &args, const Segment &seg,
-                                                 uint64_t win, int j)
+                                                 uint64_t wb, int j)
     {
         const uint32_t tid = threadIdx.x;
         uint32_t x1a, x2a, x1b, x2b;
         if (FAM == FAM_ENUM) {
-            const uint64_t q = win * T + 2u * (uint32_t(j) * B + tid);
+            const uint64_t q = wb + 2u * (uint32_t(j) * B + tid);
             const uint64_t mask = (uint64_t(1) << args.w) - 1;
             x1a = uint32_t((q >> args.w) & mask);
             x2a = uint32_t(q & mask);
             x1b = uint32_t(((q + 1) >> args.w) & mask);
             x2b = uint32_t((q + 1) & mask);
         } else {
-            const uint64_t blk = win * (T / 2) + uint32_t(j) * B + tid;
-            const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u,
-                                           seg.stream_id, uint32_t(seg.seed),
-                                           uint32_t(seg.seed >> 32));
+            const uint64_t blk = (wb >> 1) + uint32_t(j) * B + tid;
+            Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u, seg.stream_id,
+                                     uint32_t(seg.seed), uint32_t(seg.seed >> 32));
+            if (wb & 1u) {
+                // the window starts on a block's second pair: this thread's
+                // pairs are its block's second and the next block's first
+                const Words4 nx = philox4x32_10(uint32_t(blk + 1), uint32_t((blk + 1) >> 32), 0u,
+                                                seg.stream_id, uint32_t(seg.seed),
+                                                uint32_t(seg.seed >> 32));
+                r = Words4{r.v2, r.v3, nx.v0, nx.v1};
+            }
             if (FAM == FAM_PHILOX32) {
                 x1a = r.v0; x2a = r.v1; x1b = r.v2; x2b = r.v3;
             } else {
@@ -643,10 +750,10 @@ struct SpecTile {
         return FAM == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
     }
 
-    // Accepted pairs of window `win` from window offset lo_off on, without
+    // Accepted pairs of window `wb` from window offset lo_off on, without
     // storing anything.
     __device__ __forceinline__ static uint32_t count_kept(const LaunchArgs &args,
-                                                          const Segment &seg, uint64_t win,
+                                                          const Segment &seg, uint64_t wb,
                                                           uint32_t lo_off, uint32_t *s_off)
     {
         const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
@@ -655,7 +762,7 @@ struct SpecTile {
 #pragma unroll 2
         for (int j = 0; j < J; ++j) {
             const uint32_t q = 2u * (uint32_t(j) * B + tid);
-            const HiLo p = words(args, seg, win, j);
+            const HiLo p = words(args, seg, wb, j);
             rej += uint32_t(p.ha >= hm && q >= lo_off) + uint32_t(p.hb >= hm && q + 1 >= lo_off);
         }
         uint32_t kept = T - lo_off;
@@ -674,7 +781,7 @@ struct SpecTile {
         return kept;
     }
 
-    // Produce window `win` (from window offset lo_off on) at segment offset
+    // Produce window `wb` (from window offset lo_off on) at segment offset
     // excl; returns the window's number of accepted pairs.  With kSpec the
     // pairs are stored as they are generated (a window that turns out not
     // to be clean leaves stale values on up to T positions past its own
@@ -682,7 +789,7 @@ struct SpecTile {
     // writes nothing but its own outputs.
     template <bool kSpec = true>
     __device__ __forceinline__ uint32_t run(const LaunchArgs &args, const Segment &seg,
-                                            uint64_t win, uint32_t lo_off, uint64_t excl,
+                                            uint64_t wb, uint32_t lo_off, uint64_t excl,
                                             uint64_t *next_counter, uint32_t *s_off)
     {
         const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
@@ -705,7 +812,7 @@ struct SpecTile {
 #pragma unroll 2
             for (int j = 0; j < J; ++j) {
                 const uint32_t q = 2u * (uint32_t(j) * B + tid);
-                const HiLo p = words(args, seg, win, j);
+                const HiLo p = words(args, seg, wb, j);
                 mx = max(mx, max(p.ha, p.hb));
                 const double za = map_hi_lo(p.ha, p.la, tw, args);
                 const double zb = map_hi_lo(p.hb, p.lb, tw, args);
@@ -729,14 +836,14 @@ struct SpecTile {
                 return T;
 #pragma unroll 1
             for (int j = 0; j < J; ++j) {
-                const HiLo p = words(args, seg, win, j);
+                const HiLo p = words(args, seg, wb, j);
                 acc |= (uint32_t(p.ha < hm) << (2 * j)) | (uint32_t(p.hb < hm) << (2 * j + 1));
             }
         } else {
 #pragma unroll 2
             for (int j = 0; j < J; ++j) {
                 const uint32_t q = 2u * (uint32_t(j) * B + tid);
-                const HiLo p = words(args, seg, win, j);
+                const HiLo p = words(args, seg, wb, j);
                 const bool oka = p.ha < hm && q >= lo_off;
                 const bool okb = p.hb < hm && q + 1 >= lo_off;
                 acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
@@ -752,7 +859,7 @@ struct SpecTile {
                             store_one(o + q + 1, zb, args.store_mode);
                     }
                     if (q + 1 == left || q + 2 == left)
-                        *next_counter = win * T + left;
+                        *next_counter = wb + left;
                 }
             }
             dirty = __syncthreads_or(!kSpec || lo_off != 0 || acc != kAll);
@@ -781,7 +888,7 @@ struct SpecTile {
                                    uint32_t(__popcll(ba & lt) + __popcll(bb & lt));
             const uint32_t pos_b = pos_a + (oka ? 1u : 0u);
             if (oka || okb) {
-                const HiLo p = words(args, seg, win, j);
+                const HiLo p = words(args, seg, wb, j);
                 const double za = map_hi_lo(p.ha, p.la, tw, args);
                 const double zb = map_hi_lo(p.hb, p.lb, tw, args);
                 if (oka && pos_a < left)
@@ -791,9 +898,9 @@ struct SpecTile {
             }
             const uint32_t q = 2u * (uint32_t(j) * B + tid);
             if (oka && pos_a + 1 == left)
-                *next_counter = win * T + q + 1;
+                *next_counter = wb + q + 1;
             if (okb && pos_b + 1 == left)
-                *next_counter = win * T + q + 2;
+                *next_counter = wb + q + 2;
         }
         const uint32_t total = s_off[E];
         __syncthreads();
@@ -807,11 +914,6 @@ struct SpecTile {
 // compacted outputs are staged in LDS and written out by consecutive
 // threads so that the stores stay coalesced.
 // ======================================================================
-__device__ __forceinline__ uint32_t pad_index(uint32_t i)
-{
-    return i + (i >> 4);     // one spare slot per 16 doubles against bank conflicts
-}
-
 template <int PPL, uint32_t FAM>
 struct MrgTile {
     static constexpr int B = kMrgBlockThreads;
@@ -899,12 +1001,7 @@ struct MrgTile {
             }
         }
         __syncthreads();
-        double *out = seg.out;
-        for (uint32_t i = tid; i < total; i += B) {
-            const uint64_t pos = excl + i;
-            if (pos < n)
-                store_one(out + pos, s_vals[pad_index(i)], args.store_mode == 1 ? 0u : args.store_mode);
-        }
+        store_staged<B>(seg.out, excl, total, n, s_vals, args.store_mode);
         __syncthreads();       // s_vals is reused by the next window
     }
 };
@@ -1060,7 +1157,7 @@ __device__ __forceinline__ void sequential_spec_loop(const LaunchArgs &args, uin
         uint32_t lo_off = uint32_t(c0 - win * T);
         uint64_t running = 0;
         while (running < seg.n) {
-            running += Tile().run(args, seg, win, lo_off, running, next_counter, s_off);
+            running += Tile().run(args, seg, win * T, lo_off, running, next_counter, s_off);
             ++win;
             lo_off = 0;
             if (!nc0_loaded && nxt != ~0u) {
@@ -1088,7 +1185,7 @@ __device__ __forceinline__ void sequential_spec_loop(const LaunchArgs &args, uin
 template <int NW, int PPL, uint32_t FAM>
 struct PhiloxScratch {
     using Tile = PhiloxTile<NW, PPL, FAM>;
-    uint32_t off[Tile::E + 1];
+    uint32_t off[Tile::kOffWords];
     uint64_t excl;
     uint32_t next;
     LaunchState state;
@@ -1096,12 +1193,12 @@ struct PhiloxScratch {
     __device__ __forceinline__ uint32_t generate(Tile &tile, const LaunchArgs &a, const Segment &s,
                                                  uint64_t win, uint32_t lo)
     {
-        return tile.generate(a, s, win, lo, off);
+        return tile.generate(a, s, win * Tile::T, lo, off);
     }
     __device__ __forceinline__ void store(Tile &tile, const LaunchArgs &a, const Segment &s,
                                           uint64_t win, uint64_t excl, uint32_t, uint64_t *nc)
     {
-        tile.store(a, s, win, excl, nc, off);
+        tile.store(a, s, win * Tile::T, excl, nc, off);
     }
 };
 
@@ -1291,6 +1388,24 @@ __device__ __forceinline__ void publish_rejections(const LaunchArgs &args, uint3
                               __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// Window origin of a Philox-family speculative fill.  The fill's windows
+// are the T-pair ranges from pair c0 - lo0 on: tile 0 starts lo0 pairs into
+// its window, and tile t >= 1 at pair c0 - lo0 + t T, whose output (before
+// rejections) is t T - lo0.  lo0 < 512 is chosen so that those outputs
+// start on a 4 KB boundary of the output array (T is a multiple of 512); a
+// window then starts on the second pair of a Philox block when c0 - lo0 is
+// odd.  A fill that starts before pair lo0 of its stream takes the window
+// origin 0 instead (lo0 = c0).  On MI355X stores that straddle 4 KB blocks
+// written by different workgroups measured up to 1.2x slower, and 16-byte
+// stores one output off the block grid slower still.
+template <uint32_t T>
+__device__ __forceinline__ uint32_t window_lo0(const Segment &seg, uint64_t c0)
+{
+    static_assert(T % 512 == 0, "the window must cover whole 4 KB blocks of outputs");
+    const uint32_t a = uint32_t((reinterpret_cast<uintptr_t>(seg.out) >> 3) & 511u);
+    return c0 >= a ? a : uint32_t(c0);
+}
+
 template <int NW, int PPL, uint32_t FAM, bool SINGLE>
 __global__ __launch_bounds__(64 * NW) void spec_philox_kernel(LaunchArgs args)
 {
@@ -1304,21 +1419,20 @@ __global__ __launch_bounds__(64 * NW) void spec_philox_kernel(LaunchArgs args)
     const uint32_t t = ts.t, used = ts.used;
     const uint64_t c0 = ts.c0;
     uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
-    const uint64_t w0 = c0 / T;
-    const uint32_t lo0 = uint32_t(c0 - w0 * T);
-    const uint64_t win = w0 + t;
+    const uint32_t lo0 = window_lo0<T>(seg, c0);
+    const uint64_t wb = c0 - lo0 + uint64_t(t) * T;      // the window's first pair
     const uint32_t lo_off = t == 0 ? lo0 : 0u;
     const uint64_t excl = (t == 0 ? 0 : uint64_t(t) * T - lo0) - used;
     uint32_t kept;
     if (excl < seg.n)
-        kept = Tile().run(args, seg, win, lo_off, excl, next_counter, s_off);
+        kept = Tile().run(args, seg, wb, lo_off, excl, next_counter, s_off);
     else
-        kept = Tile::count_kept(args, seg, win, lo_off, s_off);
+        kept = Tile::count_kept(args, seg, wb, lo_off, s_off);
     publish_rejections(args, g, (T - lo_off) - kept);
     // the segment's last tile takes every further window until n outputs
     if (t == seg.ntiles - 1) {
         uint64_t running = excl + kept;
-        for (uint64_t w2 = win + 1; running < seg.n; ++w2)
+        for (uint64_t w2 = wb + T; running < seg.n; w2 += T)
             running += Tile().run(args, seg, w2, 0u, running, next_counter, s_off);
     }
 }
@@ -1334,27 +1448,26 @@ __global__ __launch_bounds__(64 * NW) void spec_hold_kernel(LaunchArgs args)
 {
     using Tile = PhiloxTile<NW, PPL, FAM>;
     constexpr uint32_t T = Tile::T;
-    __shared__ uint32_t s_off[Tile::E + 1];
+    __shared__ uint32_t s_off[Tile::kOffWords];
     __shared__ uint32_t s_hint;
     const uint32_t g = blockIdx.x;
     const TileStart ts = tile_start<SINGLE>(args, g);
     const Segment &seg = ts.seg;
     const uint32_t t = ts.t;
     uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
-    const uint64_t w0 = ts.c0 / T;
-    const uint32_t lo0 = uint32_t(ts.c0 - w0 * T);
-    const uint64_t win = w0 + t;
+    const uint32_t lo0 = window_lo0<T>(seg, ts.c0);
+    const uint64_t wb = ts.c0 - lo0 + uint64_t(t) * T;   // the window's first pair
     const uint32_t lo_off = t == 0 ? lo0 : 0u;
     Tile tile;
-    const uint32_t kept = tile.generate(args, seg, win, lo_off, s_off);
+    const uint32_t kept = tile.generate(args, seg, wb, lo_off, s_off);
     publish_rejections(args, g, (T - lo_off) - kept);
     const uint32_t used = read_hint(args, ts, g, &s_hint);
     const uint64_t excl = (t == 0 ? 0 : uint64_t(t) * T - lo0) - used;
     if (excl < seg.n)
-        tile.store(args, seg, win, excl, next_counter, s_off);
+        tile.store(args, seg, wb, excl, next_counter, s_off);
     if (t == seg.ntiles - 1) {
         uint64_t running = excl + kept;
-        for (uint64_t w2 = win + 1; running < seg.n; ++w2) {
+        for (uint64_t w2 = wb + T; running < seg.n; w2 += T) {
             __syncthreads();
             const uint32_t k2 = tile.generate(args, seg, w2, 0u, s_off);
             tile.store(args, seg, w2, running, next_counter, s_off);
@@ -1431,17 +1544,17 @@ __device__ __forceinline__ TileFacts tile_facts(const uint64_t *list, uint32_t c
 
 constexpr uint32_t kRepairCache = 1024;    // list entries kept in LDS
 
-// Whether tile g (of segment `seg`, tile index t, start position c0) has
-// to be produced again, and at which true offset.
+// Whether tile g (of segment `seg`, tile index t, whose first tile starts
+// lo0 pairs into its window) has to be produced again, and at which true
+// offset.
 template <uint32_t T>
 __device__ __forceinline__ bool needs_redo(const LaunchArgs &args, const uint64_t *list,
                                            uint32_t cnt, const Segment &seg, uint32_t t,
-                                           uint64_t c0, uint32_t g, uint64_t *true_off)
+                                           uint32_t lo0, uint32_t g, uint64_t *true_off)
 {
     const TileFacts f = tile_facts(list, cnt, seg.tile_begin, g);
     if (!f.after_dirty)
         return false;                 // up to the segment's first dirty tile all is exact
-    const uint32_t lo0 = uint32_t(c0 % T);
     const uint64_t off = uint64_t(t) * T - lo0 - f.P;    // t >= 1 here
     if (off >= seg.n)
         return false;                 // every output of the tile lies past n
@@ -1482,14 +1595,24 @@ struct PhiloxRedo {
     struct Scratch {
         uint32_t off[Tile::E + 1];
     };
+    // where the fill's windows start (as the speculative kernels chose), and
+    // the window argument of tile t: its first pair
+    __device__ __forceinline__ static uint32_t lo0(const Segment &seg, uint64_t c0)
+    {
+        return window_lo0<T>(seg, c0);
+    }
+    __device__ __forceinline__ static uint64_t window(uint64_t c0, uint32_t lo0, uint32_t t)
+    {
+        return c0 - lo0 + uint64_t(t) * T;
+    }
     __device__ __forceinline__ static void produce(const LaunchArgs &args, const Segment &seg,
-                                                   uint64_t win, uint64_t off, bool last,
+                                                   uint64_t wb, uint64_t off, bool last,
                                                    uint64_t *next_counter, Scratch &sh)
     {
         uint64_t running =
-            off + Tile().template run<false>(args, seg, win, 0u, off, next_counter, sh.off);
+            off + Tile().template run<false>(args, seg, wb, 0u, off, next_counter, sh.off);
         if (last)
-            for (uint64_t w2 = win + 1; running < seg.n; ++w2)
+            for (uint64_t w2 = wb + T; running < seg.n; w2 += T)
                 running += Tile().run(args, seg, w2, 0u, running, next_counter, sh.off);
     }
 };
@@ -1503,6 +1626,15 @@ struct MrgRedo {
         double vals[Tile::T + Tile::T / 16];
         uint32_t wave[kMrgBlockThreads / 64];
     };
+    // windows on the absolute grid of T pairs; tile t's window index
+    __device__ __forceinline__ static uint32_t lo0(const Segment &, uint64_t c0)
+    {
+        return uint32_t(c0 % T);
+    }
+    __device__ __forceinline__ static uint64_t window(uint64_t c0, uint32_t, uint32_t t)
+    {
+        return c0 / T + t;
+    }
     __device__ __forceinline__ static void produce(const LaunchArgs &args, const Segment &seg,
                                                    uint64_t win, uint64_t off, bool last,
                                                    uint64_t *next_counter, Scratch &sh)
@@ -1564,7 +1696,7 @@ __global__ __launch_bounds__(F::B) void spec_repair_kernel(LaunchArgs args)
             }
             const uint64_t c0 = seg.counter[seg.parity ^ flip];
             uint64_t off = 0;
-            if (t > 0 && needs_redo<T>(args, list, cnt, seg, t, c0, g, &off)) {
+            if (t > 0 && needs_redo<T>(args, list, cnt, seg, t, F::lo0(seg, c0), g, &off)) {
                 const uint32_t k = atomicAdd(&s_nq, 1u);
                 s_queue[k] = g;
                 s_qoff[k] = off;
@@ -1582,8 +1714,8 @@ __global__ __launch_bounds__(F::B) void spec_repair_kernel(LaunchArgs args)
             lookup(args, g, &seg, &t);
             const uint32_t par = seg.parity ^ flip;
             const uint64_t c0 = load_start(seg, par);
-            F::produce(args, seg, c0 / T + t, off, t == seg.ntiles - 1, seg.counter + (par ^ 1u),
-                       sh);
+            F::produce(args, seg, F::window(c0, F::lo0(seg, c0), t), off, t == seg.ntiles - 1,
+                       seg.counter + (par ^ 1u), sh);
         }
         __syncthreads();
     }
@@ -1950,7 +2082,11 @@ struct SingleState {
 
 template <int NW, uint32_t FAM>
 struct SingleScratch {
-    uint32_t words[SingleWords<NW, FAM>::T];
+    static constexpr uint32_t T = SingleWords<NW, FAM>::T;
+    union {
+        uint32_t words[T];                 // the window's words (exact walk)
+        double stage[T / 2 + T / 32];      // a clean window's outputs (staged store)
+    };
     uint32_t last[SingleWords<NW, FAM>::J][NW];   // word 3 of lane 63, per (j, wave)
     SingleState state;
 };
@@ -2084,13 +2220,18 @@ __device__ __forceinline__ void single_window_store(const LaunchArgs &args, cons
         const bool aligned = ((reinterpret_cast<uintptr_t>(o) & 15u) == 0);
         const bool whole = left > T / 2;
         const uint32_t r2_of_0 = ss.st == 0 ? 1u : 0u;
+        // a whole window not on a 4 KB boundary goes out through LDS
+        const bool staged = whole && (reinterpret_cast<uintptr_t>(o) & 4095u) != 0;
         if (ss.st == 0) {
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 const uint32_t m = uint32_t(j) * B + tid;
                 const double za = prngd_map(u[j][0], u[j][1], args, two_w);
                 const double zb = prngd_map(u[j][2], u[j][3], args, two_w);
-                if (aligned && (whole || 2 * m + 1 < left)) {
+                if (staged) {
+                    sm.stage[pad_index(2 * m)] = za;
+                    sm.stage[pad_index(2 * m + 1)] = zb;
+                } else if (aligned && (whole || 2 * m + 1 < left)) {
                     store_two(o + 2 * m, za, zb, args.store_mode);
                 } else {
                     if (2 * m < left)
@@ -2123,7 +2264,10 @@ __device__ __forceinline__ void single_window_store(const LaunchArgs &args, cons
                 }
                 const double za = prngd_map(prev, u[j][0], args, two_w);
                 const double zb = prngd_map(u[j][1], u[j][2], args, two_w);
-                if (aligned && (whole || 2 * m + 1 < left)) {
+                if (staged) {
+                    sm.stage[pad_index(2 * m)] = za;
+                    sm.stage[pad_index(2 * m + 1)] = zb;
+                } else if (aligned && (whole || 2 * m + 1 < left)) {
                     store_two(o + 2 * m, za, zb, args.store_mode);
                 } else {
                     if (2 * m < left)
@@ -2137,6 +2281,11 @@ __device__ __forceinline__ void single_window_store(const LaunchArgs &args, cons
             // the window's last word is the next pending r1
             ss.pending = sm.last[J - 1][NW - 1];
             __syncthreads();
+        }
+        if (staged) {
+            __syncthreads();
+            store_staged<B>(seg.out, ss.running, T / 2, n, sm.stage, args.store_mode);
+            __syncthreads();   // the stage is reused by the next window
         }
         ss.running += T / 2;
         return;

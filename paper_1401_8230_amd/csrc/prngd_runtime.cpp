@@ -459,7 +459,9 @@ bool philox_family(uint32_t fam)
     return fam == FAM_PHILOX || fam == FAM_ENUM || fam == FAM_PHILOX32;
 }
 
-prngd_tuning_t tuning_for(uint32_t fam, uint32_t w)
+// The launch shape for (family, w): the tuning set for it, library
+// defaults in its zero fields (default_ppl pairs per lane).
+prngd_tuning_t tuning_for(uint32_t fam, uint32_t w, uint32_t default_ppl = 16)
 {
     prngd_tuning_t t{};
     auto it = g_tuning.find(std::make_pair(fam, w));
@@ -468,9 +470,20 @@ prngd_tuning_t tuning_for(uint32_t fam, uint32_t w)
     if (t.block_threads == 0)
         t.block_threads = philox_family(fam) ? 256 : kMrgBlockThreads;
     if (t.pairs_per_lane == 0)
-        t.pairs_per_lane = 16;
+        t.pairs_per_lane = default_ppl;
     return t;
 }
+
+// Whether no pairs-per-lane value has been set for (family, w).
+bool ppl_is_default(uint32_t fam, uint32_t w)
+{
+    auto it = g_tuning.find(std::make_pair(fam, w));
+    return it == g_tuning.end() || it->second.pairs_per_lane == 0;
+}
+
+// Default pairs per lane of a single Philox fill on a tile-speculative
+// path: 2048-pair tiles measured fastest on MI355X there (batches keep 16).
+constexpr uint32_t kSingleSpecPpl = 8;
 
 // Segments of a batch with at most this many tiles are produced whole by
 // one workgroup (segment-sequential kernel); longer ones are spread over
@@ -749,9 +762,10 @@ struct LaunchPlan {
     prngd_tuning_t tune;
 };
 
-prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, LaunchPlan *lp)
+prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, LaunchPlan *lp,
+                           uint32_t default_ppl = 16)
 {
-    lp->tune = tuning_for(cfg.fam, cfg.w);
+    lp->tune = tuning_for(cfg.fam, cfg.w, default_ppl);
     lp->threads = lp->tune.block_threads;
     lp->kernel = fill_kernel_for(cfg.fam, lp->threads, lp->tune.pairs_per_lane, false);
     lp->seq_kernel = fill_kernel_for(cfg.fam, lp->threads, lp->tune.pairs_per_lane, true);
@@ -1359,13 +1373,23 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *strea
     if ((st = stream_workspace(h->device, s, &ws)) != PRNGD_OK)
         return st;
     uint64_t ntiles = 0;
-    if ((st = make_segment(h, n, out, lp.T, lp.tune.slack_mode, 0, &args.seg0, &ntiles)) !=
-        PRNGD_OK)
-        return st;
-    args.nseg = 1;
-    args.total_tiles = uint32_t(ntiles);
-    args.ctl = ws->ctl;
-    choose_path(&lp, h->cfg, args.seg0.planned, args.seg0.planned, true);
+    for (int pass = 0; pass < 2; ++pass) {
+        if ((st = make_segment(h, n, out, lp.T, lp.tune.slack_mode, 0, &args.seg0, &ntiles)) !=
+            PRNGD_OK)
+            return st;
+        args.nseg = 1;
+        args.total_tiles = uint32_t(ntiles);
+        args.ctl = ws->ctl;
+        choose_path(&lp, h->cfg, args.seg0.planned, args.seg0.planned, true);
+        if (pass == 1 || words || !lp.spec || lp.wave || !philox_family(h->cfg.fam) ||
+            !ppl_is_default(h->cfg.fam, h->cfg.w))
+            break;
+        // a tile-speculative single Philox fill: plan again in its own tile size
+        args = LaunchArgs{};
+        lp = LaunchPlan{};
+        if ((st = plan_launch(d, h->cfg, &args, &lp, kSingleSpecPpl)) != PRNGD_OK)
+            return st;
+    }
     if ((st = order_after(h, s)) != PRNGD_OK)
         return st;
     if (words) {
