@@ -357,8 +357,9 @@ def run_serving(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding of the fill is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the fill runs "
+              "on one GPU; independent streams and requests would shard across GPUs with no "
+              "communication", file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)

@@ -125,7 +125,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise PrngdError(ERR_UNSUPPORTED,
-                             f"{LIB_PATH} is not built: run __graft_entry__.build()")
+                             f"{LIB_PATH} is not built: run python -m paper_1401_8230_amd._build")
         L = ctypes.CDLL(LIB_PATH)
         for name, res, args in _SIGNATURES:
             fn = getattr(L, name)
