@@ -452,17 +452,35 @@ struct PhiloxTile {
     double v[PPL];
     uint32_t acc;                              // bit i: pair i of this thread kept
     bool clean;                                // every pair of the window kept
+    bool runs;                                 // wave-contiguous layout (odd wb)
 
     // LDS words the caller provides as s_off.
-    static constexpr int kOffWords = 2 * E + 2;
+    static constexpr int kOffWords = E + 1;
+
+    // Window offset of this thread's first pair in slot j, and the index of
+    // its (j, wave) group in pair order.  Normally a wave covers 128
+    // consecutive pairs per j (q = 2 (j B + tid)); in the wave-contiguous
+    // layout wave w covers pairs [128 J w, 128 J (w + 1)), 128 per j.
+    __device__ __forceinline__ uint32_t pair_q(int j) const
+    {
+        const uint32_t tid = threadIdx.x;
+        return runs ? 2u * ((tid >> 6) * (64u * J) + uint32_t(j) * 64u + (tid & 63u))
+                    : 2u * (uint32_t(j) * B + tid);
+    }
+    __device__ __forceinline__ uint32_t group(int j) const
+    {
+        const uint32_t wave = threadIdx.x >> 6;
+        return runs ? wave * J + uint32_t(j) : uint32_t(j) * NW + wave;
+    }
 
     // Generate the window of T pairs from pair wb, from window offset lo_off
     // on, and return its number of accepted pairs; for a window that is not
     // clean the exclusive offset of every (j, wave) group is left in s_off
     // (kOffWords words).  A window may start on the second pair of a Philox
     // block (odd wb): each thread then takes its block's second pair and the
-    // first pair of the block after it, which is the next lane's block (lane
-    // 63 reads it from LDS, and one extra block follows the window).
+    // first pair of the block after it.  With wave-contiguous blocks that is
+    // the next lane's block, or for lane 63 lane 0's block of the next slot,
+    // or the block after the wave's run, which each wave computes once.
     __device__ __forceinline__ uint32_t generate(const LaunchArgs &args, const Segment &seg,
                                                  uint64_t wb, uint32_t lo_off, uint32_t *s_off)
     {
@@ -470,11 +488,13 @@ struct PhiloxTile {
         const uint64_t blk0 = (wb >> 1);
         const uint32_t k0 = uint32_t(seg.seed), k1 = uint32_t(seg.seed >> 32);
         acc = 0;
-        if (FAM != FAM_ENUM && (wb & 1u)) {
+        runs = FAM != FAM_ENUM && (wb & 1u);
+        if (runs) {
             uint32_t a1[J], a2[J], b1[J], b2[J];
+            const uint64_t run0 = blk0 + uint64_t(wave) * (64u * J);
 #pragma unroll
             for (int j = 0; j < J; ++j) {
-                const uint64_t blk = blk0 + uint32_t(j) * B + tid;
+                const uint64_t blk = run0 + uint32_t(j) * 64u + lane;
                 const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u,
                                                seg.stream_id, k0, k1);
                 a1[j] = r.v2;
@@ -482,35 +502,22 @@ struct PhiloxTile {
                 b1[j] = r.v0;       // this block's first pair goes to the lane before
                 b2[j] = r.v1;
             }
-            if (lane == 0) {
-#pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    s_off[2 * (j * NW + wave)] = b1[j];
-                    s_off[2 * (j * NW + wave) + 1] = b2[j];
-                }
-            }
-            if (tid == 0) {
-                const uint64_t blk = blk0 + uint64_t(J) * B;
-                const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u,
-                                               seg.stream_id, k0, k1);
-                s_off[2 * E] = r.v0;
-                s_off[2 * E + 1] = r.v1;
-            }
-            __syncthreads();
+            const uint64_t nb = run0 + 64u * J;
+            const Words4 rn = philox4x32_10(uint32_t(nb), uint32_t(nb >> 32), 0u, seg.stream_id,
+                                            k0, k1);
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 uint32_t n1 = uint32_t(__shfl_down(int(b1[j]), 1u, 64));
                 uint32_t n2 = uint32_t(__shfl_down(int(b2[j]), 1u, 64));
+                const uint32_t l1 = j + 1 < J ? uint32_t(__builtin_amdgcn_readlane(int(b1[j + 1 < J ? j + 1 : j]), 0)) : rn.v0;
+                const uint32_t l2 = j + 1 < J ? uint32_t(__builtin_amdgcn_readlane(int(b2[j + 1 < J ? j + 1 : j]), 0)) : rn.v1;
                 if (lane == 63) {
-                    const uint32_t e = wave + 1 < uint32_t(NW) ? uint32_t(j) * NW + wave + 1
-                                                               : uint32_t(j + 1) * NW;
-                    n1 = s_off[2 * e];
-                    n2 = s_off[2 * e + 1];
+                    n1 = l1;
+                    n2 = l2;
                 }
                 b1[j] = n1;
                 b2[j] = n2;
             }
-            // s_off is rewritten only after the barrier of the clean test below
             const uint32_t shift = FAM == FAM_PHILOX32 ? 0u : 32u - args.w;
             const double two_w = FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
 #pragma unroll
@@ -570,7 +577,7 @@ struct PhiloxTile {
             // part of this fill
 #pragma unroll
             for (int j = 0; j < J; ++j) {
-                const uint32_t q = 2u * (uint32_t(j) * B + tid);
+                const uint32_t q = pair_q(j);
                 if (q < lo_off)
                     acc &= ~(1u << (2 * j));
                 if (q + 1 < lo_off)
@@ -585,7 +592,7 @@ struct PhiloxTile {
             const uint64_t ba = __ballot((acc >> (2 * j)) & 1u);
             const uint64_t bb = __ballot((acc >> (2 * j + 1)) & 1u);
             if (lane == 0)
-                s_off[j * NW + wave] = uint32_t(__popcll(ba) + __popcll(bb));
+                s_off[group(j)] = uint32_t(__popcll(ba) + __popcll(bb));
         }
         __syncthreads();
         if (wave == 0)
@@ -610,7 +617,7 @@ struct PhiloxTile {
                 const uint32_t lane = tid & 63u;
 #pragma unroll
                 for (int j = 0; j < J; ++j) {
-                    const uint32_t q = 2u * (uint32_t(j) * B + tid);
+                    const uint32_t q = pair_q(j);
                     if (aligned) {
                         store_two(o + q, v[2 * j], v[2 * j + 1], args.store_mode);
                     } else if (args.store_mode != 1) {
@@ -632,7 +639,7 @@ struct PhiloxTile {
                 const uint64_t left = n - excl;
 #pragma unroll
                 for (int j = 0; j < J; ++j) {
-                    const uint32_t q = 2u * (uint32_t(j) * B + tid);
+                    const uint32_t q = pair_q(j);
                     if (aligned && q + 1 < left) {
                         store_two(o + q, v[2 * j], v[2 * j + 1], args.store_mode);
                     } else {
@@ -647,7 +654,7 @@ struct PhiloxTile {
             }
             return;
         }
-        const uint32_t lane = tid & 63u, wave = tid >> 6;
+        const uint32_t lane = tid & 63u;
         const uint64_t lt = lanemask_lt(lane);
         double *out = seg.out;
 #pragma unroll
@@ -655,7 +662,7 @@ struct PhiloxTile {
             const bool oka = (acc >> (2 * j)) & 1u;
             const bool okb = (acc >> (2 * j + 1)) & 1u;
             const uint64_t ba = __ballot(oka), bb = __ballot(okb);
-            const uint64_t pos_a = excl + s_off[j * NW + wave] +
+            const uint64_t pos_a = excl + s_off[group(j)] +
                                    uint32_t(__popcll(ba & lt) + __popcll(bb & lt));
             const uint64_t pos_b = pos_a + (oka ? 1u : 0u);
             if (oka && okb && pos_b < n && args.store_mode != 1 &&
@@ -670,7 +677,7 @@ struct PhiloxTile {
             const bool last_a = oka && pos_a == n - 1;
             const bool last_b = okb && pos_b == n - 1;
             if (last_a || last_b)
-                *next_counter = wb + 2u * (uint32_t(j) * B + tid) + (last_a ? 1u : 2u);
+                *next_counter = wb + pair_q(j) + (last_a ? 1u : 2u);
         }
     }
 };
