@@ -640,3 +640,33 @@ def test_single_consumption_across_workgroups_repeated(w, forced):
         assert_bits_equal(out.cpu().numpy(), ref.fill(n), f"fill {i}")
         assert g.get_position()[1] == ref.counter
     g.close()
+
+
+# The speculative Philox fills choose their window origin from the output
+# array's address and the start position, so that every tile after the first
+# starts on a 4 KB boundary; a window then starts on a Philox block's second
+# pair whenever the two disagree in parity.  Every combination, at rejection
+# rates that make the repair pass redo most tiles.
+@pytest.mark.parametrize("gen,w", [("philox", 8), ("philox", 32), ("enumerate", 6)])
+@pytest.mark.parametrize("path", ["speculative", "speculative-hold"])
+@pytest.mark.parametrize("slot", [0, 1, 2, 255, 510, 511])
+def test_window_origin_on_the_4k_grid(gen, w, path, slot):
+    prngd.set_tuning(gen, w, path=path)
+    base = torch.empty(70000 + 1024, dtype=torch.float64, device=DEV)
+    # the view's first output sits `slot` doubles into a 4 KB block
+    shift = ((-base.data_ptr()) % 4096) // 8
+    for counter, n in [(0, 1000), (1, 50001), (2, 50001), (600, 65536), (2**33 + 1, 69999)]:
+        note(f"window origin {gen} w={w} {path} slot={slot} counter={counter} n={n}")
+        off = shift + slot
+        base.view(torch.int64).fill_(int(NAN_BITS))
+        out = base[off:off + n]
+        g = prngd.Generator(29, gen, w=w)
+        g.set_position(0, counter)
+        g.fill(out)
+        torch.cuda.synchronize()
+        host = base.cpu().numpy().view(np.uint64)
+        assert np.all(host[:off] == NAN_BITS) and np.all(host[off + n:] == NAN_BITS)
+        expect, ectr = oracle_fill(gen, w, 29, 0, counter, n)
+        assert_bits_equal(out.cpu().numpy(), expect, f"slot {slot} counter {counter}")
+        assert g.get_position()[1] == ectr
+        g.close()
