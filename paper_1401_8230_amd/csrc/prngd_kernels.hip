@@ -2036,27 +2036,35 @@ struct SingleWords {
     static constexpr int J = 4;                     // Philox blocks per thread
     static constexpr uint32_t T = uint32_t(B) * 4u * J;   // words per window
 
-    // the four words of thread-block (j, tid) of window `win`
+    // the four words of Philox block blk
+    __device__ __forceinline__ static void block(const LaunchArgs &args, const Segment &seg,
+                                                 uint64_t blk, uint32_t u[4])
+    {
+        const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u, seg.stream_id,
+                                       uint32_t(seg.seed), uint32_t(seg.seed >> 32));
+        const uint32_t sh = FAM == FAM_PHILOX32 ? 0u : 32u - args.w;
+        u[0] = r.v0 >> sh;
+        u[1] = r.v1 >> sh;
+        u[2] = r.v2 >> sh;
+        u[3] = r.v3 >> sh;
+    }
+
+    // the four words of thread-block (j, tid) of the window starting at word
+    // wb: a multiple of 4 for the Philox families, even for the test
+    // generator, whose words come two to a pair
     __device__ __forceinline__ static void words(const LaunchArgs &args, const Segment &seg,
-                                                 uint64_t win, int j, uint32_t u[4])
+                                                 uint64_t wb, int j, uint32_t u[4])
     {
         const uint32_t tid = threadIdx.x;
-        const uint64_t blk = win * (T / 4) + uint32_t(j) * B + tid;
         if (FAM == FAM_ENUM) {
             const uint64_t mask = (uint64_t(1) << args.w) - 1;
-            const uint64_t p0 = 2 * blk, p1 = 2 * blk + 1;   // pairs 2b, 2b + 1
+            const uint64_t p0 = (wb >> 1) + 2 * (uint64_t(j) * B + tid), p1 = p0 + 1;
             u[0] = uint32_t((p0 >> args.w) & mask);
             u[1] = uint32_t(p0 & mask);
             u[2] = uint32_t((p1 >> args.w) & mask);
             u[3] = uint32_t(p1 & mask);
         } else {
-            const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u, seg.stream_id,
-                                           uint32_t(seg.seed), uint32_t(seg.seed >> 32));
-            const uint32_t sh = FAM == FAM_PHILOX32 ? 0u : 32u - args.w;
-            u[0] = r.v0 >> sh;
-            u[1] = r.v1 >> sh;
-            u[2] = r.v2 >> sh;
-            u[3] = r.v3 >> sh;
+            block(args, seg, (wb >> 2) + uint32_t(j) * B + tid, u);
         }
     }
 };
@@ -2095,6 +2103,8 @@ struct SingleScratch {
         double stage[T / 2 + T / 32];      // a clean window's outputs (staged store)
     };
     uint32_t last[SingleWords<NW, FAM>::J][NW];   // word 3 of lane 63, per (j, wave)
+    uint2 head[SingleWords<NW, FAM>::J][NW];      // words 0, 1 of lane 0, per (j, wave)
+    uint2 tail;                                   // words 0, 1 of the block after the window
     SingleState state;
 };
 
@@ -2148,22 +2158,28 @@ __device__ __forceinline__ uint32_t single_word_at(const LaunchArgs &args, const
     return FAM == FAM_PHILOX32 ? v : v >> (32u - args.w);
 }
 
-// The words of window `win` into u; returns whether this thread holds a
-// word of the fill (q >= lo) equal to a0 or a.  MRG32k3a words are stepped
-// 16 consecutive ones per thread from one jump and regrouped through
-// s_stage (T words of LDS); every thread must call it.
+// The words of the window starting at word wb into u (wb even; a multiple of
+// T for MRG32k3a, whose jump tables step whole windows); returns whether
+// this thread holds a word of the fill (q >= lo) equal to a0 or a.
+// MRG32k3a words are stepped 16 consecutive ones per thread from one jump
+// and regrouped through LDS.  A Philox window that starts on a block's third
+// word gives thread-block (j, tid) words 2 and 3 of its own block and words
+// 0 and 1 of the next one, which the next lane holds (lane 63: lane 0 of the
+// next wave, through LDS; the window's last thread: one more block).  Every
+// thread must call it.
 template <int NW, uint32_t FAM>
 __device__ __forceinline__ bool single_generate(const LaunchArgs &args, const Segment &seg,
-                                                uint64_t win, uint32_t lo,
+                                                uint64_t wb, uint32_t lo,
                                                 uint32_t (&u)[SingleWords<NW, FAM>::J][4],
-                                                uint32_t *s_stage)
+                                                SingleScratch<NW, FAM> &sm)
 {
     using W = SingleWords<NW, FAM>;
     const uint32_t tid = threadIdx.x;
+    uint32_t *s_stage = sm.words;
     if (FAM == FAM_MRG) {
         static_assert(FAM != FAM_MRG || (W::T == kSingleWindowWords && W::B == 256),
                       "the MRG32k3a tables assume 256 threads and 4096-word windows");
-        Mrg g = mrg_at_window(args, seg, win, tid);
+        Mrg g = mrg_at_window(args, seg, wb / W::T, tid);
         uint32_t x[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k)
@@ -2182,11 +2198,48 @@ __device__ __forceinline__ bool single_generate(const LaunchArgs &args, const Se
             u[j][3] = v.w;
         }
     }
+    if (FAM != FAM_MRG) {
+#pragma unroll
+        for (int j = 0; j < W::J; ++j)
+            W::words(args, seg, wb, j, u[j]);
+    }
+    constexpr bool kPhilox = FAM == FAM_PHILOX || FAM == FAM_PHILOX32;
+    if (kPhilox && (wb & 2u)) {
+        // u[j] holds block (wb >> 2) + j B + tid, the block of the window's
+        // first word at j = tid = 0
+        const uint32_t lane = tid & 63u, wave = tid >> 6;
+        const uint64_t blk0 = wb >> 2;
+        if (lane == 0) {
+#pragma unroll
+            for (int j = 0; j < W::J; ++j)
+                sm.head[j][wave] = make_uint2(u[j][0], u[j][1]);
+        }
+        if (tid == W::B - 1) {
+            uint32_t x[4];
+            W::block(args, seg, blk0 + uint64_t(W::J) * W::B, x);
+            sm.tail = make_uint2(x[0], x[1]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < W::J; ++j) {
+            uint32_t n0 = uint32_t(__shfl_down(int(u[j][0]), 1u, 64));
+            uint32_t n1 = uint32_t(__shfl_down(int(u[j][1]), 1u, 64));
+            if (lane == 63) {
+                const uint2 e = wave + 1 < uint32_t(NW) ? sm.head[j][wave + 1]
+                                : j + 1 < W::J          ? sm.head[j + 1][0]
+                                                        : sm.tail;
+                n0 = e.x;
+                n1 = e.y;
+            }
+            u[j][0] = u[j][2];
+            u[j][1] = u[j][3];
+            u[j][2] = n0;
+            u[j][3] = n1;
+        }
+    }
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < W::J; ++j) {
-        if (FAM != FAM_MRG)
-            W::words(args, seg, win, j, u[j]);
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
             const uint32_t q = 4u * (uint32_t(j) * W::B + tid) + l;
@@ -2196,7 +2249,8 @@ __device__ __forceinline__ bool single_generate(const LaunchArgs &args, const Se
     return bad;
 }
 
-// Produces the outputs whose r2 word lies in window `win` (words q >= lo of
+// Produces the outputs whose r2 word lies in the window starting at word wb
+// (words q >= lo of
 // it belong to the fill), from the incoming state ss, which must be the
 // same in every thread; stores only outputs below n, and the thread that
 // stores output n - 1 writes the next word position.  Leaves ss as the
@@ -2204,7 +2258,7 @@ __device__ __forceinline__ bool single_generate(const LaunchArgs &args, const Se
 // single_generate.
 template <int NW, uint32_t FAM>
 __device__ __forceinline__ void single_window_store(const LaunchArgs &args, const Segment &seg,
-                                                    uint64_t win, uint32_t lo,
+                                                    uint64_t wb, uint32_t lo,
                                                     const uint32_t (&u)[SingleWords<NW, FAM>::J][4],
                                                     bool bad, SingleState &ss,
                                                     uint64_t *next_counter,
@@ -2247,7 +2301,7 @@ __device__ __forceinline__ void single_window_store(const LaunchArgs &args, cons
                         store_one(o + 2 * m + 1, zb, args.store_mode);
                 }
                 if (!whole && (2 * m + 1 == left || 2 * m + 2 == left))
-                    *next_counter = win * T + 2 * (left - 1) + r2_of_0 + 1;
+                    *next_counter = wb + 2 * (left - 1) + r2_of_0 + 1;
             }
         } else {
             // word 4m - 1 is word 3 of the previous thread-block
@@ -2283,11 +2337,11 @@ __device__ __forceinline__ void single_window_store(const LaunchArgs &args, cons
                         store_one(o + 2 * m + 1, zb, args.store_mode);
                 }
                 if (!whole && (2 * m + 1 == left || 2 * m + 2 == left))
-                    *next_counter = win * T + 2 * (left - 1) + r2_of_0 + 1;
+                    *next_counter = wb + 2 * (left - 1) + r2_of_0 + 1;
             }
-            // the window's last word is the next pending r1
+            // the window's last word is the next pending r1 (`last` is next
+            // written after the barrier that opens the next window's store)
             ss.pending = sm.last[J - 1][NW - 1];
-            __syncthreads();
         }
         if (staged) {
             __syncthreads();
@@ -2334,7 +2388,7 @@ __device__ __forceinline__ void single_window_store(const LaunchArgs &args, cons
                 store_one(seg.out + pos, prngd_map(x1, x, args, two_w),
                           args.store_mode == 1 ? 0u : args.store_mode);
                 if (pos == n - 1)
-                    *next_counter = win * T + q + 1;
+                    *next_counter = wb + q + 1;
             }
             running += uint64_t(__popcll(ball));
             state = uint32_t(__shfl(int(after), 63, 64));
@@ -2376,14 +2430,14 @@ __global__ __launch_bounds__(64 * NW) void seq_single_kernel(LaunchArgs args)
         const uint32_t par = seg.parity ^ st0.flip;
         const uint64_t c0 = load_start(seg, par);
         uint64_t *next_counter = seg.counter + (par ^ 1u);
-        uint64_t win = c0 / T;
-        uint32_t lo = uint32_t(c0 - win * T);
+        uint64_t wb = (c0 / T) * T;
+        uint32_t lo = uint32_t(c0 - wb);
         SingleState ss{0, 0, 0};
         while (ss.running < seg.n) {
             uint32_t u[W::J][4];
-            const bool bad = single_generate<NW, FAM>(args, seg, win, lo, u, sm.words);
-            single_window_store<NW, FAM>(args, seg, win, lo, u, bad, ss, next_counter, sm, two_w);
-            ++win;
+            const bool bad = single_generate<NW, FAM>(args, seg, wb, lo, u, sm);
+            single_window_store<NW, FAM>(args, seg, wb, lo, u, bad, ss, next_counter, sm, two_w);
+            wb += T;
             lo = 0;
         }
         if (tid == 0)
@@ -2402,7 +2456,8 @@ __global__ __launch_bounds__(64 * NW) void seq_single_kernel(LaunchArgs args)
 // E iff r - h is even and floor((r - h) / 2) outputs are complete.  Every
 // quantity a window needs thus follows from the candidates before it.
 //
-// spec_words_kernel: a one-shot grid, tile t = window w0 + t of T words.
+// spec_words_kernel: a one-shot grid, tile t = the window of T words that
+// starts at word c0 - lo0 + t T.
 // The tile generates its words, appends each of its candidates to the
 // launch's list ((t + 1) << 32 | word in window), then reads the list and
 // takes the rejected r1 among the earlier tiles' candidates it can see (its
@@ -2492,9 +2547,27 @@ __device__ __forceinline__ uint32_t read_word_hint(const LaunchArgs &args, uint3
 
 // Incoming state of tile t >= 1 of a fill that starts lo0 words into its
 // first window, with h rejected r1 before it.
+// Words of a one-word fill's first window that lie before the fill's
+// first word c0.  A clean window t >= 1 then starts at output
+// floor((t T - lo0) / 2), so lo0 = 2a (c0 even: state E) or 2a - 1 (c0 odd:
+// state P, the output taking the word before the window as r1), modulo 1024
+// words, puts its outputs on the 4 KB grid of out (a = the 8-byte slot of
+// out within its 4 KB block), and every window starts on an even word.
+// MRG32k3a keeps windows on multiples of T, the jumps its tables hold.
+template <uint32_t FAM, uint32_t T>
+__device__ __forceinline__ uint32_t word_lo0(const Segment &seg, uint64_t c0)
+{
+    static_assert(T % 1024 == 0, "the window must cover whole 4 KB blocks of outputs");
+    if (FAM == FAM_MRG)
+        return uint32_t(c0 % T);
+    const uint32_t a = uint32_t((reinterpret_cast<uintptr_t>(seg.out) >> 3) & 511u);
+    const uint32_t lo = (2u * a - (uint32_t(c0) & 1u)) & 1023u;
+    return c0 >= lo ? lo : uint32_t(c0 & 1u);
+}
+
 template <uint32_t FAM, uint32_t T>
 __device__ __forceinline__ SingleState single_entry(const LaunchArgs &args, const Segment &seg,
-                                                    uint64_t win, uint32_t t, uint32_t lo0,
+                                                    uint64_t wb, uint32_t t, uint32_t lo0,
                                                     uint32_t h)
 {
     const uint64_t done = uint64_t(t) * T - lo0 - h;   // words used by complete or pending outputs
@@ -2503,12 +2576,12 @@ __device__ __forceinline__ SingleState single_entry(const LaunchArgs &args, cons
     ss.st = uint32_t(done & 1u);
     ss.pending = 0;
     if (ss.st && threadIdx.x == 0)
-        ss.pending = single_word_at<FAM>(args, seg, win * T - 1u);
+        ss.pending = single_word_at<FAM>(args, seg, wb - 1u);
     return ss;
 }
 
 template <int NW, uint32_t FAM>
-__global__ __launch_bounds__(64 * NW) void spec_words_kernel(LaunchArgs args)
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(5))) void spec_words_kernel(LaunchArgs args)
 {
     using W = SingleWords<NW, FAM>;
     constexpr uint32_t T = W::T;
@@ -2522,12 +2595,11 @@ __global__ __launch_bounds__(64 * NW) void spec_words_kernel(LaunchArgs args)
     const TileStart ts = tile_start<true>(args, t);
     const Segment &seg = ts.seg;
     uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
-    const uint64_t w0 = ts.c0 / T;
-    const uint32_t lo0 = uint32_t(ts.c0 - w0 * T);
-    const uint64_t win = w0 + t;
+    const uint32_t lo0 = word_lo0<FAM, T>(seg, ts.c0);
+    const uint64_t wb = ts.c0 - lo0 + uint64_t(t) * T;   // the window's first word
     const uint32_t lo = t == 0 ? lo0 : 0u;
     uint32_t u[J][4];
-    const bool bad = single_generate<NW, FAM>(args, seg, win, lo, u, sm.words);
+    const bool bad = single_generate<NW, FAM>(args, seg, wb, lo, u, sm);
     if (bad) {
 #pragma unroll
         for (int j = 0; j < J; ++j)
@@ -2541,12 +2613,12 @@ __global__ __launch_bounds__(64 * NW) void spec_words_kernel(LaunchArgs args)
     const uint32_t h = read_word_hint<T>(args, t, lo0, s_vis, &s_nv, &s_h);
     SingleState ss{0, 0, 0};
     if (t > 0)
-        ss = single_entry<FAM, T>(args, seg, win, t, lo0, h);
-    single_window_store<NW, FAM>(args, seg, win, lo, u, bad, ss, next_counter, sm, two_w);
+        ss = single_entry<FAM, T>(args, seg, wb, t, lo0, h);
+    single_window_store<NW, FAM>(args, seg, wb, lo, u, bad, ss, next_counter, sm, two_w);
     if (t == seg.ntiles - 1) {
-        for (uint64_t w2 = win + 1; ss.running < seg.n; ++w2) {
+        for (uint64_t w2 = wb + T; ss.running < seg.n; w2 += T) {
             uint32_t v[J][4];
-            const bool b2 = single_generate<NW, FAM>(args, seg, w2, 0u, v, sm.words);
+            const bool b2 = single_generate<NW, FAM>(args, seg, w2, 0u, v, sm);
             single_window_store<NW, FAM>(args, seg, w2, 0u, v, b2, ss, next_counter, sm, two_w);
         }
     }
@@ -2640,8 +2712,8 @@ __global__ __launch_bounds__(64 * NW) void spec_words_repair_kernel(LaunchArgs a
     const uint32_t par = (seg.parity ^ read_flip(args)) & 1u;
     const uint64_t c0 = load_start(seg, par);
     uint64_t *next_counter = seg.counter + (par ^ 1u);
-    const uint64_t w0 = c0 / T;
-    const uint32_t lo0 = uint32_t(c0 - w0 * T);
+    const uint32_t lo0 = word_lo0<FAM, T>(seg, c0);
+    const uint64_t wb0 = c0 - lo0;   // the first window's first word
     if (cnt <= kRepairCache) {
         for (uint32_t i = tid; i < cnt; i += B) {
             const uint64_t e = __hip_atomic_load(&args.rejlist[i], __ATOMIC_RELAXED,
@@ -2682,15 +2754,15 @@ __global__ __launch_bounds__(64 * NW) void spec_words_repair_kernel(LaunchArgs a
             for (uint32_t k = 0; k < nq; ++k) {
                 const uint32_t g = __builtin_amdgcn_readfirstlane(s_queue[k]);
                 const uint32_t hg = __builtin_amdgcn_readfirstlane(s_qh[k]);
-                const uint64_t win = w0 + g;
-                SingleState ss = single_entry<FAM, T>(args, seg, win, g, lo0, hg);
+                const uint64_t wb = wb0 + uint64_t(g) * T;
+                SingleState ss = single_entry<FAM, T>(args, seg, wb, g, lo0, hg);
                 uint32_t u[J][4];
-                const bool bad = single_generate<NW, FAM>(args, seg, win, 0u, u, sm.words);
-                single_window_store<NW, FAM>(args, seg, win, 0u, u, bad, ss, next_counter, sm,
+                const bool bad = single_generate<NW, FAM>(args, seg, wb, 0u, u, sm);
+                single_window_store<NW, FAM>(args, seg, wb, 0u, u, bad, ss, next_counter, sm,
                                              two_w);
                 if (g == seg.ntiles - 1) {
-                    for (uint64_t w2 = win + 1; ss.running < seg.n; ++w2) {
-                        const bool b2 = single_generate<NW, FAM>(args, seg, w2, 0u, u, sm.words);
+                    for (uint64_t w2 = wb + T; ss.running < seg.n; w2 += T) {
+                        const bool b2 = single_generate<NW, FAM>(args, seg, w2, 0u, u, sm);
                         single_window_store<NW, FAM>(args, seg, w2, 0u, u, b2, ss, next_counter,
                                                      sm, two_w);
                     }
@@ -2714,16 +2786,16 @@ __global__ __launch_bounds__(64 * NW) void spec_words_repair_kernel(LaunchArgs a
         atomicMin(&s_first, first);
         __syncthreads();
         const uint32_t f = __builtin_amdgcn_readfirstlane(s_first);
-        uint64_t win = w0 + f;
+        uint64_t wb = wb0 + uint64_t(f) * T;
         uint32_t lo = f == 0 ? lo0 : 0u;
         SingleState ss{0, 0, 0};
         if (f > 0)
-            ss = single_entry<FAM, T>(args, seg, win, f, lo0, 0u);
+            ss = single_entry<FAM, T>(args, seg, wb, f, lo0, 0u);
         while (ss.running < seg.n) {
             uint32_t u[J][4];
-            const bool bad = single_generate<NW, FAM>(args, seg, win, lo, u, sm.words);
-            single_window_store<NW, FAM>(args, seg, win, lo, u, bad, ss, next_counter, sm, two_w);
-            ++win;
+            const bool bad = single_generate<NW, FAM>(args, seg, wb, lo, u, sm);
+            single_window_store<NW, FAM>(args, seg, wb, lo, u, bad, ss, next_counter, sm, two_w);
+            wb += T;
             lo = 0;
         }
     }

@@ -670,3 +670,33 @@ def test_window_origin_on_the_4k_grid(gen, w, path, slot):
         assert_bits_equal(out.cpu().numpy(), expect, f"slot {slot} counter {counter}")
         assert g.get_position()[1] == ectr
         g.close()
+
+
+# The one-word fills spread over workgroups choose their window origin the
+# same way, in words, from the output array's slot a within its 4 KB block
+# and the start position c0: windows that start on a Philox block's first
+# or third word, starts too close to the stream's beginning for the origin,
+# and MRG32k3a, whose windows stay on multiples of 4096 words.
+@pytest.mark.parametrize("gen,w", [("philox", 10), ("philox", 32), ("enumerate", 12),
+                                   ("mrg32k3a", 32)])
+@pytest.mark.parametrize("slot", [0, 1, 2, 3, 255, 511])
+def test_word_window_origin_on_the_4k_grid(gen, w, slot):
+    prngd.set_tuning(gen, w, path=3)
+    base = torch.empty(70000 + 1024, dtype=torch.float64, device=DEV)
+    shift = ((-base.data_ptr()) % 4096) // 8
+    for counter, n in [(0, 40000), (1, 50001), (2, 50001), (3, 65536), (1021, 2**15),
+                       (4098, 50001), (2**33 + 1, 69999)]:
+        note(f"word window origin {gen} w={w} slot={slot} counter={counter} n={n}")
+        off = shift + slot
+        base.view(torch.int64).fill_(int(NAN_BITS))
+        out = base[off:off + n]
+        g = prngd.Generator(37, gen, w=w, consume="single")
+        g.set_position(0, counter)
+        g.fill(out)
+        torch.cuda.synchronize()
+        host = base.cpu().numpy().view(np.uint64)
+        assert np.all(host[:off] == NAN_BITS) and np.all(host[off + n:] == NAN_BITS)
+        s = O.PRNGD(OGEN[gen], w, seed=37, counter=counter, consume=O.CONSUME_SINGLE)
+        assert_bits_equal(out.cpu().numpy(), s.fill(n), f"slot {slot} counter {counter}")
+        assert g.get_position()[1] == s.counter
+        g.close()

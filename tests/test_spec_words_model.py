@@ -1,16 +1,17 @@
 """A CPU model of the one-word-consumption fill across workgroups.
 
 Under Algorithm 1's one-word redraw, word r of a fill is a *candidate* when
-it equals a0 or a.  The speculative kernel lets every window of T words be
-produced by its own workgroup from a hint -- the rejected r1 it can infer
+it equals a0 or a.  The speculative kernel lets every window of T words
+(the first one starting lo0 <= c0 words before the fill's first word c0,
+lo0 < T chosen freely) be produced by its own workgroup from a hint -- the rejected r1 it can infer
 from the earlier windows' candidates published so far -- and a repair pass
 then produces again exactly the windows that (a) took a hint below the
 truth, (b) may hold values a wrong earlier window wrote past its true end,
 or (c) hold output n - 1, or are the last window, behind a wrong one.
 
 This model replays that with small windows, small w (so that candidates
-are everywhere), random start positions, random hint visibility and random
-window execution orders, and checks that the final outputs (modelled as
+are everywhere), random start positions and window origins, random hint
+visibility and random window execution orders, and checks that the final outputs (modelled as
 the word indices of each output's r1 and r2) and the final word position
 equal Algorithm 1's sequential walk.  It also checks the two facts the
 kernels rest on: a candidate is a rejected r1 exactly when its distance to
@@ -46,11 +47,11 @@ def skips_of(rs):
     return k
 
 
-def walk_window(words, a0, a, c0, T, win, lo, state, running, n, mem, counter):
-    """Produce window `win` (absolute words win*T + lo ..) from (state,
+def walk_window(words, a0, a, c0, T, wb, lo, state, running, n, mem, counter):
+    """Produce the window of words wb + lo .. wb + T - 1 from (state,
     running) exactly; writes outputs below n into mem and the counter for
     output n - 1.  Returns the state after the window."""
-    for q in range(win * T + lo, (win + 1) * T):
+    for q in range(wb + lo, wb + T):
         if running >= n:
             break
         if state == 0:
@@ -71,7 +72,8 @@ def simulate(w, T, c0, n, seed, drop_rule=None):
     total = c0 + 4 * n + 40 * T + 64
     words = [rnd.randrange(2 ** w) for _ in range(total)]
     truth, true_counter = sequential(words, a0, a, c0, n)
-    w0, lo0 = divmod(c0, T)
+    lo0 = c0 % T if rnd.random() < 0.3 else rnd.randrange(0, min(c0, T - 1) + 1)
+    wb0 = c0 - lo0   # the first window's first word
     planned_words = 2 * (n + rnd.randint(0, 3))
     ntiles = -(-planned_words // T) + 1
 
@@ -80,7 +82,7 @@ def simulate(w, T, c0, n, seed, drop_rule=None):
     for t in range(ntiles):
         lo = lo0 if t == 0 else 0
         for qq in range(lo, T):
-            q = (w0 + t) * T + qq
+            q = wb0 + t * T + qq
             if words[q] in (a0, a):
                 cands.setdefault(t, []).append(q - c0)
     all_before = lambda t: [r for v in range(t) for r in cands.get(v, [])]
@@ -102,14 +104,14 @@ def simulate(w, T, c0, n, seed, drop_rule=None):
             done = t * T - lo0 - h
             state, running = done & 1, done >> 1
         lo = lo0 if t == 0 else 0
-        state, running = walk_window(words, a0, a, c0, T, w0 + t, lo, state, running, n, mem,
-                                     counter)
+        state, running = walk_window(words, a0, a, c0, T, wb0 + t * T, lo, state, running, n,
+                                     mem, counter)
         if t == ntiles - 1:
-            w2 = w0 + t + 1
+            w2 = wb0 + (t + 1) * T
             while running < n:
                 state, running = walk_window(words, a0, a, c0, T, w2, 0, state, running, n, mem,
                                              counter)
-                w2 += 1
+                w2 += T
 
     # repair, from the complete list
     cnt = sum(len(v) for v in cands.values())
@@ -158,14 +160,14 @@ def simulate(w, T, c0, n, seed, drop_rule=None):
     rnd.shuffle(redo)
     for g, h in redo:
         done = g * T - lo0 - h
-        state, running = walk_window(words, a0, a, c0, T, w0 + g, 0, done & 1, done >> 1, n,
-                                     mem, counter)
+        state, running = walk_window(words, a0, a, c0, T, wb0 + g * T, 0, done & 1, done >> 1,
+                                     n, mem, counter)
         if g == ntiles - 1:
-            w2 = w0 + g + 1
+            w2 = wb0 + (g + 1) * T
             while running < n:
                 state, running = walk_window(words, a0, a, c0, T, w2, 0, state, running, n,
                                              mem, counter)
-                w2 += 1
+                w2 += T
     return mem == truth and counter[0] == true_counter
 
 
