@@ -677,8 +677,8 @@ def test_window_origin_on_the_4k_grid(gen, w, path, slot):
 # and the start position c0: windows that start on a Philox block's first
 # or third word, starts too close to the stream's beginning for the origin,
 # and MRG32k3a, whose windows stay on multiples of 4096 words.
-@pytest.mark.parametrize("gen,w", [("philox", 10), ("philox", 32), ("enumerate", 12),
-                                   ("mrg32k3a", 32)])
+@pytest.mark.parametrize("gen,w", [("philox", 10), ("philox", 16), ("philox", 32),
+                                   ("enumerate", 12), ("mrg32k3a", 32)])
 @pytest.mark.parametrize("slot", [0, 1, 2, 3, 255, 511])
 def test_word_window_origin_on_the_4k_grid(gen, w, slot):
     prngd.set_tuning(gen, w, path=3)
