@@ -105,6 +105,43 @@ def cpu_baseline(streams, n_each, seed):
                       f"each ({total} outputs, {dt:.1f} s, one thread)"}
 
 
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_all_cores(streams, n_each, seed, max_threads=16):
+    """The same oracle on every host core given to this process (at most
+    max_threads), one independent substream per task; the oracle's C calls
+    run without the interpreter lock."""
+    import oracle as O
+    from concurrent.futures import ThreadPoolExecutor
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    threads = max(1, min(ncpu, max_threads))
+
+    def one(s):
+        O.PRNGD(O.GEN_PHILOX, 32, seed=seed, stream=s).fill(n_each)
+        return n_each
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        total = sum(pool.map(one, range(streams)))
+    dt = time.perf_counter() - t0
+    return {"value": total / dt, "unit": "accepted FP64 uniforms/s", "cores": threads,
+            "kind": "oracle", "nproc": ncpu, "cpu_model": host_cpu_model(),
+            "sample": f"substreams 0..{streams - 1} of the same workload, {n_each} outputs "
+                      f"each ({total} outputs, {dt:.1f} s, {threads} threads)"}
+
+
 def cpu_baseline_single(n, seed):
     import oracle as O
     t0 = time.perf_counter()
@@ -392,6 +429,10 @@ def main():
         else:
             result["cpu_baseline"] = cpu_baseline(
                 min(args.cpu_sample_streams, args.streams), args.outputs_per_stream, args.seed)
+            if not args.headline_only:
+                log("cpu baseline, all cores")
+                result["cpu_baseline_all_cores"] = cpu_baseline_all_cores(
+                    args.streams, args.outputs_per_stream, args.seed)
     print(json.dumps(result), flush=True)
 
 
