@@ -165,6 +165,22 @@ def timed(fn, steps, stream):
     return start.elapsed_time(stop) / 1e3 / steps
 
 
+def per_step(fn, steps, stream):
+    """Median, min and max milliseconds of `steps` further calls of fn, each
+    between its own pair of HIP events on `stream` (after the timed region,
+    so that it does not disturb it)."""
+    import torch
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    evs[0].record(stream)
+    for i in range(steps):
+        fn()
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    ms = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
+    return {"median": ms[len(ms) // 2], "min": ms[0], "max": ms[-1], "steps": steps}
+
+
 def run_many_streams(args, result):
     import torch
     from paper_1401_8230_amd import prngd
@@ -189,6 +205,7 @@ def run_many_streams(args, result):
     step_s = timed(lambda: plan.launch(stream), args.steps, stream)
     wall = time.perf_counter() - t0
     log(f"many streams: timed {args.steps} steps, {step_s * 1e3:.3f} ms per step")
+    dist = per_step(lambda: plan.launch(stream), args.steps, stream)
     outputs = S * n
     lo, hi = float(out.min()), float(out.max())
     if not (0.0 <= lo and hi < 1.0):
@@ -207,6 +224,7 @@ def run_many_streams(args, result):
         "value": outputs / step_s,
         "ms_per_step": step_s * 1e3,
         "wall_ms_per_step": wall / args.steps * 1e3,
+        "step_ms": dist,
         "config": {
             "workload": f"{S} Philox4x32-10 substreams of seed {args.seed}, w=32, "
                         f"{n} FP64 outputs each, one resident batch per step"
@@ -247,6 +265,7 @@ def run_single(args, result):
     step_s = timed(lambda: g.fill(out, stream=stream), args.steps, stream)
     wall = time.perf_counter() - t0
     log(f"single stream: {n} outputs, {step_s * 1e3:.3f} ms per fill")
+    dist = per_step(lambda: g.fill(out, stream=stream), args.steps, stream)
     if args.calibrate:
         half = n // 2
         prngd.probe_copy(out[half:2 * half], out[:half], stream)
@@ -260,6 +279,7 @@ def run_single(args, result):
         "value": n / step_s,
         "ms_per_step": step_s * 1e3,
         "wall_ms_per_step": wall / args.steps * 1e3,
+        "step_ms": dist,
         "config": {"workload": f"one Philox4x32-10 stream of seed {args.seed}, w=32, "
                                f"{n} FP64 outputs per fill"
                                + ("" if default_form else
