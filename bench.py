@@ -56,6 +56,9 @@ def parse():
                     help="timed step: the resident many-streams batch (default), or one "
                          "prngd_fill of --single-outputs outputs of one Philox stream")
     ap.add_argument("--single-outputs", type=int, default=1 << 30)
+    ap.add_argument("--generator", choices=["philox", "mrg32k3a", "mixed"], default="philox",
+                    help="base generator of the single-stream workload (w = 32; mixed: "
+                         "x1 from Philox4x32-10, x2 from MRG32k3a)")
     ap.add_argument("--consume", choices=["pair", "single"], default="pair",
                     help="what a rejected x1 consumes (single: Algorithm 1's loop)")
     ap.add_argument("--map", choices=["eq5", "eq4", "one_minus"], default="eq5",
@@ -142,10 +145,11 @@ def cpu_baseline_all_cores(streams, n_each, seed, max_threads=16):
                       f"each ({total} outputs, {dt:.1f} s, {threads} threads)"}
 
 
-def cpu_baseline_single(n, seed):
+def cpu_baseline_single(n, seed, generator="philox"):
     import oracle as O
+    gen = {"philox": O.GEN_PHILOX, "mrg32k3a": O.GEN_MRG32K3A, "mixed": O.GEN_MIXED}[generator]
     t0 = time.perf_counter()
-    O.PRNGD(O.GEN_PHILOX, 32, seed=seed, stream=0).fill(n)
+    O.PRNGD(gen, 32, seed=seed, stream=0).fill(n)
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "accepted FP64 uniforms/s", "cores": 1, "kind": "oracle",
             "sample": f"the first {n} outputs of the same stream ({dt:.1f} s, one thread)"}
@@ -248,13 +252,17 @@ def run_many_streams(args, result):
     })
 
 
+GENERATOR_NAMES = {"philox": "Philox4x32-10", "mrg32k3a": "MRG32k3a",
+                   "mixed": "Philox4x32-10 (x1) and MRG32k3a (x2)"}
+
+
 def run_single(args, result):
-    """One Philox4x32-10 stream (seed, substream 0), w = 32: each step is one
+    """One stream of --generator (seed, substream 0), w = 32: each step is one
     prngd_fill of --single-outputs outputs, continuing the stream."""
     import torch
     from paper_1401_8230_amd import prngd
     n = args.single_outputs
-    g = prngd.Generator(args.seed, "philox", w=32, map=args.map,
+    g = prngd.Generator(args.seed, args.generator, w=32, map=args.map,
                         consume=None if args.consume == "pair" else args.consume)
     out = torch.empty(n, dtype=torch.float64, device="cuda:0")
     stream = torch.cuda.current_stream()
@@ -274,15 +282,15 @@ def run_single(args, result):
     del out
     achieved_gbs = n * BYTES_PER_OUTPUT / step_s / 1e9
     # the counters were taken on the default form (pair consumption, Eq. (5))
-    default_form = args.consume == "pair" and args.map == "eq5"
+    default_form = args.consume == "pair" and args.map == "eq5" and args.generator == "philox"
     result.update({
         "value": n / step_s,
         "ms_per_step": step_s * 1e3,
         "wall_ms_per_step": wall / args.steps * 1e3,
         "step_ms": dist,
-        "config": {"workload": f"one Philox4x32-10 stream of seed {args.seed}, w=32, "
-                               f"{n} FP64 outputs per fill"
-                               + ("" if default_form else
+        "config": {"workload": f"one {GENERATOR_NAMES[args.generator]} stream of seed "
+                               f"{args.seed}, w=32, {n} FP64 outputs per fill"
+                               + ("" if args.consume == "pair" and args.map == "eq5" else
                                   f", consume={args.consume}, map={args.map}"),
                    "outputs_per_step": n,
                    "launch": "prngd_fill (speculative fill and its repair pass)"},
@@ -445,7 +453,7 @@ def main():
         log("cpu baseline")
         if args.workload == "single":
             result["cpu_baseline"] = cpu_baseline_single(min(args.single_outputs, 1 << 28),
-                                                         args.seed)
+                                                         args.seed, args.generator)
         else:
             result["cpu_baseline"] = cpu_baseline(
                 min(args.cpu_sample_streams, args.streams), args.outputs_per_stream, args.seed)

@@ -30,6 +30,8 @@ def test_cpu_baselines_report_their_sample():
     assert "8192 outputs" in many["sample"]
     single = bench.cpu_baseline_single(2048, 42)
     assert single["cores"] == 1 and "2048 outputs" in single["sample"]
+    for gen in ("mrg32k3a", "mixed"):
+        assert bench.cpu_baseline_single(2048, 42, gen)["value"] > 0
 
 
 def test_all_core_tasks_fill_what_one_thread_fills():
