@@ -10,7 +10,13 @@ step produces new numbers.
 Prints one JSON line: accepted FP64 uniforms per second, the roofline of
 the fill kernel (HBM write bandwidth; 8 algorithmic bytes per output), the
 CPU oracle's rate on a bounded sample of the same workload, and, unless
---headline-only, two more measurements on the same GPU:
+--headline-only, more measurements on the same GPU:
+
+* single_stream: large fills of one stream, each step one prngd_fill that
+  continues the stream -- Philox4x32-10 at w = 32 with 2^30 outputs per
+  fill (8 GiB), and 2^28 outputs per fill (2 GiB) of the mixed
+  Philox/MRG32k3a generator, of MRG32k3a alone and of Philox at w = 24 --
+  each with its own roofline and a bounded oracle sample;
 
 * batched_vs_plain: 4096 requests with log-uniform sizes in [1e3, 1e7],
   each with its own seed, substream and start position, as one autotuned
@@ -67,6 +73,10 @@ def parse():
     ap.add_argument("--cpu-sample-streams", type=int, default=16384)
     ap.add_argument("--headline-only", action="store_true",
                     help="skip the batched-vs-plain and serving measurements")
+    ap.add_argument("--single-steps", type=int, default=20,
+                    help="timed fills of each single-stream leg")
+    ap.add_argument("--no-single-legs", action="store_true",
+                    help="skip the single-stream legs of the default run")
     ap.add_argument("--uneven-steps", type=int, default=5)
     ap.add_argument("--serving-requests", type=int, default=20000)
     ap.add_argument("--calibrate", action="store_true",
@@ -145,11 +155,11 @@ def cpu_baseline_all_cores(streams, n_each, seed, max_threads=16):
                       f"each ({total} outputs, {dt:.1f} s, {threads} threads)"}
 
 
-def cpu_baseline_single(n, seed, generator="philox"):
+def cpu_baseline_single(n, seed, generator="philox", w=32):
     import oracle as O
     gen = {"philox": O.GEN_PHILOX, "mrg32k3a": O.GEN_MRG32K3A, "mixed": O.GEN_MIXED}[generator]
     t0 = time.perf_counter()
-    O.PRNGD(gen, 32, seed=seed, stream=0).fill(n)
+    O.PRNGD(gen, w, seed=seed, stream=0).fill(n)
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "accepted FP64 uniforms/s", "cores": 1, "kind": "oracle",
             "sample": f"the first {n} outputs of the same stream ({dt:.1f} s, one thread)"}
@@ -256,48 +266,90 @@ GENERATOR_NAMES = {"philox": "Philox4x32-10", "mrg32k3a": "MRG32k3a",
                    "mixed": "Philox4x32-10 (x1) and MRG32k3a (x2)"}
 
 
-def run_single(args, result):
-    """One stream of --generator (seed, substream 0), w = 32: each step is one
-    prngd_fill of --single-outputs outputs, continuing the stream."""
+def measured_leg_traffic(gen, w, n):
+    """Committed HBM counters of one single-stream leg, if taken on the
+    current kernel source."""
+    name = f"traffic_single_{gen}_w{w}_n{n}.json"
+    if gen == "philox" and w == 32 and n == 1 << 30:
+        return measured_traffic(TRAFFIC_FILE_SINGLE)
+    return measured_traffic(os.path.join(ROOT, "profiles", name))
+
+
+def single_leg(gen, w, n, steps, warmup, seed=42, map="eq5", consume="pair", calibrate=False):
+    """One stream of `gen` at resolution 2^-w (seed, substream 0): each step
+    is one prngd_fill of n outputs continuing the stream."""
     import torch
     from paper_1401_8230_amd import prngd
-    n = args.single_outputs
-    g = prngd.Generator(args.seed, args.generator, w=32, map=args.map,
-                        consume=None if args.consume == "pair" else args.consume)
+    g = prngd.Generator(seed, gen, w=w, map=map,
+                        consume=None if consume == "pair" else consume)
     out = torch.empty(n, dtype=torch.float64, device="cuda:0")
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         g.fill(out, stream=stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    step_s = timed(lambda: g.fill(out, stream=stream), args.steps, stream)
+    step_s = timed(lambda: g.fill(out, stream=stream), steps, stream)
     wall = time.perf_counter() - t0
-    log(f"single stream: {n} outputs, {step_s * 1e3:.3f} ms per fill")
-    dist = per_step(lambda: g.fill(out, stream=stream), args.steps, stream)
-    if args.calibrate:
+    log(f"single stream {gen} w={w}: {n} outputs, {step_s * 1e3:.3f} ms per fill")
+    dist = per_step(lambda: g.fill(out, stream=stream), steps, stream)
+    lo, hi = float(out.min()), float(out.max())
+    if not (0.0 <= lo and hi <= 1.0):
+        raise SystemExit(f"outputs out of range: {lo} {hi}")
+    if calibrate:
         half = n // 2
         prngd.probe_copy(out[half:2 * half], out[:half], stream)
         torch.cuda.synchronize()
     g.close()
     del out
     achieved_gbs = n * BYTES_PER_OUTPUT / step_s / 1e9
-    # the counters were taken on the default form (pair consumption, Eq. (5))
-    default_form = args.consume == "pair" and args.map == "eq5" and args.generator == "philox"
-    result.update({
+    default_form = consume == "pair" and map == "eq5"
+    return {
         "value": n / step_s,
+        "unit": "accepted FP64 uniforms/s",
         "ms_per_step": step_s * 1e3,
-        "wall_ms_per_step": wall / args.steps * 1e3,
+        "wall_ms_per_step": wall / steps * 1e3,
+        "steps": steps,
         "step_ms": dist,
-        "config": {"workload": f"one {GENERATOR_NAMES[args.generator]} stream of seed "
-                               f"{args.seed}, w=32, {n} FP64 outputs per fill"
-                               + ("" if args.consume == "pair" and args.map == "eq5" else
-                                  f", consume={args.consume}, map={args.map}"),
-                   "outputs_per_step": n,
-                   "launch": "prngd_fill (speculative fill and its repair pass)"},
+        "workload": f"one {GENERATOR_NAMES[gen]} stream of seed {seed}, w={w}, {n} FP64 "
+                    f"outputs per fill, each fill continuing the stream"
+                    + ("" if default_form else f", consume={consume}, map={map}"),
+        "outputs_per_step": n,
+        "launch": "prngd_fill",
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(TRAFFIC_FILE_SINGLE) if default_form else None},
+                     "traffic": measured_leg_traffic(gen, w, n) if default_form else None},
+    }
+
+
+# the single-stream legs of the default run: (generator, w, outputs per fill)
+SINGLE_LEGS = [("philox", 32, 1 << 30), ("mixed", 32, 1 << 28), ("mrg32k3a", 32, 1 << 28),
+               ("philox", 24, 1 << 28)]
+
+
+def run_single(args, result):
+    """--workload single: the headline is one stream of --generator, w = 32."""
+    leg = single_leg(args.generator, 32, args.single_outputs, args.steps, args.warmup,
+                     seed=args.seed, map=args.map, consume=args.consume,
+                     calibrate=args.calibrate)
+    result.update({
+        "value": leg["value"],
+        "ms_per_step": leg["ms_per_step"],
+        "wall_ms_per_step": leg["wall_ms_per_step"],
+        "step_ms": leg["step_ms"],
+        "config": {"workload": leg["workload"], "outputs_per_step": leg["outputs_per_step"],
+                   "launch": "prngd_fill (speculative fill and its repair pass)"},
+        "roofline": leg["roofline"],
     })
+
+
+def run_single_legs(args):
+    legs = {}
+    for gen, w, n in SINGLE_LEGS:
+        leg = single_leg(gen, w, n, args.single_steps, args.warmup, seed=args.seed)
+        if not args.no_cpu_baseline:
+            leg["cpu_baseline"] = cpu_baseline_single(min(n, 1 << 22), args.seed, gen, w)
+        legs[f"{gen}_w{w}_n{n}"] = leg
+    return legs
 
 
 def run_uneven(args):
@@ -320,20 +372,14 @@ def run_uneven(args):
         g.set_position(r.stream_id, r.counter)
     stream = torch.cuda.current_stream()
 
-    def checksums():
-        v = arena.view(torch.int64)
-        out, o = [], 0
-        for n in sizes:
-            out.append(v[o:o + n].sum())
-            o += n
-        return torch.stack(out).cpu()
-
     # bit-identity: one batched launch (autotuned shape) and one round of
-    # plain fills (library defaults) from the same start positions
+    # plain fills (library defaults) from the same start positions, compared
+    # output by output on the device (a copy of the batched arena is kept)
     plan = prngd.Plan(list(zip(gens, outs)))
     plan.launch(stream)
     torch.cuda.synchronize()
-    batched_sums = checksums()
+    batched_copy = arena.clone()
+    batched_ends = [g.get_position()[1] for g in gens]
     plan.close()
     prngd.reset_tuning("philox", 32)
     for g, r in zip(gens, reqs):
@@ -341,9 +387,10 @@ def run_uneven(args):
     for g, o in zip(gens, outs):
         g.fill(o, stream=stream)
     torch.cuda.synchronize()
-    plain_sums = checksums()
-    identical = bool(torch.equal(batched_sums, plain_sums))
-    log(f"uneven batch: batched and plain outputs identical: {identical}")
+    identical = bool(torch.equal(batched_copy.view(torch.int64), arena.view(torch.int64))) and \
+        batched_ends == [g.get_position()[1] for g in gens]
+    del batched_copy
+    log(f"uneven batch: batched and plain outputs and end positions identical: {identical}")
 
     # the resident batch is built in the autotuned shape; plain fills keep
     # the library defaults
@@ -446,6 +493,8 @@ def main():
         run_single(args, result)
     else:
         run_many_streams(args, result)
+    if not args.headline_only and not args.no_single_legs and args.workload != "single":
+        result["single_stream"] = run_single_legs(args)
     if not args.headline_only:
         result["batched_vs_plain"] = run_uneven(args)
         result["serving"] = run_serving(args)

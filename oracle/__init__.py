@@ -84,6 +84,8 @@ def lib():
         L.orc_map.argtypes = [sp, ctypes.c_uint64, ctypes.c_uint64]
         L.orc_map.restype = ctypes.c_double
         L.orc_fill.argtypes = [sp, ctypes.c_uint64, dp, u64p]
+        L.orc_fill_pairs.argtypes = [sp, ctypes.c_uint64, ctypes.c_uint64, dp]
+        L.orc_fill_pairs.restype = ctypes.c_uint64
         L.orc_scale.argtypes = [ctypes.c_int, ctypes.c_uint64]
         L.orc_scale.restype = ctypes.c_double
         L.orc_recip.argtypes = [ctypes.c_uint64]
@@ -232,3 +234,11 @@ class PRNGD:
         lib().orc_fill(ctypes.byref(self.s), n, _ptr(out, ctypes.c_double),
                        _ptr(idx, ctypes.c_uint64) if with_index else None)
         return (out, idx) if with_index else out
+
+    def fill_pairs(self, pair_end, max_out):
+        """Outputs of the accepted pairs among [counter, pair_end), at most
+        max_out of them; the counter moves to the first pair not examined."""
+        out = np.empty(max_out, dtype=np.float64)
+        k = lib().orc_fill_pairs(ctypes.byref(self.s), pair_end, max_out,
+                                 _ptr(out, ctypes.c_double))
+        return out[:k]

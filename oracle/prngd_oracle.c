@@ -470,14 +470,12 @@ double orc_map(const orc_stream *s, uint64_t x1, uint64_t x2)
 
 /* Algorithm 1 with pair consumption: draw the next pair, drop it if x1 is
  * in a rejection interval (both of its words are used up), otherwise map
- * it. */
-void orc_fill(orc_stream *s, uint64_t n, double *out,
-              uint64_t *accepted_index)
+ * it.  The walk stops once n outputs exist or, when `bounded`, once pair
+ * `pair_end` is reached (that pair is not examined); returns the outputs
+ * made and leaves s->counter at the first pair not examined. */
+static uint64_t fill_pairs(orc_stream *s, uint64_t n, int bounded, uint64_t pair_end,
+                           double *out, uint64_t *accepted_index)
 {
-    if (s->consume == ORC_CONSUME_SINGLE) {
-        fill_single(s, n, out, accepted_index);
-        return;
-    }
     int mrg = s->generator == ORC_GEN_MRG32K3A || s->generator == ORC_GEN_MIXED;
     uint32_t st[6];
     int shift = 32 - s->w;
@@ -489,7 +487,7 @@ void orc_fill(orc_stream *s, uint64_t n, double *out,
         orc_mrg_jump(st, e, 2);
     }
     uint64_t made = 0, p = s->counter;
-    while (made < n) {
+    while (made < n && !(bounded && p >= pair_end)) {
         uint64_t x1, x2;
         uint32_t o[2];
         switch (s->generator) {
@@ -520,4 +518,22 @@ void orc_fill(orc_stream *s, uint64_t n, double *out,
         made++;
     }
     s->counter = p;
+    return made;
+}
+
+void orc_fill(orc_stream *s, uint64_t n, double *out,
+              uint64_t *accepted_index)
+{
+    if (s->consume == ORC_CONSUME_SINGLE) {
+        fill_single(s, n, out, accepted_index);
+        return;
+    }
+    fill_pairs(s, n, 0, 0, out, accepted_index);
+}
+
+uint64_t orc_fill_pairs(orc_stream *s, uint64_t pair_end, uint64_t max_out, double *out)
+{
+    if (s->consume == ORC_CONSUME_SINGLE)
+        return 0;
+    return fill_pairs(s, max_out, 1, pair_end, out, NULL);
 }

@@ -114,6 +114,13 @@ double orc_map(const orc_stream *s, uint64_t x1, uint64_t x2);
  * accepted_index, if not NULL, receives the pair index of each output. */
 void orc_fill(orc_stream *s, uint64_t n, double *out,
               uint64_t *accepted_index);
+/* The outputs of the accepted pairs among pairs [s->counter, pair_end), in
+ * order, at most max_out of them; returns how many were written and leaves
+ * s->counter at the first pair not examined.  Pair consumption only (returns
+ * 0 otherwise).  Concatenating the outputs of consecutive pair ranges gives
+ * orc_fill's sequence, so one long stream can be walked in pieces. */
+uint64_t orc_fill_pairs(orc_stream *s, uint64_t pair_end, uint64_t max_out,
+                        double *out);
 /* Exact RN((2^2w - 1) / (D * 2^2w)), the folded constant of Eq. (5). */
 double orc_scale(int w, uint64_t D);
 /* Exact RN(1 / D), the folded constant of Eq. (4). */

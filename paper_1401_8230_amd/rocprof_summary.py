@@ -4,6 +4,8 @@ dispatch from ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs scaled by a
 copy kernel of known size, and per-dispatch counter averages.
 
     python -m paper_1401_8230_amd.rocprof_summary stats STATS_CSV --command CMD
+    python -m paper_1401_8230_amd.rocprof_summary trace KERNEL_TRACE_CSV --command CMD \
+        [--skip KERNEL_SUBSTR=N ...]
     python -m paper_1401_8230_amd.rocprof_summary traffic --fetch CSV --write CSV \\
         --kernel SUBSTR --copy-kernel SUBSTR --copy-bytes B --algorithmic-bytes A \\
         --command-fetch CMD --command-write CMD --json OUT.json --md OUT.md
@@ -42,6 +44,37 @@ def stats(path, command):
         lines.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
                      f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(lines) + "\n"
+
+
+def trace(path, command, skips):
+    """Per-kernel dispatch durations from a --kernel-trace CSV: mean, median,
+    min and max, after dropping the first N dispatches of the kernels named
+    in `skips` ({substring: N}; the warm-up launches of a benchmark)."""
+    durs = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        durs[r["Kernel_Name"]].append((int(r["Start_Timestamp"]),
+                                       int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    lines = ["# rocprofv3 kernel trace, per-dispatch durations", "", "Command:", "", "```",
+             command, "```", "", f"Kernel source sha256[:16]: `{kernel_source_hash()}`", ""]
+    if skips:
+        lines += ["Warm-up dispatches left out: " +
+                  ", ".join(f"the first {n} of `{k}`" for k, n in skips.items()), ""]
+    lines += ["| kernel | dispatches | mean us | median us | min us | max us |",
+              "|---|---:|---:|---:|---:|---:|"]
+    rows = []
+    for name, v in durs.items():
+        v = [d for _, d in sorted(v)]
+        for sub, n in skips.items():
+            if sub in name:
+                v = v[n:]
+        if not v:
+            continue
+        srt = sorted(v)
+        rows.append((sum(v), name, len(v), sum(v) / len(v), srt[len(srt) // 2], srt[0], srt[-1]))
+    for _, name, cnt, mean, med, lo, hi in sorted(rows, reverse=True):
+        lines.append(f"| `{short_name(name)}` | {cnt} | {mean / 1e3:.1f} | {med / 1e3:.1f} | "
+                     f"{lo / 1e3:.1f} | {hi / 1e3:.1f} |")
     return "\n".join(lines) + "\n"
 
 
@@ -143,12 +176,23 @@ def main(argv=None):
         t.add_argument("--" + name.replace("_", "-"), dest=name, required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--algorithmic-bytes", type=float, required=True)
+    tr = sub.add_parser("trace")
+    tr.add_argument("csv")
+    tr.add_argument("--command", required=True)
+    tr.add_argument("--skip", action="append", default=[],
+                    help="KERNEL_SUBSTR=N: leave out the first N dispatches of that kernel")
     c = sub.add_parser("counters")
     c.add_argument("csv")
     c.add_argument("--command", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         sys.stdout.write(stats(a.csv, a.command))
+    elif a.cmd == "trace":
+        skips = {}
+        for item in a.skip:
+            k, n = item.rsplit("=", 1)
+            skips[k] = int(n)
+        sys.stdout.write(trace(a.csv, a.command, skips))
     elif a.cmd == "traffic":
         traffic(a)
     else:

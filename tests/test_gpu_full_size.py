@@ -1,0 +1,195 @@
+"""Full-size configurations against the oracle: every output and every
+final position, at the sizes and in the launch forms the benchmark times.
+
+* many streams: 2^16 Philox4x32-10 substreams of seed 42, 2^14 outputs
+  each (2^30 outputs, 8 GiB), one resident batch replayed twice, as the
+  benchmark steps it;
+* one Philox stream at w = 32, 2^30 outputs per fill (8 GiB), from the
+  stream's start and from an odd (mid-block) start, each followed by a
+  second fill that continues the stream;
+* one stream of 2^28 outputs (2 GiB): mixed Philox/MRG32k3a, MRG32k3a
+  alone, and Philox at w = 24 (x = u >> 8), two consecutive fills each;
+* the uneven batch: 4096 requests with sizes log-uniform in [1e3, 1e7]
+  (about 4.5e9 outputs, 36 GB), each with its own seed, substream and
+  start position, as a resident plan in every launch shape the autotuner
+  can choose, as one prngd_fill_batch, and as 4096 plain prngd_fill calls.
+
+The oracle runs on the host cores (independent streams in parallel, one
+long stream as consecutive pair ranges), its outputs go to the device, and
+the comparison is of bit patterns on the device.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle_parallel as OP
+from gpu_util import DEV, Arena, assert_device_bits_equal, note, upload
+
+torch = pytest.importorskip("torch")
+from paper_1401_8230_amd import autotune, prngd, workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+OGEN = {"philox": O.GEN_PHILOX, "mrg32k3a": O.GEN_MRG32K3A, "mixed": O.GEN_MIXED}
+
+
+def release():
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def test_many_streams_every_output_and_counter():
+    reqs = workloads.many_streams()
+    S, n = len(reqs), reqs[0].n
+    note(f"many streams: {S} handles x {n}")
+    gens = prngd.Generator.many(42, S, "philox", w=32)
+    out = torch.empty(S * n, dtype=torch.float64, device=DEV)
+    views = [out[i * n:(i + 1) * n] for i in range(S)]
+    plan = prngd.Plan(list(zip(gens, views)))
+    counters = [0] * S
+    group = 4096
+    for launch in range(2):
+        note(f"many streams: launch {launch}")
+        out.view(torch.int64).fill_(0x7FF8DEADBEEF0001)
+        plan.launch()
+        torch.cuda.synchronize()
+        for g0 in range(0, S, group):
+            ids = range(g0, g0 + group)
+            outs, ctrs = OP.fill_streams(O.GEN_PHILOX, 32, [(42, s, counters[s], n) for s in ids])
+            exp = upload(outs)
+            offs = np.arange(0, (group + 1) * n, n, dtype=np.int64)
+            assert_device_bits_equal(out[g0 * n:(g0 + group) * n], exp,
+                                     f"launch {launch} streams {g0}..", offs)
+            for s, c in zip(ids, ctrs):
+                counters[s] = c
+            del exp
+        note(f"many streams: launch {launch} positions")
+        for s in range(S):
+            assert gens[s].get_position() == (s, counters[s]), f"launch {launch} stream {s}"
+    assert sum(counters) - 2 * S * n < 64        # about one rejection per 2^31 pairs
+    plan.close()
+    for g in gens:
+        g.close()
+    del out, views
+    release()
+
+
+def long_stream(gen, w, n, start, fills=2):
+    """`fills` consecutive fills of n outputs of one stream (seed 42,
+    substream 0) from pair `start`, each compared in full."""
+    g = prngd.Generator(42, gen, w=w)
+    if start:
+        g.set_position(0, start)
+    out = torch.empty(n, dtype=torch.float64, device=DEV)
+    counter = start
+    for f in range(fills):
+        note(f"{gen} w={w}: fill {f} of {n} from pair {counter}")
+        out.view(torch.int64).fill_(0x7FF8DEADBEEF0001)
+        g.fill(out)
+        torch.cuda.synchronize()
+        exp, end = OP.fill_long(OGEN[gen], w, 42, 0, counter, n)
+        dev = upload([exp])
+        del exp
+        assert_device_bits_equal(out, dev, f"{gen} w={w} fill {f} from {counter}")
+        del dev
+        assert g.get_position() == (0, end), f"fill {f}"
+        assert end - counter - n < 1 << 20
+        counter = end
+    g.close()
+    del out
+    release()
+
+
+@pytest.mark.parametrize("start", [0, 3 * 2**30 + 1])
+def test_single_philox_stream_2_30(start):
+    long_stream("philox", 32, 1 << 30, start)
+
+
+@pytest.mark.parametrize("gen,w", [("mixed", 32), ("mrg32k3a", 32), ("philox", 24)])
+def test_single_stream_2_28(gen, w):
+    long_stream(gen, w, 1 << 28, 0)
+
+
+# ------------------------------------------------------- the uneven batch
+
+class Uneven:
+    def __init__(self):
+        self.reqs = workloads.uneven_batch()
+        note(f"uneven batch: oracle for {len(self.reqs)} requests")
+        self.arena = Arena([r.n for r in self.reqs])
+        self.expected = torch.empty(self.arena.total, dtype=torch.float64, device=DEV)
+        self.counters = []
+        specs = [(r.seed, r.stream_id, r.counter, r.n) for r in self.reqs]
+        i = 0
+        while i < len(specs):
+            j, tot = i, 0
+            while j < len(specs) and tot < (1 << 27):
+                tot += specs[j][3]
+                j += 1
+            outs, ctrs = OP.fill_streams(O.GEN_PHILOX, 32, specs[i:j])
+            o0 = int(self.arena.offsets[i])
+            self.expected[o0:o0 + tot].copy_(torch.from_numpy(np.concatenate(outs)))
+            self.counters += ctrs
+            i = j
+        self.gens = [prngd.Generator(r.seed, "philox", w=32) for r in self.reqs]
+
+    def reposition(self):
+        for g, r in zip(self.gens, self.reqs):
+            g.set_position(r.stream_id, r.counter)
+
+    def check(self, what):
+        torch.cuda.synchronize()
+        assert_device_bits_equal(self.arena.data, self.expected, what, self.arena.offsets)
+        for i, (g, r) in enumerate(zip(self.gens, self.reqs)):
+            assert g.get_position() == (r.stream_id, self.counters[i]), f"{what}: request {i}"
+
+    def close(self):
+        for g in self.gens:
+            g.close()
+
+
+@pytest.fixture(scope="module")
+def uneven():
+    u = Uneven()
+    yield u
+    u.close()
+    del u
+    release()
+
+
+FULL_SHAPES = autotune.candidates("philox", 32)
+
+
+def shape_id(c):
+    keys = [("block_threads", "t"), ("pairs_per_lane", "ppl"), ("store_mode", "st"),
+            ("path", "path"), ("seq_max_tiles", "seq")]
+    return "-".join(f"{short}{c[k]}" for k, short in keys if k in c)
+
+
+@pytest.mark.parametrize("shape", FULL_SHAPES, ids=[shape_id(c) for c in FULL_SHAPES])
+def test_uneven_batch_plan_in_every_shape(uneven, shape):
+    prngd.set_tuning("philox", 32, **shape)
+    try:
+        uneven.reposition()
+        uneven.arena.poison()
+        note(f"uneven batch: plan in shape {shape_id(shape)}")
+        plan = prngd.Plan(list(zip(uneven.gens, uneven.arena.views)))
+        plan.launch()
+        uneven.check(f"plan {shape_id(shape)}")
+        plan.close()
+    finally:
+        prngd.reset_tuning("philox", 32)
+
+
+def test_uneven_batch_fill_batch_and_plain_fills(uneven):
+    uneven.reposition()
+    uneven.arena.poison()
+    note("uneven batch: prngd_fill_batch, library defaults")
+    prngd.fill_batch(list(zip(uneven.gens, uneven.arena.views)))
+    uneven.check("fill_batch")
+    uneven.reposition()
+    uneven.arena.poison()
+    note("uneven batch: 4096 plain fills")
+    for g, o in zip(uneven.gens, uneven.arena.views):
+        g.fill(o)
+    uneven.check("plain fills")

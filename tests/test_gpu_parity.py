@@ -395,76 +395,7 @@ def test_ordered_path_at_rare_rejections(w):
         g.close()
 
 
-# ------------------------------------------------ full-size configurations
-
-def test_many_streams_full_size_sampled():
-    """2^16 substreams of seed 42, 2^14 outputs each (8 GiB), one resident
-    batch as the benchmark launches it; 64 sampled streams are compared in
-    full and every stream's counter and range are checked."""
-    from paper_1401_8230_amd import workloads
-    reqs = workloads.many_streams()
-    n = reqs[0].n
-    note("many streams: creating handles")
-    gens = prngd.Generator.many(42, len(reqs), "philox", w=32)
-    out = torch.empty(len(reqs) * n, dtype=torch.float64, device=DEV)
-    views = [out[i * n:(i + 1) * n] for i in range(len(reqs))]
-    plan = prngd.Plan(list(zip(gens, views)))
-    note("many streams: launch")
-    plan.launch()
-    torch.cuda.synchronize()
-    assert float(out.min()) >= 0.0 and float(out.max()) < 1.0
-    rng = np.random.default_rng(0)
-    sample = sorted(set([0, 1, len(reqs) - 1] + [int(v) for v in rng.integers(0, len(reqs), 61)]))
-    for s in sample:
-        expect, ectr = oracle_fill("philox", 32, 42, s, 0, n)
-        assert_bits_equal(views[s].cpu().numpy(), expect, f"stream {s}")
-        assert gens[s].get_position() == (s, ectr)
-    plan.close()
-    counters = [g.get_position()[1] for g in gens[:4096]]
-    assert all(c >= n for c in counters)
-    for g in gens:
-        g.close()
-    del out
-
-
-def _walk_back(s, end, k):
-    """The last k accepted pairs before pair `end` (oracle, one by one)."""
-    vals = []
-    p = end - 1
-    while len(vals) < k:
-        x1, x2 = s.pair(p)
-        if s.accept(x1):
-            vals.append(s.map(x1, x2))
-        p -= 1
-    return np.array(vals[::-1])
-
-
-@pytest.mark.parametrize("gen,w", [("mixed", 32), ("philox", 24)])
-def test_single_stream_2_28_sampled(gen, w):
-    """2^28 outputs of one stream (2 GiB): the first 2^20 and the last 64
-    outputs are compared with the oracle, and sampled outputs in between
-    must be the oracle's output of a pair within the total rejection
-    count of their position."""
-    n = 1 << 28
-    note(f"{gen} w={w} n=2^28")
-    g = prngd.Generator(42, gen, w=w)
-    out = torch.empty(n, dtype=torch.float64, device=DEV)
-    g.fill(out)
-    torch.cuda.synchronize()
-    _, end = g.get_position()
-    rejected = end - n
-    assert 0 <= rejected < 10000
-    assert float(out.min()) >= 0.0 and float(out.max()) < 1.0
-    head, _ = oracle_fill(gen, w, 42, 0, 0, 1 << 20)
-    assert_bits_equal(out[:1 << 20].cpu().numpy(), head, "head")
-    s = O.PRNGD(OGEN[gen], w, seed=42)
-    assert s.accept(s.pair(end - 1)[0])
-    assert_bits_equal(out[n - 64:].cpu().numpy(), _walk_back(s, end, 64), "tail")
-    rng = np.random.default_rng(3)
-    for i in sorted(int(v) for v in rng.integers(1 << 20, n - 64, 40)):
-        v = float(out[i])
-        cands = [s.map(*s.pair(p)) for p in range(i, i + rejected + 1) if s.accept(s.pair(p)[0])]
-        assert v in cands, f"output {i}"
+# Full-size configurations are compared in full in test_gpu_full_size.py.
 
 
 @pytest.mark.parametrize("gen,w", [("philox", 32), ("philox", 12), ("mixed", 32)])
