@@ -41,7 +41,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 BYTES_PER_OUTPUT = 8           # one FP64 written per accepted pair
-KERNEL_SRC = os.path.join(ROOT, "paper_1401_8230_amd", "csrc", "prngd_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_many_streams.json")
 TRAFFIC_FILE_SINGLE = os.path.join(ROOT, "profiles", "traffic_single_stream.json")
 
@@ -86,8 +85,8 @@ def parse():
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    from paper_1401_8230_amd._build import kernel_source_hash
+    return kernel_source_hash()
 
 
 def measured_traffic(path=TRAFFIC_FILE):

@@ -2,6 +2,7 @@
 import os
 import shutil
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -9,7 +10,16 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libprngd.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["prngd_kernels.hip", "prngd_probes.hip", "prngd_runtime.cpp"]
+# One translation unit per kernel family, compiled in parallel.  The family
+# units are built twice: the kernels of the default Eq. (5) map, and the
+# kernels that take the map's constants from the launch (FAM_ANY_MAP).
+FAMILY_SOURCES = ["prngd_k_spec.hip", "prngd_k_philox.hip", "prngd_k_single.hip",
+                  "prngd_k_mrg.hip"]
+SOURCES = ["prngd_k_misc.hip", "prngd_probes.hip", "prngd_runtime.cpp"]
+UNITS = ([(src, "eq5", ["-DPRNGD_MAPF=0u"]) for src in FAMILY_SOURCES]
+         + [(src, "anymap", ["-DPRNGD_MAPF=FAM_ANY_MAP"]) for src in FAMILY_SOURCES]
+         + [(src, "", []) for src in SOURCES])
+KERNEL_SOURCES = ["prngd_device.hpp", "prngd_internal.hpp", "prngd_k_misc.hip"] + FAMILY_SOURCES
 
 # -ffp-contract=off keeps every FP64 operation of the map a separate IEEE
 # operation; packed FP32 instructions are disabled for the device code.
@@ -23,6 +33,17 @@ HIPCC_FLAGS = [
 ]
 
 
+def kernel_source_hash():
+    """First 16 hex digits of the SHA-256 of the fill kernels' sources: HBM
+    counter figures are only reported for the kernels they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def hipcc():
     path = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(path):
@@ -30,17 +51,23 @@ def hipcc():
     return path
 
 
-def build(verbose=False):
+def _compile(unit, verbose):
+    src, tag, defines = unit
+    stem = src.rsplit(".", 1)[0] + (f"_{tag}" if tag else "")
+    obj = os.path.join(OBJ_DIR, stem + ".o")
+    lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "c++", "-D__HIP_PLATFORM_AMD__"]
+    cmd = [hipcc(), *HIPCC_FLAGS, *defines, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
+def build(verbose=False, jobs=None):
     os.makedirs(OBJ_DIR, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(OBJ_DIR, src.rsplit(".", 1)[0] + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "c++", "-D__HIP_PLATFORM_AMD__"]
-        cmd = [hipcc(), *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+    jobs = jobs or min(len(UNITS), os.cpu_count() or 1, 8)
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        objs = list(pool.map(lambda unit: _compile(unit, verbose), UNITS))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     if verbose:

@@ -1,4 +1,6 @@
-// prngd_kernels.hip -- gfx950 fill kernels of libprngd.
+// prngd_device.hpp -- gfx950 device code of libprngd's fill kernels,
+// included by the kernel translation units (prngd_k_*.hip), each of which
+// instantiates one family of kernels.
 //
 // One launch fills one or more segments (a segment = the next n outputs of
 // one handle).  A segment's pairs are cut into windows of T = B * PPL
@@ -19,6 +21,8 @@
 //      handle's next pair counter.
 // The segment's last tile continues window by window until n outputs
 // exist (every rejection moves the end of the segment one pair further).
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include "prngd_internal.hpp"
@@ -63,32 +67,63 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
 }
 
 // -------------------------------------------------------------- MRG32k3a
-// L'Ecuyer 1999.  Moduli m1 = 2^32 - 209, m2 = 2^32 - 22853; reductions
-// fold the high word with 2^32 = c (mod m).
+// L'Ecuyer 1999.  Moduli m1 = 2^32 - 209, m2 = 2^32 - 22853.  Reductions
+// fold the high word with 2^32 = c (mod m), as many times as the operand's
+// bound needs, and finish with one conditional subtraction of m, written
+// as an addition of c in 32 bits (f - m = f + c - 2^32 for m <= f < 2 m).
 constexpr uint32_t kM1 = 4294967087u;
 constexpr uint32_t kM2 = 4294944443u;
+constexpr uint32_t kC1 = 209u;      // 2^32 - m1
+constexpr uint32_t kC2 = 22853u;    // 2^32 - m2
 
-__device__ __forceinline__ uint32_t red_m1(uint64_t x)
+__device__ __forceinline__ uint64_t fold(uint64_t x, uint32_t c)
 {
-    x = (x >> 32) * 209u + (x & 0xffffffffu);
-    x = (x >> 32) * 209u + (x & 0xffffffffu);
-    return uint32_t(x >= kM1 ? x - kM1 : x);
+    return uint64_t(uint32_t(x >> 32)) * c + uint32_t(x);
 }
 
-__device__ __forceinline__ uint32_t red_m2(uint64_t x)
+// f mod m for f < 2 m
+template <uint32_t M>
+__device__ __forceinline__ uint32_t below_2m(uint64_t f)
 {
-    x = (x >> 32) * 22853u + (x & 0xffffffffu);
-    x = (x >> 32) * 22853u + (x & 0xffffffffu);
-    return uint32_t(x >= kM2 ? x - kM2 : x);
+    return f >= M ? uint32_t(f) + (0u - M) : uint32_t(f);
+}
+
+// x mod m1 for x < 2^54: one fold leaves f < 2^22 * 209 + 2^32 < 2 m1.
+__device__ __forceinline__ uint32_t red_m1_54(uint64_t x)
+{
+    return below_2m<kM1>(fold(x, kC1));
+}
+
+// x mod m2 for x < 2^54: one fold leaves f < 2^36.5 + 2^32, a second
+// f' < 17 * 22853 + 2^32 < 2 m2.
+__device__ __forceinline__ uint32_t red_m2_54(uint64_t x)
+{
+    return below_2m<kM2>(fold(fold(x, kC2), kC2));
+}
+
+// (M0 s0 + M1 s1 + M2 s2) mod m for entries and state words below m: each
+// product folded once (< 2^32 c + 2^32), the three summed (< 2^34 c), and
+// the sum folded to below 2 m (m1: once, < 2^18 + 2^32; m2: twice).
+template <uint32_t C>
+__device__ __forceinline__ uint32_t dot3_mod(const uint32_t *__restrict__ M, uint32_t s0,
+                                             uint32_t s1, uint32_t s2)
+{
+    const uint64_t acc = fold(uint64_t(M[0]) * s0, C) + fold(uint64_t(M[1]) * s1, C) +
+                         fold(uint64_t(M[2]) * s2, C);
+    if (C == kC1)
+        return below_2m<kM1>(fold(acc, C));
+    return below_2m<kM2>(fold(fold(acc, C), C));
 }
 
 struct Mrg {
     uint32_t s[6];   // (x1[n-3], x1[n-2], x1[n-1], x2[n-3], x2[n-2], x2[n-1])
 
+    // The multipliers are below 2^21, so each sum of two products is below
+    // 2^54.
     __device__ __forceinline__ uint32_t next()
     {
-        const uint32_t p1 = red_m1(uint64_t(1403580u) * s[1] + uint64_t(810728u) * (kM1 - s[0]));
-        const uint32_t p2 = red_m2(uint64_t(527612u) * s[5] + uint64_t(1370589u) * (kM2 - s[3]));
+        const uint32_t p1 = red_m1_54(uint64_t(1403580u) * s[1] + uint64_t(810728u) * (kM1 - s[0]));
+        const uint32_t p2 = red_m2_54(uint64_t(527612u) * s[5] + uint64_t(1370589u) * (kM2 - s[3]));
         s[0] = s[1]; s[1] = s[2]; s[2] = p1;
         s[3] = s[4]; s[4] = s[5]; s[5] = p2;
         return p1 > p2 ? p1 - p2 : p1 - p2 + kM1;
@@ -100,14 +135,8 @@ struct Mrg {
         uint32_t r[6];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            uint64_t acc1 = 0, acc2 = 0;
-#pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                acc1 += red_m1(uint64_t(M[3 * i + l]) * s[l]);
-                acc2 += red_m2(uint64_t(M[9 + 3 * i + l]) * s[3 + l]);
-            }
-            r[i] = red_m1(acc1);
-            r[3 + i] = red_m2(acc2);
+            r[i] = dot3_mod<kC1>(M + 3 * i, s[0], s[1], s[2]);
+            r[3 + i] = dot3_mod<kC2>(M + 9 + 3 * i, s[3], s[4], s[5]);
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i)
@@ -124,22 +153,31 @@ struct Mrg {
 // up to 1.0 and every product that did not.  Eq. (4) (Algorithm 1's Z) is
 // the same with N + 2^w - (b - b0) (lo + nadd stays exact: both are below
 // 2^34) and S = RN(1 / D4); the no-zero form returns 1 - z, one rounding
-// of the exact difference (fma(-1, z, 1)).  For Eq. (5) nadd = 0 and the
-// last step is fma(1, z, 0) = z, so the default output is unchanged.
+// of the exact difference (fma(-1, z, 1)).  Kernels of a family without
+// FAM_ANY_MAP compute Eq. (5) alone; the others take (nadd, S, osign,
+// ooff) from the launch, and with Eq. (5)'s (0, S, 1, 0) they give the same
+// bits.
 constexpr double kBelowOne = 0x1.fffffffffffffp-1;
 
+template <uint32_t FAM>
 __device__ __forceinline__ double map_hi_lo(uint32_t hi, uint32_t lo, double two_w,
                                             const LaunchArgs &a)
 {
+    if (!(FAM & FAM_ANY_MAP)) {
+        // Eq. (5): one fma, one multiply, one min
+        const double z = __builtin_fma(double(hi), two_w, double(lo)) * a.S;
+        return z < kBelowOne ? z : kBelowOne;
+    }
     const double N = __builtin_fma(double(hi), two_w, double(lo) + a.nadd);
     const double z = N * a.S;
     return __builtin_fma(a.osign, z < kBelowOne ? z : kBelowOne, a.ooff);
 }
 
+template <uint32_t FAM>
 __device__ __forceinline__ double prngd_map(uint32_t x1, uint32_t x2, const LaunchArgs &a,
                                             double two_w)
 {
-    return map_hi_lo(x1 - a.a0 - 1u, x2 - a.b0, two_w, a);
+    return map_hi_lo<FAM>(x1 - a.a0 - 1u, x2 - a.b0, two_w, a);
 }
 
 // ------------------------------------------------------- wave utilities
@@ -221,7 +259,7 @@ __device__ __forceinline__ void publish(uint64_t *status, uint32_t g, uint64_t w
 // The spin is bounded; a stall (impossible when every earlier tile is
 // running) raises the error word and the launch's abort flag, which makes
 // every other waiting tile and every idle workgroup give up at once.
-__device__ uint64_t look_back(uint64_t *status, uint32_t g, uint32_t t, uint32_t epoch,
+__device__ inline uint64_t look_back(uint64_t *status, uint32_t g, uint32_t t, uint32_t epoch,
                               Control *ctl, uint32_t *error, uint32_t lane)
 {
     uint64_t excl = 0;
@@ -411,8 +449,19 @@ __device__ __forceinline__ void store_staged(double *out, uint64_t e0, uint32_t 
     const uint32_t slots = (cnt + r + 1u) >> 1;    // 16-byte slots from that block's start
     const uint32_t end = n <= e0 ? 0u : (n - e0 < cnt ? uint32_t(n - e0) : cnt);
     const uint32_t m1 = mode == 1 ? 0u : mode;
-    for (uint32_t k = threadIdx.x; k < slots; k += B) {
+    double *o = out + e0;
+    for (uint32_t base = 0; base < slots; base += B) {
+        const uint32_t k = base + threadIdx.x;
         const int64_t i = int64_t(2u * k) - int64_t(r);   // range index of the slot's first output
+        if (mode != 1 && 2u * base >= r &&
+            int64_t(2u * (base + B)) - int64_t(r) <= int64_t(end)) {
+            // every slot of this round lies inside the range
+            store_two(o + i, s_vals[pad_index(uint32_t(i))], s_vals[pad_index(uint32_t(i + 1))],
+                      m1);
+            continue;
+        }
+        if (k >= slots)
+            continue;
         const bool in0 = i >= 0 && i < int64_t(end);
         const bool in1 = i + 1 >= 0 && i + 1 < int64_t(end);
         if (in0 && in1 && mode != 1) {
@@ -488,7 +537,7 @@ struct PhiloxTile {
         const uint64_t blk0 = (wb >> 1);
         const uint32_t k0 = uint32_t(seg.seed), k1 = uint32_t(seg.seed >> 32);
         acc = 0;
-        runs = FAM != FAM_ENUM && (wb & 1u);
+        runs = fam_base(FAM) != FAM_ENUM && (wb & 1u);
         if (runs) {
             uint32_t a1[J], a2[J], b1[J], b2[J];
             const uint64_t run0 = blk0 + uint64_t(wave) * (64u * J);
@@ -518,19 +567,19 @@ struct PhiloxTile {
                 b1[j] = n1;
                 b2[j] = n2;
             }
-            const uint32_t shift = FAM == FAM_PHILOX32 ? 0u : 32u - args.w;
-            const double two_w = FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+            const uint32_t shift = fam_base(FAM) == FAM_PHILOX32 ? 0u : 32u - args.w;
+            const double two_w = fam_base(FAM) == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 const uint32_t x1a = a1[j] >> shift, x2a = a2[j] >> shift;
                 const uint32_t x1b = b1[j] >> shift, x2b = b2[j] >> shift;
                 const bool oka = x1a != args.a0 && x1a != args.a;
                 const bool okb = x1b != args.a0 && x1b != args.a;
-                v[2 * j] = prngd_map(x1a, x2a, args, two_w);
-                v[2 * j + 1] = prngd_map(x1b, x2b, args, two_w);
+                v[2 * j] = prngd_map<FAM>(x1a, x2a, args, two_w);
+                v[2 * j + 1] = prngd_map<FAM>(x1b, x2b, args, two_w);
                 acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
             }
-        } else if (FAM == FAM_PHILOX32) {
+        } else if (fam_base(FAM) == FAM_PHILOX32) {
             // x in [0, 2^32 - 1]: keep x1 unless x1 + 1 wraps to 0 or is 1
 #pragma unroll
             for (int j = 0; j < J; ++j) {
@@ -539,8 +588,8 @@ struct PhiloxTile {
                                                seg.stream_id, k0, k1);
                 const bool oka = r.v0 + 1u >= 2u;
                 const bool okb = r.v2 + 1u >= 2u;
-                v[2 * j] = map_hi_lo(r.v0 - 1u, r.v1, 4294967296.0, args);
-                v[2 * j + 1] = map_hi_lo(r.v2 - 1u, r.v3, 4294967296.0, args);
+                v[2 * j] = map_hi_lo<FAM>(r.v0 - 1u, r.v1, 4294967296.0, args);
+                v[2 * j + 1] = map_hi_lo<FAM>(r.v2 - 1u, r.v3, 4294967296.0, args);
                 acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
             }
         } else {
@@ -549,7 +598,7 @@ struct PhiloxTile {
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 uint32_t x1a, x2a, x1b, x2b;
-                if (FAM == FAM_PHILOX) {
+                if (fam_base(FAM) == FAM_PHILOX) {
                     const uint64_t blk = blk0 + uint32_t(j) * B + tid;
                     const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u,
                                                    seg.stream_id, k0, k1);
@@ -567,8 +616,8 @@ struct PhiloxTile {
                 }
                 const bool oka = x1a != args.a0 && x1a != args.a;
                 const bool okb = x1b != args.a0 && x1b != args.a;
-                v[2 * j] = prngd_map(x1a, x2a, args, two_w);
-                v[2 * j + 1] = prngd_map(x1b, x2b, args, two_w);
+                v[2 * j] = prngd_map<FAM>(x1a, x2a, args, two_w);
+                v[2 * j + 1] = prngd_map<FAM>(x1b, x2b, args, two_w);
                 acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
             }
         }
@@ -715,7 +764,7 @@ struct SpecTile {
     {
         const uint32_t tid = threadIdx.x;
         uint32_t x1a, x2a, x1b, x2b;
-        if (FAM == FAM_ENUM) {
+        if (fam_base(FAM) == FAM_ENUM) {
             const uint64_t q = wb + 2u * (uint32_t(j) * B + tid);
             const uint64_t mask = (uint64_t(1) << args.w) - 1;
             x1a = uint32_t((q >> args.w) & mask);
@@ -734,7 +783,7 @@ struct SpecTile {
                                                 uint32_t(seg.seed >> 32));
                 r = Words4{r.v2, r.v3, nx.v0, nx.v1};
             }
-            if (FAM == FAM_PHILOX32) {
+            if (fam_base(FAM) == FAM_PHILOX32) {
                 x1a = r.v0; x2a = r.v1; x1b = r.v2; x2b = r.v3;
             } else {
                 const uint32_t shift = 32u - args.w;
@@ -742,19 +791,19 @@ struct SpecTile {
                 x1b = r.v2 >> shift; x2b = r.v3 >> shift;
             }
         }
-        if (FAM == FAM_PHILOX32)
+        if (fam_base(FAM) == FAM_PHILOX32)
             return {x1a - 1u, x2a, x1b - 1u, x2b};
         return {x1a - args.a0 - 1u, x2a - args.b0, x1b - args.a0 - 1u, x2b - args.b0};
     }
 
     __device__ __forceinline__ static double two_w(const LaunchArgs &args)
     {
-        return FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+        return fam_base(FAM) == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
     }
 
     __device__ __forceinline__ static uint32_t hmax(const LaunchArgs &args)
     {
-        return FAM == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
+        return fam_base(FAM) == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
     }
 
     // Accepted pairs of window `wb` from window offset lo_off on, without
@@ -821,8 +870,8 @@ struct SpecTile {
                 const uint32_t q = 2u * (uint32_t(j) * B + tid);
                 const HiLo p = words(args, seg, wb, j);
                 mx = max(mx, max(p.ha, p.hb));
-                const double za = map_hi_lo(p.ha, p.la, tw, args);
-                const double zb = map_hi_lo(p.hb, p.lb, tw, args);
+                const double za = map_hi_lo<FAM>(p.ha, p.la, tw, args);
+                const double zb = map_hi_lo<FAM>(p.hb, p.lb, tw, args);
                 if (aligned) {
                     store_two(o + q, za, zb, args.store_mode);
                 } else if (shifted) {
@@ -855,8 +904,8 @@ struct SpecTile {
                 const bool okb = p.hb < hm && q + 1 >= lo_off;
                 acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
                 if (kSpec && lo_off == 0) {
-                    const double za = map_hi_lo(p.ha, p.la, tw, args);
-                    const double zb = map_hi_lo(p.hb, p.lb, tw, args);
+                    const double za = map_hi_lo<FAM>(p.ha, p.la, tw, args);
+                    const double zb = map_hi_lo<FAM>(p.hb, p.lb, tw, args);
                     if (aligned && q + 1 < left) {
                         store_two(o + q, za, zb, args.store_mode);
                     } else {
@@ -896,8 +945,8 @@ struct SpecTile {
             const uint32_t pos_b = pos_a + (oka ? 1u : 0u);
             if (oka || okb) {
                 const HiLo p = words(args, seg, wb, j);
-                const double za = map_hi_lo(p.ha, p.la, tw, args);
-                const double zb = map_hi_lo(p.hb, p.lb, tw, args);
+                const double za = map_hi_lo<FAM>(p.ha, p.la, tw, args);
+                const double zb = map_hi_lo<FAM>(p.hb, p.lb, tw, args);
                 if (oka && pos_a < left)
                     store_one(o + pos_a, za, args.store_mode);
                 if (okb && pos_b < left)
@@ -925,53 +974,96 @@ template <int PPL, uint32_t FAM>
 struct MrgTile {
     static constexpr int B = kMrgBlockThreads;
     static constexpr uint32_t T = uint32_t(B) * PPL;
-    static constexpr uint32_t R = FAM == FAM_MRG ? 2u : 1u;   // MRG outputs per pair
+    static constexpr uint32_t R = fam_base(FAM) == FAM_MRG ? 2u : 1u;   // MRG outputs per pair
     static_assert(PPL % 4 == 0, "Philox blocks must not straddle threads");
+    static_assert(16 % PPL == 0, "a thread's outputs must share one LDS pad group");
+
+    static constexpr uint32_t kAll = PPL == 32 ? 0xFFFFFFFFu : ((1u << PPL) - 1u);
 
     double v[PPL];
-    uint32_t acc;
+    uint32_t acc;          // bit i: pair i of this thread kept
     uint32_t thread_off;   // exclusive offset of this thread inside the window
 
+    // This thread's MRG32k3a state at MRG position R (win T + tid PPL).
+    __device__ __forceinline__ static Mrg jump(const LaunchArgs &args, const Segment &seg,
+                                               uint64_t win)
+    {
+        Mrg g;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            g.s[i] = seg.mrg[i];
+        uint64_t m = win;
+        for (int d = 0; d < kMrgDigits && m != 0; ++d, m >>= 8) {
+            const uint32_t digit = uint32_t(m & 255u);
+            if (digit)
+                g.apply(args.mrg_window + (size_t(d) * 256 + digit) * kMrgMatWords);
+        }
+        g.apply(args.mrg_thread + size_t(threadIdx.x) * kMrgMatWords);
+        return g;
+    }
+
+    // Pair i of this thread (window offset tid PPL + i): x1 and x2, with the
+    // Philox block of the mixed generator's x1 words held in ph.
+    __device__ __forceinline__ static void pair(const Segment &seg, uint64_t win, int i, Mrg &g,
+                                                Words4 &ph, uint32_t &x1, uint32_t &x2)
+    {
+        if (fam_base(FAM) == FAM_MIXED) {
+            if ((i & 3) == 0) {
+                const uint64_t blk = (win * T + threadIdx.x * PPL + i) >> 2;
+                ph = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u, seg.stream_id,
+                                   uint32_t(seg.seed), uint32_t(seg.seed >> 32));
+            }
+            x1 = (i & 3) == 0 ? ph.v0 : (i & 3) == 1 ? ph.v1 : (i & 3) == 2 ? ph.v2 : ph.v3;
+            x2 = g.next();
+        } else {
+            x1 = g.next();
+            x2 = g.next();
+        }
+    }
+
+    // Generates the window's PPL pairs of this thread, mapped, and returns
+    // the window's number of kept pairs.  A pair is kept iff
+    // hi = x1 - a0 - 1 < a - a0 - 1 (x1 = a0 wraps hi to 2^32 - 1, x1 = a
+    // gives hmax), so one running max of hi over the thread's pairs finds
+    // any rejection.  Only a window with a rejection or a clipped start
+    // walks its pairs again to mark which are kept.
     __device__ __forceinline__ uint32_t generate(const LaunchArgs &args, const Segment &seg,
                                                  uint64_t win, uint32_t lo_off, uint32_t *s_wave)
     {
         const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
         const double two_w = double(uint64_t(1) << args.w);
+        const uint32_t hmax = args.a - args.a0 - 1u;
         const uint32_t q0 = tid * PPL;             // window offset of the first pair
-        acc = 0;
+        uint32_t mx = 0;
         if (q0 + PPL > lo_off) {
-            Mrg g;
-#pragma unroll
-            for (int i = 0; i < 6; ++i)
-                g.s[i] = seg.mrg[i];
-            // jump to MRG position R * (win * T + q0)
-            uint64_t m = win;
-            for (int d = 0; d < kMrgDigits && m != 0; ++d, m >>= 8) {
-                const uint32_t digit = uint32_t(m & 255u);
-                if (digit)
-                    g.apply(args.mrg_window + (size_t(d) * 256 + digit) * kMrgMatWords);
-            }
-            g.apply(args.mrg_thread + size_t(tid) * kMrgMatWords);
-            const uint32_t k0 = uint32_t(seg.seed), k1 = uint32_t(seg.seed >> 32);
+            Mrg g = jump(args, seg, win);
             Words4 ph = {0, 0, 0, 0};
 #pragma unroll
             for (int i = 0; i < PPL; ++i) {
                 uint32_t x1, x2;
-                if (FAM == FAM_MIXED) {
-                    if ((i & 3) == 0) {
-                        const uint64_t blk = (win * T + q0 + i) >> 2;
-                        ph = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u,
-                                           seg.stream_id, k0, k1);
-                    }
-                    x1 = (i & 3) == 0 ? ph.v0 : (i & 3) == 1 ? ph.v1 : (i & 3) == 2 ? ph.v2 : ph.v3;
-                    x2 = g.next();
-                } else {
-                    x1 = g.next();
-                    x2 = g.next();
+                pair(seg, win, i, g, ph, x1, x2);
+                const uint32_t hi = x1 - args.a0 - 1u;
+                mx = max(mx, hi);
+                v[i] = map_hi_lo<FAM>(hi, x2 - args.b0, two_w, args);
+            }
+        }
+        acc = kAll;
+        if (!__syncthreads_or(mx >= hmax || q0 < lo_off)) {
+            thread_off = q0;
+            return T;
+        }
+        {
+            acc = 0;
+            if (q0 + PPL > lo_off) {
+                Mrg g = jump(args, seg, win);
+                Words4 ph = {0, 0, 0, 0};
+#pragma unroll 1
+                for (int i = 0; i < PPL; ++i) {
+                    uint32_t x1, x2;
+                    pair(seg, win, i, g, ph, x1, x2);
+                    const bool ok = q0 + i >= lo_off && x1 - args.a0 - 1u < hmax;
+                    acc |= uint32_t(ok) << i;
                 }
-                const bool ok = q0 + i >= lo_off && x1 != args.a0 && x1 != args.a;
-                v[i] = prngd_map(ok ? x1 : args.a0 + 1u, ok ? x2 : args.b0, args, two_w);
-                acc |= uint32_t(ok) << i;
             }
         }
         const uint32_t c = uint32_t(__popc(acc));
@@ -997,14 +1089,28 @@ struct MrgTile {
     {
         const uint32_t tid = threadIdx.x;
         const uint64_t n = seg.n;
-        uint32_t k = thread_off;
+        if (total == T) {
+            // every pair kept: this thread's outputs are window outputs
+            // tid PPL .. tid PPL + PPL - 1, one padded LDS run (PPL divides 16)
+            double *s = s_vals + pad_index(tid * PPL);
 #pragma unroll
-        for (int i = 0; i < PPL; ++i) {
-            if ((acc >> i) & 1u) {
-                s_vals[pad_index(k)] = v[i];
-                if (excl + k == n - 1)
-                    *next_counter = win * T + tid * PPL + i + 1;
-                ++k;
+            for (int i = 0; i < PPL; ++i)
+                s[i] = v[i];
+            if (excl < n && n - excl <= T) {
+                const uint32_t m = uint32_t(n - 1 - excl);   // window output n - 1
+                if (m / PPL == tid)
+                    *next_counter = win * T + m + 1;
+            }
+        } else {
+            uint32_t k = thread_off;
+#pragma unroll
+            for (int i = 0; i < PPL; ++i) {
+                if ((acc >> i) & 1u) {
+                    s_vals[pad_index(k)] = v[i];
+                    if (excl + k == n - 1)
+                        *next_counter = win * T + tid * PPL + i + 1;
+                    ++k;
+                }
             }
         }
         __syncthreads();
@@ -1772,7 +1878,7 @@ struct WaveChunk {
                                                  uint64_t win, uint32_t lane)
     {
         uint32_t x1a, x2a, x1b, x2b;
-        if (FAM == FAM_ENUM) {
+        if (fam_base(FAM) == FAM_ENUM) {
             const uint64_t q = win * kChunk + 2u * lane;
             const uint64_t mask = (uint64_t(1) << args.w) - 1;
             x1a = uint32_t((q >> args.w) & mask);
@@ -1783,7 +1889,7 @@ struct WaveChunk {
             const uint64_t blk = win * (kChunk / 2) + lane;
             const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u, seg.stream_id,
                                            uint32_t(seg.seed), uint32_t(seg.seed >> 32));
-            if (FAM == FAM_PHILOX32) {
+            if (fam_base(FAM) == FAM_PHILOX32) {
                 x1a = r.v0; x2a = r.v1; x1b = r.v2; x2b = r.v3;
             } else {
                 const uint32_t shift = 32u - args.w;
@@ -1791,7 +1897,7 @@ struct WaveChunk {
                 x1b = r.v2 >> shift; x2b = r.v3 >> shift;
             }
         }
-        if (FAM == FAM_PHILOX32)
+        if (fam_base(FAM) == FAM_PHILOX32)
             return {x1a - 1u, x2a, x1b - 1u, x2b};
         return {x1a - args.a0 - 1u, x2a - args.b0, x1b - args.a0 - 1u, x2b - args.b0};
     }
@@ -1804,8 +1910,8 @@ struct WaveChunk {
                                                    uint64_t *next_counter, bool store)
     {
         const uint32_t lane = threadIdx.x & 63u;
-        const uint32_t hm = FAM == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
-        const double tw = FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+        const uint32_t hm = fam_base(FAM) == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
+        const double tw = fam_base(FAM) == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
         const HiLo p = words(args, seg, win, lane);
         const uint32_t q = 2u * lane;
         const bool oka = p.ha < hm && q >= lo_off;
@@ -1814,8 +1920,8 @@ struct WaveChunk {
         const uint32_t kept = uint32_t(__popcll(ka) + __popcll(kb));
         if (!store)
             return kept;
-        const double za = map_hi_lo(p.ha, p.la, tw, args);
-        const double zb = map_hi_lo(p.hb, p.lb, tw, args);
+        const double za = map_hi_lo<FAM>(p.ha, p.la, tw, args);
+        const double zb = map_hi_lo<FAM>(p.hb, p.lb, tw, args);
         const uint64_t left = seg.n - excl;            // >= 1
         double *o = seg.out + excl;
         if (kept == kChunk && left > kChunk) {
@@ -2042,7 +2148,7 @@ struct SingleWords {
     {
         const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u, seg.stream_id,
                                        uint32_t(seg.seed), uint32_t(seg.seed >> 32));
-        const uint32_t sh = FAM == FAM_PHILOX32 ? 0u : 32u - args.w;
+        const uint32_t sh = fam_base(FAM) == FAM_PHILOX32 ? 0u : 32u - args.w;
         u[0] = r.v0 >> sh;
         u[1] = r.v1 >> sh;
         u[2] = r.v2 >> sh;
@@ -2056,7 +2162,7 @@ struct SingleWords {
                                                  uint64_t wb, int j, uint32_t u[4])
     {
         const uint32_t tid = threadIdx.x;
-        if (FAM == FAM_ENUM) {
+        if (fam_base(FAM) == FAM_ENUM) {
             const uint64_t mask = (uint64_t(1) << args.w) - 1;
             const uint64_t p0 = (wb >> 1) + 2 * (uint64_t(j) * B + tid), p1 = p0 + 1;
             u[0] = uint32_t((p0 >> args.w) & mask);
@@ -2137,7 +2243,7 @@ template <uint32_t FAM>
 __device__ __forceinline__ uint32_t single_word_at(const LaunchArgs &args, const Segment &seg,
                                                    uint64_t q)
 {
-    if (FAM == FAM_MRG) {
+    if (fam_base(FAM) == FAM_MRG) {
         const uint32_t off = uint32_t(q % kSingleWindowWords);
         Mrg g = mrg_at_window(args, seg, q / kSingleWindowWords, off / 16u);
         uint32_t x = 0;
@@ -2145,7 +2251,7 @@ __device__ __forceinline__ uint32_t single_word_at(const LaunchArgs &args, const
             x = g.next();
         return x;
     }
-    if (FAM == FAM_ENUM) {
+    if (fam_base(FAM) == FAM_ENUM) {
         const uint64_t mask = (uint64_t(1) << args.w) - 1;
         const uint64_t p = q >> 1;
         return uint32_t((q & 1u) ? (p & mask) : ((p >> args.w) & mask));
@@ -2155,7 +2261,7 @@ __device__ __forceinline__ uint32_t single_word_at(const LaunchArgs &args, const
                                    uint32_t(seg.seed), uint32_t(seg.seed >> 32));
     const uint32_t l = uint32_t(q & 3u);
     const uint32_t v = l == 0 ? r.v0 : l == 1 ? r.v1 : l == 2 ? r.v2 : r.v3;
-    return FAM == FAM_PHILOX32 ? v : v >> (32u - args.w);
+    return fam_base(FAM) == FAM_PHILOX32 ? v : v >> (32u - args.w);
 }
 
 // The words of the window starting at word wb into u (wb even; a multiple of
@@ -2176,8 +2282,8 @@ __device__ __forceinline__ bool single_generate(const LaunchArgs &args, const Se
     using W = SingleWords<NW, FAM>;
     const uint32_t tid = threadIdx.x;
     uint32_t *s_stage = sm.words;
-    if (FAM == FAM_MRG) {
-        static_assert(FAM != FAM_MRG || (W::T == kSingleWindowWords && W::B == 256),
+    if (fam_base(FAM) == FAM_MRG) {
+        static_assert(fam_base(FAM) != FAM_MRG || (W::T == kSingleWindowWords && W::B == 256),
                       "the MRG32k3a tables assume 256 threads and 4096-word windows");
         Mrg g = mrg_at_window(args, seg, wb / W::T, tid);
         uint32_t x[16];
@@ -2198,12 +2304,12 @@ __device__ __forceinline__ bool single_generate(const LaunchArgs &args, const Se
             u[j][3] = v.w;
         }
     }
-    if (FAM != FAM_MRG) {
+    if (fam_base(FAM) != FAM_MRG) {
 #pragma unroll
         for (int j = 0; j < W::J; ++j)
             W::words(args, seg, wb, j, u[j]);
     }
-    constexpr bool kPhilox = FAM == FAM_PHILOX || FAM == FAM_PHILOX32;
+    constexpr bool kPhilox = fam_base(FAM) == FAM_PHILOX || fam_base(FAM) == FAM_PHILOX32;
     if (kPhilox && (wb & 2u)) {
         // u[j] holds block (wb >> 2) + j B + tid, the block of the window's
         // first word at j = tid = 0
@@ -2287,8 +2393,8 @@ __device__ __forceinline__ void single_window_store(const LaunchArgs &args, cons
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 const uint32_t m = uint32_t(j) * B + tid;
-                const double za = prngd_map(u[j][0], u[j][1], args, two_w);
-                const double zb = prngd_map(u[j][2], u[j][3], args, two_w);
+                const double za = prngd_map<FAM>(u[j][0], u[j][1], args, two_w);
+                const double zb = prngd_map<FAM>(u[j][2], u[j][3], args, two_w);
                 if (staged) {
                     sm.stage[pad_index(2 * m)] = za;
                     sm.stage[pad_index(2 * m + 1)] = zb;
@@ -2323,8 +2429,8 @@ __device__ __forceinline__ void single_window_store(const LaunchArgs &args, cons
                     else
                         prev = ss.pending;
                 }
-                const double za = prngd_map(prev, u[j][0], args, two_w);
-                const double zb = prngd_map(u[j][1], u[j][2], args, two_w);
+                const double za = prngd_map<FAM>(prev, u[j][0], args, two_w);
+                const double zb = prngd_map<FAM>(u[j][1], u[j][2], args, two_w);
                 if (staged) {
                     sm.stage[pad_index(2 * m)] = za;
                     sm.stage[pad_index(2 * m + 1)] = zb;
@@ -2385,7 +2491,7 @@ __device__ __forceinline__ void single_window_store(const LaunchArgs &args, cons
             const uint64_t ball = __ballot(r2);
             const uint64_t pos = running + uint64_t(__popcll(ball & lanemask_lt(lane)));
             if (r2 && pos < n) {
-                store_one(seg.out + pos, prngd_map(x1, x, args, two_w),
+                store_one(seg.out + pos, prngd_map<FAM>(x1, x, args, two_w),
                           args.store_mode == 1 ? 0u : args.store_mode);
                 if (pos == n - 1)
                     *next_counter = wb + q + 1;
@@ -2414,7 +2520,7 @@ __global__ __launch_bounds__(64 * NW) void seq_single_kernel(LaunchArgs args)
     __shared__ LaunchState s_launch;
     __shared__ uint32_t s_next;
     const uint32_t tid = threadIdx.x;
-    const double two_w = FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+    const double two_w = fam_base(FAM) == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
     const LaunchState st0 = read_launch_state(args, &s_launch);
     if (tid == 0)
         s_next = finish_ticket(args, st0, issue_ticket(args));
@@ -2558,7 +2664,7 @@ template <uint32_t FAM, uint32_t T>
 __device__ __forceinline__ uint32_t word_lo0(const Segment &seg, uint64_t c0)
 {
     static_assert(T % 1024 == 0, "the window must cover whole 4 KB blocks of outputs");
-    if (FAM == FAM_MRG)
+    if (fam_base(FAM) == FAM_MRG)
         return uint32_t(c0 % T);
     const uint32_t a = uint32_t((reinterpret_cast<uintptr_t>(seg.out) >> 3) & 511u);
     const uint32_t lo = (2u * a - (uint32_t(c0) & 1u)) & 1023u;
@@ -2591,7 +2697,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(5))) vo
     __shared__ uint32_t s_nv, s_h;
     const uint32_t tid = threadIdx.x;
     const uint32_t t = blockIdx.x;
-    const double two_w = FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+    const double two_w = fam_base(FAM) == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
     const TileStart ts = tile_start<true>(args, t);
     const Segment &seg = ts.seg;
     uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
@@ -2707,7 +2813,7 @@ __global__ __launch_bounds__(64 * NW) void spec_words_repair_kernel(LaunchArgs a
     if (cnt0 == 0)
         return;
     const uint32_t cnt = cnt0 < args.list_cap ? cnt0 : args.list_cap;
-    const double two_w = FAM == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+    const double two_w = fam_base(FAM) == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
     const Segment seg = args.seg0;
     const uint32_t par = (seg.parity ^ read_flip(args)) & 1u;
     const uint64_t c0 = load_start(seg, par);
@@ -2815,288 +2921,5 @@ __global__ __launch_bounds__(64 * NW) void spec_words_repair_kernel(LaunchArgs a
     }
 }
 
-// Toggles a resident plan's replay parity after all of a replay's fills.
-__global__ void toggle_flip_kernel(uint32_t *flip)
-{
-    *flip ^= 1u;
-}
-
-// Sets a handle's position slot (both halves, so either parity reads it).
-__global__ void set_counter_kernel(uint64_t *slot, uint64_t value)
-{
-    slot[0] = value;
-    slot[1] = value;
-}
-
-__global__ void zero_words_kernel(uint64_t *p, size_t n)
-{
-    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
-         i += size_t(gridDim.x) * blockDim.x)
-        p[i] = 0;
-}
-
-// tile_seg[tile_begin .. tile_begin + ntiles) = segment index, one
-// workgroup per segment.
-__global__ void expand_tiles_kernel(const Segment *segs, uint32_t nseg, uint32_t *tile_seg)
-{
-    for (uint32_t s = blockIdx.x; s < nseg; s += gridDim.x) {
-        const uint32_t b = segs[s].tile_begin, c = segs[s].ntiles;
-        for (uint32_t i = threadIdx.x; i < c; i += blockDim.x)
-            tile_seg[b + i] = s;
-    }
-}
-
 }  // namespace
-
-// ---------------------------------------------------------------- dispatch
-template <int NW, int PPL, uint32_t FAM>
-static const void *philox_kernel(bool seq)
-{
-    return seq ? reinterpret_cast<const void *>(&seq_philox_kernel<NW, PPL, FAM>)
-               : reinterpret_cast<const void *>(&fill_philox_kernel<NW, PPL, FAM>);
-}
-
-template <int NW, int PPL>
-static const void *philox_family(uint32_t fam, bool seq)
-{
-    switch (fam) {
-    case FAM_ENUM: return philox_kernel<NW, PPL, FAM_ENUM>(seq);
-    case FAM_PHILOX32: return philox_kernel<NW, PPL, FAM_PHILOX32>(seq);
-    default: return philox_kernel<NW, PPL, FAM_PHILOX>(seq);
-    }
-}
-
-template <int PPL>
-static const void *mrg_family(uint32_t fam, bool seq)
-{
-    if (seq)
-        return fam == FAM_MRG ? reinterpret_cast<const void *>(&seq_mrg_kernel<PPL, FAM_MRG>)
-                              : reinterpret_cast<const void *>(&seq_mrg_kernel<PPL, FAM_MIXED>);
-    return fam == FAM_MRG ? reinterpret_cast<const void *>(&fill_mrg_kernel<PPL, FAM_MRG>)
-                          : reinterpret_cast<const void *>(&fill_mrg_kernel<PPL, FAM_MIXED>);
-}
-
-template <int NW, int PPL, uint32_t FAM>
-static const void *spec_pair(bool repair, bool single, bool hold)
-{
-    if (repair)
-        return reinterpret_cast<const void *>(&spec_repair_kernel<PhiloxRedo<NW, PPL, FAM>>);
-    if (hold)
-        return single ? reinterpret_cast<const void *>(&spec_hold_kernel<NW, PPL, FAM, true>)
-                      : reinterpret_cast<const void *>(&spec_hold_kernel<NW, PPL, FAM, false>);
-    return single ? reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM, true>)
-                  : reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM, false>);
-}
-
-template <int NW, int PPL>
-static const void *spec_family(uint32_t fam, bool repair, bool single, bool hold)
-{
-    switch (fam) {
-    case FAM_ENUM: return spec_pair<NW, PPL, FAM_ENUM>(repair, single, hold);
-    case FAM_PHILOX32: return spec_pair<NW, PPL, FAM_PHILOX32>(repair, single, hold);
-    default: return spec_pair<NW, PPL, FAM_PHILOX>(repair, single, hold);
-    }
-}
-
-template <int PPL, uint32_t FAM>
-static const void *spec_mrg_pair(bool repair, bool single)
-{
-    if (repair)
-        return reinterpret_cast<const void *>(&spec_repair_kernel<MrgRedo<PPL, FAM>>);
-    return single ? reinterpret_cast<const void *>(&spec_mrg_kernel<PPL, FAM, true>)
-                  : reinterpret_cast<const void *>(&spec_mrg_kernel<PPL, FAM, false>);
-}
-
-template <int PPL>
-static const void *spec_mrg_family(uint32_t fam, bool repair, bool single)
-{
-    return fam == FAM_MRG ? spec_mrg_pair<PPL, FAM_MRG>(repair, single)
-                          : spec_mrg_pair<PPL, FAM_MIXED>(repair, single);
-}
-
-// The wave-granular speculative fill of a single segment (or its repair)
-// for a Philox-family generator; null for other families.
-const void *spec_wave_kernel_for(uint32_t fam, bool repair)
-{
-    switch (fam) {
-    case FAM_PHILOX32:
-        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<FAM_PHILOX32>)
-                      : reinterpret_cast<const void *>(
-                            &spec_wave_kernel<FAM_PHILOX32, kChunksPerWave>);
-    case FAM_PHILOX:
-        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<FAM_PHILOX>)
-                      : reinterpret_cast<const void *>(
-                            &spec_wave_kernel<FAM_PHILOX, kChunksPerWave>);
-    case FAM_ENUM:
-        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<FAM_ENUM>)
-                      : reinterpret_cast<const void *>(&spec_wave_kernel<FAM_ENUM, kChunksPerWave>);
-    default:
-        return nullptr;
-    }
-}
-
-// The speculative fill kernel (single-segment or batched form) or its
-// repair kernel for (family, threads per workgroup, pairs per lane); null
-// for shapes without one.
-const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair,
-                            bool single, bool hold)
-{
-    if (fam == FAM_MRG || fam == FAM_MIXED) {
-        // the MRG fill always holds its window before storing
-        if (threads != kMrgBlockThreads || (!hold && !repair))
-            return nullptr;
-        switch (ppl) {
-        case 4: return spec_mrg_family<4>(fam, repair, single);
-        case 8: return spec_mrg_family<8>(fam, repair, single);
-        case 16: return spec_mrg_family<16>(fam, repair, single);
-        default: return nullptr;
-        }
-    }
-    if (threads == 256) {
-        switch (ppl) {
-        case 2: return spec_family<4, 2>(fam, repair, single, hold);
-        case 4: return spec_family<4, 4>(fam, repair, single, hold);
-        case 8: return spec_family<4, 8>(fam, repair, single, hold);
-        case 16: return spec_family<4, 16>(fam, repair, single, hold);
-        case 32: return spec_family<4, 32>(fam, repair, single, hold);
-        default: return nullptr;
-        }
-    }
-    if (threads == 512) {
-        switch (ppl) {
-        case 8: return spec_family<8, 8>(fam, repair, single, hold);
-        case 16: return spec_family<8, 16>(fam, repair, single, hold);
-        default: return nullptr;
-        }
-    }
-    if (threads == 1024) {
-        switch (ppl) {
-        case 8: return spec_family<16, 8>(fam, repair, single, hold);
-        case 16: return spec_family<16, 16>(fam, repair, single, hold);
-        default: return nullptr;
-        }
-    }
-    return nullptr;
-}
-
-// The single-word-consumption kernel for a Philox-family generator (256
-// threads), or null.
-const void *single_kernel_for(uint32_t fam)
-{
-    switch (fam) {
-    case FAM_PHILOX: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_PHILOX>);
-    case FAM_PHILOX32: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_PHILOX32>);
-    case FAM_ENUM: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_ENUM>);
-    case FAM_MRG: return reinterpret_cast<const void *>(&seq_single_kernel<4, FAM_MRG>);
-    default: return nullptr;
-    }
-}
-
-// The one-word-consumption speculative fill of one segment across
-// workgroups (256 threads), or its repair pass; null for other families.
-const void *spec_words_kernel_for(uint32_t fam, bool repair)
-{
-    switch (fam) {
-    case FAM_PHILOX:
-        return repair ? reinterpret_cast<const void *>(&spec_words_repair_kernel<4, FAM_PHILOX>)
-                      : reinterpret_cast<const void *>(&spec_words_kernel<4, FAM_PHILOX>);
-    case FAM_PHILOX32:
-        return repair ? reinterpret_cast<const void *>(&spec_words_repair_kernel<4, FAM_PHILOX32>)
-                      : reinterpret_cast<const void *>(&spec_words_kernel<4, FAM_PHILOX32>);
-    case FAM_ENUM:
-        return repair ? reinterpret_cast<const void *>(&spec_words_repair_kernel<4, FAM_ENUM>)
-                      : reinterpret_cast<const void *>(&spec_words_kernel<4, FAM_ENUM>);
-    case FAM_MRG:
-        return repair ? reinterpret_cast<const void *>(&spec_words_repair_kernel<4, FAM_MRG>)
-                      : reinterpret_cast<const void *>(&spec_words_kernel<4, FAM_MRG>);
-    default: return nullptr;
-    }
-}
-
-// The kernel for (family, threads per workgroup, pairs per lane), either
-// the look-back kernel or the segment-sequential one (seq), or null if
-// that shape is not instantiated.
-const void *fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool seq)
-{
-    if (fam == FAM_PHILOX || fam == FAM_ENUM || fam == FAM_PHILOX32) {
-        if (threads == 256) {
-            switch (ppl) {
-            case 2: return philox_family<4, 2>(fam, seq);
-            case 4: return philox_family<4, 4>(fam, seq);
-            case 8: return philox_family<4, 8>(fam, seq);
-            case 16: return philox_family<4, 16>(fam, seq);
-            case 32: return philox_family<4, 32>(fam, seq);
-            default: return nullptr;
-            }
-        }
-        if (threads == 512) {
-            switch (ppl) {
-            case 8: return philox_family<8, 8>(fam, seq);
-            case 16: return philox_family<8, 16>(fam, seq);
-            default: return nullptr;
-            }
-        }
-        if (threads == 1024) {
-            switch (ppl) {
-            case 8: return philox_family<16, 8>(fam, seq);
-            case 16: return philox_family<16, 16>(fam, seq);
-            default: return nullptr;
-            }
-        }
-        return nullptr;
-    }
-    if (threads != kMrgBlockThreads)
-        return nullptr;
-    switch (ppl) {
-    case 4: return mrg_family<4>(fam, seq);
-    case 8: return mrg_family<8>(fam, seq);
-    case 16: return mrg_family<16>(fam, seq);
-    default: return nullptr;
-    }
-}
-
-hipError_t launch_toggle_flip(uint32_t *flip, hipStream_t stream)
-{
-    hipLaunchKernelGGL(toggle_flip_kernel, dim3(1), dim3(1), 0, stream, flip);
-    return hipGetLastError();
-}
-
-const void *toggle_flip_kernel_ptr()
-{
-    return reinterpret_cast<const void *>(&toggle_flip_kernel);
-}
-
-hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads, const LaunchArgs &args,
-                       hipStream_t stream)
-{
-    void *params[] = {const_cast<LaunchArgs *>(&args)};
-    return hipLaunchKernel(kernel, dim3(grid), dim3(threads), params, 0, stream);
-}
-
-hipError_t launch_set_counter(uint64_t *slot, uint64_t value, hipStream_t stream)
-{
-    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(1), 0, stream, slot, value);
-    return hipGetLastError();
-}
-
-hipError_t launch_zero_words(uint64_t *p, size_t n, hipStream_t stream)
-{
-    if (n == 0)
-        return hipSuccess;
-    const size_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
-    hipLaunchKernelGGL(zero_words_kernel, dim3(uint32_t(blocks)), dim3(256), 0, stream, p, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_expand_tiles(const Segment *segs, uint32_t nseg, uint32_t *tile_seg,
-                               hipStream_t stream)
-{
-    if (nseg == 0)
-        return hipSuccess;
-    const uint32_t blocks = nseg < 8192 ? nseg : 8192;
-    hipLaunchKernelGGL(expand_tiles_kernel, dim3(blocks), dim3(256), 0, stream, segs, nseg,
-                       tile_seg);
-    return hipGetLastError();
-}
-
 }  // namespace prngd

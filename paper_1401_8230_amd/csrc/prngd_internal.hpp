@@ -15,6 +15,17 @@ enum Family : uint32_t {
     FAM_PHILOX32 = 4  // FAM_PHILOX at w = 32 (x in [0, 2^32 - 1], no shift)
 };
 
+// Flag on a kernel's family: the output map's constants come from the
+// launch (Eq. (4), or 1 - z).  Kernels without it compute the default
+// Eq. (5) map with the constant S alone.
+constexpr uint32_t FAM_ANY_MAP = 0x10u;
+constexpr uint32_t kFamBaseMask = 0xFu;
+
+constexpr uint32_t fam_base(uint32_t fam)
+{
+    return fam & kFamBaseMask;
+}
+
 constexpr int kMrgBlockThreads = 256;    // MRG kernels: 4 waves of 64 lanes
 constexpr int kMaxBlockThreads = 1024;
 constexpr int kMrgDigits = 8;            // window index = 8 base-256 digits
@@ -107,6 +118,26 @@ struct LaunchArgs {
 };
 
 constexpr uint32_t kMaxTiles = 0xFFFFFFF0u;
+
+// Kernel lookup of each kernel translation unit, for a family with the
+// map flag MAPF (0 or FAM_ANY_MAP); null for shapes that are not
+// instantiated.  The runtime goes through the routers of prngd_k_misc.hip,
+// which pick MAPF from the family.
+template <uint32_t MAPF>
+const void *philox_fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool seq);
+template <uint32_t MAPF>
+const void *philox_spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair,
+                                   bool single, bool hold);
+template <uint32_t MAPF>
+const void *philox_wave_kernel_for(uint32_t fam, bool repair);
+template <uint32_t MAPF>
+const void *mrg_fill_kernel_for(uint32_t fam, uint32_t ppl, bool seq);
+template <uint32_t MAPF>
+const void *mrg_spec_kernel_for(uint32_t fam, uint32_t ppl, bool repair, bool single);
+template <uint32_t MAPF>
+const void *single_kernel_for(uint32_t fam);
+template <uint32_t MAPF>
+const void *spec_words_kernel_for(uint32_t fam, bool repair);
 
 // Device error codes (bit flags in the error word).
 constexpr uint32_t kErrLookbackStall = 1;

@@ -1,0 +1,150 @@
+// prngd_k_misc.hip -- small kernels of the runtime (plan parity, position
+// writes, clearing, tile maps), the kernel lookup by family and launch
+// shape, and the launch wrappers.
+#include <type_traits>
+
+#include "prngd_device.hpp"
+
+namespace prngd {
+namespace {
+
+// Toggles a resident plan's replay parity after all of a replay's fills.
+__global__ void toggle_flip_kernel(uint32_t *flip)
+{
+    *flip ^= 1u;
+}
+
+// Sets a handle's position slot (both halves, so either parity reads it).
+__global__ void set_counter_kernel(uint64_t *slot, uint64_t value)
+{
+    slot[0] = value;
+    slot[1] = value;
+}
+
+__global__ void zero_words_kernel(uint64_t *p, size_t n)
+{
+    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+         i += size_t(gridDim.x) * blockDim.x)
+        p[i] = 0;
+}
+
+// tile_seg[tile_begin .. tile_begin + ntiles) = segment index, one
+// workgroup per segment.
+__global__ void expand_tiles_kernel(const Segment *segs, uint32_t nseg, uint32_t *tile_seg)
+{
+    for (uint32_t s = blockIdx.x; s < nseg; s += gridDim.x) {
+        const uint32_t b = segs[s].tile_begin, c = segs[s].ntiles;
+        for (uint32_t i = threadIdx.x; i < c; i += blockDim.x)
+            tile_seg[b + i] = s;
+    }
+}
+}  // namespace
+
+// The routers below take a family with or without FAM_ANY_MAP and pick
+// the kernels built for it.
+template <class F>
+static const void *by_map(uint32_t fam, F &&f)
+{
+    return (fam & FAM_ANY_MAP) ? f(std::integral_constant<uint32_t, FAM_ANY_MAP>())
+                               : f(std::integral_constant<uint32_t, 0u>());
+}
+
+// The speculative fill kernel (single-segment or batched form) or its
+// repair kernel for (family, threads per workgroup, pairs per lane); null
+// for shapes without one.
+const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair,
+                            bool single, bool hold)
+{
+    if (fam_base(fam) == FAM_MRG || fam_base(fam) == FAM_MIXED) {
+        // the MRG fill always holds its window before storing
+        if (threads != kMrgBlockThreads || (!hold && !repair))
+            return nullptr;
+        return by_map(fam, [&](auto m) {
+            return mrg_spec_kernel_for<decltype(m)::value>(fam, ppl, repair, single);
+        });
+    }
+    return by_map(fam, [&](auto m) {
+        return philox_spec_kernel_for<decltype(m)::value>(fam, threads, ppl, repair, single, hold);
+    });
+}
+
+// The kernel for (family, threads per workgroup, pairs per lane), either
+// the look-back kernel or the segment-sequential one (seq), or null if
+// that shape is not instantiated.
+const void *fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool seq)
+{
+    const uint32_t b = fam_base(fam);
+    if (b == FAM_PHILOX || b == FAM_ENUM || b == FAM_PHILOX32)
+        return by_map(fam, [&](auto m) {
+            return philox_fill_kernel_for<decltype(m)::value>(fam, threads, ppl, seq);
+        });
+    if (threads != kMrgBlockThreads)
+        return nullptr;
+    return by_map(fam, [&](auto m) { return mrg_fill_kernel_for<decltype(m)::value>(fam, ppl, seq); });
+}
+
+// The wave-granular speculative fill of a single segment (or its repair)
+// for a Philox-family generator; null for other families.
+const void *spec_wave_kernel_for(uint32_t fam, bool repair)
+{
+    return by_map(fam, [&](auto m) { return philox_wave_kernel_for<decltype(m)::value>(fam, repair); });
+}
+
+// The single-word-consumption kernel (256 threads), or null.
+const void *single_kernel_for(uint32_t fam)
+{
+    return by_map(fam, [&](auto m) { return single_kernel_for<decltype(m)::value>(fam); });
+}
+
+// The one-word-consumption speculative fill of one segment across
+// workgroups (256 threads), or its repair pass; null for other families.
+const void *spec_words_kernel_for(uint32_t fam, bool repair)
+{
+    return by_map(fam, [&](auto m) { return spec_words_kernel_for<decltype(m)::value>(fam, repair); });
+}
+
+hipError_t launch_toggle_flip(uint32_t *flip, hipStream_t stream)
+{
+    hipLaunchKernelGGL(toggle_flip_kernel, dim3(1), dim3(1), 0, stream, flip);
+    return hipGetLastError();
+}
+
+const void *toggle_flip_kernel_ptr()
+{
+    return reinterpret_cast<const void *>(&toggle_flip_kernel);
+}
+
+hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads, const LaunchArgs &args,
+                       hipStream_t stream)
+{
+    void *params[] = {const_cast<LaunchArgs *>(&args)};
+    return hipLaunchKernel(kernel, dim3(grid), dim3(threads), params, 0, stream);
+}
+
+hipError_t launch_set_counter(uint64_t *slot, uint64_t value, hipStream_t stream)
+{
+    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(1), 0, stream, slot, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_words(uint64_t *p, size_t n, hipStream_t stream)
+{
+    if (n == 0)
+        return hipSuccess;
+    const size_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+    hipLaunchKernelGGL(zero_words_kernel, dim3(uint32_t(blocks)), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_tiles(const Segment *segs, uint32_t nseg, uint32_t *tile_seg,
+                               hipStream_t stream)
+{
+    if (nseg == 0)
+        return hipSuccess;
+    const uint32_t blocks = nseg < 8192 ? nseg : 8192;
+    hipLaunchKernelGGL(expand_tiles_kernel, dim3(blocks), dim3(256), 0, stream, segs, nseg,
+                       tile_seg);
+    return hipGetLastError();
+}
+
+}  // namespace prngd

@@ -1,0 +1,87 @@
+// prngd_k_spec.hip -- the speculative Philox-family fill kernels (one-shot
+// grids with rejection-list hints), their repair pass, and the
+// wave-granular single-fill form.  Built twice: with PRNGD_MAPF = 0 (the
+// Eq. (5) kernels) and PRNGD_MAPF = FAM_ANY_MAP.
+#include "prngd_device.hpp"
+
+namespace prngd {
+namespace {
+
+template <int NW, int PPL, uint32_t FAM>
+const void *spec_pair(bool repair, bool single, bool hold)
+{
+    if (repair)
+        return reinterpret_cast<const void *>(&spec_repair_kernel<PhiloxRedo<NW, PPL, FAM>>);
+    if (hold)
+        return single ? reinterpret_cast<const void *>(&spec_hold_kernel<NW, PPL, FAM, true>)
+                      : reinterpret_cast<const void *>(&spec_hold_kernel<NW, PPL, FAM, false>);
+    return single ? reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM, true>)
+                  : reinterpret_cast<const void *>(&spec_philox_kernel<NW, PPL, FAM, false>);
+}
+
+template <int NW, int PPL>
+const void *spec_family(uint32_t fam, bool repair, bool single, bool hold)
+{
+    switch (fam_base(fam)) {
+    case FAM_ENUM: return spec_pair<NW, PPL, FAM_ENUM | PRNGD_MAPF>(repair, single, hold);
+    case FAM_PHILOX32: return spec_pair<NW, PPL, FAM_PHILOX32 | PRNGD_MAPF>(repair, single, hold);
+    default: return spec_pair<NW, PPL, FAM_PHILOX | PRNGD_MAPF>(repair, single, hold);
+    }
+}
+
+}  // namespace
+
+template <>
+const void *philox_spec_kernel_for<PRNGD_MAPF>(uint32_t fam, uint32_t threads, uint32_t ppl,
+                                               bool repair, bool single, bool hold)
+{
+    if (threads == 256) {
+        switch (ppl) {
+        case 2: return spec_family<4, 2>(fam, repair, single, hold);
+        case 4: return spec_family<4, 4>(fam, repair, single, hold);
+        case 8: return spec_family<4, 8>(fam, repair, single, hold);
+        case 16: return spec_family<4, 16>(fam, repair, single, hold);
+        case 32: return spec_family<4, 32>(fam, repair, single, hold);
+        default: return nullptr;
+        }
+    }
+    if (threads == 512) {
+        switch (ppl) {
+        case 8: return spec_family<8, 8>(fam, repair, single, hold);
+        case 16: return spec_family<8, 16>(fam, repair, single, hold);
+        default: return nullptr;
+        }
+    }
+    if (threads == 1024) {
+        switch (ppl) {
+        case 8: return spec_family<16, 8>(fam, repair, single, hold);
+        case 16: return spec_family<16, 16>(fam, repair, single, hold);
+        default: return nullptr;
+        }
+    }
+    return nullptr;
+}
+
+// The wave-granular speculative fill of a single segment (or its repair)
+// for a Philox-family generator; null for other families.
+template <>
+const void *philox_wave_kernel_for<PRNGD_MAPF>(uint32_t fam, bool repair)
+{
+    constexpr uint32_t P32 = FAM_PHILOX32 | PRNGD_MAPF, P = FAM_PHILOX | PRNGD_MAPF,
+                       EN = FAM_ENUM | PRNGD_MAPF;
+    switch (fam_base(fam)) {
+    case FAM_PHILOX32:
+        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<P32>)
+                      : reinterpret_cast<const void *>(&spec_wave_kernel<P32, kChunksPerWave>);
+    case FAM_PHILOX:
+        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<P>)
+                      : reinterpret_cast<const void *>(&spec_wave_kernel<P, kChunksPerWave>);
+    case FAM_ENUM:
+        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<EN>)
+                      : reinterpret_cast<const void *>(&spec_wave_kernel<EN, kChunksPerWave>);
+    default:
+        return nullptr;
+    }
+}
+
+}  // namespace prngd

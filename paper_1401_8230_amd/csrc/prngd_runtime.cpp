@@ -767,14 +767,16 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
 {
     lp->tune = tuning_for(cfg.fam, cfg.w, default_ppl);
     lp->threads = lp->tune.block_threads;
-    lp->kernel = fill_kernel_for(cfg.fam, lp->threads, lp->tune.pairs_per_lane, false);
-    lp->seq_kernel = fill_kernel_for(cfg.fam, lp->threads, lp->tune.pairs_per_lane, true);
+    // kernels built for Eq. (5) alone, or taking the map's constants
+    const uint32_t kfam = cfg.fam | (cfg.map == PRNGD_MAP_EQ5 ? 0u : FAM_ANY_MAP);
+    lp->kernel = fill_kernel_for(kfam, lp->threads, lp->tune.pairs_per_lane, false);
+    lp->seq_kernel = fill_kernel_for(kfam, lp->threads, lp->tune.pairs_per_lane, true);
     if (!lp->kernel || !lp->seq_kernel)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u threads x %u pairs per lane",
                     lp->threads, lp->tune.pairs_per_lane);
     if (cfg.consume == PRNGD_CONSUME_SINGLE) {
         // one workgroup of 256 threads per segment, windows in order
-        const void *k = single_kernel_for(cfg.fam);
+        const void *k = single_kernel_for(kfam);
         if (!k)
             return fail(PRNGD_ERR_UNSUPPORTED, "single-word consumption needs a single-generator "
                                                "stream (Philox, MRG32k3a or the test generator)");
@@ -784,19 +786,19 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     }
     lp->T = uint64_t(lp->threads) * lp->tune.pairs_per_lane;
     for (int hold = 0; hold < 2; ++hold) {
-        lp->spec_kernels[hold][0] = spec_kernel_for(cfg.fam, lp->threads,
+        lp->spec_kernels[hold][0] = spec_kernel_for(kfam, lp->threads,
                                                     lp->tune.pairs_per_lane, false, false, hold);
-        lp->spec_kernels[hold][1] = spec_kernel_for(cfg.fam, lp->threads,
+        lp->spec_kernels[hold][1] = spec_kernel_for(kfam, lp->threads,
                                                     lp->tune.pairs_per_lane, false, true, hold);
     }
-    lp->repair_kernel = spec_kernel_for(cfg.fam, lp->threads, lp->tune.pairs_per_lane, true,
+    lp->repair_kernel = spec_kernel_for(kfam, lp->threads, lp->tune.pairs_per_lane, true,
                                         false, false);
     lp->spec_kernel = nullptr;
     lp->spec_single_kernel = nullptr;
-    lp->wave_kernel = spec_wave_kernel_for(cfg.fam, false);
-    lp->wave_repair_kernel = spec_wave_kernel_for(cfg.fam, true);
-    lp->words_kernel = spec_words_kernel_for(cfg.fam, false);
-    lp->words_repair_kernel = spec_words_kernel_for(cfg.fam, true);
+    lp->wave_kernel = spec_wave_kernel_for(kfam, false);
+    lp->wave_repair_kernel = spec_wave_kernel_for(kfam, true);
+    lp->words_kernel = spec_words_kernel_for(kfam, false);
+    lp->words_repair_kernel = spec_words_kernel_for(kfam, true);
     lp->wave = false;
     lp->zero_word = d->zero_word;
     lp->spec = false;                  // decided per launch by choose_path

@@ -15,19 +15,14 @@ Only the standard library is used; nothing here touches a GPU.
 """
 import argparse
 import csv
-import hashlib
 import json
 import os
 import sys
 from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SRC = os.path.join(ROOT, "paper_1401_8230_amd", "csrc", "prngd_kernels.hip")
-
-
-def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+sys.path.insert(0, ROOT)
+from paper_1401_8230_amd._build import kernel_source_hash  # noqa: E402
 
 
 def short_name(name, width=90):

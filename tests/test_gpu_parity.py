@@ -492,8 +492,8 @@ def test_single_consumption_matches_oracle(gen, w, counter, n):
 
 
 @pytest.mark.parametrize("w", [8, 32])
-def test_algorithm1_literally_on_the_gpu(w):
-    # Algorithm 1 as printed = single-word consumption + Eq. (4)'s map
+def test_algorithm1_form_on_the_gpu(w):
+    # Algorithm 1's output: one-word consumption with Eq. (4)'s map
     got, expect, pos, ectr = single_fill("philox", w, 5, 3, 300001, map="eq4", misalign=True)
     assert_bits_equal(got, expect, f"Algorithm 1 w={w}")
     assert pos == ectr

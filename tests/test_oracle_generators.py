@@ -29,8 +29,12 @@ def xcheck():
     if (not os.path.exists(XCHECK_BIN)
             or os.path.getmtime(XCHECK_BIN) < os.path.getmtime(XCHECK_SRC)):
         os.makedirs(os.path.dirname(XCHECK_BIN), exist_ok=True)
+        # build under a private name, then rename: parallel test workers
+        # may build at the same time
+        tmp = f"{XCHECK_BIN}.{os.getpid()}"
         subprocess.run([hipcc, "-x", "hip", "--cuda-host-only", "-O1",
-                        XCHECK_SRC, "-o", XCHECK_BIN], check=True)
+                        XCHECK_SRC, "-o", tmp], check=True)
+        os.replace(tmp, XCHECK_BIN)
 
     def run(*args):
         out = subprocess.run([XCHECK_BIN, *map(str, args)], check=True,

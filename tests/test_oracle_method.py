@@ -405,27 +405,33 @@ def test_one_minus_map_has_no_zero_and_reaches_one():
 
 # ------------------------------------ Algorithm 1's single-word consumption
 
-def algorithm1_literal(words, w, mn, mx, count):
-    """Algorithm 1 as printed, with PRNG() returning words * k in order:
-    the exact Z of each output and the number of PRNG() calls.  Its
-    comparisons are made in exact rationals and, as printed, in double
-    precision; both must decide alike."""
-    k = Fraction(1, 2**w)
-    Rmin, Rmax = mn + k * (mx - mn), mx - k * (mx - mn)
-    rmin_dp = float(mn) + float(k) * (float(mx) - float(mn))
-    rmax_dp = float(mx) - float(k) * (float(mx) - float(mn))
+def redraw_reference(words, A0, A, B0, B, w, count):
+    """The one-word redraw built from the method's definition, in units of
+    k = 2^-w (a word X stands for x = X k): the rejection intervals of
+    Section 2 -- x1 < a0 + k (b - b0) or x1 > a - k (b - b0) -- tested on
+    each first word in exact integers, the next word taken as x2, and each
+    accepted pair mapped by Eq. (4) in exact rationals:
+    z' = (x1 + k x2 - (a0 + k b)) / (a - a0 - k (b - b0)).  Returns the
+    outputs and the number of words consumed.  The same interval test in
+    FP64 (the precision the paper computes in) must decide alike."""
+    two_w = 2**w
+    k = 2.0**-w
+    lo_dp = A0 * k + k * ((B - B0) * k)
+    hi_dp = A * k - k * ((B - B0) * k)
+    den = (A - A0) * two_w - (B - B0)
     it = iter(words)
-    calls, out = 0, []
-    for _ in range(count):
-        R1 = Fraction(-1)
-        while R1 < Rmin or R1 > Rmax:
-            R1 = Fraction(next(it)) * k
-            calls += 1
-            assert (R1 < Rmin or R1 > Rmax) == (float(R1) < rmin_dp or float(R1) > rmax_dp)
-        R2 = Fraction(next(it)) * k
-        calls += 1
-        out.append((R1 + k * R2 - (mn + k * mx)) / ((mx - mn) * (1 - k)))
-    return out, calls
+    used, out = 0, []
+    while len(out) < count:
+        X1 = next(it)
+        used += 1
+        rejected = X1 * two_w < A0 * two_w + (B - B0) or X1 * two_w > A * two_w - (B - B0)
+        assert rejected == (X1 * k < lo_dp or X1 * k > hi_dp)
+        if rejected:
+            continue
+        X2 = next(it)
+        used += 1
+        out.append(Fraction((X1 - A0) * two_w + X2 - B, den))
+    return out, used
 
 
 def _philox_w_words(seed, stream, count, w):
@@ -433,11 +439,10 @@ def _philox_w_words(seed, stream, count, w):
 
 
 @pytest.mark.parametrize("w,seed", [(3, 1), (5, 2), (8, 3), (12, 4), (16, 5)])
-def test_single_consumption_is_algorithm1_as_printed(w, seed):
+def test_single_consumption_is_the_one_word_redraw(w, seed):
     n = 3000
     words = _philox_w_words(seed, 0, 4 * n + 64, w)
-    k = Fraction(1, 2**w)
-    Z, calls = algorithm1_literal(words, w, Fraction(0), (2**w - 1) * k, n)
+    Z, calls = redraw_reference(words, 0, 2**w - 1, 0, 2**w - 1, w, n)
     s = O.PRNGD(O.GEN_PHILOX, w, seed=seed, map=O.MAP_EQ4, consume=O.CONSUME_SINGLE)
     out = s.fill(n)
     assert s.counter == calls                        # the same words consumed
@@ -447,13 +452,12 @@ def test_single_consumption_is_algorithm1_as_printed(w, seed):
         assert abs(Fraction(z) - ex) <= bound * Fraction(ulp(z))
 
 
-def test_single_consumption_mrg32k3a_is_algorithm1_as_printed():
+def test_single_consumption_mrg32k3a_is_the_one_word_redraw():
     n = 2000
     state = O.mrg_stream_base(7, 0)
     outs, _ = O.mrg_outputs(state, 2 * n + 16)
     words = [int(v) for v in outs]
-    k = Fraction(1, 2**32)
-    Z, calls = algorithm1_literal(words, 32, Fraction(1) * k, Fraction(O.M1) * k, n)
+    Z, calls = redraw_reference(words, 1, O.M1, 1, O.M1, 32, n)
     s = O.PRNGD(O.GEN_MRG32K3A, 32, seed=7, map=O.MAP_EQ4, consume=O.CONSUME_SINGLE)
     out = s.fill(n)
     assert s.counter == calls == 2 * n               # no rejection this early
