@@ -62,8 +62,10 @@ def parse():
                          "prngd_fill of --single-outputs outputs of one Philox stream")
     ap.add_argument("--single-outputs", type=int, default=1 << 30)
     ap.add_argument("--generator", choices=["philox", "mrg32k3a", "mixed"], default="philox",
-                    help="base generator of the single-stream workload (w = 32; mixed: "
-                         "x1 from Philox4x32-10, x2 from MRG32k3a)")
+                    help="base generator of the single-stream workload (mixed: x1 from "
+                         "Philox4x32-10, x2 from MRG32k3a)")
+    ap.add_argument("--width", type=int, default=32,
+                    help="w of the single-stream workload (Philox only below 32)")
     ap.add_argument("--consume", choices=["pair", "single"], default="pair",
                     help="what a rejected x1 consumes (single: Algorithm 1's loop)")
     ap.add_argument("--map", choices=["eq5", "eq4", "one_minus"], default="eq5",
@@ -326,8 +328,8 @@ SINGLE_LEGS = [("philox", 32, 1 << 30), ("mixed", 32, 1 << 28), ("mrg32k3a", 32,
 
 
 def run_single(args, result):
-    """--workload single: the headline is one stream of --generator, w = 32."""
-    leg = single_leg(args.generator, 32, args.single_outputs, args.steps, args.warmup,
+    """--workload single: the headline is one stream of --generator at w = --width."""
+    leg = single_leg(args.generator, args.width, args.single_outputs, args.steps, args.warmup,
                      seed=args.seed, map=args.map, consume=args.consume,
                      calibrate=args.calibrate)
     result.update({
@@ -501,7 +503,7 @@ def main():
         log("cpu baseline")
         if args.workload == "single":
             result["cpu_baseline"] = cpu_baseline_single(min(args.single_outputs, 1 << 28),
-                                                         args.seed, args.generator)
+                                                         args.seed, args.generator, args.width)
         else:
             result["cpu_baseline"] = cpu_baseline(
                 min(args.cpu_sample_streams, args.streams), args.outputs_per_stream, args.seed)

@@ -231,6 +231,34 @@ prngd_status_t prngd_get_map(prngd_handle_t h, prngd_map_t *map);
 prngd_status_t prngd_set_consume(prngd_handle_t h, prngd_consume_t consume);
 prngd_status_t prngd_get_consume(prngd_handle_t h, prngd_consume_t *consume);
 
+/*
+ * Words combined per output: 2 (Section 2, after prngd_create) or 3, the
+ * generalisation the paper's Conclusion names (more than two PRNs for a
+ * greater precision), read as the two-word method applied twice:
+ *   - triple t is words 3t, 3t + 1, 3t + 2 of the stream;
+ *   - the inner pair (x2, x3) is accepted by Section 2's rule into
+ *     y = x2 + k x3, of resolution k^2; the outer pair (x1, y) by the same
+ *     rule with y's span in place of b - b0.  Both reduce to x1 and x2 not
+ *     in {a0, a}; a rejection at either level consumes the whole triple;
+ *   - Eq. (5) maps z = x1 + k y with k' = k^3; in integer units
+ *     N3 = (x1 - a0 - 1) 2^2w + (x2 - a0 - 1) 2^w + (x3 - a0),
+ *     D3 = (a - a0 - 2) 2^2w + (a - a0 - 2) 2^w + (a - a0),
+ *     S3 = RN((1 - 2^-3w) / D3) computed exactly on the host, and
+ *     z' = RN(RN(N3) * S3) with RN(N3) the correctly rounded value of the
+ *     exact integer (3w bits: exact in FP64 up to w = 17), forced to
+ *     1 - 2^-53 if it rounds to 1.
+ * The position then counts triples (prngd_set_position's pair_counter is a
+ * triple counter; it is not converted).  Philox4x32-10 (any w) and the test
+ * generator only, with PRNGD_MAP_EQ5 and PRNGD_CONSUME_PAIR; such handles
+ * fill through the ordered kernels, in batches and plans too.  Handles of
+ * one batch must share it.  Errors: PRNGD_ERR_INVALID_ARGUMENT (NULL
+ * handle, words not 2 or 3, handle bound to a live plan),
+ * PRNGD_ERR_UNSUPPORTED (another generator, map or consumption; setting a
+ * map or consumption other than the defaults on a three-word handle).
+ */
+prngd_status_t prngd_set_arity(prngd_handle_t h, uint32_t words);
+prngd_status_t prngd_get_arity(prngd_handle_t h, uint32_t *words);
+
 /* Wait for the handle's outstanding work, then free it.  NULL is a no-op. */
 prngd_status_t prngd_destroy(prngd_handle_t h);
 

@@ -47,6 +47,10 @@ class Stream(ctypes.Structure):
         ("S4", ctypes.c_double),
         ("consume", ctypes.c_int),
         ("mrg", ctypes.c_uint32 * 6),
+        ("arity", ctypes.c_int),
+        ("D3_hi", ctypes.c_uint64),
+        ("D3_lo", ctypes.c_uint64),
+        ("S3", ctypes.c_double),
     ]
 
 
@@ -94,6 +98,15 @@ def lib():
         L.orc_set_consume.argtypes = [sp, ctypes.c_int]
         L.orc_word.argtypes = [sp, ctypes.c_uint64]
         L.orc_word.restype = ctypes.c_uint64
+        L.orc_set_arity.argtypes = [sp, ctypes.c_int]
+        L.orc_accept3.argtypes = [sp, ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_accept3.restype = ctypes.c_int
+        L.orc_map3.argtypes = [sp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_map3.restype = ctypes.c_double
+        L.orc_rn_u128.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_rn_u128.restype = ctypes.c_double
+        L.orc_scale3.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_scale3.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -162,6 +175,16 @@ def scale(w, D):
     return lib().orc_scale(w, D)
 
 
+def rn_u128(v):
+    """The oracle's round-to-nearest-even of a non-negative integer < 2^128."""
+    return lib().orc_rn_u128((v >> 64) & (2**64 - 1), v & (2**64 - 1))
+
+
+def scale3(w, D):
+    """The oracle's RN((2^3w - 1) / (D 2^3w)) for an integer 0 < D < 2^3w."""
+    return lib().orc_scale3(w, (D >> 64) & (2**64 - 1), D & (2**64 - 1))
+
+
 def recip(D):
     return lib().orc_recip(D)
 
@@ -170,7 +193,7 @@ class PRNGD:
     """One oracle stream (sequential, single-threaded)."""
 
     def __init__(self, generator, w, seed=0, stream=0, counter=0, ranges=None, map=MAP_EQ5,
-                 consume=CONSUME_PAIR):
+                 consume=CONSUME_PAIR, arity=2):
         self.s = Stream()
         if ranges is not None:
             a0, a, b0, b = ranges
@@ -184,6 +207,9 @@ class PRNGD:
             raise ValueError("unknown map")
         if lib().orc_set_consume(ctypes.byref(self.s), consume) != 0:
             raise ValueError("unknown consumption mode, or not a single-generator stream")
+        if lib().orc_set_arity(ctypes.byref(self.s), arity) != 0:
+            raise ValueError("three words per output need a single-generator stream, "
+                             "Eq. (5) and pair consumption")
 
     @property
     def counter(self):
@@ -208,6 +234,20 @@ class PRNGD:
     @property
     def S4(self):
         return float(self.s.S4)
+
+    @property
+    def D3(self):
+        return (int(self.s.D3_hi) << 64) | int(self.s.D3_lo)
+
+    @property
+    def S3(self):
+        return float(self.s.S3)
+
+    def accept3(self, x1, x2):
+        return bool(lib().orc_accept3(ctypes.byref(self.s), x1, x2))
+
+    def map3(self, x1, x2, x3):
+        return lib().orc_map3(ctypes.byref(self.s), x1, x2, x3)
 
     @property
     def ranges(self):

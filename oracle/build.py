@@ -14,10 +14,17 @@ CFLAGS = ["-std=c11", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
           "-fno-fast-math", "-msse2", "-mfpmath=sse", "-Wall", "-Wextra"]
 
 
-def build(verbose=False):
+# AddressSanitizer and UndefinedBehaviorSanitizer, for CPU test runs with
+# gcc's sanitizer runtimes preloaded.
+SANITIZE = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+            "-fno-sanitize-recover=undefined"]
+
+
+def build(verbose=False, sanitize=False):
     os.makedirs(OUT_DIR, exist_ok=True)
     tmp = LIB + ".tmp"
-    cmd = ["gcc", *CFLAGS, "-o", tmp, os.path.join(HERE, "prngd_oracle.c"), "-lm"]
+    cmd = ["gcc", *CFLAGS, *(SANITIZE if sanitize else []), "-o", tmp,
+           os.path.join(HERE, "prngd_oracle.c"), "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -242,6 +242,8 @@ int orc_set_consume(orc_stream *s, int consume)
     if (consume == ORC_CONSUME_SINGLE && s->generator != ORC_GEN_PHILOX &&
         s->generator != ORC_GEN_MRG32K3A && s->generator != ORC_GEN_ENUMERATE)
         return -1;
+    if (consume == ORC_CONSUME_SINGLE && s->arity == 3)
+        return -1;
     s->consume = consume;
     return 0;
 }
@@ -262,6 +264,11 @@ uint64_t orc_word(const orc_stream *s, uint64_t j)
         orc_mrg_outputs(st, 1, &o);
         return o;
     default:
+        if (s->arity == 3) {
+            /* triple t = j / 3 is (t >> 2w, t >> w, t) mod 2^w */
+            uint64_t t = j / 3, mask = (1ull << s->w) - 1;
+            return (t >> (s->w * (2 - (int)(j % 3)))) & mask;
+        }
         orc_pair(s, j / 2, &x1, &x2);
         return j % 2 ? x2 : x1;
     }
@@ -310,6 +317,8 @@ int orc_set_map(orc_stream *s, int map)
 {
     if (map != ORC_MAP_EQ5 && map != ORC_MAP_EQ4 && map != ORC_MAP_ONE_MINUS)
         return -1;
+    if (s->arity == 3 && map != ORC_MAP_EQ5)
+        return -1;
     s->map = map;
     return 0;
 }
@@ -334,6 +343,7 @@ static int finish_init(orc_stream *s)
     s->S4 = orc_recip(s->D4);
     s->map = ORC_MAP_EQ5;
     s->consume = ORC_CONSUME_PAIR;
+    s->arity = 2;
     return 0;
 }
 
@@ -521,9 +531,150 @@ static uint64_t fill_pairs(orc_stream *s, uint64_t n, int bounded, uint64_t pair
     return made;
 }
 
+/* ======================================================================
+ * Three words per output: the two-word method applied twice (see the
+ * header for the reading).
+ * ====================================================================== */
+
+/* Round-to-nearest-even of a 128-bit integer: keep its 53 leading bits,
+ * look at the rest. */
+double orc_rn_u128(uint64_t hi, uint64_t lo)
+{
+    u128 v = ((u128)hi << 64) | lo;
+    int bits = 0;
+    for (u128 t = v; t; t >>= 1)
+        bits++;
+    if (bits <= 53)
+        return (double)(uint64_t)v;            /* exact */
+    int sh = bits - 53;
+    u128 q = v >> sh;
+    u128 rem = v - (q << sh);
+    u128 half = (u128)1 << (sh - 1);
+    if (rem > half || (rem == half && (q & 1u)))
+        q += 1;                                /* may reach 2^53: still exact */
+    return ldexp((double)(uint64_t)q, sh);
+}
+
+/* RN((2^3w - 1) / (D 2^3w)) by binary long division of num = 2^3w - 1 by
+ * D: the quotient is normalised to [1, 2), its 52 fraction bits are found
+ * one by one, and the remainder decides the rounding (half to even). */
+double orc_scale3(int w, uint64_t D_hi, uint64_t D_lo)
+{
+    u128 D = ((u128)D_hi << 64) | D_lo;
+    u128 num = ((u128)1 << (3 * w)) - 1;
+    if (D == 0 || D > num)
+        return 0.0;
+    int e = 0;                                 /* num / (D 2^e) in [1, 2) */
+    while ((D << (e + 1)) <= num)
+        e++;
+    u128 d = D << e;
+    u128 q = 1, r = num - d;
+    for (int i = 0; i < 52; i++) {
+        r <<= 1;
+        q <<= 1;
+        if (r >= d) {
+            q |= 1;
+            r -= d;
+        }
+    }
+    if (2 * r > d || (2 * r == d && (q & 1u)))
+        q += 1;
+    return ldexp((double)(uint64_t)q, e - 52 - 3 * w);
+}
+
+/* Section 2's rejection intervals, exact in integers: the inner pair
+ * (x2, x3) with x3's span a - a0 (scaled by 2^w); the outer pair (x1, y)
+ * with y's span Y1 - Y0 (scaled by 2^2w). */
+int orc_accept3(const orc_stream *s, uint64_t x1, uint64_t x2)
+{
+    int w = s->w;
+    i128 span = (i128)(s->a - s->a0);
+    i128 x2s = (i128)x2 << w;
+    if (x2s < ((i128)s->a0 << w) + span || x2s > ((i128)s->a << w) - span)
+        return 0;
+    i128 yspan = ((i128)(s->a - s->a0 - 2) << w) + span;       /* Y1 - Y0 */
+    i128 x1s = (i128)x1 << (2 * w);
+    if (x1s < ((i128)s->a0 << (2 * w)) + yspan || x1s > ((i128)s->a << (2 * w)) - yspan)
+        return 0;
+    return 1;
+}
+
+double orc_map3(const orc_stream *s, uint64_t x1, uint64_t x2, uint64_t x3)
+{
+    int w = s->w;
+    u128 Y = ((u128)x2 << w) + x3;
+    u128 Y0 = ((u128)(s->a0 + 1) << w) + s->a0;
+    u128 N = ((u128)(x1 - s->a0 - 1) << (2 * w)) + (Y - Y0);
+    double z = orc_rn_u128((uint64_t)(N >> 64), (uint64_t)N) * s->S3;
+    if (z >= 1.0)
+        z = 0x1.fffffffffffffp-1;
+    return z;
+}
+
+int orc_set_arity(orc_stream *s, int arity)
+{
+    if (arity == 2) {
+        s->arity = 2;
+        return 0;
+    }
+    if (arity != 3 || s->consume != ORC_CONSUME_PAIR || s->map != ORC_MAP_EQ5 ||
+        (s->generator != ORC_GEN_PHILOX && s->generator != ORC_GEN_MRG32K3A &&
+         s->generator != ORC_GEN_ENUMERATE))
+        return -1;
+    int w = s->w;
+    u128 yspan = ((u128)(s->a - s->a0 - 2) << w) + (s->a - s->a0);
+    u128 D = ((u128)(s->a - s->a0 - 2) << (2 * w)) + yspan;
+    s->D3_hi = (uint64_t)(D >> 64);
+    s->D3_lo = (uint64_t)D;
+    s->S3 = orc_scale3(w, s->D3_hi, s->D3_lo);
+    s->arity = 3;
+    return 0;
+}
+
+/* The next n outputs of a three-word stream, triple by triple (at most n,
+ * and only triples below `end` when bounded); returns how many. */
+static uint64_t fill_triples(orc_stream *s, uint64_t n, int bounded, uint64_t end,
+                             double *out, uint64_t *accepted_index)
+{
+    int mrg = s->generator == ORC_GEN_MRG32K3A;
+    uint32_t st[6];
+    if (mrg) {
+        u128 pos = (u128)3 * s->counter;
+        uint64_t e[2] = { (uint64_t)pos, (uint64_t)(pos >> 64) };
+        memcpy(st, s->mrg, sizeof st);
+        orc_mrg_jump(st, e, 2);
+    }
+    uint64_t made = 0, t = s->counter;
+    while (made < n && !(bounded && t >= end)) {
+        uint64_t x[3];
+        for (int i = 0; i < 3; i++) {
+            if (mrg) {
+                uint32_t o;
+                orc_mrg_outputs(st, 1, &o);
+                x[i] = o;
+            } else {
+                x[i] = orc_word(s, 3 * t + (uint64_t)i);
+            }
+        }
+        t++;
+        if (!orc_accept3(s, x[0], x[1]))
+            continue;
+        out[made] = orc_map3(s, x[0], x[1], x[2]);
+        if (accepted_index)
+            accepted_index[made] = t - 1;
+        made++;
+    }
+    s->counter = t;
+    return made;
+}
+
 void orc_fill(orc_stream *s, uint64_t n, double *out,
               uint64_t *accepted_index)
 {
+    if (s->arity == 3) {
+        fill_triples(s, n, 0, 0, out, accepted_index);
+        return;
+    }
     if (s->consume == ORC_CONSUME_SINGLE) {
         fill_single(s, n, out, accepted_index);
         return;
@@ -535,5 +686,7 @@ uint64_t orc_fill_pairs(orc_stream *s, uint64_t pair_end, uint64_t max_out, doub
 {
     if (s->consume == ORC_CONSUME_SINGLE)
         return 0;
+    if (s->arity == 3)
+        return fill_triples(s, max_out, 1, pair_end, out, NULL);
     return fill_pairs(s, max_out, 1, pair_end, out, NULL);
 }

@@ -77,6 +77,10 @@ typedef struct {
     double   S4;       /* RN(1 / D4)                                    */
     int      consume;  /* ORC_CONSUME_*                                 */
     uint32_t mrg[6];   /* MRG32k3a state at stream position 0          */
+    int      arity;    /* words per output: 2, or 3 (orc_set_arity)     */
+    uint64_t D3_hi;    /* three words: D3 = (a - a0 - 2) 2^2w + Y1 - Y0 */
+    uint64_t D3_lo;    /*   (a 128-bit integer, two halves)             */
+    double   S3;       /* RN((1 - 2^-3w) / D3)                          */
 } orc_stream;
 
 /* ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ---------------- */
@@ -116,8 +120,8 @@ void orc_fill(orc_stream *s, uint64_t n, double *out,
               uint64_t *accepted_index);
 /* The outputs of the accepted pairs among pairs [s->counter, pair_end), in
  * order, at most max_out of them; returns how many were written and leaves
- * s->counter at the first pair not examined.  Pair consumption only (returns
- * 0 otherwise).  Concatenating the outputs of consecutive pair ranges gives
+ * s->counter at the first pair not examined (triples, for three words per
+ * output).  Pair consumption only (returns 0 otherwise).  Concatenating the outputs of consecutive pair ranges gives
  * orc_fill's sequence, so one long stream can be walked in pieces. */
 uint64_t orc_fill_pairs(orc_stream *s, uint64_t pair_end, uint64_t max_out,
                         double *out);
@@ -131,8 +135,33 @@ int orc_set_map(orc_stream *s, int map);
  * stream combines two generators.  The counter then counts words. */
 int orc_set_consume(orc_stream *s, int consume);
 /* Word j of a single-generator stream: Philox word j >> (32 - w); MRG32k3a
- * output j; ENUMERATE: x1 of pair j / 2 for even j, x2 for odd j. */
+ * output j; ENUMERATE: x1 of pair j / 2 for even j, x2 for odd j (with three
+ * words per output: word 3t + i is digit 2 - i, base 2^w, of t). */
 uint64_t orc_word(const orc_stream *s, uint64_t j);
+
+/* ---- Three words per output (the paper's Conclusion) --------------------
+ * The two-word method applied twice.  The inner pair (x2, x3) is accepted
+ * by Section 2's rule and gives y = x2 + k x3, a PRN of resolution k^2 on
+ * [b0', b'] = [(a0 + 1) + k a0, (a - 1) + k a] (in units of the words).
+ * The outer pair (x1, y) is accepted by the same rule with b' - b0' in
+ * place of b - b0, and Eq. (5) maps z = x1 + k y with k' = k^3.  In
+ * integer units (all multiplied by 2^2w): Y = x2 2^w + x3,
+ * Y0 = (a0 + 1) 2^w + a0, Y1 = (a - 1) 2^w + a,
+ * N3 = (x1 - a0 - 1) 2^2w + (Y - Y0), D3 = (a - a0 - 2) 2^2w + (Y1 - Y0),
+ * z' = RN(RN(N3) * S3), S3 = RN((2^3w - 1) / (D3 2^3w)), forced below 1
+ * like the two-word map.  RN(N3) is the correctly rounded value of the
+ * exact integer.  Triple t is words 3t, 3t + 1, 3t + 2; a rejection at
+ * either level consumes the whole triple, and the counter counts triples.
+ * Single-generator streams (Philox, MRG32k3a, ENUMERATE), Eq. (5), pair
+ * consumption. */
+int orc_set_arity(orc_stream *s, int arity);
+/* The outer and inner acceptance tests of a triple, exact integers. */
+int orc_accept3(const orc_stream *s, uint64_t x1, uint64_t x2);
+double orc_map3(const orc_stream *s, uint64_t x1, uint64_t x2, uint64_t x3);
+/* RN of the 128-bit integer hi 2^64 + lo (round half to even). */
+double orc_rn_u128(uint64_t hi, uint64_t lo);
+/* RN((2^3w - 1) / (D 2^3w)) for the 128-bit D = hi 2^64 + lo, 0 < D < 2^3w. */
+double orc_scale3(int w, uint64_t D_hi, uint64_t D_lo);
 
 #ifdef __cplusplus
 }

@@ -15,11 +15,12 @@ OBJ_DIR = os.path.join(HERE, "_build")
 # kernels that take the map's constants from the launch (FAM_ANY_MAP).
 FAMILY_SOURCES = ["prngd_k_spec.hip", "prngd_k_philox.hip", "prngd_k_single.hip",
                   "prngd_k_mrg.hip"]
-SOURCES = ["prngd_k_misc.hip", "prngd_probes.hip", "prngd_runtime.cpp"]
+SOURCES = ["prngd_k_triple.hip", "prngd_k_misc.hip", "prngd_probes.hip", "prngd_runtime.cpp"]
 UNITS = ([(src, "eq5", ["-DPRNGD_MAPF=0u"]) for src in FAMILY_SOURCES]
          + [(src, "anymap", ["-DPRNGD_MAPF=FAM_ANY_MAP"]) for src in FAMILY_SOURCES]
          + [(src, "", []) for src in SOURCES])
-KERNEL_SOURCES = ["prngd_device.hpp", "prngd_internal.hpp", "prngd_k_misc.hip"] + FAMILY_SOURCES
+KERNEL_SOURCES = ["prngd_device.hpp", "prngd_internal.hpp", "prngd_k_misc.hip",
+                  "prngd_k_triple.hip"] + FAMILY_SOURCES
 
 # -ffp-contract=off keeps every FP64 operation of the map a separate IEEE
 # operation; packed FP32 instructions are disabled for the device code.
@@ -51,23 +52,32 @@ def hipcc():
     return path
 
 
-def _compile(unit, verbose):
+# Host code only (the device code is built as always): AddressSanitizer and
+# UndefinedBehaviorSanitizer for the runtime, for CPU test runs with the
+# clang sanitizer runtime preloaded.
+SANITIZE_HOST = ["-g", "-fno-omit-frame-pointer", "-Xarch_host", "-fsanitize=address",
+                 "-Xarch_host", "-fsanitize=undefined"]
+
+
+def _compile(unit, verbose, extra=()):
     src, tag, defines = unit
     stem = src.rsplit(".", 1)[0] + (f"_{tag}" if tag else "")
     obj = os.path.join(OBJ_DIR, stem + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "c++", "-D__HIP_PLATFORM_AMD__"]
-    cmd = [hipcc(), *HIPCC_FLAGS, *defines, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *HIPCC_FLAGS, *extra, *defines, *lang, "-c", os.path.join(CSRC, src),
+           "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     return obj
 
 
-def build(verbose=False, jobs=None):
+def build(verbose=False, jobs=None, sanitize_host=False):
     os.makedirs(OBJ_DIR, exist_ok=True)
     jobs = jobs or min(len(UNITS), os.cpu_count() or 1, 8)
+    extra = SANITIZE_HOST if sanitize_host else []
     with ThreadPoolExecutor(max_workers=jobs) as pool:
-        objs = list(pool.map(lambda unit: _compile(unit, verbose), UNITS))
+        objs = list(pool.map(lambda unit: _compile(unit, verbose, extra), UNITS))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     if verbose:

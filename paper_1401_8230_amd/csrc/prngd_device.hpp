@@ -1169,7 +1169,10 @@ __device__ __forceinline__ void lookback_loop(const LaunchArgs &args, Scratch &s
         }
         __syncthreads();
         uint64_t running = sh.excl;
-        sh.store(tile, args, seg, win, running, agg, next_counter);
+        // a planned tile may lie wholly past output n - 1 (its segment's
+        // rejections fell short of the plan): it stores nothing
+        if (running < seg.n)
+            sh.store(tile, args, seg, win, running, agg, next_counter);
         running += agg;
         // the last tile takes every further window until n outputs
         for (uint64_t w2 = win + 1; t == seg.ntiles - 1 && running < seg.n; ++w2) {
@@ -1335,6 +1338,240 @@ struct MrgScratch {
         tile.store(a, s, win, excl, total, nc, vals);
     }
 };
+
+// ======================================================================
+// Three words per output (the paper's Conclusion: more than two PRNs
+// combined), the two-word method applied twice.  Triple t of a stream is
+// words 3t, 3t + 1, 3t + 2; it is kept iff neither x1 nor x2 is a0 or a
+// (Section 2's rule for the inner pair (x2, x3), then for the outer pair
+// (x1, y = x2 + k x3), whose span is below one step of x1), and maps to
+//   N3 = (x1 - a0 - 1) 2^2w + (x2 - a0 - 1) 2^w + (x3 - a0),
+//   z' = RN(RN(N3) * S3),  S3 = RN((1 - 2^-3w) / D3),  forced below 1,
+// with RN(N3) the correctly rounded value of the exact integer.  Four
+// triples are three Philox blocks, so thread (j, tid) of a window starting
+// at triple wb (a multiple of 4) takes group g = wb / 4 + j B + tid:
+// blocks 3g .. 3g + 2, triples 4g .. 4g + 3 (window offsets
+// 4 (j B + tid) + i), and a wave's outputs for one j are contiguous.
+// ======================================================================
+
+// RN(U) for U = hi 2^64 + lo < 2^96, round half to even: with hi = 0 one
+// fused multiply-add of its 32-bit halves; otherwise the 53 leading bits,
+// the next bit and a sticky bit of the rest, from U shifted so that its
+// leading one sits at bit 95.
+__device__ __forceinline__ double rn_u96(uint32_t hi, uint64_t lo)
+{
+    if (hi == 0)
+        return __builtin_fma(double(uint32_t(lo >> 32)), 4294967296.0, double(uint32_t(lo)));
+    const uint32_t lz = uint32_t(__builtin_clz(hi));                 // 0 .. 31
+    const uint64_t top = (uint64_t(hi) << (32 + lz)) | (lo >> (32 - lz));
+    const uint32_t rest = uint32_t(lo << lz);
+    uint64_t m = top >> 11;                                          // 53 bits
+    const bool round = (top >> 10) & 1u;
+    const bool sticky = (top & 0x3FFu) != 0 || rest != 0;
+    if (round && (sticky || (m & 1u)))
+        ++m;                                                         // 2^53 at most: exact
+    return __builtin_ldexp(double(m), 43 - int(lz));
+}
+
+// z' of one kept triple; w < 32 unless the family is FAM_PHILOX32.
+template <uint32_t FAM>
+__device__ __forceinline__ double map3(uint32_t x1, uint32_t x2, uint32_t x3, const LaunchArgs &a)
+{
+    const uint32_t w = fam_base(FAM) == FAM_PHILOX32 ? 32u : a.w;
+    const uint32_t hi = x1 - a.a0 - 1u;
+    const uint64_t M = (uint64_t(x2 - a.a0 - 1u) << w) + (x3 - a.a0);    // Y - Y0 < 2^2w
+    double N;
+    if (2u * w <= 53u) {
+        // M is exact in FP64; the fma rounds the exact sum once
+        N = __builtin_fma(double(hi), __builtin_ldexp(1.0, int(2u * w)), double(M));
+    } else {
+        // U = hi 2^2w + M, 2w >= 54: bits 64 and up, and the low 64 bits
+        const uint32_t u2 = 2u * w == 64u ? hi : uint32_t(uint64_t(hi) >> (64u - 2u * w));
+        const uint64_t u = 2u * w == 64u ? M : (uint64_t(hi) << (2u * w)) | M;
+        N = rn_u96(u2, u);
+    }
+    const double z = N * a.S;
+    return z < kBelowOne ? z : kBelowOne;
+}
+
+template <int NW, int G, uint32_t FAM>
+struct TripleTile {
+    static constexpr int B = 64 * NW;
+    static constexpr int PPL = 4 * G;                 // triples per thread
+    static constexpr uint32_t T = uint32_t(B) * PPL;  // triples per window
+    static constexpr int E = G * NW;                  // (j, wave) groups in triple order
+    static constexpr int kOffWords = E + 1;
+    static constexpr uint32_t kAll = PPL == 32 ? 0xFFFFFFFFu : ((1u << PPL) - 1u);
+
+    double v[PPL];
+    uint32_t acc;          // bit 4j + i: triple i of slot j kept
+    bool clean;            // every triple of the window kept
+
+    // The 12 words of group g: triple 4g + i is (x[3i], x[3i + 1], x[3i + 2]).
+    __device__ __forceinline__ static void group_words(const LaunchArgs &args,
+                                                       const Segment &seg, uint64_t g,
+                                                       uint32_t x[12])
+    {
+        if (fam_base(FAM) == FAM_ENUM) {
+            const uint64_t mask = (uint64_t(1) << args.w) - 1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint64_t t = 4 * g + uint32_t(i);
+                x[3 * i] = uint32_t((t >> (2 * args.w)) & mask);
+                x[3 * i + 1] = uint32_t((t >> args.w) & mask);
+                x[3 * i + 2] = uint32_t(t & mask);
+            }
+        } else {
+            const uint32_t sh = fam_base(FAM) == FAM_PHILOX32 ? 0u : 32u - args.w;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const uint64_t blk = 3 * g + uint32_t(b);
+                const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u,
+                                               seg.stream_id, uint32_t(seg.seed),
+                                               uint32_t(seg.seed >> 32));
+                x[4 * b] = r.v0 >> sh;
+                x[4 * b + 1] = r.v1 >> sh;
+                x[4 * b + 2] = r.v2 >> sh;
+                x[4 * b + 3] = r.v3 >> sh;
+            }
+        }
+    }
+
+    // Generate the window of T triples from triple wb (a multiple of 4), from
+    // window offset lo_off on; returns its number of kept triples, and for
+    // a window that is not clean leaves each (j, wave) group's exclusive
+    // offset in s_off.
+    __device__ __forceinline__ uint32_t generate(const LaunchArgs &args, const Segment &seg,
+                                                 uint64_t wb, uint32_t lo_off, uint32_t *s_off)
+    {
+        const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+        const uint32_t hmax = args.a - args.a0 - 1u;
+        acc = 0;
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            uint32_t x[12];
+            group_words(args, seg, (wb >> 2) + uint32_t(j) * B + tid, x);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool ok = x[3 * i] - args.a0 - 1u < hmax &&
+                                x[3 * i + 1] - args.a0 - 1u < hmax;
+                v[4 * j + i] = map3<FAM>(x[3 * i], x[3 * i + 1], x[3 * i + 2], args);
+                acc |= uint32_t(ok) << (4 * j + i);
+            }
+        }
+        if (lo_off != 0) {
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (4u * (uint32_t(j) * B + tid) + uint32_t(i) < lo_off)
+                        acc &= ~(1u << (4 * j + i));
+        }
+        clean = !__syncthreads_or(lo_off != 0 || acc != kAll);
+        if (clean)
+            return T;
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const uint32_t c = uint32_t(__popc((acc >> (4 * j)) & 15u));
+            const uint32_t inc = wave_incl_scan(c, lane);
+            if (lane == 63)
+                s_off[j * NW + wave] = inc;
+        }
+        __syncthreads();
+        if (wave == 0)
+            wave0_scan<E>(s_off, lane);
+        __syncthreads();
+        return s_off[E];
+    }
+
+    // Store the kept outputs of window wb at segment offset excl.
+    __device__ __forceinline__ void store(const LaunchArgs &args, const Segment &seg,
+                                          uint64_t wb, uint64_t excl, uint64_t *next_counter,
+                                          const uint32_t *s_off)
+    {
+        const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+        const uint64_t n = seg.n;
+        if (clean) {
+            // triple q of the window is output excl + q
+            double *o = seg.out + excl;
+            const bool aligned = args.store_mode != 1 &&
+                                 (reinterpret_cast<uintptr_t>(o) & 15u) == 0;
+            const bool past = excl + T < n;    // the window does not hold output n - 1
+            const uint64_t left = n - excl;
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const uint32_t q = 4u * (uint32_t(j) * B + tid);
+                if (aligned && (past || q + 3 < left)) {
+                    store_two(o + q, v[4 * j], v[4 * j + 1], args.store_mode);
+                    store_two(o + q + 2, v[4 * j + 2], v[4 * j + 3], args.store_mode);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (past || q + i < left)
+                            store_one(o + q + i, v[4 * j + i], args.store_mode);
+                }
+                if (!past && q < left && left <= q + 4)
+                    *next_counter = wb + left;
+            }
+            return;
+        }
+        const uint64_t lt = lanemask_lt(lane);
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const uint32_t bits = (acc >> (4 * j)) & 15u;
+            // exclusive rank of this thread's first kept triple in its (j, wave) group
+            const uint32_t c = uint32_t(__popc(bits));
+            const uint32_t before = wave_incl_scan(c, lane) - c;
+            uint64_t pos = excl + s_off[j * NW + wave] + before;
+            const uint32_t q = 4u * (uint32_t(j) * B + tid);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if ((bits >> i) & 1u) {
+                    if (pos < n)
+                        store_one(seg.out + pos, v[4 * j + i], args.store_mode);
+                    if (pos == n - 1)
+                        *next_counter = wb + q + uint32_t(i) + 1;
+                    ++pos;
+                }
+            }
+        }
+        (void)lt;
+    }
+};
+
+template <int NW, int G, uint32_t FAM>
+struct TripleScratch {
+    using Tile = TripleTile<NW, G, FAM>;
+    uint32_t off[Tile::kOffWords];
+    uint64_t excl;
+    uint32_t next;
+    LaunchState state;
+
+    __device__ __forceinline__ uint32_t generate(Tile &tile, const LaunchArgs &a, const Segment &s,
+                                                 uint64_t win, uint32_t lo)
+    {
+        return tile.generate(a, s, win * Tile::T, lo, off);
+    }
+    __device__ __forceinline__ void store(Tile &tile, const LaunchArgs &a, const Segment &s,
+                                          uint64_t win, uint64_t excl, uint32_t, uint64_t *nc)
+    {
+        tile.store(a, s, win * Tile::T, excl, nc, off);
+    }
+};
+
+template <int NW, int G, uint32_t FAM>
+__global__ __launch_bounds__(64 * NW) void fill_triple_kernel(LaunchArgs args)
+{
+    __shared__ TripleScratch<NW, G, FAM> sh;
+    lookback_loop<TripleTile<NW, G, FAM>>(args, sh);
+}
+
+template <int NW, int G, uint32_t FAM>
+__global__ __launch_bounds__(64 * NW) void seq_triple_kernel(LaunchArgs args)
+{
+    __shared__ TripleScratch<NW, G, FAM> sh;
+    sequential_loop<TripleTile<NW, G, FAM>>(args, sh);
+}
 
 template <int NW, int PPL, uint32_t FAM>
 __global__ __launch_bounds__(64 * NW) void fill_philox_kernel(LaunchArgs args)

@@ -25,6 +25,7 @@ const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool r
 const void *spec_wave_kernel_for(uint32_t fam, bool repair);
 const void *single_kernel_for(uint32_t fam);
 const void *spec_words_kernel_for(uint32_t fam, bool repair);
+const void *triple_kernel_for(uint32_t fam, bool seq);
 hipError_t launch_toggle_flip(uint32_t *flip, hipStream_t stream);
 const void *toggle_flip_kernel_ptr();
 hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads,
@@ -81,6 +82,8 @@ struct Config {
     uint32_t consume; // prngd_consume_t
     uint64_t D4;      // Eq. (4) denominator in integer units: (a - a0) 2^w - (b - b0)
     double S4;        // RN(1 / D4)
+    uint32_t arity;   // words per output: 2, or 3 (the two-word method applied twice)
+    double S3;        // three words: RN((1 - 2^-3w) / D3)
 };
 
 // The map constants a launch passes to the kernels.
@@ -133,8 +136,51 @@ double folded_recip(uint64_t D)
     return std::ldexp(static_cast<double>(keep), drop - sh);
 }
 
+// RN((1 - 2^-3w) / D3) for 0 < D3 < 2^3w <= 2^96: (2^3w - 1) / D3 by long
+// division in 31-bit digits (each step divides a remainder below 2^127),
+// until 64 significant quotient bits are known; then rounded half-to-even to
+// 53 bits with the last remainder as sticky bit.
+double folded_constant3(uint32_t w, unsigned __int128 D3)
+{
+    const unsigned __int128 num = (static_cast<unsigned __int128>(1) << (3 * w)) - 1;
+    unsigned __int128 q = num / D3;   // integer part: 1 .. 2^3w
+    unsigned __int128 r = num % D3;
+    int frac = 0;
+    auto bits_of = [](unsigned __int128 x) {
+        int b = 0;
+        while (x) {
+            ++b;
+            x >>= 1;
+        }
+        return b;
+    };
+    while (bits_of(q) < 64) {
+        const unsigned __int128 r2 = r << 31;
+        q = (q << 31) | (r2 / D3);
+        r = r2 % D3;
+        frac += 31;
+    }
+    const int drop = bits_of(q) - 53;
+    uint64_t keep = static_cast<uint64_t>(q >> drop);
+    const unsigned __int128 dropped = q & ((static_cast<unsigned __int128>(1) << drop) - 1);
+    const unsigned __int128 half = static_cast<unsigned __int128>(1) << (drop - 1);
+    if (dropped > half || (dropped == half && (r != 0 || (keep & 1u))))
+        ++keep;
+    return std::ldexp(static_cast<double>(keep), drop - frac - int(3 * w));
+}
+
+// D3 = (a - a0 - 2) 2^2w + (a - a0 - 2) 2^w + (a - a0): the Eq. (5)
+// denominator of three words per output, in integer units.
+unsigned __int128 triple_denominator(const Config &c)
+{
+    const unsigned __int128 span = c.a - c.a0;
+    return ((span - 2) << (2 * c.w)) + ((span - 2) << c.w) + span;
+}
+
 MapConsts map_consts(const Config &c)
 {
+    if (c.arity == 3)
+        return {c.S3, 0.0, 1.0, 0.0};
     if (c.map == PRNGD_MAP_EQ4)
         return {c.S4, double((uint64_t(1) << c.w) - (c.b - c.b0)), 1.0, 0.0};
     if (c.map == PRNGD_MAP_ONE_MINUS)
@@ -195,6 +241,8 @@ prngd_status_t make_config(prngd_generator_t gen, double k, uint64_t min, uint64
     c->map = PRNGD_MAP_EQ5;
     c->consume = PRNGD_CONSUME_PAIR;
     c->fam = kernel_family(gen, c->w);
+    c->arity = 2;
+    c->S3 = 0.0;
     return PRNGD_OK;
 }
 
@@ -722,8 +770,10 @@ uint64_t planned_pairs(const Config &c, uint64_t n, uint32_t slack_mode)
 {
     if (slack_mode == 1)
         return n;
-    // expected rejections before n acceptances (x1 uniform on [a0, a])
-    const double rho = 2.0 / double(c.a - c.a0 + 1);
+    // expected rejections before n acceptances (x1 uniform on [a0, a]; with
+    // three words per output x1 and x2 are tested)
+    const double r1 = 2.0 / double(c.a - c.a0 + 1);
+    const double rho = c.arity == 3 ? 1.0 - (1.0 - r1) * (1.0 - r1) : r1;
     const double mean = double(n) * rho / (1.0 - rho);
     const double extra = std::floor(mean + 4.0 * std::sqrt(mean) + 0.5);
     return n + static_cast<uint64_t>(extra);
@@ -774,6 +824,18 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     if (!lp->kernel || !lp->seq_kernel)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u threads x %u pairs per lane",
                     lp->threads, lp->tune.pairs_per_lane);
+    if (cfg.arity == 3) {
+        // three words per output: the ordered kernels in their one shape
+        // (256 threads, 16 triples per thread); no speculative forms
+        lp->threads = 256;
+        lp->tune.block_threads = 256;
+        lp->tune.pairs_per_lane = 16;
+        lp->kernel = triple_kernel_for(cfg.fam, false);
+        lp->seq_kernel = triple_kernel_for(cfg.fam, true);
+        if (!lp->kernel || !lp->seq_kernel)
+            return fail(PRNGD_ERR_UNSUPPORTED, "three words per output: no kernel for this "
+                                               "generator");
+    }
     if (cfg.consume == PRNGD_CONSUME_SINGLE) {
         // one workgroup of 256 threads per segment, windows in order
         const void *k = single_kernel_for(kfam);
@@ -785,20 +847,22 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
         lp->kernel = k;
     }
     lp->T = uint64_t(lp->threads) * lp->tune.pairs_per_lane;
-    for (int hold = 0; hold < 2; ++hold) {
+    for (int hold = 0; hold < 2 && cfg.arity == 2; ++hold) {
         lp->spec_kernels[hold][0] = spec_kernel_for(kfam, lp->threads,
                                                     lp->tune.pairs_per_lane, false, false, hold);
         lp->spec_kernels[hold][1] = spec_kernel_for(kfam, lp->threads,
                                                     lp->tune.pairs_per_lane, false, true, hold);
     }
-    lp->repair_kernel = spec_kernel_for(kfam, lp->threads, lp->tune.pairs_per_lane, true,
-                                        false, false);
+    const bool two = cfg.arity == 2;
+    lp->repair_kernel = two ? spec_kernel_for(kfam, lp->threads, lp->tune.pairs_per_lane, true,
+                                              false, false)
+                            : nullptr;
     lp->spec_kernel = nullptr;
     lp->spec_single_kernel = nullptr;
-    lp->wave_kernel = spec_wave_kernel_for(kfam, false);
-    lp->wave_repair_kernel = spec_wave_kernel_for(kfam, true);
-    lp->words_kernel = spec_words_kernel_for(kfam, false);
-    lp->words_repair_kernel = spec_words_kernel_for(kfam, true);
+    lp->wave_kernel = two ? spec_wave_kernel_for(kfam, false) : nullptr;
+    lp->wave_repair_kernel = two ? spec_wave_kernel_for(kfam, true) : nullptr;
+    lp->words_kernel = two ? spec_words_kernel_for(kfam, false) : nullptr;
+    lp->words_repair_kernel = two ? spec_words_kernel_for(kfam, true) : nullptr;
     lp->wave = false;
     lp->zero_word = d->zero_word;
     lp->spec = false;                  // decided per launch by choose_path
@@ -1021,7 +1085,7 @@ prngd_status_t make_segment(prngd_handle_t h, uint64_t n, double *out, uint64_t 
 bool same_config(const Config &x, const Config &y)
 {
     return x.fam == y.fam && x.w == y.w && x.a0 == y.a0 && x.a == y.a && x.b0 == y.b0 &&
-           x.b == y.b && x.map == y.map && x.consume == y.consume;
+           x.b == y.b && x.map == y.map && x.consume == y.consume && x.arity == y.arity;
 }
 
 prngd_status_t current_device(int *dev)
@@ -1167,6 +1231,8 @@ prngd_status_t prngd_set_map(prngd_handle_t h, prngd_map_t map)
     std::lock_guard<std::recursive_mutex> lock(g_mutex);
     if (h->plan)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle is bound to a live plan");
+    if (map != PRNGD_MAP_EQ5 && h->cfg.arity == 3)
+        return fail(PRNGD_ERR_UNSUPPORTED, "three words per output take Eq. (5)");
     h->cfg.map = uint32_t(map);
     return PRNGD_OK;
 }
@@ -1180,11 +1246,43 @@ prngd_status_t prngd_set_consume(prngd_handle_t h, prngd_consume_t consume)
     std::lock_guard<std::recursive_mutex> lock(g_mutex);
     if (h->plan)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle is bound to a live plan");
+    if (consume != PRNGD_CONSUME_PAIR && h->cfg.arity == 3)
+        return fail(PRNGD_ERR_UNSUPPORTED, "three words per output take pair consumption");
     if (consume == PRNGD_CONSUME_SINGLE && !single_kernel_for(h->cfg.fam))
         return fail(PRNGD_ERR_UNSUPPORTED,
                     "single-word consumption needs a single-generator stream (Philox, MRG32k3a "
                     "or the test generator)");
     h->cfg.consume = uint32_t(consume);
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_set_arity(prngd_handle_t h, uint32_t words)
+{
+    if (!h)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "NULL handle");
+    if (words != 2 && words != 3)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "words per output must be 2 or 3, not %u", words);
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    if (h->plan)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle is bound to a live plan");
+    if (words == 3) {
+        if (!triple_kernel_for(h->cfg.fam, false))
+            return fail(PRNGD_ERR_UNSUPPORTED, "three words per output: Philox4x32-10 and the "
+                                               "test generator only");
+        if (h->cfg.map != PRNGD_MAP_EQ5 || h->cfg.consume != PRNGD_CONSUME_PAIR)
+            return fail(PRNGD_ERR_UNSUPPORTED, "three words per output take Eq. (5) and pair "
+                                               "consumption");
+        h->cfg.S3 = folded_constant3(h->cfg.w, triple_denominator(h->cfg));
+    }
+    h->cfg.arity = words;
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_get_arity(prngd_handle_t h, uint32_t *words)
+{
+    if (!h || !words)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "NULL argument");
+    *words = h->cfg.arity;
     return PRNGD_OK;
 }
 

@@ -107,6 +107,8 @@ _SIGNATURES = [
     ("prngd_set_consume", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("prngd_get_consume", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
     ("prngd_get_map", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
+    ("prngd_set_arity", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    ("prngd_get_arity", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
     ("prngd_probe_write", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     ("prngd_probe_copy", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
@@ -211,7 +213,7 @@ class Generator:
     generator and a seed, positioned at (stream_id, pair counter)."""
 
     def __init__(self, seed, generator="philox", w=32, k=None, min=None, max=None,
-                 _handle=None, map=None, consume=None):
+                 _handle=None, map=None, consume=None, words=None):
         g = _gen(generator)
         if k is None:
             k = 2.0 ** -w
@@ -232,6 +234,18 @@ class Generator:
             self.set_map(map)
         if consume is not None:
             self.set_consume(consume)
+        if words is not None:
+            self.set_arity(words)
+
+    def set_arity(self, words):
+        """Words combined per output: 2 (default) or 3 (the two-word method
+        applied twice; the position then counts triples)."""
+        _check(lib().prngd_set_arity(self.handle, int(words)))
+
+    def get_arity(self):
+        a = ctypes.c_uint32()
+        _check(lib().prngd_get_arity(self.handle, ctypes.byref(a)))
+        return a.value
 
     def set_consume(self, consume):
         """"pair" (default) or "single" (Algorithm 1: a rejected r1 consumes

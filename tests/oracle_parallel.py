@@ -23,12 +23,12 @@ def host_threads(cap=16):
     return max(1, min(n, cap))
 
 
-def fill_streams(gen, w, specs, threads=None, map=O.MAP_EQ5):
+def fill_streams(gen, w, specs, threads=None, map=O.MAP_EQ5, arity=2):
     """specs: [(seed, stream, counter, n), ...].  Returns (outputs, counters):
     a list of float64 arrays and the counter after each, in order."""
     def one(spec):
         seed, stream, counter, n = spec
-        s = O.PRNGD(gen, w, seed=seed, stream=stream, counter=counter, map=map)
+        s = O.PRNGD(gen, w, seed=seed, stream=stream, counter=counter, map=map, arity=arity)
         return s.fill(n), s.counter
 
     with ThreadPoolExecutor(max_workers=threads or host_threads()) as pool:
@@ -36,9 +36,9 @@ def fill_streams(gen, w, specs, threads=None, map=O.MAP_EQ5):
     return [r[0] for r in res], [r[1] for r in res]
 
 
-def fill_long(gen, w, seed, stream, counter, n, threads=None, chunk_pairs=1 << 24):
-    """The first n outputs of one stream from pair `counter`, and the pair
-    counter after them, walked as consecutive pair ranges on several
+def fill_long(gen, w, seed, stream, counter, n, threads=None, chunk_pairs=1 << 24, arity=2):
+    """The first n outputs of one stream from pair (or triple) `counter`, and
+    the counter after them, walked as consecutive ranges on several
     threads."""
     threads = threads or host_threads()
     out = np.empty(n, dtype=np.float64)
@@ -46,7 +46,7 @@ def fill_long(gen, w, seed, stream, counter, n, threads=None, chunk_pairs=1 << 2
 
     def walk(start):
         end = min(start + chunk_pairs, top)
-        s = O.PRNGD(gen, w, seed=seed, stream=stream, counter=start)
+        s = O.PRNGD(gen, w, seed=seed, stream=stream, counter=start, arity=arity)
         return start, s.fill_pairs(end, end - start)
 
     made = 0
@@ -69,7 +69,8 @@ def fill_long(gen, w, seed, stream, counter, n, threads=None, chunk_pairs=1 << 2
                 made += take
                 if made == n:
                     # the counter: walk this range again up to the n-th output
-                    s = O.PRNGD(gen, w, seed=seed, stream=stream, counter=first)
+                    s = O.PRNGD(gen, w, seed=seed, stream=stream, counter=first,
+                                arity=arity)
                     s.fill(take)
                     return out, s.counter
     raise AssertionError("unreachable")

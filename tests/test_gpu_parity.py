@@ -631,3 +631,52 @@ def test_word_window_origin_on_the_4k_grid(gen, w, slot):
         assert_bits_equal(out.cpu().numpy(), s.fill(n), f"slot {slot} counter {counter}")
         assert g.get_position()[1] == s.counter
         g.close()
+
+
+def _planned_pairs(n, w):
+    """The pairs the library plans for n outputs of a full-range stream:
+    n plus the expected rejections plus four standard deviations."""
+    rho = 2.0 / 2**w
+    mean = n * rho / (1.0 - rho)
+    return n + int(np.floor(mean + 4.0 * np.sqrt(mean) + 0.5))
+
+
+def test_lookback_tile_past_the_last_output():
+    # A fill planned for more pairs than its rejections end up needing has
+    # tiles that lie wholly past output n - 1.  Such a tile of the ordered
+    # look-back kernel must store nothing, clean window or not.  Pick n so
+    # that the last planned tile starts past the n-th accepted pair and its
+    # window has no rejection, then check the outputs and a guard of two
+    # windows after them.
+    w, seed, T = 14, 77, 4096
+    top = 1 << 24
+    ref = O.PRNGD(O.GEN_PHILOX, w, seed=seed)
+    _, idx = ref.fill(top + 4 * T, with_index=True)
+    idx = idx.astype(np.int64)
+    chosen = None
+    for n in range(top - 3000, top - 1000):
+        tiles = -(-_planned_pairs(n, w) // T)
+        start = (tiles - 1) * T
+        before = int(np.searchsorted(idx, start))          # outputs before the tile
+        inside = int(np.searchsorted(idx, start + T)) - before
+        if before >= n and inside == T:
+            chosen = n
+            break
+    assert chosen is not None, "no size puts a clean tile past the last output"
+    n = chosen
+    prngd.set_tuning("philox", w, path=1)
+    try:
+        g = prngd.Generator(seed, "philox", w=w)
+        base = torch.empty(n + 2 * T, dtype=torch.float64, device=DEV)
+        base.view(torch.int64).fill_(int(NAN_BITS))
+        note(f"look-back tile past the last output: w={w} n={n}")
+        g.fill(base[:n])
+        torch.cuda.synchronize()
+        host = base.cpu().numpy()
+        assert np.all(host[n:].view(np.uint64) == NAN_BITS), "written past output n - 1"
+        expect = O.PRNGD(O.GEN_PHILOX, w, seed=seed)
+        assert_bits_equal(host[:n], expect.fill(n), "outputs")
+        assert g.get_position() == (0, expect.counter)
+        g.close()
+    finally:
+        prngd.reset_tuning("philox", w)

@@ -81,6 +81,50 @@ def test_served_requests_equal_the_same_requests_alone(mode):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("mode", ["batched", "plain"])
+def test_served_large_requests_sampled(mode):
+    # the serving trace's own shape: 1024 clients, sizes log-uniform in
+    # [1e2, 1e8]; every request's first and last 512 outputs and all outputs
+    # of every 40th request and of the largest ones are checked against the
+    # oracle walking each client's stream through its requests in order
+    pytest.importorskip("torch")
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle_parallel as OP
+    from paper_1401_8230_amd import serving, workloads
+    clients = 1024
+    trace = workloads.poisson_trace(count=400, rate=4e3, lo=1e2, hi=1e8, clients=clients,
+                                    rng_seed=777)
+    note(f"serving {mode}, large: {len(trace)} requests, {sum(a.n for a in trace)} outputs")
+    res = serving.run_trace(trace, mode=mode, clients=clients, budget_bytes=12e9,
+                            keep_outputs="sample")
+    served = res["served"]
+    assert len(served) == len(trace)
+    assert max(r.n for r in served) > 5 * 10**7
+    by_client = {}
+    for r in sorted(served, key=lambda r: r.rid):
+        by_client.setdefault(r.client, []).append(r)
+
+    def check(client):
+        ref = O.PRNGD(O.GEN_PHILOX, 32, seed=42, stream=client)
+        for r in by_client[client]:
+            expect = ref.fill(r.n)
+            kept = r.out
+            for part, want in (("head", expect[:512]), ("tail", expect[-512:]),
+                               ("full", expect if kept["full"] is not None else None)):
+                if want is None:
+                    continue
+                got = np.ascontiguousarray(kept[part])
+                if not np.array_equal(got.view(np.uint64), want.view(np.uint64)):
+                    return f"request {r.rid} (client {client}, n={r.n}): {part} differs"
+        return None
+
+    with ThreadPoolExecutor(max_workers=OP.host_threads()) as pool:
+        errors = [e for e in pool.map(check, list(by_client)) if e]
+    assert not errors, errors[:3]
+
+
+@pytest.mark.gpu
 def test_autotuned_batch_keeps_bytes(tmp_path):
     torch = pytest.importorskip("torch")
     from paper_1401_8230_amd import autotune, prngd, workloads
