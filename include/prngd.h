@@ -294,6 +294,28 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out,
                           void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * output and the same new position as prngd_fill, from a variant that
+ * allocates nothing.  Its launch state (the look-back kernel's ticket
+ * counter and one 8-byte status word per tile) lives in a fixed 4 MiB
+ * device array that each GPU holds until the process ends, set up when the
+ * library first meets the device (prngd_create); so n is limited to
+ * 524224 tiles of the handle's launch shape (threads x pairs per lane
+ * pairs, 4096 by default: about 2.1e9 outputs).  Every call on one GPU
+ * shares that array and finds it as the previous call left it: calls on
+ * one GPU must not overlap -- issue them on one stream, or order them
+ * yourself; calls that overlap race.  Pair consumption only.  MRG32k3a
+ * and mixed handles use the jump tables built when they were created (for
+ * the launch shape set then).  Errors: as prngd_fill, plus
+ * PRNGD_ERR_INVALID_ARGUMENT when n needs more tiles than the array holds,
+ * PRNGD_ERR_UNSUPPORTED for one-word consumption or a launch shape whose
+ * MRG32k3a tables do not exist yet.
+ */
+prngd_status_t prngd_fill_noalloc(prngd_handle_t h, uint64_t n, double *out,
+                                  void *stream);
+
+/*
  * Fill several handles in one persistent launch: request i receives
  * exactly what prngd_fill(reqs[i].h, reqs[i].n, reqs[i].out) would give,
  * bit for bit, and each handle advances as it would.  `reqs` is read

@@ -15,7 +15,8 @@ OBJ_DIR = os.path.join(HERE, "_build")
 # kernels that take the map's constants from the launch (FAM_ANY_MAP).
 FAMILY_SOURCES = ["prngd_k_spec.hip", "prngd_k_philox.hip", "prngd_k_single.hip",
                   "prngd_k_mrg.hip"]
-SOURCES = ["prngd_k_triple.hip", "prngd_k_misc.hip", "prngd_probes.hip", "prngd_runtime.cpp"]
+SOURCES = ["prngd_k_triple.hip", "prngd_k_misc.hip", "prngd_noalloc.hip", "prngd_probes.hip",
+           "prngd_runtime.cpp"]
 UNITS = ([(src, "eq5", ["-DPRNGD_MAPF=0u"]) for src in FAMILY_SOURCES]
          + [(src, "anymap", ["-DPRNGD_MAPF=FAM_ANY_MAP"]) for src in FAMILY_SOURCES]
          + [(src, "", []) for src in SOURCES])

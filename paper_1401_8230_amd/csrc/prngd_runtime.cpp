@@ -34,6 +34,10 @@ hipError_t launch_expand_tiles(const Segment *segs, uint32_t nseg, uint32_t *til
                                hipStream_t stream);
 hipError_t launch_set_counter(uint64_t *slot, uint64_t value, hipStream_t stream);
 hipError_t launch_zero_words(uint64_t *p, size_t n, hipStream_t stream);
+hipError_t noalloc_setup(int dev);
+Control *noalloc_control(int dev);
+uint64_t *noalloc_status(int dev);
+size_t noalloc_status_words();
 }  // namespace prngd
 
 using namespace prngd;
@@ -413,6 +417,10 @@ struct DeviceInfo {
     std::vector<uint64_t *> free_slots;    // returned by destroyed handles
     std::map<std::pair<uint32_t, uint32_t>, std::pair<uint32_t *, uint32_t *>> mrg_tables;
     std::map<const void *, int> occupancy;
+    // prngd_fill_noalloc: launches made on the fixed scratch, and the event
+    // recorded after each (both set up here, never by the entry point)
+    uint64_t noalloc_launches = 0;
+    hipEvent_t noalloc_event = nullptr;
 };
 
 std::map<int, DeviceInfo> g_devices;
@@ -436,6 +444,16 @@ prngd_status_t device_info(int dev, DeviceInfo **out)
     HIP_TRY(hipMalloc(&dp, 256));
     HIP_TRY(hipMemset(dp, 0, 256));
     d.zero_word = static_cast<uint32_t *>(dp);
+    // the fixed scratch of prngd_fill_noalloc, with this device current
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != dev)
+        HIP_TRY(hipSetDevice(dev));
+    const hipError_t se = noalloc_setup(dev);
+    if (se == hipSuccess && cur != dev)
+        HIP_TRY(hipSetDevice(cur));
+    HIP_TRY(se);
+    HIP_TRY(hipEventCreateWithFlags(&d.noalloc_event, hipEventDisableTiming));
     *out = &g_devices.emplace(dev, std::move(d)).first->second;
     return PRNGD_OK;
 }
@@ -479,11 +497,14 @@ prngd_status_t alloc_slot(DeviceInfo *d, uint64_t **slot)
 }
 
 prngd_status_t mrg_tables_for(DeviceInfo *d, uint32_t r, uint32_t ppl, const uint32_t **thread,
-                              const uint32_t **window)
+                              const uint32_t **window, bool may_alloc = true)
 {
     auto key = std::make_pair(r, ppl);
     auto it = d->mrg_tables.find(key);
     if (it == d->mrg_tables.end()) {
+        if (!may_alloc)
+            return fail(PRNGD_ERR_UNSUPPORTED, "no MRG32k3a jump tables for %u pairs per lane "
+                                               "yet: they are built by prngd_fill", ppl);
         std::vector<uint32_t> th, wi;
         build_mrg_tables(r, ppl, th, wi);
         void *pt = nullptr, *pw = nullptr;
@@ -813,7 +834,7 @@ struct LaunchPlan {
 };
 
 prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, LaunchPlan *lp,
-                           uint32_t default_ppl = 16)
+                           uint32_t default_ppl = 16, bool may_alloc = true)
 {
     lp->tune = tuning_for(cfg.fam, cfg.w, default_ppl);
     lp->threads = lp->tune.block_threads;
@@ -889,7 +910,8 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
         const uint32_t r = cfg.fam == FAM_MRG ? 2u : 1u;
         // one-word consumption steps 16 outputs per thread (8 pairs of 2)
         const uint32_t ppl = cfg.consume == PRNGD_CONSUME_SINGLE ? 8u : lp->tune.pairs_per_lane;
-        prngd_status_t st = mrg_tables_for(d, r, ppl, &args->mrg_thread, &args->mrg_window);
+        prngd_status_t st = mrg_tables_for(d, r, ppl, &args->mrg_thread, &args->mrg_window,
+                                           may_alloc);
         if (st != PRNGD_OK)
             return st;
     }
@@ -1086,6 +1108,17 @@ bool same_config(const Config &x, const Config &y)
 {
     return x.fam == y.fam && x.w == y.w && x.a0 == y.a0 && x.a == y.a && x.b0 == y.b0 &&
            x.b == y.b && x.map == y.map && x.consume == y.consume && x.arity == y.arity;
+}
+
+// The MRG32k3a jump tables the look-back kernel of a handle with this
+// configuration takes in its current launch shape, built when the handle
+// is created (so that prngd_fill_noalloc finds them).
+prngd_status_t default_mrg_tables(DeviceInfo *d, const Config &cfg)
+{
+    const uint32_t r = cfg.fam == FAM_MRG ? 2u : 1u;
+    const uint32_t ppl = tuning_for(cfg.fam, cfg.w).pairs_per_lane;
+    const uint32_t *t = nullptr, *w = nullptr;
+    return mrg_tables_for(d, r, ppl, &t, &w);
 }
 
 prngd_status_t current_device(int *dev)
@@ -1324,8 +1357,11 @@ prngd_status_t prngd_create(uint64_t seed, prngd_generator_t generator, double k
     h->gen = generator;
     h->cfg = cfg;
     h->seed = seed;
-    if (cfg.fam == FAM_MRG || cfg.fam == FAM_MIXED)
+    if (cfg.fam == FAM_MRG || cfg.fam == FAM_MIXED) {
         mrg_stream_base(seed, 0, h->mrg);
+        if ((st = default_mrg_tables(d, cfg)) != PRNGD_OK)
+            return st;
+    }
     if ((st = alloc_slot(d, &h->slot)) != PRNGD_OK)
         return st;
     *out_handle = h.release();
@@ -1350,6 +1386,9 @@ prngd_status_t prngd_create_many(uint64_t seed, prngd_generator_t generator, dou
         return st;
     DeviceInfo *d = nullptr;
     if ((st = device_info(dev, &d)) != PRNGD_OK)
+        return st;
+    if ((cfg.fam == FAM_MRG || cfg.fam == FAM_MIXED) &&
+        (st = default_mrg_tables(d, cfg)) != PRNGD_OK)
         return st;
     for (uint32_t i = 0; i < count; ++i) {
         std::unique_ptr<prngd_handle_s> h(new prngd_handle_s);
@@ -1513,6 +1552,67 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *strea
     HIP_TRY(hipEventRecord(ws->last, s));
     h->parity ^= 1u;
     h->last_event = ws->last;
+    h->last_stream = s;
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_fill_noalloc(prngd_handle_t h, uint64_t n, double *out, void *stream)
+{
+    if (!h)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "NULL handle");
+    if (h->plan)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle is bound to a live plan");
+    if (n == 0)
+        return PRNGD_OK;
+    std::lock_guard<std::recursive_mutex> lock(g_mutex);
+    auto it = g_devices.find(h->device);
+    if (it == g_devices.end())
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle's device is not set up");
+    DeviceInfo *d = &it->second;
+    prngd_status_t st = check_device_errors(d);
+    if (st != PRNGD_OK)
+        return st;
+    if (h->cfg.consume != PRNGD_CONSUME_PAIR)
+        return fail(PRNGD_ERR_UNSUPPORTED, "prngd_fill_noalloc takes pair consumption only");
+    Control *ctl = noalloc_control(h->device);
+    uint64_t *status = noalloc_status(h->device);
+    if (!ctl || !status)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle's device has no fixed scratch");
+    LaunchArgs args{};
+    LaunchPlan lp{};
+    if ((st = plan_launch(d, h->cfg, &args, &lp, 16, false)) != PRNGD_OK)
+        return st;
+    uint64_t ntiles = 0;
+    if ((st = make_segment(h, n, out, lp.T, lp.tune.slack_mode, 0, &args.seg0, &ntiles)) !=
+        PRNGD_OK)
+        return st;
+    const size_t cap = noalloc_status_words();
+    if (ntiles > cap)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT,
+                    "n = %llu needs %llu tiles of %llu pairs; the fixed scratch holds %llu",
+                    (unsigned long long)n, (unsigned long long)ntiles,
+                    (unsigned long long)lp.T, (unsigned long long)cap);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    args.nseg = 1;
+    args.total_tiles = uint32_t(ntiles);
+    args.ctl = ctl;
+    args.status = status;
+    // status words carry a 24-bit epoch: clear them before it wraps
+    if (d->noalloc_launches > 0 && d->noalloc_launches % kEpochMask == 0)
+        HIP_TRY(launch_zero_words(status, cap, s));
+    if ((st = order_after(h, s)) != PRNGD_OK)
+        return st;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, lp.kernel, int(lp.threads), 0) !=
+            hipSuccess || occ <= 0)
+        occ = 1;
+    const uint64_t per_cu = lp.tune.blocks_per_cu ? lp.tune.blocks_per_cu : uint64_t(occ);
+    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(per_cu * d->cus, ntiles));
+    HIP_TRY(launch_fill(lp.kernel, uint32_t(grid), lp.threads, args, s));
+    d->noalloc_launches++;
+    HIP_TRY(hipEventRecord(d->noalloc_event, s));
+    h->parity ^= 1u;
+    h->last_event = d->noalloc_event;
     h->last_stream = s;
     return PRNGD_OK;
 }

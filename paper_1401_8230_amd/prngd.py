@@ -89,6 +89,8 @@ _SIGNATURES = [
       ctypes.c_void_p]),
     ("prngd_fill", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+    ("prngd_fill_noalloc", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
     ("prngd_fill_batch", ctypes.c_int,
      [ctypes.POINTER(Request), ctypes.c_uint32, ctypes.c_void_p]),
     ("prngd_plan_create", ctypes.c_int,
@@ -292,6 +294,11 @@ class Generator:
     def fill(self, out, n=None, stream=None):
         ptr, n = _out_ptr(out, n)
         _check(lib().prngd_fill(self.handle, n, ptr, _stream_ptr(stream)))
+        return out
+
+    def fill_noalloc(self, out, n=None, stream=None):
+        ptr, n = _out_ptr(out, n)
+        _check(lib().prngd_fill_noalloc(self.handle, n, ptr, _stream_ptr(stream)))
         return out
 
     def set_position(self, stream_id, pair_counter, stream=None):

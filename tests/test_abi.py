@@ -109,6 +109,7 @@ def test_null_arguments():
     L = prngd.lib()
     assert L.prngd_create(1, 0, 2.0**-8, 0, 255, None) == prngd.ERR_INVALID_ARGUMENT
     assert L.prngd_fill(None, 10, None, None) == prngd.ERR_INVALID_ARGUMENT
+    assert L.prngd_fill_noalloc(None, 10, None, None) == prngd.ERR_INVALID_ARGUMENT
     assert L.prngd_fill_batch(None, 0, None) == prngd.ERR_INVALID_ARGUMENT
     assert L.prngd_plan_create(None, 0, None) == prngd.ERR_INVALID_ARGUMENT
     assert L.prngd_plan_launch(None, None) == prngd.ERR_INVALID_ARGUMENT
