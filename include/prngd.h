@@ -148,7 +148,15 @@ typedef struct {
                               /* wrong); 3 speculative, holding the window  */
                               /* in registers until its offset is read;     */
                               /* 4 speculative in 128-pair chunks, one per  */
-                              /* wave, for single fills (batches take 2).   */
+                              /* wave, for single fills (batches take 2);   */
+                              /* 5 as 4, and batches in chunks of           */
+                              /* pairs_per_lane / 2 windows of 128 pairs    */
+                              /* (1, 2 or 4), one per wave: every chunk     */
+                              /* of every request stores                    */
+                              /* at the offset no earlier rejection gives,  */
+                              /* a repair pass redoes each request from its */
+                              /* first chunk with a rejection (Philox and   */
+                              /* the test generator; others take 2).        */
                               /* Automatic: ordered unless some request has */
                               /* at least 2^18 pairs; then 3 when the launch*/
                               /* expects at most 2 rejections, 4 (single    */

@@ -38,6 +38,9 @@ def candidates(generator, w):
                             "path": 1})
             out.append({"block_threads": 256, "pairs_per_lane": ppl, "path": 2})
         return out
+    for ppl in (2, 4, 8):
+        # the chunk form: one chunk of ppl / 2 windows of 128 pairs per wave
+        out.append({"pairs_per_lane": ppl, "path": 5})
     for threads, ppl in _philox_shapes():
         for store_mode in (0, 2):
             for path in (2, 3):

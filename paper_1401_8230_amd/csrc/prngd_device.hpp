@@ -196,6 +196,21 @@ __device__ __forceinline__ uint64_t lanemask_lt(uint32_t lane)
     return (uint64_t(1) << lane) - 1;
 }
 
+// Whether p holds in any thread of the workgroup, as a value the compiler
+// knows to be uniform: the block vote returns it through LDS, which would
+// make every branch and loop that depends on it divergent (exec-mask
+// bookkeeping on the scalar unit, loop state in vector registers).
+__device__ __forceinline__ bool block_any(bool p)
+{
+    return __builtin_amdgcn_readfirstlane(uint32_t(__syncthreads_or(p))) != 0u;
+}
+
+// A workgroup-uniform value read back from LDS, marked uniform.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
 {
 #pragma unroll
@@ -633,7 +648,7 @@ struct PhiloxTile {
                     acc &= ~(1u << (2 * j + 1));
             }
         }
-        clean = !__syncthreads_or(lo_off != 0 || acc != kAll);
+        clean = !block_any(lo_off != 0 || acc != kAll);
         if (clean)
             return T;
 #pragma unroll
@@ -647,7 +662,7 @@ struct PhiloxTile {
         if (wave == 0)
             wave0_scan<E>(s_off, lane);
         __syncthreads();
-        return s_off[E];
+        return uniform_u32(s_off[E]);
     }
 
     // Store the kept outputs of window `wb` at segment offset `excl`.
@@ -822,7 +837,7 @@ struct SpecTile {
             rej += uint32_t(p.ha >= hm && q >= lo_off) + uint32_t(p.hb >= hm && q + 1 >= lo_off);
         }
         uint32_t kept = T - lo_off;
-        if (__syncthreads_or(rej != 0)) {
+        if (block_any(rej != 0)) {
             const uint32_t r = wave_incl_scan(rej, lane);
             if (lane == 63)
                 s_off[wave] = r;
@@ -831,7 +846,7 @@ struct SpecTile {
 #pragma unroll
             for (int k = 0; k < NW; ++k)
                 total += s_off[k];
-            kept -= total;
+            kept -= uniform_u32(total);
             __syncthreads();
         }
         return kept;
@@ -887,7 +902,7 @@ struct SpecTile {
                     store_one(o + q + 1, zb, args.store_mode);
                 }
             }
-            dirty = __syncthreads_or(mx >= hm);
+            dirty = block_any(mx >= hm);
             if (!dirty)
                 return T;
 #pragma unroll 1
@@ -918,7 +933,7 @@ struct SpecTile {
                         *next_counter = wb + left;
                 }
             }
-            dirty = __syncthreads_or(!kSpec || lo_off != 0 || acc != kAll);
+            dirty = block_any(!kSpec || lo_off != 0 || acc != kAll);
             if (!dirty)
                 return T;
         }
@@ -958,7 +973,7 @@ struct SpecTile {
             if (okb && pos_b + 1 == left)
                 *next_counter = wb + q + 2;
         }
-        const uint32_t total = s_off[E];
+        const uint32_t total = uniform_u32(s_off[E]);
         __syncthreads();
         return total;
     }
@@ -1048,7 +1063,7 @@ struct MrgTile {
             }
         }
         acc = kAll;
-        if (!__syncthreads_or(mx >= hmax || q0 < lo_off)) {
+        if (!block_any(mx >= hmax || q0 < lo_off)) {
             thread_off = q0;
             return T;
         }
@@ -1080,7 +1095,7 @@ struct MrgTile {
         }
         thread_off = before + inc - c;
         __syncthreads();       // s_wave is reused by the next window
-        return total;
+        return uniform_u32(total);
     }
 
     __device__ __forceinline__ void store(const LaunchArgs &args, const Segment &seg,
@@ -1467,7 +1482,7 @@ struct TripleTile {
                     if (4u * (uint32_t(j) * B + tid) + uint32_t(i) < lo_off)
                         acc &= ~(1u << (4 * j + i));
         }
-        clean = !__syncthreads_or(lo_off != 0 || acc != kAll);
+        clean = !block_any(lo_off != 0 || acc != kAll);
         if (clean)
             return T;
 #pragma unroll
@@ -1481,7 +1496,7 @@ struct TripleTile {
         if (wave == 0)
             wave0_scan<E>(s_off, lane);
         __syncthreads();
-        return s_off[E];
+        return uniform_u32(s_off[E]);
     }
 
     // Store the kept outputs of window wb at segment offset excl.
@@ -2104,13 +2119,38 @@ __global__ __launch_bounds__(kMrgBlockThreads) void seq_mrg_kernel(LaunchArgs ar
 // LDS.  Each wave reads the rejection list once, at its start; a chunk
 // records its hint only when it is nonzero, tagged with the launch epoch.
 // ======================================================================
-constexpr uint32_t kChunk = 128;
+constexpr uint32_t kChunk = kChunkPairs;
 constexpr uint32_t kChunksPerWave = 2;
+
+// Lanes at or above `first` (0 .. 64) of a wave, as a 64-bit lane mask.
+__device__ __forceinline__ uint64_t lanes_from(uint32_t first)
+{
+    return first >= 64u ? 0ull : ~0ull << first;
+}
+
+// a < b for wave-uniform a, b below 2^63, decided on the scalar unit from
+// the sign of a - b.  (A 64-bit ordered compare would go to the vector
+// unit.)
+__device__ __forceinline__ bool uniform_lt(uint64_t a, uint64_t b)
+{
+    return int32_t(__builtin_amdgcn_readfirstlane(uint32_t((a - b) >> 32))) < 0;
+}
+
+// Whether a chunk at wave-uniform offset excl holds 128 outputs below
+// n - 1: all its outputs are stored and none of them is the last one
+// (whose chunk writes the next position).
+__device__ __forceinline__ bool chunk_fits(uint64_t excl, uint64_t n)
+{
+    return uniform_lt(excl + kChunk, n);
+}
 
 template <uint32_t FAM>
 struct WaveChunk {
     using HiLo = typename SpecTile<4, 4, FAM>::HiLo;
 
+    // Window `win` of 128 pairs: lane l holds pairs 2l and 2l + 1.  The
+    // window's first Philox block is a multiple of 64, so a lane's block
+    // index carries nothing into its high word.
     __device__ __forceinline__ static HiLo words(const LaunchArgs &args, const Segment &seg,
                                                  uint64_t win, uint32_t lane)
     {
@@ -2123,8 +2163,9 @@ struct WaveChunk {
             x1b = uint32_t(((q + 1) >> args.w) & mask);
             x2b = uint32_t((q + 1) & mask);
         } else {
-            const uint64_t blk = win * (kChunk / 2) + lane;
-            const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u, seg.stream_id,
+            const uint32_t blk_lo = uint32_t(win << 6) | lane;
+            const uint32_t blk_hi = uint32_t(win >> 26);
+            const Words4 r = philox4x32_10(blk_lo, blk_hi, 0u, seg.stream_id,
                                            uint32_t(seg.seed), uint32_t(seg.seed >> 32));
             if (fam_base(FAM) == FAM_PHILOX32) {
                 x1a = r.v0; x2a = r.v1; x1b = r.v2; x2b = r.v3;
@@ -2141,27 +2182,35 @@ struct WaveChunk {
 
     // Produce chunk window `win` (from window offset lo_off on) at segment
     // offset excl (outputs at or past n are dropped); returns the chunk's
-    // kept pairs.  Writes nothing but its own outputs.
+    // kept pairs.  Writes nothing but its own outputs.  `full`: the caller
+    // knows that lo_off is 0 and that excl + 128 < n, so that a chunk
+    // without rejections stores all its outputs with no further test (and
+    // holds no last output).
     __device__ __forceinline__ static uint32_t run(const LaunchArgs &args, const Segment &seg,
                                                    uint64_t win, uint32_t lo_off, uint64_t excl,
-                                                   uint64_t *next_counter, bool store)
+                                                   uint64_t *next_counter, bool store,
+                                                   bool full)
     {
         const uint32_t lane = threadIdx.x & 63u;
         const uint32_t hm = fam_base(FAM) == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
         const double tw = fam_base(FAM) == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
         const HiLo p = words(args, seg, win, lane);
-        const uint32_t q = 2u * lane;
-        const bool oka = p.ha < hm && q >= lo_off;
-        const bool okb = p.hb < hm && q + 1 >= lo_off;
-        const uint64_t ka = __ballot(oka), kb = __ballot(okb);
+        // the ballots straight from the compares; pairs below lo_off
+        // (2l < lo_off, 2l + 1 < lo_off) are masked out on the scalar unit
+        uint64_t ka = __builtin_amdgcn_ballot_w64(p.ha < hm);
+        uint64_t kb = __builtin_amdgcn_ballot_w64(p.hb < hm);
+        if (lo_off != 0) {
+            ka &= lanes_from((lo_off + 1u) >> 1);
+            kb &= lanes_from(lo_off >> 1);
+        }
         const uint32_t kept = uint32_t(__popcll(ka) + __popcll(kb));
         if (!store)
             return kept;
         const double za = map_hi_lo<FAM>(p.ha, p.la, tw, args);
         const double zb = map_hi_lo<FAM>(p.hb, p.lb, tw, args);
-        const uint64_t left = seg.n - excl;            // >= 1
         double *o = seg.out + excl;
-        if (kept == kChunk && left > kChunk) {
+        const uint32_t q = 2u * lane;
+        if (full && kept == kChunk) {
             if (args.store_mode != 1 && (reinterpret_cast<uintptr_t>(o) & 15u) == 0) {
                 store_two(o + q, za, zb, args.store_mode);
             } else if (args.store_mode != 1) {
@@ -2178,6 +2227,9 @@ struct WaveChunk {
             }
             return kept;
         }
+        const bool oka = (ka >> lane) & 1u;
+        const bool okb = (kb >> lane) & 1u;
+        const uint64_t left = seg.n - excl;            // >= 1
         const uint64_t lt = lanemask_lt(lane);
         const uint32_t pos_a = uint32_t(__popcll(ka & lt) + __popcll(kb & lt));
         const uint32_t pos_b = pos_a + (oka ? 1u : 0u);
@@ -2202,7 +2254,10 @@ __device__ __forceinline__ uint32_t chunk_hint(const LaunchArgs &args, uint32_t 
 template <uint32_t FAM, uint32_t CPW>
 __global__ __launch_bounds__(256) void spec_wave_kernel(LaunchArgs args)
 {
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    // the wave index is uniform in the wave: say so, so that everything
+    // derived from it (chunk, segment, offsets) lives in scalar registers
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t total = args.total_tiles;
     const TileStart ts = tile_start<true>(args, 0);
     const Segment &seg = ts.seg;
@@ -2239,7 +2294,8 @@ __global__ __launch_bounds__(256) void spec_wave_kernel(LaunchArgs args)
         const uint32_t lo_off = k == 0 ? lo0 : 0u;
         const uint64_t excl = (k == 0 ? 0 : uint64_t(k) * kChunk - lo0) - used;
         const uint32_t kept =
-            WaveChunk<FAM>::run(args, seg, win, lo_off, excl, next_counter, excl < seg.n);
+            WaveChunk<FAM>::run(args, seg, win, lo_off, excl, next_counter,
+                                uniform_lt(excl, seg.n), lo_off == 0 && chunk_fits(excl, seg.n));
         const uint32_t rej = (kChunk - lo_off) - kept;
         if (rej != 0 && lane == 0) {
             const uint32_t slot = __hip_atomic_fetch_add(&args.spec->count, 1u, __ATOMIC_RELAXED,
@@ -2253,9 +2309,228 @@ __global__ __launch_bounds__(256) void spec_wave_kernel(LaunchArgs args)
         }
         if (k == total - 1) {
             uint64_t running = excl + kept;
-            for (uint64_t w2 = win + 1; running < seg.n; ++w2)
-                running += WaveChunk<FAM>::run(args, seg, w2, 0u, running, next_counter, true);
+            for (uint64_t w2 = win + 1; uniform_lt(running, seg.n); ++w2)
+                running += WaveChunk<FAM>::run(args, seg, w2, 0u, running, next_counter, true,
+                                               chunk_fits(running, seg.n));
         }
+    }
+}
+
+// ======================================================================
+// Chunk-speculative fill of a batch (rare rejections): the one-shot grid of
+// the chunks of every segment of the batch, one chunk per wave, a chunk
+// NWIN consecutive 128-pair windows (one Philox block per lane in each),
+// the chunks of one segment consecutive and the segments one after another,
+// so the waves in flight write one contiguous stretch of the output arena.
+// A prologue kernel writes each segment's record (start chunk, output,
+// position slot) for the launch; a wave then needs one scalar load.  Each
+// chunk assumes that no earlier chunk of its segment rejected a pair and
+// stores at that offset at once; a chunk whose outputs all lie below output
+// n - 1 also assumes that it rejects nothing itself and stores each window
+// as it is generated (one running maximum finds a rejection afterwards).
+// A chunk that rejects marks its segment dirty from its index on; the
+// repair kernel then produces every dirty segment again, exactly and in
+// order, from its first dirty chunk.  A speculative chunk never writes
+// below its true offset (it can only have assumed too few earlier
+// rejections) nor past output n - 1, so what a dirty segment's chunks wrote
+// lies in the range its repair writes again, and the repair writes the true
+// next position last.  A chunk that holds output n - 1 and rejects pairs is
+// produced exactly; it marks nothing, since no later chunk holds an output.
+// ======================================================================
+__device__ __forceinline__ ChunkSeg load_chunk_seg(const ChunkSeg *recs, uint32_t i)
+{
+    constexpr int kWords = sizeof(ChunkSeg) / 8;
+    const constant_u64 *src = (const constant_u64 *)(recs + i);
+    uint64_t w[kWords];
+#pragma unroll
+    for (int k = 0; k < kWords; ++k)
+        w[k] = src[k];
+    ChunkSeg r;
+    __builtin_memcpy(&r, w, sizeof r);
+    return r;
+}
+
+// The segment of launch-local chunk c: a division by the common chunk count
+// (at least 2; multiply-high and shifts), or the chunk -> segment table.
+__device__ __forceinline__ uint32_t chunk_segment(const LaunchArgs &args, uint32_t c)
+{
+    if (args.chunks_per_seg != 0) {
+        const uint32_t t = __umulhi(c, args.cps_magic);
+        return (t + ((c - t) >> 1)) >> args.cps_shift;
+    }
+    return ((constant_u32 *)args.tile_seg)[c];
+}
+
+__device__ __forceinline__ Segment chunk_segment_view(const ChunkSeg &r)
+{
+    Segment seg;
+    seg.seed = r.seed;
+    seg.out = r.out;
+    seg.n = r.n;
+    seg.stream_id = r.stream_id;
+    return seg;
+}
+
+template <uint32_t FAM, uint32_t NWIN>
+struct BatchChunk {
+    static constexpr uint32_t P = NWIN * kChunk;      // pairs per chunk
+
+    // Chunk `ch` (pairs P ch ..) whose P outputs all lie below output
+    // n - 1, stored at segment offset excl as if it rejected no pair;
+    // returns whether that held.
+    __device__ __forceinline__ static bool run_clean(const LaunchArgs &args, const Segment &seg,
+                                                     uint64_t ch, uint64_t excl)
+    {
+        const uint32_t lane = threadIdx.x & 63u;
+        const uint32_t hm = fam_base(FAM) == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
+        const double tw = fam_base(FAM) == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+        double *o = seg.out + excl;
+        const bool aligned = (reinterpret_cast<uintptr_t>(o) & 15u) == 0;
+        const uint32_t mode = args.store_mode;
+        const uint32_t q = 2u * lane;
+        uint32_t mx = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < NWIN; ++j) {
+            const auto p = WaveChunk<FAM>::words(args, seg, ch * NWIN + j, lane);
+            mx = max(mx, max(p.ha, p.hb));
+            const double za = map_hi_lo<FAM>(p.ha, p.la, tw, args);
+            const double zb = map_hi_lo<FAM>(p.hb, p.lb, tw, args);
+            double *oj = o + j * kChunk;
+            if (mode != 1 && aligned) {
+                store_two(oj + q, za, zb, mode);
+            } else if (mode != 1) {
+                const double prev = wave_shr1(zb);
+                if (lane == 0)
+                    store_one(oj + q, za, mode);
+                else
+                    store_two(oj + q - 1, prev, za, mode);
+                if (lane == 63)
+                    store_one(oj + q + 1, zb, mode);
+            } else {
+                store_one(oj + q, za, mode);
+                store_one(oj + q + 1, zb, mode);
+            }
+        }
+        return __builtin_amdgcn_ballot_w64(mx >= hm) == 0;
+    }
+
+    // Chunk `ch` produced exactly from chunk offset lo_off on, at segment
+    // offset excl, window by window; returns its accepted pairs, or
+    // P - lo_off once output n - 1 has been stored (nothing after it
+    // matters then).
+    __device__ __forceinline__ static uint32_t run_exact(const LaunchArgs &args,
+                                                         const Segment &seg, uint64_t ch,
+                                                         uint32_t lo_off, uint64_t excl,
+                                                         uint64_t *next_counter)
+    {
+        uint64_t running = excl;
+#pragma unroll 1
+        for (uint32_t j = lo_off / kChunk; j < NWIN; ++j) {
+            if (!uniform_lt(running, seg.n))
+                return P - lo_off;
+            const uint32_t lo_j = j == lo_off / kChunk ? lo_off % kChunk : 0u;
+            running += WaveChunk<FAM>::run(args, seg, ch * NWIN + j, lo_j, running, next_counter,
+                                           true, lo_j == 0 && chunk_fits(running, seg.n));
+        }
+        return uniform_lt(running, seg.n) ? uint32_t(running - excl) : P - lo_off;
+    }
+};
+
+// Wave v of the grid takes launch-local chunk v.
+template <uint32_t FAM, uint32_t NWIN>
+__global__ __launch_bounds__(256) void chunk_batch_kernel(LaunchArgs args)
+{
+    using C = BatchChunk<FAM, NWIN>;
+    constexpr uint32_t P = C::P;
+    const uint32_t lane = threadIdx.x & 63u;
+    // the wave index is uniform in the wave: say so, so that everything
+    // derived from it (chunk, segment, offsets) lives in scalar registers
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t c = blockIdx.x * 4u + wave;
+    // Every argument the wave reads, requested at once (one round trip to
+    // the scalar cache instead of one per first use), and the segment's
+    // record likewise: a wave lives for a few hundred instructions, so its
+    // start latency counts.
+    {
+        const uint32_t total = args.total_tiles, cps = args.chunks_per_seg;
+        const uint32_t magic = args.cps_magic, shift = args.cps_shift, mode = args.store_mode;
+        const ChunkSeg *recs = args.chunk_segs;
+        const uint32_t *tseg = args.tile_seg;
+        const double S = args.S;
+        asm volatile("" ::"s"(total), "s"(cps), "s"(magic), "s"(shift), "s"(mode), "s"(recs),
+                     "s"(tseg), "s"(S));
+    }
+    if (c >= args.total_tiles)
+        return;
+    const uint32_t si = chunk_segment(args, c);
+    const ChunkSeg r = load_chunk_seg(args.chunk_segs, si);
+    asm volatile("" ::"s"(r.seed), "s"(r.out), "s"(r.w0), "s"(r.n), "s"(r.next_counter),
+                 "s"(r.stream_id), "s"(r.lo0), "s"(r.tile_begin), "s"(r.ntiles));
+    const Segment seg = chunk_segment_view(r);
+    const uint32_t k = c - r.tile_begin;
+    // chunks below k_full hold P outputs below n - 1; chunks from k_end on
+    // hold none (n < 2^38, so both fit in 32 bits).  A chunk past n only
+    // matters when an earlier chunk rejected, and then that one marks the
+    // segment and the repair produces it.
+    const uint64_t nl = r.n + r.lo0;
+    if (k >= uint32_t((nl + (P - 1)) / P))
+        return;
+    const uint64_t ch = r.w0 + k;
+    const uint32_t lo_off = k == 0 ? r.lo0 : 0u;
+    const uint64_t excl = k == 0 ? 0 : uint64_t(k) * P - r.lo0;
+    bool clean;
+    if (lo_off == 0 && k < uint32_t((nl - 1) / P))
+        clean = C::run_clean(args, seg, ch, excl);
+    else
+        clean = C::run_exact(args, seg, ch, lo_off, excl, r.next_counter) == P - lo_off;
+    if (!clean) {
+        if (lane == 0) {
+            const uint32_t old = __hip_atomic_fetch_max(&args.first_dirty[si], ~k,
+                                                        __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            if (old == 0u) {
+                const uint32_t slot = __hip_atomic_fetch_add(&args.spec->count, 1u,
+                                                             __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                args.dirty_list[slot] = si;    // each segment once: slot < nseg
+            }
+        }
+    } else if (k == r.ntiles - 1) {
+        // the segment's last chunk takes every further chunk until n
+        // outputs (a dirty segment is left to the repair)
+        uint64_t running = excl + (P - lo_off);
+        for (uint64_t c2 = ch + 1; uniform_lt(running, r.n); ++c2)
+            running += C::run_exact(args, seg, c2, 0u, running, r.next_counter);
+    }
+}
+
+// One wave per workgroup; workgroup b repairs dirty segments b, b + G, ...
+template <uint32_t FAM, uint32_t NWIN>
+__global__ __launch_bounds__(64) void chunk_repair_kernel(LaunchArgs args)
+{
+    using C = BatchChunk<FAM, NWIN>;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t cnt = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(&args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const uint32_t si = __builtin_amdgcn_readfirstlane(args.dirty_list[i]);
+        const uint32_t k0 = ~__builtin_amdgcn_readfirstlane(args.first_dirty[si]);
+        const ChunkSeg r = load_chunk_seg(args.chunk_segs, si);
+        const Segment seg = chunk_segment_view(r);
+        // no chunk before k0 rejected a pair: k0's true offset is the plain one
+        uint64_t running = k0 == 0 ? 0 : uint64_t(k0) * C::P - r.lo0;
+        for (uint64_t ch = r.w0 + k0; uniform_lt(running, r.n); ++ch)
+            running += C::run_exact(args, seg, ch, ch == r.w0 ? r.lo0 : 0u, running,
+                                    r.next_counter);
+        if (lane == 0)
+            args.first_dirty[si] = 0u;
+    }
+    // the last workgroup out empties the list for the next launch
+    if (lane == 0 &&
+        __hip_atomic_fetch_add(&args.spec->done, 1u, __ATOMIC_ACQ_REL,
+                               __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
+        __hip_atomic_store(&args.spec->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&args.spec->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -2334,10 +2609,11 @@ __global__ __launch_bounds__(256) void spec_wave_repair_kernel(LaunchArgs args)
             const uint64_t o = uint64_t(uint32_t(__shfl(uint32_t(off), l, 64))) |
                                uint64_t(uint32_t(__shfl(uint32_t(off >> 32), l, 64))) << 32;
             uint64_t running = o + WaveChunk<FAM>::run(args, seg, w0 + g, 0u, o, next_counter,
-                                                       true);
+                                                       true, chunk_fits(o, seg.n));
             if (g == total - 1)
-                for (uint64_t w2 = w0 + g + 1; running < seg.n; ++w2)
-                    running += WaveChunk<FAM>::run(args, seg, w2, 0u, running, next_counter, true);
+                for (uint64_t w2 = w0 + g + 1; uniform_lt(running, seg.n); ++w2)
+                    running += WaveChunk<FAM>::run(args, seg, w2, 0u, running, next_counter, true,
+                                                   chunk_fits(running, seg.n));
         }
     }
     __shared__ bool s_last;
@@ -2612,7 +2888,7 @@ __device__ __forceinline__ void single_window_store(const LaunchArgs &args, cons
     constexpr int B = W::B, J = W::J;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const uint64_t n = seg.n;
-    const bool exact = __syncthreads_or(bad) || lo != 0;
+    const bool exact = block_any(bad) || lo != 0;
     if (ss.running >= n)
         return;
     if (!exact) {

@@ -88,6 +88,27 @@ static_assert(sizeof(SpecControl) == 256, "SpecControl layout");
 // that tile's window; 0 is an empty slot.
 constexpr uint32_t kHintEntries = 256;    // entries a tile reads for its hint
 
+// Pairs per chunk of the wave-granular forms: one wave of 64 lanes, two
+// pairs per lane.  The batch form's chunks hold 1, 2 or 4 such windows.
+constexpr uint32_t kChunkPairs = 128;
+
+// Per-segment record of the chunk-speculative batch fill, written by its
+// prologue kernel at every launch (the start position changes from launch
+// to launch), read by the chunk kernel with one scalar load.  64 bytes.
+struct ChunkSeg {
+    uint64_t seed;
+    double *out;
+    uint64_t w0;              // first chunk of the segment (absolute)
+    uint64_t n;
+    uint64_t *next_counter;   // the position slot half this launch writes
+    uint32_t stream_id;
+    uint32_t lo0;             // pairs of chunk w0 before the start position
+    uint32_t tile_begin;      // first launch-local chunk of the segment
+    uint32_t ntiles;          // its chunks; the last one continues until n
+    uint32_t pad[2];
+};
+static_assert(sizeof(ChunkSeg) == 64, "ChunkSeg layout");
+
 struct LaunchArgs {
     const Segment *segs;      // nseg descriptors, or null for seg0
     const uint32_t *tile_seg; // launch-local tile -> segment index (segs only)
@@ -115,6 +136,14 @@ struct LaunchArgs {
     uint64_t epoch;           // launch number of the workspace (from 1)
     const uint32_t *mrg_thread;  // [256][18]: A^(r * tid * PPL)
     const uint32_t *mrg_window;  // [8][256][18]: A^(r * T * d * 256^i)
+    // chunk-speculative batch fill
+    ChunkSeg *chunk_segs;     // nseg records
+    uint32_t *first_dirty;    // per segment: ~(first chunk with a rejection), 0 = none
+    uint32_t *dirty_list;     // segments with a rejection, spec->count of them
+    uint32_t chunks_per_seg;  // every segment's chunk count when they are all equal, else 0
+    uint32_t cps_magic;       // c / chunks_per_seg as (t + ((c - t) >> 1)) >> cps_shift,
+    uint32_t cps_shift;       // t = mulhi(c, cps_magic) (chunks_per_seg >= 2)
+    uint32_t chunk_shift;     // log2 of the pairs per chunk
 };
 
 constexpr uint32_t kMaxTiles = 0xFFFFFFF0u;
@@ -138,6 +167,8 @@ template <uint32_t MAPF>
 const void *single_kernel_for(uint32_t fam);
 template <uint32_t MAPF>
 const void *spec_words_kernel_for(uint32_t fam, bool repair);
+template <uint32_t MAPF>
+const void *philox_chunk_kernel_for(uint32_t fam, bool repair, uint32_t windows);
 
 // Device error codes (bit flags in the error word).
 constexpr uint32_t kErrLookbackStall = 1;

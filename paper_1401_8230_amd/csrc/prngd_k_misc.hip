@@ -38,6 +38,31 @@ __global__ void expand_tiles_kernel(const Segment *segs, uint32_t nseg, uint32_t
             tile_seg[b + i] = s;
     }
 }
+// The chunk-speculative batch fill's prologue: one thread per segment
+// writes the segment's record for this launch (start window and offset,
+// output, the position slot half it writes).
+__global__ void chunk_prep_kernel(LaunchArgs args)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= args.nseg)
+        return;
+    const Segment s = args.segs[i];
+    const uint32_t par = (s.parity ^ read_flip(args)) & 1u;
+    const uint64_t c0 = s.counter[par];
+    ChunkSeg r;
+    r.seed = s.seed;
+    r.out = s.out;
+    r.w0 = c0 >> args.chunk_shift;
+    r.n = s.n;
+    r.next_counter = s.counter + (par ^ 1u);
+    r.stream_id = s.stream_id;
+    r.lo0 = uint32_t(c0 & ((uint64_t(1) << args.chunk_shift) - 1));
+    r.tile_begin = s.tile_begin;
+    r.ntiles = s.ntiles;
+    r.pad[0] = r.pad[1] = 0;
+    args.chunk_segs[i] = r;
+}
+
 }  // namespace
 
 // The routers below take a family with or without FAM_ANY_MAP and pick
@@ -88,6 +113,20 @@ const void *fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool s
 const void *spec_wave_kernel_for(uint32_t fam, bool repair)
 {
     return by_map(fam, [&](auto m) { return philox_wave_kernel_for<decltype(m)::value>(fam, repair); });
+}
+
+// The chunk-speculative batch fill (256 threads, chunks of `windows`
+// 128-pair windows) or its repair (64 threads), or null.
+const void *chunk_kernel_for(uint32_t fam, bool repair, uint32_t windows)
+{
+    return by_map(fam, [&](auto m) {
+        return philox_chunk_kernel_for<decltype(m)::value>(fam, repair, windows);
+    });
+}
+
+const void *chunk_prep_kernel_ptr()
+{
+    return reinterpret_cast<const void *>(&chunk_prep_kernel);
 }
 
 // The single-word-consumption kernel (256 threads), or null.

@@ -84,4 +84,40 @@ const void *philox_wave_kernel_for<PRNGD_MAPF>(uint32_t fam, bool repair)
     }
 }
 
+// The chunk-speculative batch fill of a Philox-family generator in chunks
+// of `windows` 128-pair windows (1, 2 or 4), or its repair; null for other
+// families and chunk sizes.
+template <uint32_t F>
+const void *chunk_for(uint32_t windows, bool repair)
+{
+    switch (windows) {
+    case 1:
+        return repair ? reinterpret_cast<const void *>(&chunk_repair_kernel<F, 1>)
+                      : reinterpret_cast<const void *>(&chunk_batch_kernel<F, 1>);
+    case 2:
+        return repair ? reinterpret_cast<const void *>(&chunk_repair_kernel<F, 2>)
+                      : reinterpret_cast<const void *>(&chunk_batch_kernel<F, 2>);
+    case 4:
+        return repair ? reinterpret_cast<const void *>(&chunk_repair_kernel<F, 4>)
+                      : reinterpret_cast<const void *>(&chunk_batch_kernel<F, 4>);
+    default:
+        return nullptr;
+    }
+}
+
+template <>
+const void *philox_chunk_kernel_for<PRNGD_MAPF>(uint32_t fam, bool repair, uint32_t windows)
+{
+    switch (fam_base(fam)) {
+    case FAM_PHILOX32:
+        return chunk_for<FAM_PHILOX32 | PRNGD_MAPF>(windows, repair);
+    case FAM_PHILOX:
+        return chunk_for<FAM_PHILOX | PRNGD_MAPF>(windows, repair);
+    case FAM_ENUM:
+        return chunk_for<FAM_ENUM | PRNGD_MAPF>(windows, repair);
+    default:
+        return nullptr;
+    }
+}
+
 }  // namespace prngd

@@ -26,6 +26,8 @@ const void *spec_wave_kernel_for(uint32_t fam, bool repair);
 const void *single_kernel_for(uint32_t fam);
 const void *spec_words_kernel_for(uint32_t fam, bool repair);
 const void *triple_kernel_for(uint32_t fam, bool seq);
+const void *chunk_kernel_for(uint32_t fam, bool repair, uint32_t cpw);
+const void *chunk_prep_kernel_ptr();
 hipError_t launch_toggle_flip(uint32_t *flip, hipStream_t stream);
 const void *toggle_flip_kernel_ptr();
 hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads,
@@ -582,6 +584,12 @@ struct Workspace {
     uint64_t *hint64 = nullptr;           // wave-granular form: per chunk
     size_t hint64_cap = 0;
     uint64_t spec_epoch = 0;
+    // chunk-speculative batch form: per segment record, first dirty chunk
+    // (zero between launches) and the list of dirty segments
+    ChunkSeg *chunk_segs = nullptr;
+    uint32_t *first_dirty = nullptr;
+    uint32_t *dirty_list = nullptr;
+    size_t chunk_cap = 0;
     // buffers replaced by larger ones: kept until the workspace is released,
     // so that growing never waits for work in flight (freeing would)
     std::vector<void *> retired_dev;
@@ -632,6 +640,9 @@ void ws_release(Workspace *ws)
     (void)hipFree(ws->rejlist);
     (void)hipFree(ws->hint);
     (void)hipFree(ws->hint64);
+    (void)hipFree(ws->chunk_segs);
+    (void)hipFree(ws->first_dirty);
+    (void)hipFree(ws->dirty_list);
     (void)hipFree(ws->dsegs);
     (void)hipFree(ws->tile_seg);
     for (int i = 0; i < 2; ++i) {
@@ -703,6 +714,35 @@ prngd_status_t ws_prepare_hint64(Workspace *ws, size_t chunks, hipStream_t strea
     ws->hint64 = static_cast<uint64_t *>(p);
     ws->hint64_cap = cap;
     HIP_TRY(launch_zero_words(ws->hint64, cap, stream));
+    return PRNGD_OK;
+}
+
+// Room for the chunk-speculative batch form's per-segment buffers of
+// `nseg` segments.  A new first-dirty array starts zero; afterwards every
+// repair launch leaves it zero again.
+prngd_status_t ws_prepare_chunk(Workspace *ws, size_t nseg, hipStream_t stream)
+{
+    if (nseg <= ws->chunk_cap)
+        return PRNGD_OK;
+    // even, so that the first-dirty array is whole 8-byte words
+    const size_t cap = (std::max<size_t>({nseg, size_t(1024), 2 * ws->chunk_cap}) + 1) & ~size_t(1);
+    if (ws->chunk_segs) {
+        ws->retired_dev.push_back(ws->chunk_segs);
+        ws->retired_dev.push_back(ws->first_dirty);
+        ws->retired_dev.push_back(ws->dirty_list);
+        ws->chunk_segs = nullptr;
+        ws->first_dirty = nullptr;
+        ws->dirty_list = nullptr;
+    }
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, cap * sizeof(ChunkSeg)));
+    ws->chunk_segs = static_cast<ChunkSeg *>(p);
+    HIP_TRY(hipMalloc(&p, cap * sizeof(uint32_t)));
+    ws->first_dirty = static_cast<uint32_t *>(p);
+    HIP_TRY(hipMalloc(&p, cap * sizeof(uint32_t)));
+    ws->dirty_list = static_cast<uint32_t *>(p);
+    ws->chunk_cap = cap;
+    HIP_TRY(launch_zero_words(reinterpret_cast<uint64_t *>(ws->first_dirty), cap / 2, stream));
     return PRNGD_OK;
 }
 
@@ -825,7 +865,12 @@ struct LaunchPlan {
     const void *wave_repair_kernel;
     const void *words_kernel;         // one-word consumption across workgroups
     const void *words_repair_kernel;
+    const void *chunk_kernel;         // chunk-speculative batch form, if any
+    const void *chunk_repair_kernel;
     bool wave;                // single fills take the wave-granular form
+    bool chunk;               // batches take the chunk-speculative form
+    uint32_t chunk_windows;   // its 128-pair windows per chunk (1, 2, 4)
+    uint32_t chunk_pairs;     // its pairs per chunk
     uint32_t *zero_word;
     bool spec;
     uint32_t threads;
@@ -884,7 +929,16 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     lp->wave_repair_kernel = two ? spec_wave_kernel_for(kfam, true) : nullptr;
     lp->words_kernel = two ? spec_words_kernel_for(kfam, false) : nullptr;
     lp->words_repair_kernel = two ? spec_words_kernel_for(kfam, true) : nullptr;
+    // the chunk form: a wave takes one chunk of pairs_per_lane / 2 windows
+    // (2 pairs per lane each; 1, 2 or 4 windows)
+    lp->chunk_windows = std::min<uint32_t>(4, std::max<uint32_t>(1, lp->tune.pairs_per_lane / 2));
+    if (lp->chunk_windows == 3)
+        lp->chunk_windows = 2;
+    lp->chunk_pairs = kChunkPairs * lp->chunk_windows;
+    lp->chunk_kernel = two ? chunk_kernel_for(kfam, false, lp->chunk_windows) : nullptr;
+    lp->chunk_repair_kernel = two ? chunk_kernel_for(kfam, true, lp->chunk_windows) : nullptr;
     lp->wave = false;
+    lp->chunk = false;
     lp->zero_word = d->zero_word;
     lp->spec = false;                  // decided per launch by choose_path
     args->store_mode = lp->tune.store_mode;
@@ -928,17 +982,26 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
 // more (up to 1024) a single fill is fastest in 128-pair chunks, a batch
 // in the holding form (up to 128); beyond that the ordered kernels win.
 void choose_path(LaunchPlan *lp, const Config &c, uint64_t pairs, uint64_t longest,
-                 bool single)
+                 bool single, uint64_t nseg = 1)
 {
     lp->spec = false;
     lp->wave = false;
+    lp->chunk = false;
     if (!lp->repair_kernel || lp->tune.path == 1 || c.consume == PRNGD_CONSUME_SINGLE)
         return;
     const double rho = 2.0 / double(c.a - c.a0 + 1);
     const double expected = double(pairs) * rho;
     const bool wave_ok = single && lp->wave_kernel && lp->wave_repair_kernel;
+    // the chunk form's one-shot grid: 4 chunks per workgroup of 256 threads,
+    // at most 2^32 - 1 threads; a segment adds at most one chunk
+    const bool chunk_ok = !single && lp->chunk_kernel && lp->chunk_repair_kernel &&
+                          pairs / lp->chunk_pairs + nseg < (uint64_t(1) << 26);
     int hold = -1;
-    if (lp->tune.path == 4) {
+    if (lp->tune.path == 5 && chunk_ok) {
+        lp->chunk = true;
+        return;
+    }
+    if (lp->tune.path == 4 || lp->tune.path == 5) {
         lp->wave = wave_ok;
         hold = 0;
     } else if (lp->tune.path == 2) {
@@ -1076,6 +1139,62 @@ prngd_status_t launch_spec_wave(DeviceInfo *d, const LaunchPlan &lp, Workspace *
     return PRNGD_OK;
 }
 
+// Workgroups (of one wave) of the chunk form's repair: each takes dirty
+// segments b, b + G, ...; the launch never knows how many there are.
+uint32_t chunk_repair_grid(DeviceInfo *d, uint64_t nseg)
+{
+    return uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(nseg, 4 * uint64_t(d->cus))));
+}
+
+// Workgroups of the chunk form's one-shot grid over `chunks` chunks: 4
+// waves of one chunk each.
+uint32_t chunk_grid(uint64_t chunks)
+{
+    return uint32_t((chunks + 3) / 4);
+}
+
+// Kernel arguments of the chunk-speculative fill of args.nseg segments in
+// args.total_tiles chunks; chunks_per_seg (if nonzero) with the constants
+// of the division by it (multiply-high, add, shift: Granlund and
+// Montgomery's round-up method, exact for every 32-bit dividend).
+LaunchArgs chunk_args(const LaunchPlan &lp, Workspace *ws, LaunchArgs args,
+                      uint32_t chunks_per_seg)
+{
+    args.spec = ws->spec;
+    args.chunk_segs = ws->chunk_segs;
+    args.first_dirty = ws->first_dirty;
+    args.dirty_list = ws->dirty_list;
+    args.chunks_per_seg = chunks_per_seg;
+    args.cps_magic = 0;
+    args.cps_shift = 0;
+    if (chunks_per_seg >= 2) {
+        uint32_t l = 0;
+        while ((uint64_t(1) << l) < chunks_per_seg)
+            ++l;
+        const uint64_t num = (uint64_t(1) << 32) * ((uint64_t(1) << l) - chunks_per_seg);
+        args.cps_magic = uint32_t(num / chunks_per_seg + 1);
+        args.cps_shift = l - 1;
+    }
+    args.chunk_shift = 0;
+    while ((uint32_t(1) << args.chunk_shift) < lp.chunk_pairs)
+        ++args.chunk_shift;
+    if (!args.flip)
+        args.flip = lp.zero_word;
+    return args;
+}
+
+// Enqueue the chunk-speculative fill of a batch: the segments' records for
+// this launch, the one-shot grid of chunks (4 per workgroup), the repair.
+prngd_status_t launch_chunk(DeviceInfo *d, const LaunchPlan &lp, Workspace *ws,
+                            const LaunchArgs &in, uint32_t chunks_per_seg, hipStream_t s)
+{
+    const LaunchArgs args = chunk_args(lp, ws, in, chunks_per_seg);
+    HIP_TRY(launch_fill(chunk_prep_kernel_ptr(), (args.nseg + 255) / 256, 256, args, s));
+    HIP_TRY(launch_fill(lp.chunk_kernel, chunk_grid(args.total_tiles), 256, args, s));
+    HIP_TRY(launch_fill(lp.chunk_repair_kernel, chunk_repair_grid(d, args.nseg), 64, args, s));
+    return PRNGD_OK;
+}
+
 // Fill the descriptor of one request; returns its number of tiles.
 prngd_status_t make_segment(prngd_handle_t h, uint64_t n, double *out, uint64_t T,
                             uint32_t slack_mode, uint64_t tile_begin, Segment *s,
@@ -1135,6 +1254,7 @@ struct BatchPlan {
     std::vector<Segment> seq;
     std::vector<prngd_handle_t> handles;
     uint64_t lb_tiles = 0;
+    uint32_t chunks_per_seg = 0;   // chunk form: every segment's chunk count, if equal and >= 2
 };
 
 prngd_status_t build_batch(DeviceInfo *d, LaunchPlan &lp, const prngd_request_t *reqs,
@@ -1146,8 +1266,8 @@ prngd_status_t build_batch(DeviceInfo *d, LaunchPlan &lp, const prngd_request_t 
     const prngd_handle_t first = reqs[0].h;
     if (!first)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "request 0 has a NULL handle");
-    std::vector<Segment> all;
-    uint64_t total = 0, pairs = 0, max_seg_pairs = 0;
+    // validate, and plan the pairs that decide the path
+    uint64_t pairs = 0, max_seg_pairs = 0, live = 0;
     for (uint32_t i = 0; i < count; ++i) {
         const prngd_request_t &r = reqs[i];
         if (!r.h)
@@ -1160,26 +1280,37 @@ prngd_status_t build_batch(DeviceInfo *d, LaunchPlan &lp, const prngd_request_t 
                         i);
         if (r.h->plan)
             return fail(PRNGD_ERR_INVALID_ARGUMENT, "request %u: handle bound to a plan", i);
+        if (r.n == 0 || r.n > kMaxOutputs)
+            continue;
+        const uint64_t planned = planned_pairs(r.h->cfg, r.n, lp.tune.slack_mode);
+        pairs += planned;
+        max_seg_pairs = std::max<uint64_t>(max_seg_pairs, planned);
+        ++live;
+    }
+    choose_path(&lp, first->cfg, pairs, max_seg_pairs, false, live);
+    // the chunk form plans its segments in chunks, the others in tiles
+    const uint64_t T = lp.chunk ? lp.chunk_pairs : lp.T;
+    std::vector<Segment> all;
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        const prngd_request_t &r = reqs[i];
         if (r.n == 0)
             continue;
         Segment s;
         uint64_t nt = 0;
-        prngd_status_t st = make_segment(r.h, r.n, r.out, lp.T, lp.tune.slack_mode, 0, &s, &nt);
+        prngd_status_t st = make_segment(r.h, r.n, r.out, T, lp.tune.slack_mode, 0, &s, &nt);
         if (st != PRNGD_OK)
             return st;
         total += nt;
-        pairs += s.planned;
-        max_seg_pairs = std::max<uint64_t>(max_seg_pairs, s.planned);
         all.push_back(s);
         bp->handles.push_back(r.h);
     }
-    choose_path(&lp, first->cfg, pairs, max_seg_pairs, false);
     const uint64_t wg = uint64_t(occupancy_of(d, lp.seq_kernel, lp.threads)) * uint64_t(d->cus);
-    // the speculative fill takes every segment tile by tile; single-word
+    // the speculative fills take every segment tile by tile; single-word
     // consumption every segment whole
     const uint64_t limit = first->cfg.consume == PRNGD_CONSUME_SINGLE
                                ? ~uint64_t(0)
-                               : lp.spec ? 0 : seq_limit(lp.tune, total, wg);
+                               : lp.spec || lp.chunk ? 0 : seq_limit(lp.tune, total, wg);
     for (const Segment &s : all) {
         if (s.ntiles <= limit) {
             bp->seq.push_back(s);
@@ -1194,6 +1325,12 @@ prngd_status_t build_batch(DeviceInfo *d, LaunchPlan &lp, const prngd_request_t 
     }
     std::stable_sort(bp->seq.begin(), bp->seq.end(),
                      [](const Segment &x, const Segment &y) { return x.ntiles > y.ntiles; });
+    // segments of equal length (two chunks or more) find theirs by a division
+    bp->chunks_per_seg = 0;
+    if (lp.chunk && !bp->lb.empty() && bp->lb[0].ntiles >= 2 &&
+        std::all_of(bp->lb.begin(), bp->lb.end(),
+                    [&](const Segment &x) { return x.ntiles == bp->lb[0].ntiles; }))
+        bp->chunks_per_seg = bp->lb[0].ntiles;
     return PRNGD_OK;
 }
 
@@ -1663,8 +1800,9 @@ static prngd_status_t fill_batch_impl(const prngd_request_t *reqs, uint32_t coun
         if (h->last_event && h->last_stream != s && waited.insert(h->last_event).second)
             HIP_TRY(hipStreamWaitEvent(s, h->last_event, 0));
     const size_t nseg = bp.lb.size() + bp.seq.size();
-    if ((st = lp.spec ? ws_prepare_spec(ws, bp.lb_tiles, s) : ws_prepare(ws, bp.lb_tiles, s)) !=
-        PRNGD_OK)
+    if ((st = lp.chunk  ? ws_prepare_chunk(ws, nseg, s)
+              : lp.spec ? ws_prepare_spec(ws, bp.lb_tiles, s)
+                        : ws_prepare(ws, bp.lb_tiles, s)) != PRNGD_OK)
         return st;
     if ((st = ws_grow(ws, &ws->dsegs, &ws->dsegs_cap, nseg, s)) != PRNGD_OK)
         return st;
@@ -1700,12 +1838,16 @@ static prngd_status_t fill_batch_impl(const prngd_request_t *reqs, uint32_t coun
                             lp.threads, sa, s));
     }
     if (!bp.lb.empty()) {
-        HIP_TRY(launch_expand_tiles(ws->dsegs, uint32_t(bp.lb.size()), ws->tile_seg, s));
+        if (!lp.chunk || bp.chunks_per_seg == 0)
+            HIP_TRY(launch_expand_tiles(ws->dsegs, uint32_t(bp.lb.size()), ws->tile_seg, s));
         args.segs = ws->dsegs;
         args.tile_seg = ws->tile_seg;
         args.nseg = uint32_t(bp.lb.size());
         args.total_tiles = uint32_t(bp.lb_tiles);
-        if (lp.spec) {
+        if (lp.chunk) {
+            if ((st = launch_chunk(d, lp, ws, args, bp.chunks_per_seg, s)) != PRNGD_OK)
+                return st;
+        } else if (lp.spec) {
             if ((st = launch_spec(d, lp, ws, args, bp.lb_tiles, s)) != PRNGD_OK)
                 return st;
         } else {
@@ -1758,12 +1900,13 @@ prngd_status_t prngd_plan_create(const prngd_request_t *reqs, uint32_t count,
     for (prngd_handle_t h : p->handles)
         if (h->last_event)
             HIP_TRY(hipEventSynchronize(h->last_event));
-    if ((st = lp.spec ? ws_prepare_spec(&p->ws, bp.lb_tiles, nullptr)
-                      : ws_prepare(&p->ws, bp.lb_tiles, nullptr)) != PRNGD_OK) {
+    const size_t nseg = bp.lb.size() + bp.seq.size();
+    if ((st = lp.chunk  ? ws_prepare_chunk(&p->ws, nseg, nullptr)
+              : lp.spec ? ws_prepare_spec(&p->ws, bp.lb_tiles, nullptr)
+                        : ws_prepare(&p->ws, bp.lb_tiles, nullptr)) != PRNGD_OK) {
         ws_release(&p->ws);
         return st;
     }
-    const size_t nseg = bp.lb.size() + bp.seq.size();
     std::vector<Segment> all(bp.lb);
     all.insert(all.end(), bp.seq.begin(), bp.seq.end());
     std::vector<uint32_t> map(std::max<uint64_t>(bp.lb_tiles, 1), 0u);
@@ -1805,7 +1948,31 @@ prngd_status_t prngd_plan_create(const prngd_request_t *reqs, uint32_t count,
         HIP_TRY(hipGraphAddKernelNode(&node, p->graph, nullptr, 0, &kp));
         fills.push_back(node);
     }
-    if (!bp.lb.empty() && lp.spec) {
+    if (!bp.lb.empty() && lp.chunk) {
+        // chunk-speculative fill: the records, the chunks, the repair
+        p->spec = true;
+        p->lb_args.segs = p->dsegs;
+        p->lb_args.tile_seg = p->tile_seg;
+        p->lb_args.nseg = uint32_t(bp.lb.size());
+        p->lb_args.total_tiles = uint32_t(bp.lb_tiles);
+        p->lb_args = chunk_args(lp, &p->ws, p->lb_args, bp.chunks_per_seg);
+        hipKernelNodeParams kp{};
+        void *params[] = {&p->lb_args};
+        kp.func = const_cast<void *>(chunk_prep_kernel_ptr());
+        kp.gridDim = dim3((p->lb_args.nseg + 255) / 256);
+        kp.blockDim = dim3(256);
+        kp.kernelParams = params;
+        hipGraphNode_t pnode, cnode, rnode;
+        HIP_TRY(hipGraphAddKernelNode(&pnode, p->graph, nullptr, 0, &kp));
+        kp.func = const_cast<void *>(lp.chunk_kernel);
+        kp.gridDim = dim3(chunk_grid(bp.lb_tiles));
+        HIP_TRY(hipGraphAddKernelNode(&cnode, p->graph, &pnode, 1, &kp));
+        kp.func = const_cast<void *>(lp.chunk_repair_kernel);
+        kp.gridDim = dim3(chunk_repair_grid(d, p->lb_args.nseg));
+        kp.blockDim = dim3(64);
+        HIP_TRY(hipGraphAddKernelNode(&rnode, p->graph, &cnode, 1, &kp));
+        fills.push_back(rnode);
+    } else if (!bp.lb.empty() && lp.spec) {
         // speculative fill, then its repair
         p->spec = true;
         p->lb_args.segs = p->dsegs;
@@ -1938,7 +2105,7 @@ prngd_status_t prngd_set_tuning(prngd_generator_t generator, uint32_t w,
     if (!fill_kernel_for(fam, threads, ppl, false))
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u threads x %u pairs per lane",
                     threads, ppl);
-    if (t.store_mode > 2 || t.slack_mode > 1 || t.path > 4)
+    if (t.store_mode > 2 || t.slack_mode > 1 || t.path > 5)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "bad store_mode, slack_mode or path");
     if (t.path >= 2 && !spec_kernel_for(fam, threads, ppl, false, false, true))
         return fail(PRNGD_ERR_INVALID_ARGUMENT,

@@ -38,18 +38,23 @@ def release():
     torch.cuda.empty_cache()
 
 
-def test_many_streams_every_output_and_counter():
+@pytest.mark.parametrize("path", ["auto", "speculative-chunk"])
+def test_many_streams_every_output_and_counter(path):
     reqs = workloads.many_streams()
     S, n = len(reqs), reqs[0].n
-    note(f"many streams: {S} handles x {n}")
+    note(f"many streams ({path}): {S} handles x {n}")
     gens = prngd.Generator.many(42, S, "philox", w=32)
     out = torch.empty(S * n, dtype=torch.float64, device=DEV)
     views = [out[i * n:(i + 1) * n] for i in range(S)]
-    plan = prngd.Plan(list(zip(gens, views)))
+    prngd.set_tuning("philox", 32, path=path)
+    try:
+        plan = prngd.Plan(list(zip(gens, views)))
+    finally:
+        prngd.reset_tuning("philox", 32)
     counters = [0] * S
     group = 4096
     for launch in range(2):
-        note(f"many streams: launch {launch}")
+        note(f"many streams ({path}): launch {launch}")
         out.view(torch.int64).fill_(0x7FF8DEADBEEF0001)
         plan.launch()
         torch.cuda.synchronize()
