@@ -157,10 +157,13 @@ typedef struct {
                               /* a repair pass redoes each request from its */
                               /* first chunk with a rejection (Philox and   */
                               /* the test generator; others take 2).        */
-                              /* Automatic: ordered unless some request has */
-                              /* at least 2^18 pairs; then 3 when the launch*/
-                              /* expects at most 2 rejections, 4 (single    */
-                              /* fills) up to 1024, 3 (batches) up to 128.  */
+                              /* Automatic: 5 for a batch of Philox or test */
+                              /* generator requests of at most 2^16 pairs   */
+                              /* that expects at most 256 rejections;       */
+                              /* otherwise ordered unless some request has  */
+                              /* at least 2^18 pairs; then, single fills: 3 */
+                              /* at w = 32 up to 2 expected rejections, 4   */
+                              /* up to 1024; batches: 3 up to 128.          */
                               /* MRG32k3a and mixed have form 3 only        */
 } prngd_tuning_t;
 

@@ -2375,17 +2375,17 @@ template <uint32_t FAM, uint32_t NWIN>
 struct BatchChunk {
     static constexpr uint32_t P = NWIN * kChunk;      // pairs per chunk
 
-    // Chunk `ch` (pairs P ch ..) whose P outputs all lie below output
-    // n - 1, stored at segment offset excl as if it rejected no pair;
-    // returns whether that held.
-    __device__ __forceinline__ static bool run_clean(const LaunchArgs &args, const Segment &seg,
-                                                     uint64_t ch, uint64_t excl)
+    // The windows of a clean chunk stored in one of three ways: V = 0
+    // 16-byte stores, V = 1 16-byte stores of outputs shifted by one lane
+    // (an output arena 8 bytes off a 16-byte boundary), V = 2 8-byte
+    // stores.  Returns the running maximum of the windows' hi operands.
+    template <int V>
+    __device__ __forceinline__ static uint32_t store_windows(const LaunchArgs &args,
+                                                             const Segment &seg, uint64_t ch,
+                                                             double *o)
     {
         const uint32_t lane = threadIdx.x & 63u;
-        const uint32_t hm = fam_base(FAM) == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
         const double tw = fam_base(FAM) == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
-        double *o = seg.out + excl;
-        const bool aligned = (reinterpret_cast<uintptr_t>(o) & 15u) == 0;
         const uint32_t mode = args.store_mode;
         const uint32_t q = 2u * lane;
         uint32_t mx = 0;
@@ -2396,9 +2396,9 @@ struct BatchChunk {
             const double za = map_hi_lo<FAM>(p.ha, p.la, tw, args);
             const double zb = map_hi_lo<FAM>(p.hb, p.lb, tw, args);
             double *oj = o + j * kChunk;
-            if (mode != 1 && aligned) {
+            if (V == 0) {
                 store_two(oj + q, za, zb, mode);
-            } else if (mode != 1) {
+            } else if (V == 1) {
                 const double prev = wave_shr1(zb);
                 if (lane == 0)
                     store_one(oj + q, za, mode);
@@ -2411,6 +2411,25 @@ struct BatchChunk {
                 store_one(oj + q + 1, zb, mode);
             }
         }
+        return mx;
+    }
+
+    // Chunk `ch` (pairs P ch ..) whose P outputs all lie below output
+    // n - 1, stored at segment offset excl as if it rejected no pair;
+    // returns whether that held.
+    __device__ __forceinline__ static bool run_clean(const LaunchArgs &args, const Segment &seg,
+                                                     uint64_t ch, uint64_t excl)
+    {
+        const uint32_t hm = fam_base(FAM) == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
+        double *o = seg.out + excl;
+        const bool aligned = (reinterpret_cast<uintptr_t>(o) & 15u) == 0;
+        uint32_t mx;
+        if (args.store_mode != 1 && aligned)
+            mx = store_windows<0>(args, seg, ch, o);
+        else if (args.store_mode != 1)
+            mx = store_windows<1>(args, seg, ch, o);
+        else
+            mx = store_windows<2>(args, seg, ch, o);
         return __builtin_amdgcn_ballot_w64(mx >= hm) == 0;
     }
 
@@ -2465,21 +2484,19 @@ __global__ __launch_bounds__(256) void chunk_batch_kernel(LaunchArgs args)
     const uint32_t si = chunk_segment(args, c);
     const ChunkSeg r = load_chunk_seg(args.chunk_segs, si);
     asm volatile("" ::"s"(r.seed), "s"(r.out), "s"(r.w0), "s"(r.n), "s"(r.next_counter),
-                 "s"(r.stream_id), "s"(r.lo0), "s"(r.tile_begin), "s"(r.ntiles));
+                 "s"(r.stream_id), "s"(r.lo0), "s"(r.tile_begin), "s"(r.ntiles), "s"(r.k_full),
+                 "s"(r.k_end));
     const Segment seg = chunk_segment_view(r);
     const uint32_t k = c - r.tile_begin;
-    // chunks below k_full hold P outputs below n - 1; chunks from k_end on
-    // hold none (n < 2^38, so both fit in 32 bits).  A chunk past n only
-    // matters when an earlier chunk rejected, and then that one marks the
-    // segment and the repair produces it.
-    const uint64_t nl = r.n + r.lo0;
-    if (k >= uint32_t((nl + (P - 1)) / P))
+    // A chunk past n only matters when an earlier chunk rejected, and then
+    // that one marks the segment and the repair produces it.
+    if (k >= r.k_end)
         return;
     const uint64_t ch = r.w0 + k;
     const uint32_t lo_off = k == 0 ? r.lo0 : 0u;
     const uint64_t excl = k == 0 ? 0 : uint64_t(k) * P - r.lo0;
     bool clean;
-    if (lo_off == 0 && k < uint32_t((nl - 1) / P))
+    if (lo_off == 0 && k < r.k_full)
         clean = C::run_clean(args, seg, ch, excl);
     else
         clean = C::run_exact(args, seg, ch, lo_off, excl, r.next_counter) == P - lo_off;

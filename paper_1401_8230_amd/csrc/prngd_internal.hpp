@@ -94,7 +94,9 @@ constexpr uint32_t kChunkPairs = 128;
 
 // Per-segment record of the chunk-speculative batch fill, written by its
 // prologue kernel at every launch (the start position changes from launch
-// to launch), read by the chunk kernel with one scalar load.  64 bytes.
+// to launch), read by a wave of the chunk kernel in one scalar batch: one
+// 64-byte line (a wave's start latency counts: a larger record, say with
+// the Philox round keys, measured slower than the scalar adds it saves).
 struct ChunkSeg {
     uint64_t seed;
     double *out;
@@ -105,7 +107,8 @@ struct ChunkSeg {
     uint32_t lo0;             // pairs of chunk w0 before the start position
     uint32_t tile_begin;      // first launch-local chunk of the segment
     uint32_t ntiles;          // its chunks; the last one continues until n
-    uint32_t pad[2];
+    uint32_t k_full;          // chunks below k_full hold P outputs below n - 1
+    uint32_t k_end;           // chunks from k_end on hold no output
 };
 static_assert(sizeof(ChunkSeg) == 64, "ChunkSeg layout");
 

@@ -39,8 +39,8 @@ __global__ void expand_tiles_kernel(const Segment *segs, uint32_t nseg, uint32_t
     }
 }
 // The chunk-speculative batch fill's prologue: one thread per segment
-// writes the segment's record for this launch (start window and offset,
-// output, the position slot half it writes).
+// writes the segment's record for this launch (start chunk and offset,
+// output, the position slot half it writes, the chunk bounds).
 __global__ void chunk_prep_kernel(LaunchArgs args)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -49,17 +49,21 @@ __global__ void chunk_prep_kernel(LaunchArgs args)
     const Segment s = args.segs[i];
     const uint32_t par = (s.parity ^ read_flip(args)) & 1u;
     const uint64_t c0 = s.counter[par];
+    const uint32_t sh = args.chunk_shift;
+    const uint64_t P = uint64_t(1) << sh;
     ChunkSeg r;
     r.seed = s.seed;
     r.out = s.out;
-    r.w0 = c0 >> args.chunk_shift;
+    r.w0 = c0 >> sh;
     r.n = s.n;
     r.next_counter = s.counter + (par ^ 1u);
     r.stream_id = s.stream_id;
-    r.lo0 = uint32_t(c0 & ((uint64_t(1) << args.chunk_shift) - 1));
+    r.lo0 = uint32_t(c0 & (P - 1));
     r.tile_begin = s.tile_begin;
     r.ntiles = s.ntiles;
-    r.pad[0] = r.pad[1] = 0;
+    // n < 2^38: both fit in 32 bits
+    r.k_full = uint32_t((s.n + r.lo0 - 1) >> sh);
+    r.k_end = uint32_t((s.n + r.lo0 + (P - 1)) >> sh);
     args.chunk_segs[i] = r;
 }
 

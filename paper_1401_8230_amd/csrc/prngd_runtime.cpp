@@ -972,15 +972,24 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     return PRNGD_OK;
 }
 
+// The longest request (planned pairs) the chunk form takes automatically:
+// its repair produces a dirty request again on one wave, about 0.2 us per
+// 128-pair window, so a request of 2^16 pairs costs at most about 100 us.
+constexpr uint64_t kChunkFormMaxPairs = uint64_t(1) << 16;
+
 // Whether a launch of `pairs` planned pairs whose longest segment has
 // `longest` planned pairs takes a speculative fill, and which form.  Automatic
 // choice (x1 uniform on [a0, a] rejects 2 / (a - a0 + 1) of the pairs):
 // speculation pays when some segment is long enough that ordering its
 // tiles across workgroups would cost, and the launch expects few enough
 // rejections that the repair pass has little to redo.  Measured on
-// MI355X: up to 2 expected rejections the holding form is fastest; with
-// more (up to 1024) a single fill is fastest in 128-pair chunks, a batch
-// in the holding form (up to 128); beyond that the ordered kernels win.
+// MI355X: a batch of requests of at most 2^16 pairs that expects at most
+// 256 rejections is fastest in the chunk form (2^16 requests of 2^14
+// outputs: 1.56 ms against 1.62 ms ordered).  A single fill at w = 32 that
+// expects at most 2 rejections is fastest in the holding form; at w < 32
+// (up to 1024) and at w = 32 with more, in 128-pair chunks (w = 24, 2^22
+// outputs: 21 us against 74 us holding).  Other batches take the holding
+// form up to 128 expected rejections; beyond that the ordered kernels win.
 void choose_path(LaunchPlan *lp, const Config &c, uint64_t pairs, uint64_t longest,
                  bool single, uint64_t nseg = 1)
 {
@@ -1001,6 +1010,10 @@ void choose_path(LaunchPlan *lp, const Config &c, uint64_t pairs, uint64_t longe
         lp->chunk = true;
         return;
     }
+    if (lp->tune.path == 0 && chunk_ok && longest <= kChunkFormMaxPairs && expected <= 256.0) {
+        lp->chunk = true;
+        return;
+    }
     if (lp->tune.path == 4 || lp->tune.path == 5) {
         lp->wave = wave_ok;
         hold = 0;
@@ -1009,7 +1022,7 @@ void choose_path(LaunchPlan *lp, const Config &c, uint64_t pairs, uint64_t longe
     } else if (lp->tune.path == 3) {
         hold = 1;
     } else if (longest >= (uint64_t(64) << 12)) {
-        if (expected <= 2.0)
+        if (expected <= 2.0 && (c.fam == FAM_PHILOX32 || !wave_ok))
             hold = 1;
         else if (wave_ok && expected <= 1024.0) {
             lp->wave = true;

@@ -3,7 +3,8 @@ final position, at the sizes and in the launch forms the benchmark times.
 
 * many streams: 2^16 Philox4x32-10 substreams of seed 42, 2^14 outputs
   each (2^30 outputs, 8 GiB), one resident batch replayed twice, as the
-  benchmark steps it;
+  benchmark steps it (the chunk form, chosen automatically) and in the
+  ordered kernels;
 * one Philox stream at w = 32, 2^30 outputs per fill (8 GiB), from the
   stream's start and from an odd (mid-block) start, each followed by a
   second fill that continues the stream;
@@ -38,7 +39,7 @@ def release():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("path", ["auto", "speculative-chunk"])
+@pytest.mark.parametrize("path", ["auto", "ordered"])
 def test_many_streams_every_output_and_counter(path):
     reqs = workloads.many_streams()
     S, n = len(reqs), reqs[0].n

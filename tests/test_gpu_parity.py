@@ -264,7 +264,7 @@ def test_batch_matches_oracle(gen, w, seq_max_tiles):
     look-back kernel in every proportion give the oracle's bytes."""
     from paper_1401_8230_amd import workloads
     note(f"batch {gen} w={w} seq_max_tiles={seq_max_tiles}")
-    prngd.set_tuning(gen, w, seq_max_tiles=seq_max_tiles)
+    prngd.set_tuning(gen, w, seq_max_tiles=seq_max_tiles, path="ordered")
     reqs = workloads.uneven_batch(count=200, lo=1, hi=3e4, rng_seed=w)
     gens = make_handles(reqs, gen, w)
     outs = [torch.empty(r.n, dtype=torch.float64, device=DEV) for r in reqs]
@@ -435,8 +435,10 @@ def test_map_variants_match_oracle(map, gen, w, path):
         g.close()
 
 
-def test_map_variants_in_batches_and_plans():
+@pytest.mark.parametrize("path", ["auto", "ordered"])
+def test_map_variants_in_batches_and_plans(path):
     from paper_1401_8230_amd import workloads
+    prngd.set_tuning("philox", 32, path=path)
     reqs = workloads.uneven_batch(count=40, lo=1, hi=3e4, rng_seed=5)
     for map in ("eq4", "one_minus"):
         gens = make_handles(reqs, "philox", 32)
