@@ -2120,7 +2120,6 @@ __global__ __launch_bounds__(kMrgBlockThreads) void seq_mrg_kernel(LaunchArgs ar
 // records its hint only when it is nonzero, tagged with the launch epoch.
 // ======================================================================
 constexpr uint32_t kChunk = kChunkPairs;
-constexpr uint32_t kChunksPerWave = 2;
 
 // Lanes at or above `first` (0 .. 64) of a wave, as a 64-bit lane mask.
 __device__ __forceinline__ uint64_t lanes_from(uint32_t first)
@@ -2251,71 +2250,6 @@ __device__ __forceinline__ uint32_t chunk_hint(const LaunchArgs &args, uint32_t 
     return (r >> 24) == args.epoch ? uint32_t(r & 0xFFFFFFu) : 0u;
 }
 
-template <uint32_t FAM, uint32_t CPW>
-__global__ __launch_bounds__(256) void spec_wave_kernel(LaunchArgs args)
-{
-    // the wave index is uniform in the wave: say so, so that everything
-    // derived from it (chunk, segment, offsets) lives in scalar registers
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t total = args.total_tiles;
-    const TileStart ts = tile_start<true>(args, 0);
-    const Segment &seg = ts.seg;
-    uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
-    const uint64_t w0 = ts.c0 / kChunk;
-    const uint32_t lo0 = uint32_t(ts.c0 - w0 * kChunk);
-    // the wave's hint source: the list as this wave sees it at its start
-    const uint32_t cnt = __builtin_amdgcn_readfirstlane(
-        __hip_atomic_load(&args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    uint64_t entry = 0;
-    if (cnt != 0 && lane < cnt)
-        entry = __hip_atomic_load(&args.rejlist[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // the workgroup covers 4 CPW consecutive chunks; wave w takes every
-    // fourth of them
-#pragma unroll
-    for (uint32_t i = 0; i < CPW; ++i) {
-        const uint32_t k = (blockIdx.x * CPW + i) * 4u + wave;
-        if (k >= total)
-            break;
-        uint32_t used = 0;
-        if (k > 0) {
-            const uint32_t et = uint32_t(entry >> 32);     // chunk + 1; 0 = none
-            const uint32_t mine = et != 0 && et <= k ? uint32_t(entry) : 0u;
-            if (__ballot(mine != 0)) {
-                used = mine;
-#pragma unroll
-                for (int d = 32; d >= 1; d >>= 1)
-                    used += __shfl_xor(used, d, 64);
-                if (lane == 0)
-                    args.hint64[k] = (args.epoch << 24) | used;
-            }
-        }
-        const uint64_t win = w0 + k;
-        const uint32_t lo_off = k == 0 ? lo0 : 0u;
-        const uint64_t excl = (k == 0 ? 0 : uint64_t(k) * kChunk - lo0) - used;
-        const uint32_t kept =
-            WaveChunk<FAM>::run(args, seg, win, lo_off, excl, next_counter,
-                                uniform_lt(excl, seg.n), lo_off == 0 && chunk_fits(excl, seg.n));
-        const uint32_t rej = (kChunk - lo_off) - kept;
-        if (rej != 0 && lane == 0) {
-            const uint32_t slot = __hip_atomic_fetch_add(&args.spec->count, 1u, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-            if (slot < total)
-                __hip_atomic_store(&args.rejlist[slot], (uint64_t(k) + 1u) << 32 | rej,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            else
-                __hip_atomic_fetch_or(args.error, kErrSpecList, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_SYSTEM);
-        }
-        if (k == total - 1) {
-            uint64_t running = excl + kept;
-            for (uint64_t w2 = win + 1; uniform_lt(running, seg.n); ++w2)
-                running += WaveChunk<FAM>::run(args, seg, w2, 0u, running, next_counter, true,
-                                               chunk_fits(running, seg.n));
-        }
-    }
-}
-
 // ======================================================================
 // Chunk-speculative fill of a batch (rare rejections): the one-shot grid of
 // the chunks of every segment of the batch, one chunk per wave, a chunk
@@ -2434,24 +2368,38 @@ struct BatchChunk {
     }
 
     // Chunk `ch` produced exactly from chunk offset lo_off on, at segment
-    // offset excl, window by window; returns its accepted pairs, or
-    // P - lo_off once output n - 1 has been stored (nothing after it
-    // matters then).
+    // offset excl, window by window; returns its accepted pairs.  Windows
+    // at or past output n are counted without storing when COUNT_ALL;
+    // otherwise the count stops there and P - lo_off is returned (nothing
+    // after output n - 1 matters then).
+    template <bool COUNT_ALL>
     __device__ __forceinline__ static uint32_t run_exact(const LaunchArgs &args,
                                                          const Segment &seg, uint64_t ch,
                                                          uint32_t lo_off, uint64_t excl,
                                                          uint64_t *next_counter)
     {
         uint64_t running = excl;
+        uint32_t kept = 0;
 #pragma unroll 1
         for (uint32_t j = lo_off / kChunk; j < NWIN; ++j) {
-            if (!uniform_lt(running, seg.n))
-                return P - lo_off;
             const uint32_t lo_j = j == lo_off / kChunk ? lo_off % kChunk : 0u;
-            running += WaveChunk<FAM>::run(args, seg, ch * NWIN + j, lo_j, running, next_counter,
-                                           true, lo_j == 0 && chunk_fits(running, seg.n));
+            const bool store = uniform_lt(running, seg.n);
+            if (!store && !COUNT_ALL)
+                return P - lo_off;
+            const uint32_t kj =
+                WaveChunk<FAM>::run(args, seg, ch * NWIN + j, lo_j, running, next_counter, store,
+                                    store && lo_j == 0 && chunk_fits(running, seg.n));
+            running += kj;
+            kept += kj;
         }
-        return uniform_lt(running, seg.n) ? uint32_t(running - excl) : P - lo_off;
+        return COUNT_ALL || uniform_lt(running, seg.n) ? kept : P - lo_off;
+    }
+
+    // Whether a chunk at wave-uniform offset excl holds P outputs below
+    // n - 1.
+    __device__ __forceinline__ static bool fits(uint64_t excl, uint64_t n)
+    {
+        return uniform_lt(excl + P, n);
     }
 };
 
@@ -2499,7 +2447,8 @@ __global__ __launch_bounds__(256) void chunk_batch_kernel(LaunchArgs args)
     if (lo_off == 0 && k < r.k_full)
         clean = C::run_clean(args, seg, ch, excl);
     else
-        clean = C::run_exact(args, seg, ch, lo_off, excl, r.next_counter) == P - lo_off;
+        clean = C::template run_exact<false>(args, seg, ch, lo_off, excl, r.next_counter) ==
+                P - lo_off;
     if (!clean) {
         if (lane == 0) {
             const uint32_t old = __hip_atomic_fetch_max(&args.first_dirty[si], ~k,
@@ -2517,7 +2466,7 @@ __global__ __launch_bounds__(256) void chunk_batch_kernel(LaunchArgs args)
         // outputs (a dirty segment is left to the repair)
         uint64_t running = excl + (P - lo_off);
         for (uint64_t c2 = ch + 1; uniform_lt(running, r.n); ++c2)
-            running += C::run_exact(args, seg, c2, 0u, running, r.next_counter);
+            running += C::template run_exact<false>(args, seg, c2, 0u, running, r.next_counter);
     }
 }
 
@@ -2537,8 +2486,8 @@ __global__ __launch_bounds__(64) void chunk_repair_kernel(LaunchArgs args)
         // no chunk before k0 rejected a pair: k0's true offset is the plain one
         uint64_t running = k0 == 0 ? 0 : uint64_t(k0) * C::P - r.lo0;
         for (uint64_t ch = r.w0 + k0; uniform_lt(running, r.n); ++ch)
-            running += C::run_exact(args, seg, ch, ch == r.w0 ? r.lo0 : 0u, running,
-                                    r.next_counter);
+            running += C::template run_exact<false>(args, seg, ch, ch == r.w0 ? r.lo0 : 0u,
+                                                    running, r.next_counter);
         if (lane == 0)
             args.first_dirty[si] = 0u;
     }
@@ -2551,8 +2500,91 @@ __global__ __launch_bounds__(64) void chunk_repair_kernel(LaunchArgs args)
     }
 }
 
+// ======================================================================
+// Wave-granular speculative fill of one segment: the one-shot grid of its
+// chunks (NWIN windows of 128 pairs), one per wave.  A wave reads the
+// rejection list once at its start; chunk k stores at the offset that the
+// rejections published so far by chunks before it give (its hint,
+// recorded when nonzero, tagged with the launch epoch).  A chunk whose
+// outputs all lie below output n - 1 stores each window as it is
+// generated and checks for rejections afterwards; one that rejected then
+// produces itself exactly at the same offset.  Every chunk publishes its
+// rejected pairs (chunk + 1, count), also past output n, so that the
+// repair pass can compute every chunk's true offset from the complete list.
+// ======================================================================
+template <uint32_t FAM, uint32_t NWIN>
+__global__ __launch_bounds__(256) void spec_wave_kernel(LaunchArgs args)
+{
+    using C = BatchChunk<FAM, NWIN>;
+    constexpr uint32_t P = C::P;
+    const uint32_t lane = threadIdx.x & 63u;
+    // the wave index is uniform in the wave: say so, so that everything
+    // derived from it (chunk, offsets) lives in scalar registers
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t total = args.total_tiles;
+    const uint32_t k = blockIdx.x * 4u + wave;
+    if (k >= total)
+        return;
+    const TileStart ts = tile_start<true>(args, 0);
+    const Segment &seg = ts.seg;
+    uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
+    const uint64_t w0 = ts.c0 / P;
+    const uint32_t lo0 = uint32_t(ts.c0 % P);
+    // the hint: the list as this wave sees it at its start
+    uint32_t used = 0;
+    if (k > 0) {
+        const uint32_t cnt = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (cnt != 0) {
+            uint64_t entry = 0;
+            if (lane < cnt)
+                entry = __hip_atomic_load(&args.rejlist[lane], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t et = uint32_t(entry >> 32);     // chunk + 1; 0 = none
+            const uint32_t mine = et != 0 && et <= k ? uint32_t(entry) : 0u;
+            if (__ballot(mine != 0)) {
+                used = mine;
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1)
+                    used += __shfl_xor(used, d, 64);
+                used = __builtin_amdgcn_readfirstlane(used);
+                if (lane == 0)
+                    args.hint64[k] = (args.epoch << 24) | used;
+            }
+        }
+    }
+    const uint64_t ch = w0 + k;
+    const uint32_t lo_off = k == 0 ? lo0 : 0u;
+    const uint64_t excl = (k == 0 ? 0 : uint64_t(k) * P - lo0) - used;
+    uint32_t kept;
+    if (lo_off == 0 && C::fits(excl, seg.n))
+        kept = C::run_clean(args, seg, ch, excl)
+                   ? P
+                   : C::template run_exact<true>(args, seg, ch, 0u, excl, next_counter);
+    else
+        kept = C::template run_exact<true>(args, seg, ch, lo_off, excl, next_counter);
+    const uint32_t rej = (P - lo_off) - kept;
+    if (rej != 0 && lane == 0) {
+        const uint32_t slot = __hip_atomic_fetch_add(&args.spec->count, 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        if (slot < total)
+            __hip_atomic_store(&args.rejlist[slot], (uint64_t(k) + 1u) << 32 | rej,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            __hip_atomic_fetch_or(args.error, kErrSpecList, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    // the last chunk takes every further chunk until n outputs
+    if (k == total - 1) {
+        uint64_t running = excl + kept;
+        for (uint64_t c2 = ch + 1; uniform_lt(running, seg.n); ++c2)
+            running += C::template run_exact<false>(args, seg, c2, 0u, running, next_counter);
+    }
+}
+
 // Whether chunk g (of the single segment) has to be produced again, and
 // at which true offset: the rules of needs_redo with chunk hints.
+template <uint32_t P>
 __device__ __forceinline__ bool chunk_needs_redo(const LaunchArgs &args, const uint64_t *list,
                                                  uint32_t cnt, uint32_t g, uint32_t lo0,
                                                  uint64_t *true_off)
@@ -2561,13 +2593,13 @@ __device__ __forceinline__ bool chunk_needs_redo(const LaunchArgs &args, const u
     const TileFacts f = tile_facts(list, cnt, 0u, g);
     if (!f.after_dirty)
         return false;
-    const uint64_t off = uint64_t(g) * kChunk - lo0 - f.P;   // g >= 1 here
+    const uint64_t off = uint64_t(g) * P - lo0 - f.P;   // g >= 1 here
     if (off >= seg.n)
         return false;
     *true_off = off;
     if (chunk_hint(args, g) != f.P)
         return true;
-    if (off + (kChunk - f.rej) >= seg.n || g == args.total_tiles - 1)
+    if (off + (P - f.rej) >= seg.n || g == args.total_tiles - 1)
         return true;
     uint64_t gap = 0;
     for (uint32_t v = g - 1;; --v) {
@@ -2577,16 +2609,18 @@ __device__ __forceinline__ bool chunk_needs_redo(const LaunchArgs &args, const u
             return true;
         if (!fv.after_dirty || v == 0)
             break;
-        gap += uint64_t(kChunk) - (v == 0 ? lo0 : 0u) - fv.rej;
-        if (gap >= uint64_t(f.P) + kChunk)
+        gap += uint64_t(P) - (v == 0 ? lo0 : 0u) - fv.rej;
+        if (gap >= uint64_t(f.P) + P)
             break;
     }
     return false;
 }
 
-template <uint32_t FAM>
+template <uint32_t FAM, uint32_t NWIN>
 __global__ __launch_bounds__(256) void spec_wave_repair_kernel(LaunchArgs args)
 {
+    using C = BatchChunk<FAM, NWIN>;
+    constexpr uint32_t P = C::P;
     __shared__ uint64_t s_list[kRepairCache];
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     const uint32_t cnt0 =
@@ -2608,8 +2642,8 @@ __global__ __launch_bounds__(256) void spec_wave_repair_kernel(LaunchArgs args)
     const uint32_t par = (seg.parity ^ flip) & 1u;
     const uint64_t c0 = load_start(seg, par);
     uint64_t *next_counter = seg.counter + (par ^ 1u);
-    const uint64_t w0 = c0 / kChunk;
-    const uint32_t lo0 = uint32_t(c0 - w0 * kChunk);
+    const uint64_t w0 = c0 / P;
+    const uint32_t lo0 = uint32_t(c0 - w0 * P);
     // each wave checks 64 chunks per pass, one per lane, spread over waves
     const uint64_t wid = blockIdx.x * 4u + (tid >> 6);
     const uint64_t W = uint64_t(gridDim.x) * 4u;
@@ -2617,7 +2651,7 @@ __global__ __launch_bounds__(256) void spec_wave_repair_kernel(LaunchArgs args)
         const uint64_t g64 = (p * 64 + lane) * W + wid;
         uint64_t off = 0;
         const bool redo = g64 < total && g64 > 0 &&
-                          chunk_needs_redo(args, list, cnt, uint32_t(g64), lo0, &off);
+                          chunk_needs_redo<P>(args, list, cnt, uint32_t(g64), lo0, &off);
         uint64_t todo = __ballot(redo);
         while (todo) {
             const uint32_t l = uint32_t(__builtin_ctzll(todo));
@@ -2625,12 +2659,12 @@ __global__ __launch_bounds__(256) void spec_wave_repair_kernel(LaunchArgs args)
             const uint32_t g = uint32_t(__shfl(uint32_t(g64), l, 64));
             const uint64_t o = uint64_t(uint32_t(__shfl(uint32_t(off), l, 64))) |
                                uint64_t(uint32_t(__shfl(uint32_t(off >> 32), l, 64))) << 32;
-            uint64_t running = o + WaveChunk<FAM>::run(args, seg, w0 + g, 0u, o, next_counter,
-                                                       true, chunk_fits(o, seg.n));
+            uint64_t running =
+                o + C::template run_exact<false>(args, seg, w0 + g, 0u, o, next_counter);
             if (g == total - 1)
-                for (uint64_t w2 = w0 + g + 1; uniform_lt(running, seg.n); ++w2)
-                    running += WaveChunk<FAM>::run(args, seg, w2, 0u, running, next_counter, true,
-                                                   chunk_fits(running, seg.n));
+                for (uint64_t c2 = w0 + g + 1; uniform_lt(running, seg.n); ++c2)
+                    running += C::template run_exact<false>(args, seg, c2, 0u, running,
+                                                            next_counter);
         }
     }
     __shared__ bool s_last;

@@ -161,7 +161,7 @@ template <uint32_t MAPF>
 const void *philox_spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair,
                                    bool single, bool hold);
 template <uint32_t MAPF>
-const void *philox_wave_kernel_for(uint32_t fam, bool repair);
+const void *philox_wave_kernel_for(uint32_t fam, bool repair, uint32_t windows);
 template <uint32_t MAPF>
 const void *mrg_fill_kernel_for(uint32_t fam, uint32_t ppl, bool seq);
 template <uint32_t MAPF>

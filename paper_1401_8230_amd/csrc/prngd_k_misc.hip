@@ -114,9 +114,11 @@ const void *fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool s
 
 // The wave-granular speculative fill of a single segment (or its repair)
 // for a Philox-family generator; null for other families.
-const void *spec_wave_kernel_for(uint32_t fam, bool repair)
+const void *spec_wave_kernel_for(uint32_t fam, bool repair, uint32_t windows)
 {
-    return by_map(fam, [&](auto m) { return philox_wave_kernel_for<decltype(m)::value>(fam, repair); });
+    return by_map(fam, [&](auto m) {
+        return philox_wave_kernel_for<decltype(m)::value>(fam, repair, windows);
+    });
 }
 
 // The chunk-speculative batch fill (256 threads, chunks of `windows`

@@ -62,23 +62,37 @@ const void *philox_spec_kernel_for<PRNGD_MAPF>(uint32_t fam, uint32_t threads, u
     return nullptr;
 }
 
-// The wave-granular speculative fill of a single segment (or its repair)
-// for a Philox-family generator; null for other families.
-template <>
-const void *philox_wave_kernel_for<PRNGD_MAPF>(uint32_t fam, bool repair)
+// The wave-granular speculative fill of a single segment in chunks of
+// `windows` 128-pair windows (1, 2 or 4), or its repair, for a
+// Philox-family generator; null for other families and chunk sizes.
+template <uint32_t F>
+const void *wave_for(uint32_t windows, bool repair)
 {
-    constexpr uint32_t P32 = FAM_PHILOX32 | PRNGD_MAPF, P = FAM_PHILOX | PRNGD_MAPF,
-                       EN = FAM_ENUM | PRNGD_MAPF;
+    switch (windows) {
+    case 1:
+        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<F, 1>)
+                      : reinterpret_cast<const void *>(&spec_wave_kernel<F, 1>);
+    case 2:
+        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<F, 2>)
+                      : reinterpret_cast<const void *>(&spec_wave_kernel<F, 2>);
+    case 4:
+        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<F, 4>)
+                      : reinterpret_cast<const void *>(&spec_wave_kernel<F, 4>);
+    default:
+        return nullptr;
+    }
+}
+
+template <>
+const void *philox_wave_kernel_for<PRNGD_MAPF>(uint32_t fam, bool repair, uint32_t windows)
+{
     switch (fam_base(fam)) {
     case FAM_PHILOX32:
-        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<P32>)
-                      : reinterpret_cast<const void *>(&spec_wave_kernel<P32, kChunksPerWave>);
+        return wave_for<FAM_PHILOX32 | PRNGD_MAPF>(windows, repair);
     case FAM_PHILOX:
-        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<P>)
-                      : reinterpret_cast<const void *>(&spec_wave_kernel<P, kChunksPerWave>);
+        return wave_for<FAM_PHILOX | PRNGD_MAPF>(windows, repair);
     case FAM_ENUM:
-        return repair ? reinterpret_cast<const void *>(&spec_wave_repair_kernel<EN>)
-                      : reinterpret_cast<const void *>(&spec_wave_kernel<EN, kChunksPerWave>);
+        return wave_for<FAM_ENUM | PRNGD_MAPF>(windows, repair);
     default:
         return nullptr;
     }

@@ -22,7 +22,7 @@ namespace prngd {
 const void *fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool seq);
 const void *spec_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool repair,
                             bool single, bool hold);
-const void *spec_wave_kernel_for(uint32_t fam, bool repair);
+const void *spec_wave_kernel_for(uint32_t fam, bool repair, uint32_t windows);
 const void *single_kernel_for(uint32_t fam);
 const void *spec_words_kernel_for(uint32_t fam, bool repair);
 const void *triple_kernel_for(uint32_t fam, bool seq);
@@ -553,8 +553,10 @@ bool ppl_is_default(uint32_t fam, uint32_t w)
 }
 
 // Default pairs per lane of a single Philox fill on a tile-speculative
-// path: 2048-pair tiles measured fastest on MI355X there (batches keep 16).
+// path: 2048-pair tiles measured fastest on MI355X there (batches keep 16);
+// on the wave-granular path, chunks of one 128-pair window.
 constexpr uint32_t kSingleSpecPpl = 8;
+constexpr uint32_t kSingleWavePpl = 2;
 
 // Segments of a batch with at most this many tiles are produced whole by
 // one workgroup (segment-sequential kernel); longer ones are spread over
@@ -925,8 +927,7 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
                             : nullptr;
     lp->spec_kernel = nullptr;
     lp->spec_single_kernel = nullptr;
-    lp->wave_kernel = two ? spec_wave_kernel_for(kfam, false) : nullptr;
-    lp->wave_repair_kernel = two ? spec_wave_kernel_for(kfam, true) : nullptr;
+
     lp->words_kernel = two ? spec_words_kernel_for(kfam, false) : nullptr;
     lp->words_repair_kernel = two ? spec_words_kernel_for(kfam, true) : nullptr;
     // the chunk form: a wave takes one chunk of pairs_per_lane / 2 windows
@@ -937,6 +938,8 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     lp->chunk_pairs = kChunkPairs * lp->chunk_windows;
     lp->chunk_kernel = two ? chunk_kernel_for(kfam, false, lp->chunk_windows) : nullptr;
     lp->chunk_repair_kernel = two ? chunk_kernel_for(kfam, true, lp->chunk_windows) : nullptr;
+    lp->wave_kernel = two ? spec_wave_kernel_for(kfam, false, lp->chunk_windows) : nullptr;
+    lp->wave_repair_kernel = two ? spec_wave_kernel_for(kfam, true, lp->chunk_windows) : nullptr;
     lp->wave = false;
     lp->chunk = false;
     lp->zero_word = d->zero_word;
@@ -1120,11 +1123,12 @@ prngd_status_t launch_spec_words(DeviceInfo *d, const LaunchPlan &lp, Workspace 
 }
 
 // Enqueue the wave-granular speculative fill of one segment (args.seg0)
-// and its repair.
+// and its repair: one chunk of lp.chunk_pairs pairs per wave.
 prngd_status_t launch_spec_wave(DeviceInfo *d, const LaunchPlan &lp, Workspace *ws,
                                 LaunchArgs args, hipStream_t s)
 {
-    const uint64_t chunks = std::max<uint64_t>(1, (args.seg0.planned + 127) / 128);
+    const uint64_t chunks =
+        std::max<uint64_t>(1, (args.seg0.planned + lp.chunk_pairs - 1) / lp.chunk_pairs);
     if (chunks > kMaxTiles)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "fill too large for the wave-granular form");
     prngd_status_t st;
@@ -1140,9 +1144,8 @@ prngd_status_t launch_spec_wave(DeviceInfo *d, const LaunchPlan &lp, Workspace *
     args.total_tiles = uint32_t(chunks);
     if (!args.flip)
         args.flip = lp.zero_word;
-    // one-shot grid: a workgroup covers 4 waves x 2 chunks
-    const uint64_t per_wg = 4 * 2;
-    const uint64_t grid = (chunks + per_wg - 1) / per_wg;
+    // one-shot grid: a workgroup covers 4 waves of one chunk each
+    const uint64_t grid = (chunks + 3) / 4;
     if (grid > 0xFFFFFFFFull)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "fill too large for the wave-granular form");
     HIP_TRY(launch_fill(lp.wave_kernel, uint32_t(grid), 256, args, s));
@@ -1670,13 +1673,16 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *strea
         args.total_tiles = uint32_t(ntiles);
         args.ctl = ws->ctl;
         choose_path(&lp, h->cfg, args.seg0.planned, args.seg0.planned, true);
-        if (pass == 1 || words || !lp.spec || lp.wave || !philox_family(h->cfg.fam) ||
+        if (pass == 1 || words || !lp.spec || !philox_family(h->cfg.fam) ||
             !ppl_is_default(h->cfg.fam, h->cfg.w))
             break;
-        // a tile-speculative single Philox fill: plan again in its own tile size
+        // a speculative single Philox fill: plan again in its own tile size
+        // (the wave-granular form in chunks of one window)
         args = LaunchArgs{};
+        const bool wave = lp.wave;
         lp = LaunchPlan{};
-        if ((st = plan_launch(d, h->cfg, &args, &lp, kSingleSpecPpl)) != PRNGD_OK)
+        if ((st = plan_launch(d, h->cfg, &args, &lp, wave ? kSingleWavePpl : kSingleSpecPpl)) !=
+            PRNGD_OK)
             return st;
     }
     if ((st = order_after(h, s)) != PRNGD_OK)

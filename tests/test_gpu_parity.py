@@ -338,6 +338,17 @@ def test_speculative_fill_at_any_rejection_rate(gen, w, ppl, path):
         parity(gen, w, seed=19, counter=counter, n=n)
 
 
+@pytest.mark.parametrize("w", [3, 8, 24, 32])
+@pytest.mark.parametrize("ppl", [2, 4, 8])
+def test_wave_form_chunk_sizes(w, ppl):
+    """The wave-granular single fill in chunks of ppl / 2 windows of 128
+    pairs: store-first clean chunks, exact chunks, published rejections,
+    hints and the repair pass."""
+    prngd.set_tuning("philox", w, path="speculative-wave", pairs_per_lane=ppl)
+    for counter, n in [(0, 1), (7, 4097), (3, 100003), (4095, 300001), (511, 1 << 20)]:
+        parity("philox", w, seed=31, counter=counter, n=n)
+
+
 @pytest.mark.parametrize("path", ["speculative", "speculative-hold", "speculative-wave"])
 def test_speculative_fill_with_a_long_rejection_list(path):
     # more dirty tiles than the repair caches in LDS
