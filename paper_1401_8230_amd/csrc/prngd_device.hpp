@@ -2470,29 +2470,65 @@ __global__ __launch_bounds__(256) void chunk_batch_kernel(LaunchArgs args)
     }
 }
 
-// One wave per workgroup; workgroup b repairs dirty segments b, b + G, ...
+// The repair of the chunk form: workgroup b (16 waves) produces dirty
+// segments b, b + G, ... again from their first dirty chunk, 16 windows of
+// 128 pairs per step: each wave counts its window's accepted pairs, the
+// counts meet in LDS (double-buffered, one barrier a step), and each wave
+// stores its window at the offset the counts before it give.
+constexpr uint32_t kRepairWaves = 16;
+
 template <uint32_t FAM, uint32_t NWIN>
-__global__ __launch_bounds__(64) void chunk_repair_kernel(LaunchArgs args)
+__global__ __launch_bounds__(64 * kRepairWaves) void chunk_repair_kernel(LaunchArgs args)
 {
     using C = BatchChunk<FAM, NWIN>;
+    __shared__ uint32_t s_kept[2][kRepairWaves];
     const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t cnt = __builtin_amdgcn_readfirstlane(
         __hip_atomic_load(&args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    uint32_t phase = 0;
     for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
         const uint32_t si = __builtin_amdgcn_readfirstlane(args.dirty_list[i]);
         const uint32_t k0 = ~__builtin_amdgcn_readfirstlane(args.first_dirty[si]);
         const ChunkSeg r = load_chunk_seg(args.chunk_segs, si);
         const Segment seg = chunk_segment_view(r);
-        // no chunk before k0 rejected a pair: k0's true offset is the plain one
+        // no chunk before k0 rejected a pair: k0's true offset is the plain
+        // one; the first window to produce is the one that holds it
         uint64_t running = k0 == 0 ? 0 : uint64_t(k0) * C::P - r.lo0;
-        for (uint64_t ch = r.w0 + k0; uniform_lt(running, r.n); ++ch)
-            running += C::template run_exact<false>(args, seg, ch, ch == r.w0 ? r.lo0 : 0u,
-                                                    running, r.next_counter);
-        if (lane == 0)
+        const uint32_t lo = k0 == 0 ? r.lo0 : 0u;
+        uint64_t win = (r.w0 + k0) * NWIN + lo / kChunk;
+        uint32_t lo_first = lo % kChunk;
+        while (uniform_lt(running, r.n)) {
+            const uint64_t w = win + wave;
+            const uint32_t lo_w = wave == 0 ? lo_first : 0u;
+            const uint32_t kept = WaveChunk<FAM>::run(args, seg, w, lo_w, 0, nullptr, false, false);
+            if (lane == 0)
+                s_kept[phase][wave] = kept;
+            __syncthreads();
+            uint32_t before = 0, total = 0;
+#pragma unroll
+            for (uint32_t v = 0; v < kRepairWaves; ++v) {
+                const uint32_t t = s_kept[phase][v];
+                before += v < wave ? t : 0u;
+                total += t;
+            }
+            before = uniform_u32(before);
+            total = uniform_u32(total);
+            const uint64_t off = running + before;
+            if (uniform_lt(off, r.n))
+                WaveChunk<FAM>::run(args, seg, w, lo_w, off, r.next_counter, true,
+                                    lo_w == 0 && chunk_fits(off, r.n));
+            running += total;
+            win += kRepairWaves;
+            lo_first = 0;
+            phase ^= 1u;
+        }
+        if (threadIdx.x == 0)
             args.first_dirty[si] = 0u;
     }
     // the last workgroup out empties the list for the next launch
-    if (lane == 0 &&
+    __syncthreads();
+    if (threadIdx.x == 0 &&
         __hip_atomic_fetch_add(&args.spec->done, 1u, __ATOMIC_ACQ_REL,
                                __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
         __hip_atomic_store(&args.spec->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -1155,11 +1155,13 @@ prngd_status_t launch_spec_wave(DeviceInfo *d, const LaunchPlan &lp, Workspace *
     return PRNGD_OK;
 }
 
-// Workgroups (of one wave) of the chunk form's repair: each takes dirty
+// Workgroups (of 16 waves) of the chunk form's repair: each takes dirty
 // segments b, b + G, ...; the launch never knows how many there are.
+constexpr uint32_t kChunkRepairThreads = 1024;
+
 uint32_t chunk_repair_grid(DeviceInfo *d, uint64_t nseg)
 {
-    return uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(nseg, 4 * uint64_t(d->cus))));
+    return uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(nseg, 2 * uint64_t(d->cus))));
 }
 
 // Workgroups of the chunk form's one-shot grid over `chunks` chunks: 4
@@ -1207,7 +1209,8 @@ prngd_status_t launch_chunk(DeviceInfo *d, const LaunchPlan &lp, Workspace *ws,
     const LaunchArgs args = chunk_args(lp, ws, in, chunks_per_seg);
     HIP_TRY(launch_fill(chunk_prep_kernel_ptr(), (args.nseg + 255) / 256, 256, args, s));
     HIP_TRY(launch_fill(lp.chunk_kernel, chunk_grid(args.total_tiles), 256, args, s));
-    HIP_TRY(launch_fill(lp.chunk_repair_kernel, chunk_repair_grid(d, args.nseg), 64, args, s));
+    HIP_TRY(launch_fill(lp.chunk_repair_kernel, chunk_repair_grid(d, args.nseg),
+                        kChunkRepairThreads, args, s));
     return PRNGD_OK;
 }
 
@@ -1988,7 +1991,7 @@ prngd_status_t prngd_plan_create(const prngd_request_t *reqs, uint32_t count,
         HIP_TRY(hipGraphAddKernelNode(&cnode, p->graph, &pnode, 1, &kp));
         kp.func = const_cast<void *>(lp.chunk_repair_kernel);
         kp.gridDim = dim3(chunk_repair_grid(d, p->lb_args.nseg));
-        kp.blockDim = dim3(64);
+        kp.blockDim = dim3(kChunkRepairThreads);
         HIP_TRY(hipGraphAddKernelNode(&rnode, p->graph, &cnode, 1, &kp));
         fills.push_back(rnode);
     } else if (!bp.lb.empty() && lp.spec) {
