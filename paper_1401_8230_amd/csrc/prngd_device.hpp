@@ -2561,32 +2561,29 @@ __global__ __launch_bounds__(256) void spec_wave_kernel(LaunchArgs args)
     const uint32_t k = blockIdx.x * 4u + wave;
     if (k >= total)
         return;
+    // The hint: the first 64 list entries as this wave sees them at its
+    // start.  Slots not yet written read 0; the list holds at least 64
+    // slots.  The load is issued first so that it overlaps the position
+    // loads.
+    const uint64_t entry =
+        __hip_atomic_load(&args.rejlist[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const TileStart ts = tile_start<true>(args, 0);
     const Segment &seg = ts.seg;
     uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
     const uint64_t w0 = ts.c0 / P;
     const uint32_t lo0 = uint32_t(ts.c0 % P);
-    // the hint: the list as this wave sees it at its start
     uint32_t used = 0;
-    if (k > 0) {
-        const uint32_t cnt = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_load(&args.spec->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        if (cnt != 0) {
-            uint64_t entry = 0;
-            if (lane < cnt)
-                entry = __hip_atomic_load(&args.rejlist[lane], __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t et = uint32_t(entry >> 32);     // chunk + 1; 0 = none
-            const uint32_t mine = et != 0 && et <= k ? uint32_t(entry) : 0u;
-            if (__ballot(mine != 0)) {
-                used = mine;
+    {
+        const uint32_t et = uint32_t(entry >> 32);     // chunk + 1; 0 = none
+        const uint32_t mine = et != 0 && et <= k ? uint32_t(entry) : 0u;
+        if (__builtin_amdgcn_ballot_w64(mine != 0) != 0) {
+            used = mine;
 #pragma unroll
-                for (int d = 32; d >= 1; d >>= 1)
-                    used += __shfl_xor(used, d, 64);
-                used = __builtin_amdgcn_readfirstlane(used);
-                if (lane == 0)
-                    args.hint64[k] = (args.epoch << 24) | used;
-            }
+            for (int d = 32; d >= 1; d >>= 1)
+                used += __shfl_xor(used, d, 64);
+            used = __builtin_amdgcn_readfirstlane(used);
+            if (lane == 0)
+                args.hint64[k] = (args.epoch << 24) | used;
         }
     }
     const uint64_t ch = w0 + k;
