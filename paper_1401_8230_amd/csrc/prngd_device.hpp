@@ -2526,13 +2526,16 @@ __global__ __launch_bounds__(64 * kRepairWaves) void chunk_repair_kernel(LaunchA
         if (threadIdx.x == 0)
             args.first_dirty[si] = 0u;
     }
-    // the last workgroup out empties the list for the next launch
+    // the last workgroup out empties the list for the next launch and, in a
+    // resident plan, flips the replay parity (the plan's last step)
     __syncthreads();
     if (threadIdx.x == 0 &&
         __hip_atomic_fetch_add(&args.spec->done, 1u, __ATOMIC_ACQ_REL,
                                __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
         __hip_atomic_store(&args.spec->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&args.spec->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (args.toggle)
+            *args.toggle ^= 1u;
     }
 }
 

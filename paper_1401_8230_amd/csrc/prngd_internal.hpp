@@ -147,6 +147,7 @@ struct LaunchArgs {
     uint32_t cps_magic;       // c / chunks_per_seg as (t + ((c - t) >> 1)) >> cps_shift,
     uint32_t cps_shift;       // t = mulhi(c, cps_magic) (chunks_per_seg >= 2)
     uint32_t chunk_shift;     // log2 of the pairs per chunk
+    uint32_t *toggle;         // plan replay parity the chunk repair flips last, or null
 };
 
 constexpr uint32_t kMaxTiles = 0xFFFFFFF0u;

@@ -871,6 +871,7 @@ struct LaunchPlan {
     const void *chunk_repair_kernel;
     bool wave;                // single fills take the wave-granular form
     bool chunk;               // batches take the chunk-speculative form
+    double expected_rejections;  // of the launch, as choose_path estimated
     uint32_t chunk_windows;   // its 128-pair windows per chunk (1, 2, 4)
     uint32_t chunk_pairs;     // its pairs per chunk
     uint32_t *zero_word;
@@ -942,6 +943,7 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     lp->wave_repair_kernel = two ? spec_wave_kernel_for(kfam, true, lp->chunk_windows) : nullptr;
     lp->wave = false;
     lp->chunk = false;
+    lp->expected_rejections = 0.0;
     lp->zero_word = d->zero_word;
     lp->spec = false;                  // decided per launch by choose_path
     args->store_mode = lp->tune.store_mode;
@@ -1003,6 +1005,7 @@ void choose_path(LaunchPlan *lp, const Config &c, uint64_t pairs, uint64_t longe
         return;
     const double rho = 2.0 / double(c.a - c.a0 + 1);
     const double expected = double(pairs) * rho;
+    lp->expected_rejections = expected;
     const bool wave_ok = single && lp->wave_kernel && lp->wave_repair_kernel;
     // the chunk form's one-shot grid: 4 chunks per workgroup of 256 threads,
     // at most 2^32 - 1 threads; a segment adds at most one chunk
@@ -1159,9 +1162,13 @@ prngd_status_t launch_spec_wave(DeviceInfo *d, const LaunchPlan &lp, Workspace *
 // segments b, b + G, ...; the launch never knows how many there are.
 constexpr uint32_t kChunkRepairThreads = 1024;
 
-uint32_t chunk_repair_grid(DeviceInfo *d, uint64_t nseg)
+uint32_t chunk_repair_grid(DeviceInfo *d, uint64_t nseg, double expected)
 {
-    return uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(nseg, 2 * uint64_t(d->cus))));
+    // sized to the dirty requests expected (a launch of idle workgroups
+    // costs), at least 8, at most two per CU
+    const double want = std::max(8.0, std::ceil(4.0 * expected));
+    const uint64_t g = std::min<uint64_t>(2 * uint64_t(d->cus), uint64_t(want));
+    return uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(nseg, g)));
 }
 
 // Workgroups of the chunk form's one-shot grid over `chunks` chunks: 4
@@ -1209,7 +1216,8 @@ prngd_status_t launch_chunk(DeviceInfo *d, const LaunchPlan &lp, Workspace *ws,
     const LaunchArgs args = chunk_args(lp, ws, in, chunks_per_seg);
     HIP_TRY(launch_fill(chunk_prep_kernel_ptr(), (args.nseg + 255) / 256, 256, args, s));
     HIP_TRY(launch_fill(lp.chunk_kernel, chunk_grid(args.total_tiles), 256, args, s));
-    HIP_TRY(launch_fill(lp.chunk_repair_kernel, chunk_repair_grid(d, args.nseg),
+    HIP_TRY(launch_fill(lp.chunk_repair_kernel,
+                        chunk_repair_grid(d, args.nseg, lp.expected_rejections),
                         kChunkRepairThreads, args, s));
     return PRNGD_OK;
 }
@@ -1978,6 +1986,7 @@ prngd_status_t prngd_plan_create(const prngd_request_t *reqs, uint32_t count,
         p->lb_args.nseg = uint32_t(bp.lb.size());
         p->lb_args.total_tiles = uint32_t(bp.lb_tiles);
         p->lb_args = chunk_args(lp, &p->ws, p->lb_args, bp.chunks_per_seg);
+        p->lb_args.toggle = p->flip;           // the repair flips the parity last
         hipKernelNodeParams kp{};
         void *params[] = {&p->lb_args};
         kp.func = const_cast<void *>(chunk_prep_kernel_ptr());
@@ -1990,7 +1999,7 @@ prngd_status_t prngd_plan_create(const prngd_request_t *reqs, uint32_t count,
         kp.gridDim = dim3(chunk_grid(bp.lb_tiles));
         HIP_TRY(hipGraphAddKernelNode(&cnode, p->graph, &pnode, 1, &kp));
         kp.func = const_cast<void *>(lp.chunk_repair_kernel);
-        kp.gridDim = dim3(chunk_repair_grid(d, p->lb_args.nseg));
+        kp.gridDim = dim3(chunk_repair_grid(d, p->lb_args.nseg, lp.expected_rejections));
         kp.blockDim = dim3(kChunkRepairThreads);
         HIP_TRY(hipGraphAddKernelNode(&rnode, p->graph, &cnode, 1, &kp));
         fills.push_back(rnode);
@@ -2033,7 +2042,7 @@ prngd_status_t prngd_plan_create(const prngd_request_t *reqs, uint32_t count,
         HIP_TRY(hipGraphAddKernelNode(&node, p->graph, nullptr, 0, &kp));
         fills.push_back(node);
     }
-    {
+    if (!(lp.chunk && !bp.lb.empty())) {
         hipKernelNodeParams kp{};
         uint32_t *flip = p->flip;
         void *params[] = {&flip};
