@@ -156,9 +156,20 @@ typedef struct {
                               /* at the offset no earlier rejection gives,  */
                               /* a repair pass redoes each request from its */
                               /* first chunk with a rejection (Philox and   */
-                              /* the test generator; others take 2).        */
-                              /* Automatic: 5 for a batch of Philox or test */
-                              /* generator requests of at most 2^16 pairs   */
+                              /* the test generator; others take 2);        */
+                              /* 6 counted, for single fills of Philox or   */
+                              /* the test generator: one kernel counts the  */
+                              /* accepted pairs of every 512-pair chunk, a  */
+                              /* scan turns counts into offsets, a second   */
+                              /* kernel produces every chunk at its offset  */
+                              /* (nothing is redone; at most 2^31 pairs;    */
+                              /* other fills as automatic).                 */
+                              /* Automatic: 6 for a single fill of Philox   */
+                              /* or the test generator of at least 2^18     */
+                              /* pairs that expects more than 2             */
+                              /* rejections; 5 for a batch of Philox or     */
+                              /* test generator requests of at most 2^16    */
+                              /* pairs                                      */
                               /* that expects at most 256 rejections;       */
                               /* otherwise ordered unless some request has  */
                               /* at least 2^18 pairs; then, single fills: 3 */

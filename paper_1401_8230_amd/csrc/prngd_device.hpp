@@ -2618,6 +2618,143 @@ __global__ __launch_bounds__(256) void spec_wave_kernel(LaunchArgs args)
     }
 }
 
+// ======================================================================
+// Counted fill of one segment, for streams that reject often enough that
+// speculation would redo much of the fill: pass 1 counts every chunk's
+// accepted pairs (Philox and the test only, nothing stored), a two-level
+// scan turns the counts into exact offsets, and pass 2 produces every chunk
+// at its exact offset (a chunk without rejections below output n - 1 in
+// 16-byte stores as it is generated, any other one by ranks).  Chunks are
+// kCountedWindows windows of 128 pairs on the stream's own grid; chunk 0
+// starts lo0 pairs in.  No chunk waits for another and nothing is redone.
+// ======================================================================
+constexpr uint32_t kCountedWindows = 4;
+
+template <uint32_t FAM>
+__global__ __launch_bounds__(256) void counted_count_kernel(LaunchArgs args)
+{
+    using C = BatchChunk<FAM, kCountedWindows>;
+    constexpr uint32_t P = C::P;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t k = blockIdx.x * 4u + wave;
+    if (k >= args.total_tiles)
+        return;
+    const TileStart ts = tile_start<true>(args, 0);
+    const Segment &seg = ts.seg;
+    const uint64_t w0 = ts.c0 / P;
+    const uint32_t lo0 = uint32_t(ts.c0 % P);
+    const uint32_t lo_off = k == 0 ? lo0 : 0u;
+    uint32_t kept = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kCountedWindows; ++j) {
+        const uint32_t base = j * kChunk;
+        if (lo_off >= base + kChunk)
+            continue;
+        const uint32_t lo_j = lo_off > base ? lo_off - base : 0u;
+        kept += WaveChunk<FAM>::run(args, seg, (w0 + k) * kCountedWindows + j, lo_j, 0,
+                                    nullptr, false, false);
+    }
+    if (lane == 0)
+        args.chunk_counts[k] = kept;
+}
+
+// Level 1: workgroup b scans the counts of chunks [b B, (b + 1) B)
+// (B = kScanBlock, 4 per thread), writes each chunk's offset in its block
+// and the block's total to block_offs[b].
+__global__ __launch_bounds__(1024) void counted_scan_blocks_kernel(LaunchArgs args)
+{
+    __shared__ uint32_t s_wave[16];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t total = args.total_tiles;
+    const uint64_t c0 = uint64_t(blockIdx.x) * kScanBlock + 4u * tid;
+    uint32_t v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        v[i] = c0 + uint32_t(i) < total ? args.chunk_counts[c0 + i] : 0u;
+    const uint32_t mine = v[0] + v[1] + v[2] + v[3];
+    const uint32_t incl = wave_incl_scan(mine, lane);
+    if (lane == 63)
+        s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, sum = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < 16; ++w) {
+        const uint32_t t = s_wave[w];
+        before += w < wave ? t : 0u;
+        sum += t;
+    }
+    uint32_t run = before + incl - mine;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (c0 + uint32_t(i) < total)
+            args.chunk_offs[c0 + i] = run;
+        run += v[i];
+    }
+    if (tid == 0)
+        args.block_offs[blockIdx.x] = sum;
+}
+
+// Level 2: one workgroup turns the block totals (at most kScanBlocksMax)
+// into exclusive offsets, in place.
+__global__ __launch_bounds__(1024) void counted_scan_top_kernel(LaunchArgs args)
+{
+    __shared__ uint64_t s_wave[16];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t nblocks = (args.total_tiles + kScanBlock - 1) / kScanBlock;
+    const uint64_t mine = tid < nblocks ? args.block_offs[tid] : 0u;
+    uint64_t incl = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t u = uint64_t(uint32_t(__shfl_up(uint32_t(incl), d, 64))) |
+                           uint64_t(uint32_t(__shfl_up(uint32_t(incl >> 32), d, 64))) << 32;
+        if (lane >= uint32_t(d))
+            incl += u;
+    }
+    if (lane == 63)
+        s_wave[wave] = incl;
+    __syncthreads();
+    uint64_t before = 0;
+    for (uint32_t w = 0; w < wave; ++w)
+        before += s_wave[w];
+    if (tid < nblocks)
+        args.block_offs[tid] = before + incl - mine;
+}
+
+template <uint32_t FAM>
+__global__ __launch_bounds__(256) void counted_produce_kernel(LaunchArgs args)
+{
+    using C = BatchChunk<FAM, kCountedWindows>;
+    constexpr uint32_t P = C::P;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t total = args.total_tiles;
+    const uint32_t k = blockIdx.x * 4u + wave;
+    if (k >= total)
+        return;
+    const TileStart ts = tile_start<true>(args, 0);
+    const Segment &seg = ts.seg;
+    uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
+    const uint64_t w0 = ts.c0 / P;
+    const uint32_t lo0 = uint32_t(ts.c0 % P);
+    const uint64_t off = __builtin_amdgcn_readfirstlane(args.block_offs[k / kScanBlock]) +
+                         __builtin_amdgcn_readfirstlane(args.chunk_offs[k]);
+    const uint32_t kept = __builtin_amdgcn_readfirstlane(args.chunk_counts[k]);
+    const uint64_t ch = w0 + k;
+    const uint32_t lo_off = k == 0 ? lo0 : 0u;
+    if (uniform_lt(off, seg.n)) {
+        if (lo_off == 0 && kept == P && C::fits(off, seg.n))
+            (void)C::run_clean(args, seg, ch, off);     // known clean: exact as stored
+        else
+            (void)C::template run_exact<false>(args, seg, ch, lo_off, off, next_counter);
+    }
+    // the last chunk takes every further chunk until n outputs
+    if (k == total - 1) {
+        uint64_t running = off + kept;
+        for (uint64_t c2 = ch + 1; uniform_lt(running, seg.n); ++c2)
+            running += C::template run_exact<false>(args, seg, c2, 0u, running, next_counter);
+    }
+}
+
 // Whether chunk g (of the single segment) has to be produced again, and
 // at which true offset: the rules of needs_redo with chunk hints.
 template <uint32_t P>

@@ -148,7 +148,17 @@ struct LaunchArgs {
     uint32_t cps_shift;       // t = mulhi(c, cps_magic) (chunks_per_seg >= 2)
     uint32_t chunk_shift;     // log2 of the pairs per chunk
     uint32_t *toggle;         // plan replay parity the chunk repair flips last, or null
+    // counted single fill: accepted pairs per chunk, each chunk's offset in
+    // its block of kScanBlock chunks, and the blocks' exclusive offsets
+    uint32_t *chunk_counts;
+    uint32_t *chunk_offs;
+    uint64_t *block_offs;
 };
+
+// Chunks per block of the counted fill's two-level scan (one workgroup of
+// 1024 threads, 4 chunks each), and the most blocks its top level takes.
+constexpr uint32_t kScanBlock = 4096;
+constexpr uint32_t kScanBlocksMax = 1024;
 
 constexpr uint32_t kMaxTiles = 0xFFFFFFF0u;
 
@@ -173,6 +183,8 @@ template <uint32_t MAPF>
 const void *spec_words_kernel_for(uint32_t fam, bool repair);
 template <uint32_t MAPF>
 const void *philox_chunk_kernel_for(uint32_t fam, bool repair, uint32_t windows);
+template <uint32_t MAPF>
+const void *philox_counted_kernel_for(uint32_t fam, bool produce);
 
 // Device error codes (bit flags in the error word).
 constexpr uint32_t kErrLookbackStall = 1;

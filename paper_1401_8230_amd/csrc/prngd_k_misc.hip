@@ -130,6 +130,22 @@ const void *chunk_kernel_for(uint32_t fam, bool repair, uint32_t windows)
     });
 }
 
+// The counted single fill: its counting or producing pass (256 threads),
+// or null.
+const void *counted_kernel_for(uint32_t fam, bool produce)
+{
+    return by_map(fam, [&](auto m) {
+        return philox_counted_kernel_for<decltype(m)::value>(fam, produce);
+    });
+}
+
+// The two levels of its scan (1024 threads each).
+const void *counted_scan_kernel_ptr(bool top)
+{
+    return top ? reinterpret_cast<const void *>(&counted_scan_top_kernel)
+               : reinterpret_cast<const void *>(&counted_scan_blocks_kernel);
+}
+
 const void *chunk_prep_kernel_ptr()
 {
     return reinterpret_cast<const void *>(&chunk_prep_kernel);

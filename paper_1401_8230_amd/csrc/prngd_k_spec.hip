@@ -134,4 +134,26 @@ const void *philox_chunk_kernel_for<PRNGD_MAPF>(uint32_t fam, bool repair, uint3
     }
 }
 
+// The counted single fill's counting pass or producing pass for a
+// Philox-family generator; null for other families.
+template <>
+const void *philox_counted_kernel_for<PRNGD_MAPF>(uint32_t fam, bool produce)
+{
+    constexpr uint32_t P32 = FAM_PHILOX32 | PRNGD_MAPF, P = FAM_PHILOX | PRNGD_MAPF,
+                       EN = FAM_ENUM | PRNGD_MAPF;
+    switch (fam_base(fam)) {
+    case FAM_PHILOX32:
+        return produce ? reinterpret_cast<const void *>(&counted_produce_kernel<P32>)
+                       : reinterpret_cast<const void *>(&counted_count_kernel<P32>);
+    case FAM_PHILOX:
+        return produce ? reinterpret_cast<const void *>(&counted_produce_kernel<P>)
+                       : reinterpret_cast<const void *>(&counted_count_kernel<P>);
+    case FAM_ENUM:
+        return produce ? reinterpret_cast<const void *>(&counted_produce_kernel<EN>)
+                       : reinterpret_cast<const void *>(&counted_count_kernel<EN>);
+    default:
+        return nullptr;
+    }
+}
+
 }  // namespace prngd

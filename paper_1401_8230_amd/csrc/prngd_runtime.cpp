@@ -28,6 +28,8 @@ const void *spec_words_kernel_for(uint32_t fam, bool repair);
 const void *triple_kernel_for(uint32_t fam, bool seq);
 const void *chunk_kernel_for(uint32_t fam, bool repair, uint32_t cpw);
 const void *chunk_prep_kernel_ptr();
+const void *counted_kernel_for(uint32_t fam, bool produce);
+const void *counted_scan_kernel_ptr(bool top);
 hipError_t launch_toggle_flip(uint32_t *flip, hipStream_t stream);
 const void *toggle_flip_kernel_ptr();
 hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads,
@@ -592,6 +594,11 @@ struct Workspace {
     uint32_t *first_dirty = nullptr;
     uint32_t *dirty_list = nullptr;
     size_t chunk_cap = 0;
+    // counted single fill: per-chunk counts and offsets, per-block offsets
+    uint32_t *counts = nullptr;
+    uint32_t *count_offs = nullptr;
+    uint64_t *block_offs = nullptr;
+    size_t counts_cap = 0;
     // buffers replaced by larger ones: kept until the workspace is released,
     // so that growing never waits for work in flight (freeing would)
     std::vector<void *> retired_dev;
@@ -645,6 +652,9 @@ void ws_release(Workspace *ws)
     (void)hipFree(ws->chunk_segs);
     (void)hipFree(ws->first_dirty);
     (void)hipFree(ws->dirty_list);
+    (void)hipFree(ws->counts);
+    (void)hipFree(ws->count_offs);
+    (void)hipFree(ws->block_offs);
     (void)hipFree(ws->dsegs);
     (void)hipFree(ws->tile_seg);
     for (int i = 0; i < 2; ++i) {
@@ -745,6 +755,33 @@ prngd_status_t ws_prepare_chunk(Workspace *ws, size_t nseg, hipStream_t stream)
     ws->dirty_list = static_cast<uint32_t *>(p);
     ws->chunk_cap = cap;
     HIP_TRY(launch_zero_words(reinterpret_cast<uint64_t *>(ws->first_dirty), cap / 2, stream));
+    return PRNGD_OK;
+}
+
+// Room for the counted fill's per-chunk counts and offsets of `chunks`
+// chunks (and its fixed per-block offsets).
+prngd_status_t ws_prepare_counted(Workspace *ws, size_t chunks)
+{
+    if (!ws->block_offs) {
+        void *p = nullptr;
+        HIP_TRY(hipMalloc(&p, kScanBlocksMax * sizeof(uint64_t)));
+        ws->block_offs = static_cast<uint64_t *>(p);
+    }
+    if (chunks <= ws->counts_cap)
+        return PRNGD_OK;
+    const size_t cap = std::max<size_t>({chunks, size_t(1) << 16, 2 * ws->counts_cap});
+    if (ws->counts) {
+        ws->retired_dev.push_back(ws->counts);
+        ws->retired_dev.push_back(ws->count_offs);
+        ws->counts = nullptr;
+        ws->count_offs = nullptr;
+    }
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, cap * sizeof(uint32_t)));
+    ws->counts = static_cast<uint32_t *>(p);
+    HIP_TRY(hipMalloc(&p, cap * sizeof(uint32_t)));
+    ws->count_offs = static_cast<uint32_t *>(p);
+    ws->counts_cap = cap;
     return PRNGD_OK;
 }
 
@@ -870,6 +907,8 @@ struct LaunchPlan {
     const void *chunk_kernel;         // chunk-speculative batch form, if any
     const void *chunk_repair_kernel;
     bool wave;                // single fills take the wave-granular form
+    const void *counted_kernels[2];   // counted single fill: count, produce
+    bool counted;             // a single fill takes the counted form
     bool chunk;               // batches take the chunk-speculative form
     double expected_rejections;  // of the launch, as choose_path estimated
     uint32_t chunk_windows;   // its 128-pair windows per chunk (1, 2, 4)
@@ -939,6 +978,9 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     lp->chunk_pairs = kChunkPairs * lp->chunk_windows;
     lp->chunk_kernel = two ? chunk_kernel_for(kfam, false, lp->chunk_windows) : nullptr;
     lp->chunk_repair_kernel = two ? chunk_kernel_for(kfam, true, lp->chunk_windows) : nullptr;
+    lp->counted_kernels[0] = two ? counted_kernel_for(kfam, false) : nullptr;
+    lp->counted_kernels[1] = two ? counted_kernel_for(kfam, true) : nullptr;
+    lp->counted = false;
     lp->wave_kernel = two ? spec_wave_kernel_for(kfam, false, lp->chunk_windows) : nullptr;
     lp->wave_repair_kernel = two ? spec_wave_kernel_for(kfam, true, lp->chunk_windows) : nullptr;
     lp->wave = false;
@@ -977,6 +1019,16 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     return PRNGD_OK;
 }
 
+// Pairs per chunk of the counted single fill (4 windows of 128), and the
+// rejections a single fill must expect before it takes that form: with more,
+// speculation redoes every chunk in flight when a rejection is published.
+// MI355X, 2^22 outputs: w = 24 (0.5 expected) 21 us in 128-pair chunks
+// against 25 us counted; w = 20 (8 expected) 52 us against 25 us.  2^28
+// outputs: w = 24 881 us against 623 us, w = 17 2781 us ordered against
+// 655 us.
+constexpr uint64_t kCountedPairs = 512;
+constexpr double kCountedMinRejections = 2.0;
+
 // The longest request (planned pairs) the chunk form takes automatically:
 // its repair produces a dirty request again on one wave, about 0.2 us per
 // 128-pair window, so a request of 2^16 pairs costs at most about 100 us.
@@ -990,17 +1042,19 @@ constexpr uint64_t kChunkFormMaxPairs = uint64_t(1) << 16;
 // rejections that the repair pass has little to redo.  Measured on
 // MI355X: a batch of requests of at most 2^16 pairs that expects at most
 // 256 rejections is fastest in the chunk form (2^16 requests of 2^14
-// outputs: 1.56 ms against 1.62 ms ordered).  A single fill at w = 32 that
-// expects at most 2 rejections is fastest in the holding form; at w < 32
-// (up to 1024) and at w = 32 with more, in 128-pair chunks (w = 24, 2^22
-// outputs: 21 us against 74 us holding).  Other batches take the holding
-// form up to 128 expected rejections; beyond that the ordered kernels win.
+// outputs: 1.56 ms against 1.62 ms ordered).  A single fill of Philox or
+// the test generator that expects more than 2 rejections is fastest
+// counted; with fewer, at w = 32 in the holding form, at w < 32 in 128-pair
+// chunks (w = 24, 2^22 outputs: 21 us against 74 us holding).  Other
+// batches take the holding form up to 128 expected rejections; beyond that
+// the ordered kernels win.
 void choose_path(LaunchPlan *lp, const Config &c, uint64_t pairs, uint64_t longest,
                  bool single, uint64_t nseg = 1)
 {
     lp->spec = false;
     lp->wave = false;
     lp->chunk = false;
+    lp->counted = false;
     if (!lp->repair_kernel || lp->tune.path == 1 || c.consume == PRNGD_CONSUME_SINGLE)
         return;
     const double rho = 2.0 / double(c.a - c.a0 + 1);
@@ -1011,6 +1065,16 @@ void choose_path(LaunchPlan *lp, const Config &c, uint64_t pairs, uint64_t longe
     // at most 2^32 - 1 threads; a segment adds at most one chunk
     const bool chunk_ok = !single && lp->chunk_kernel && lp->chunk_repair_kernel &&
                           pairs / lp->chunk_pairs + nseg < (uint64_t(1) << 26);
+    // the counted form's two-level scan: at most kScanBlocksMax blocks of
+    // kScanBlock chunks of 512 pairs (a chunk more for the start offset)
+    const bool counted_ok = single && lp->counted_kernels[0] && lp->counted_kernels[1] &&
+                            pairs / kCountedPairs + 2 <= uint64_t(kScanBlock) * kScanBlocksMax;
+    if (counted_ok && (lp->tune.path == 6 ||
+                       (lp->tune.path == 0 && longest >= (uint64_t(64) << 12) &&
+                        expected > kCountedMinRejections))) {
+        lp->counted = true;
+        return;
+    }
     int hold = -1;
     if (lp->tune.path == 5 && chunk_ok) {
         lp->chunk = true;
@@ -1219,6 +1283,33 @@ prngd_status_t launch_chunk(DeviceInfo *d, const LaunchPlan &lp, Workspace *ws,
     HIP_TRY(launch_fill(lp.chunk_repair_kernel,
                         chunk_repair_grid(d, args.nseg, lp.expected_rejections),
                         kChunkRepairThreads, args, s));
+    return PRNGD_OK;
+}
+
+// Enqueue the counted fill of one segment (args.seg0): count every chunk,
+// scan the counts in two levels, produce every chunk at its offset.
+prngd_status_t launch_counted(const LaunchPlan &lp, Workspace *ws, LaunchArgs args,
+                              hipStream_t s)
+{
+    const uint64_t chunks =
+        std::max<uint64_t>(1, (args.seg0.planned + kCountedPairs - 1) / kCountedPairs);
+    if (chunks > uint64_t(kScanBlock) * kScanBlocksMax)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "fill too large for the counted form");
+    prngd_status_t st;
+    if ((st = ws_prepare_counted(ws, chunks)) != PRNGD_OK)
+        return st;
+    args.chunk_counts = ws->counts;
+    args.chunk_offs = ws->count_offs;
+    args.block_offs = ws->block_offs;
+    args.total_tiles = uint32_t(chunks);
+    if (!args.flip)
+        args.flip = lp.zero_word;
+    const uint32_t grid = uint32_t((chunks + 3) / 4);
+    const uint32_t nblocks = uint32_t((chunks + kScanBlock - 1) / kScanBlock);
+    HIP_TRY(launch_fill(lp.counted_kernels[0], grid, 256, args, s));
+    HIP_TRY(launch_fill(counted_scan_kernel_ptr(false), nblocks, 1024, args, s));
+    HIP_TRY(launch_fill(counted_scan_kernel_ptr(true), 1, 1024, args, s));
+    HIP_TRY(launch_fill(lp.counted_kernels[1], grid, 256, args, s));
     return PRNGD_OK;
 }
 
@@ -1701,6 +1792,9 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *strea
     if (words) {
         if ((st = launch_spec_words(d, lp, ws, args, s)) != PRNGD_OK)
             return st;
+    } else if (lp.counted) {
+        if ((st = launch_counted(lp, ws, args, s)) != PRNGD_OK)
+            return st;
     } else if (lp.spec && lp.wave) {
         if ((st = launch_spec_wave(d, lp, ws, args, s)) != PRNGD_OK)
             return st;
@@ -2136,7 +2230,7 @@ prngd_status_t prngd_set_tuning(prngd_generator_t generator, uint32_t w,
     if (!fill_kernel_for(fam, threads, ppl, false))
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "no kernel for %u threads x %u pairs per lane",
                     threads, ppl);
-    if (t.store_mode > 2 || t.slack_mode > 1 || t.path > 5)
+    if (t.store_mode > 2 || t.slack_mode > 1 || t.path > 6)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "bad store_mode, slack_mode or path");
     if (t.path >= 2 && !spec_kernel_for(fam, threads, ppl, false, false, true))
         return fail(PRNGD_ERR_INVALID_ARGUMENT,

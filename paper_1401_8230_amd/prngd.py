@@ -395,7 +395,7 @@ class Plan:
 
 
 PATHS = {"auto": 0, "ordered": 1, "speculative": 2, "speculative-hold": 3,
-         "speculative-wave": 4, "speculative-chunk": 5}
+         "speculative-wave": 4, "speculative-chunk": 5, "counted": 6}
 
 
 def set_tuning(generator, w, pairs_per_lane=0, blocks_per_cu=0, store_mode=0, slack_mode=0,
@@ -404,7 +404,8 @@ def set_tuning(generator, w, pairs_per_lane=0, blocks_per_cu=0, store_mode=0, sl
     2/"speculative", 3/"speculative-hold", 4/"speculative-wave" (single
     fills in 128-pair chunks) or 5/"speculative-chunk" (batches in chunks of
     pairs_per_lane / 2 windows of 128 pairs, one per wave; single fills as
-    4)."""
+    4) or 6/"counted" (single fills: count the accepted pairs of every
+    512-pair chunk, scan, produce each chunk at its offset)."""
     path = PATHS.get(path, path)
     t = Tuning(pairs_per_lane, blocks_per_cu, store_mode, slack_mode, block_threads,
                seq_max_tiles, path)

@@ -149,8 +149,10 @@ def test_tuning_round_trip_and_validation():
     assert prngd.get_tuning("philox", 13)["path"] == 4
     prngd.set_tuning("philox", 13, path="speculative-chunk")
     assert prngd.get_tuning("philox", 13)["path"] == 5
+    prngd.set_tuning("philox", 13, path="counted")
+    assert prngd.get_tuning("philox", 13)["path"] == 6
     with pytest.raises(prngd.PrngdError):
-        prngd.set_tuning("philox", 13, path=6)
+        prngd.set_tuning("philox", 13, path=7)
     prngd.set_tuning("mixed", 32, path="speculative")
     assert prngd.get_tuning("mixed", 32)["path"] == 2
     prngd.reset_tuning("mixed", 32)

@@ -137,3 +137,68 @@ def test_no_planned_slack_and_many_rejections():
     for trial in range(30):
         out, ctr, truth, tctr = chunk_fill(3000, trial % 7, 128, 0.3, 0, seed=trial)
         assert out == truth and ctr == tctr
+
+
+def counted_fill(n, lo0, P, p, planned_extra, seed, block=4):
+    """The counted single fill: chunk k covers pairs [k P, (k + 1) P) of
+    the stream's grid (chunk 0 from lo0); pass 1 counts each chunk's
+    accepted pairs, a two-level scan (blocks of `block` chunks, then the
+    block totals) gives exact offsets, pass 2 stores each chunk's accepted
+    pairs below output n at its offset; the last chunk continues."""
+    rnd = random.Random(seed)
+    planned = n + planned_extra
+    chunks = max(1, -(-planned // P))
+    span = (chunks + 64) * P + 20 * n + 4096
+    acc = [rnd.random() >= p for _ in range(span)]
+    truth, q = [], lo0
+    while len(truth) < n:
+        if acc[q]:
+            truth.append(q)
+        q += 1
+    lo = lambda k: lo0 if k == 0 else 0          # noqa: E731
+    counts = [sum(acc[k * P + lo(k):(k + 1) * P]) for k in range(chunks)]
+    nblocks = -(-chunks // block)
+    local, totals = [0] * chunks, []
+    for b in range(nblocks):
+        run = 0
+        for k in range(b * block, min(chunks, (b + 1) * block)):
+            local[k] = run
+            run += counts[k]
+        totals.append(run)
+    block_off = [sum(totals[:b]) for b in range(nblocks)]
+    out, counter = [None] * n, None
+
+    def produce(k, off):
+        nonlocal counter
+        for x in range(k * P + lo(k), (k + 1) * P):
+            if acc[x]:
+                if off < n:
+                    out[off] = x
+                    if off == n - 1:
+                        counter = x + 1
+                off += 1
+        return off
+
+    order = list(range(chunks))
+    rnd.shuffle(order)
+    for k in order:
+        off = block_off[k // block] + local[k]
+        end = produce(k, off) if off < n else off + counts[k]
+        if k == chunks - 1:
+            c2 = k + 1
+            while end < n:
+                end = produce(c2, end)
+                c2 += 1
+    return out, counter, truth, truth[-1] + 1
+
+
+@pytest.mark.parametrize("p", [0.0, 1e-3, 0.05, 0.25, 0.6])
+def test_counted_form_equals_the_sequential_fill(p):
+    rnd = random.Random(int(p * 1e6) + 5)
+    for trial in range(60):
+        P = rnd.choice([8, 16, 512])
+        n = rnd.choice([1, 2, P - 1, P, P + 1, 7 * P + 3, rnd.randint(1, 40 * P)])
+        lo0 = rnd.choice([0, 1, P - 1, rnd.randrange(P)])
+        extra = rnd.choice([0, 1, P, 5 * P])
+        out, ctr, truth, tctr = counted_fill(n, lo0, P, p, extra, seed=trial * 31 + n)
+        assert out == truth and ctr == tctr, (p, trial, P, n, lo0, extra)
