@@ -17,6 +17,7 @@ GEN_PHILOX = 0
 GEN_MRG32K3A = 1
 GEN_MIXED = 2
 GEN_ENUMERATE = 3
+GEN_RANMAR = 4
 
 MAP_EQ5 = 0          # Eq. (5): [0, 1)
 MAP_EQ4 = 1          # Eq. (4), Algorithm 1's Z: (0, 1)
@@ -51,6 +52,7 @@ class Stream(ctypes.Structure):
         ("D3_hi", ctypes.c_uint64),
         ("D3_lo", ctypes.c_uint64),
         ("S3", ctypes.c_double),
+        ("ranmar", ctypes.c_uint32 * 97),
     ]
 
 
@@ -107,6 +109,11 @@ def lib():
         L.orc_rn_u128.restype = ctypes.c_double
         L.orc_scale3.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
         L.orc_scale3.restype = ctypes.c_double
+        L.orc_ranmar_seed.argtypes = [ctypes.c_uint32, ctypes.c_uint32, u32p]
+        L.orc_ranmar_stream_seeds.argtypes = [ctypes.c_uint64, ctypes.c_uint32, u32p, u32p]
+        L.orc_ranmar_step_to.argtypes = [u32p, ctypes.c_uint64, u32p, u32p]
+        L.orc_ranmar_jump.argtypes = [u32p, ctypes.c_uint64, ctypes.c_uint64, u32p, u32p]
+        L.orc_ranmar_words.argtypes = [u32p, ctypes.c_uint64, ctypes.c_uint64, u32p]
         _lib = L
     return _lib
 
@@ -168,6 +175,46 @@ def mrg_matpow(component, exponent):
 def mrg_stream_base(seed, stream):
     out = np.zeros(6, dtype=np.uint32)
     lib().orc_mrg_stream_base(seed, stream, _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def ranmar_seed(ij, kl):
+    """RANMAR's seed values L[-96..0] (the window at word position 0)."""
+    out = np.zeros(97, dtype=np.uint32)
+    lib().orc_ranmar_seed(ij, kl, _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def ranmar_stream_seeds(seed, stream):
+    ij, kl = ctypes.c_uint32(), ctypes.c_uint32()
+    lib().orc_ranmar_stream_seeds(seed, stream, ctypes.byref(ij), ctypes.byref(kl))
+    return int(ij.value), int(kl.value)
+
+
+def ranmar_step_to(window0, n):
+    """The window and C at word position n, by stepping."""
+    w0 = np.ascontiguousarray(window0, dtype=np.uint32)
+    out = np.zeros(97, dtype=np.uint32)
+    C = ctypes.c_uint32()
+    lib().orc_ranmar_step_to(_ptr(w0, ctypes.c_uint32), n, _ptr(out, ctypes.c_uint32),
+                             ctypes.byref(C))
+    return out, int(C.value)
+
+
+def ranmar_jump(window0, n):
+    """The window and C at word position n (< 2^128), by the jump polynomial."""
+    w0 = np.ascontiguousarray(window0, dtype=np.uint32)
+    out = np.zeros(97, dtype=np.uint32)
+    C = ctypes.c_uint32()
+    lib().orc_ranmar_jump(_ptr(w0, ctypes.c_uint32), n & (2**64 - 1), n >> 64,
+                          _ptr(out, ctypes.c_uint32), ctypes.byref(C))
+    return out, int(C.value)
+
+
+def ranmar_words(window0, first, count):
+    w0 = np.ascontiguousarray(window0, dtype=np.uint32)
+    out = np.zeros(count, dtype=np.uint32)
+    lib().orc_ranmar_words(_ptr(w0, ctypes.c_uint32), first, count, _ptr(out, ctypes.c_uint32))
     return out
 
 

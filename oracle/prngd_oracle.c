@@ -189,6 +189,162 @@ void orc_mrg_stream_base(uint64_t seed, uint32_t stream, uint32_t out[6])
 }
 
 /* ======================================================================
+ * RANMAR.  Marsaglia, Zaman, Tsang, "Toward a universal random number
+ * generator", Stat. Prob. Lett. 9 (1990) 35, in the form F. James gives
+ * (Comput. Phys. Commun. 60 (1990) 329): a lagged Fibonacci generator
+ * with lags 97 and 33 under subtraction mod 1, minus an arithmetic
+ * sequence mod 16777213/16777216, all values multiples of 2^-24.  Here in
+ * integer units of 2^-24 (the header states the sequence).
+ * ====================================================================== */
+#define ORC_RANMAR_MASK 0xFFFFFFu
+#define ORC_RANMAR_CD   7654321u
+#define ORC_RANMAR_CM   16777213u
+#define ORC_RANMAR_C0   362436u
+#define ORC_RANMAR_IJ   31329u
+#define ORC_RANMAR_KL   30082u
+
+/* The 97 seed values: four small generators (a lagged Fibonacci generator
+ * on three values mod 179 and a congruential one mod 169) give one bit
+ * each step, 24 steps per value, most significant bit first.  The values
+ * come out for L[0], L[-1], ..., L[-96] in that order. */
+void orc_ranmar_seed(uint32_t ij, uint32_t kl, uint32_t window[97])
+{
+    uint32_t i = (ij / 177) % 177 + 2;
+    uint32_t j = ij % 177 + 2;
+    uint32_t k = (kl / 169) % 178 + 1;
+    uint32_t l = kl % 169;
+    for (int v = 0; v < 97; v++) {
+        uint32_t value = 0;
+        for (int bit = 0; bit < 24; bit++) {
+            uint32_t m = (((i * j) % 179) * k) % 179;
+            i = j;
+            j = k;
+            k = m;
+            l = (53 * l + 1) % 169;
+            value = 2 * value + ((l * m) % 64 >= 32 ? 1u : 0u);
+        }
+        window[96 - v] = value;       /* value v is L[-v] */
+    }
+}
+
+void orc_ranmar_stream_seeds(uint64_t seed, uint32_t stream, uint32_t *ij,
+                             uint32_t *kl)
+{
+    u128 s = (((u128)seed << 32) | stream) % ((u128)ORC_RANMAR_IJ * ORC_RANMAR_KL);
+    *ij = (uint32_t)(s / ORC_RANMAR_KL);
+    *kl = (uint32_t)(s % ORC_RANMAR_KL);
+}
+
+/* C[n] = (C[0] - n * 7654321) mod 16777213, n = n_hi 2^64 + n_lo. */
+static uint32_t ranmar_c_at(uint64_t n_lo, uint64_t n_hi)
+{
+    u128 n = ((u128)n_hi << 64) | n_lo;
+    uint64_t t = (uint64_t)(n % ORC_RANMAR_CM) * ORC_RANMAR_CD % ORC_RANMAR_CM;
+    return (uint32_t)((ORC_RANMAR_C0 + ORC_RANMAR_CM - t) % ORC_RANMAR_CM);
+}
+
+/* A stepping generator: the window as a ring (slot (head + i) mod 97 holds
+ * window[i]) and C. */
+typedef struct {
+    uint32_t L[97];
+    unsigned head;
+    uint32_t C;
+} ranmar_cursor;
+
+static void ranmar_cursor_set(ranmar_cursor *g, const uint32_t window[97], uint32_t C)
+{
+    memcpy(g->L, window, sizeof g->L);
+    g->head = 0;
+    g->C = C;
+}
+
+/* The next word: L[n+1] = L[n-96] - L[n-32] replaces L[n-96]. */
+static uint32_t ranmar_next(ranmar_cursor *g)
+{
+    uint32_t oldest = g->L[g->head];
+    uint32_t lag33 = g->L[(g->head + 64) % 97];
+    uint32_t v = (oldest - lag33) & ORC_RANMAR_MASK;
+    g->L[g->head] = v;
+    g->head = (g->head + 1) % 97;
+    g->C = g->C >= ORC_RANMAR_CD ? g->C - ORC_RANMAR_CD : g->C + ORC_RANMAR_CM - ORC_RANMAR_CD;
+    return (v - g->C) & ORC_RANMAR_MASK;
+}
+
+static void ranmar_cursor_window(const ranmar_cursor *g, uint32_t window[97])
+{
+    for (int i = 0; i < 97; i++)
+        window[i] = g->L[(g->head + (unsigned)i) % 97];
+}
+
+void orc_ranmar_step_to(const uint32_t window0[97], uint64_t n,
+                        uint32_t window[97], uint32_t *C)
+{
+    ranmar_cursor g;
+    ranmar_cursor_set(&g, window0, ORC_RANMAR_C0);
+    for (uint64_t t = 0; t < n; t++)
+        (void)ranmar_next(&g);
+    ranmar_cursor_window(&g, window);
+    *C = g.C;
+}
+
+/* r <- r * q mod (x^97 + x^64 - 1), coefficients mod 2^24: the product of
+ * degree <= 192, then every term x^d with d >= 97 folded down by
+ * x^d = x^(d-97) - x^(d-33), from the top. */
+static void ranmar_polymulmod(uint32_t r[97], const uint32_t q[97])
+{
+    uint32_t prod[193];
+    memset(prod, 0, sizeof prod);
+    for (int i = 0; i < 97; i++)
+        for (int j = 0; j < 97; j++)
+            prod[i + j] += r[i] * q[j];
+    for (int d = 192; d >= 97; d--) {
+        prod[d - 97] += prod[d];
+        prod[d - 33] -= prod[d];
+    }
+    for (int i = 0; i < 97; i++)
+        r[i] = prod[i] & ORC_RANMAR_MASK;
+}
+
+void orc_ranmar_jump(const uint32_t window0[97], uint64_t n_lo, uint64_t n_hi,
+                     uint32_t window[97], uint32_t *C)
+{
+    /* r = x^n mod P by square-and-multiply over the bits of n */
+    uint32_t r[97], x[97];
+    memset(r, 0, sizeof r);
+    memset(x, 0, sizeof x);
+    r[0] = 1;
+    x[1] = 1;
+    for (int bit = 127; bit >= 0; bit--) {
+        uint32_t sq[97];
+        memcpy(sq, r, sizeof sq);
+        ranmar_polymulmod(r, sq);
+        uint64_t word = bit >= 64 ? n_hi : n_lo;
+        if ((word >> (bit & 63)) & 1u)
+            ranmar_polymulmod(r, x);
+    }
+    /* window[s] = L[n - 96 + s] = sum_i (x^(n+s) mod P)_i L[-96 + i] */
+    for (int s = 0; s < 97; s++) {
+        uint32_t acc = 0;
+        for (int i = 0; i < 97; i++)
+            acc += r[i] * window0[i];
+        window[s] = acc & ORC_RANMAR_MASK;
+        ranmar_polymulmod(r, x);
+    }
+    *C = ranmar_c_at(n_lo, n_hi);
+}
+
+void orc_ranmar_words(const uint32_t window0[97], uint64_t first,
+                      uint64_t count, uint32_t *out)
+{
+    uint32_t window[97], C;
+    orc_ranmar_jump(window0, first, 0, window, &C);
+    ranmar_cursor g;
+    ranmar_cursor_set(&g, window, C);
+    for (uint64_t t = 0; t < count; t++)
+        out[t] = ranmar_next(&g);
+}
+
+/* ======================================================================
  * PRNGD.
  * ====================================================================== */
 
@@ -262,6 +418,9 @@ uint64_t orc_word(const orc_stream *s, uint64_t j)
             orc_mrg_jump(st, e, 1);
         }
         orc_mrg_outputs(st, 1, &o);
+        return o;
+    case ORC_GEN_RANMAR:
+        orc_ranmar_words(s->ranmar, j, 1, &o);
         return o;
     default:
         if (s->arity == 3) {
@@ -387,6 +546,15 @@ int orc_init(orc_stream *s, int generator, int w, uint64_t seed,
         if (w > 16) return -1;
         s->a0 = 0; s->a = top; s->b0 = 0; s->b = top;
         break;
+    case ORC_GEN_RANMAR:
+        if (w != 24) return -1;
+        s->a0 = 0; s->a = top; s->b0 = 0; s->b = top;
+        {
+            uint32_t ij, kl;
+            orc_ranmar_stream_seeds(seed, stream, &ij, &kl);
+            orc_ranmar_seed(ij, kl, s->ranmar);
+        }
+        break;
     default:
         return -1;
     }
@@ -437,6 +605,21 @@ void orc_pair(const orc_stream *s, uint64_t p, uint64_t *x1, uint64_t *x2)
         *x1 = (p >> s->w) & ((1ull << s->w) - 1);
         *x2 = p & ((1ull << s->w) - 1);
         break;
+    case ORC_GEN_RANMAR: {
+        uint32_t wd[2];
+        {
+            u128 first = (u128)2 * p;
+            uint32_t window[97], C;
+            orc_ranmar_jump(s->ranmar, (uint64_t)first, (uint64_t)(first >> 64), window, &C);
+            ranmar_cursor g;
+            ranmar_cursor_set(&g, window, C);
+            wd[0] = ranmar_next(&g);
+            wd[1] = ranmar_next(&g);
+        }
+        *x1 = wd[0];
+        *x2 = wd[1];
+        break;
+    }
     default:
         *x1 = *x2 = 0;
     }
@@ -489,6 +672,14 @@ static uint64_t fill_pairs(orc_stream *s, uint64_t n, int bounded, uint64_t pair
     int mrg = s->generator == ORC_GEN_MRG32K3A || s->generator == ORC_GEN_MIXED;
     uint32_t st[6];
     int shift = 32 - s->w;
+    ranmar_cursor rm;
+    if (s->generator == ORC_GEN_RANMAR) {
+        /* words 2 counter, 2 counter + 1, ... from the window there */
+        u128 first = (u128)2 * s->counter;
+        uint32_t window[97], C;
+        orc_ranmar_jump(s->ranmar, (uint64_t)first, (uint64_t)(first >> 64), window, &C);
+        ranmar_cursor_set(&rm, window, C);
+    }
     if (mrg) {
         /* position r * counter may need 65 bits */
         u128 pos = (u128)mrg_per_pair(s) * s->counter;
@@ -514,6 +705,10 @@ static uint64_t fill_pairs(orc_stream *s, uint64_t n, int bounded, uint64_t pair
             x1 = philox_word(s->seed, s->stream, p);
             orc_mrg_outputs(st, 1, o);
             x2 = o[0];
+            break;
+        case ORC_GEN_RANMAR:
+            x1 = ranmar_next(&rm);
+            x2 = ranmar_next(&rm);
             break;
         default:
             orc_pair(s, p, &x1, &x2);

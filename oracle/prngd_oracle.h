@@ -9,6 +9,8 @@
  * shares no code, header, table or constant generator with the GPU library.
  *
  * Parity status of each part (what pins it is listed in the tests):
+ *   - RANMAR: pinned by the check values its published description gives
+ *     (seeds 1802, 9373: words 20000 .. 20005), and jump == stepping.
  *   - Philox4x32-10 block function: pinned against an independent library
  *     implementation (rocRAND, built from its source headers for the host)
  *     and by counter-carry / split invariants.
@@ -43,7 +45,8 @@ enum {
     ORC_GEN_PHILOX    = 0, /* pair p = (word 2p, word 2p+1) >> (32 - w)       */
     ORC_GEN_MRG32K3A  = 1, /* pair p = (output 2p, output 2p+1), w = 32       */
     ORC_GEN_MIXED     = 2, /* pair p = (Philox word p, MRG32k3a output p)      */
-    ORC_GEN_ENUMERATE = 3  /* pair p = ((p >> w) mod 2^w, p mod 2^w), tests    */
+    ORC_GEN_ENUMERATE = 3, /* pair p = ((p >> w) mod 2^w, p mod 2^w), tests    */
+    ORC_GEN_RANMAR    = 4  /* pair p = (RANMAR word 2p, word 2p+1), w = 24     */
 };
 
 /* How an accepted pair becomes an output (Section 2). */
@@ -81,6 +84,7 @@ typedef struct {
     uint64_t D3_hi;    /* three words: D3 = (a - a0 - 2) 2^2w + Y1 - Y0 */
     uint64_t D3_lo;    /*   (a 128-bit integer, two halves)             */
     double   S3;       /* RN((1 - 2^-3w) / D3)                          */
+    uint32_t ranmar[97]; /* RANMAR lagged values L[-96..0] of the stream  */
 } orc_stream;
 
 /* ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ---------------- */
@@ -102,6 +106,32 @@ void orc_mrg_matpow(int component, const uint64_t *exponent, int nlimbs,
 /* State at position 0 of stream (seed, stream): the six-fold 12345 state
  * advanced by seed * 2^127 + stream * 2^76 steps. */
 void orc_mrg_stream_base(uint64_t seed, uint32_t stream, uint32_t out[6]);
+
+/* ---- RANMAR (Marsaglia, Zaman, Tsang, Stat. Prob. Lett. 9 (1990) 35;
+ * F. James, Comput. Phys. Commun. 60 (1990) 329) ------------------------
+ * In integer units of 2^-24.  Lagged values L[n] = (L[n-97] - L[n-33])
+ * mod 2^24 for n >= 1 from 97 seed values L[-96..0]; an arithmetic part
+ * C[n] = (C[n-1] - 7654321) mod 16777213, C[0] = 362436; word j of the
+ * stream (j = 0, 1, ...) is (L[j+1] - C[j+1]) mod 2^24.  The seed values
+ * come from the generator's two seeds ij in [0, 31328], kl in [0, 30081]
+ * (a lagged Fibonacci and a congruential generator, 24 bits each); a
+ * PRNGD stream (seed, stream) uses sequence s = (seed 2^32 + stream) mod
+ * (31329 * 30082), ij = s / 30082, kl = s mod 30082.
+ * A "window" at word position n is L[n-96 .. n] (window[i] = L[n-96+i])
+ * with C[n]; the next word is made from window[0] - window[64]. */
+void orc_ranmar_seed(uint32_t ij, uint32_t kl, uint32_t window[97]);
+void orc_ranmar_stream_seeds(uint64_t seed, uint32_t stream, uint32_t *ij,
+                             uint32_t *kl);
+/* The window at word position n by stepping n times (O(n)). */
+void orc_ranmar_step_to(const uint32_t window0[97], uint64_t n,
+                        uint32_t window[97], uint32_t *C);
+/* The same by the jump polynomial x^n mod (x^97 + x^64 - 1) over the
+ * integers mod 2^24 (O(97^2 log n)). */
+void orc_ranmar_jump(const uint32_t window0[97], uint64_t n_lo, uint64_t n_hi,
+                     uint32_t window[97], uint32_t *C);
+/* Words [first, first + count) of the sequence with seed window window0. */
+void orc_ranmar_words(const uint32_t window0[97], uint64_t first,
+                      uint64_t count, uint32_t *out);
 
 /* ---- PRNGD ------------------------------------------------------------- */
 /* 0 on success, -1 on invalid parameters. */
