@@ -37,6 +37,22 @@
  *       p in [1, 4294967087]; w = 32.
  *   PRNGD_ENUMERATE: a test generator, pair p = ((p >> w) mod 2^w,
  *       p mod 2^w), 2 <= w <= 16; it visits every pair once per 2^2w.
+ *   PRNGD_RANMAR: RANMAR (Marsaglia, Zaman, Tsang 1990, in F. James's
+ *       form, Comput. Phys. Commun. 60 (1990) 329), one of the 24-bit
+ *       generators Section 2 names as suitable; w = 24, words in
+ *       [0, 2^24 - 1].  In units of 2^-24: L[n] = (L[n-97] - L[n-33]) mod
+ *       2^24 from the 97 values of its seeds (ij, kl), C[n] = (C[n-1] -
+ *       7654321) mod 16777213 from C[0] = 362436, word j = (L[j+1] -
+ *       C[j+1]) mod 2^24.  Stream (seed, stream_id) is the sequence s =
+ *       (seed 2^32 + stream_id) mod (31329 * 30082), ij = s / 30082,
+ *       kl = s mod 30082; pair p = (word 2p, word 2p + 1).  A lagged
+ *       generator: each handle keeps the 97 lagged values and C at its
+ *       position on the device (about 1 KB), prngd_set_position computes
+ *       them on the host (x^n mod (x^97 + x^64 - 1), about a millisecond),
+ *       and a long fill starts its segments by the same jump, from a table
+ *       the library builds on the host once per size.  Pair consumption,
+ *       two words per output, no plans and no prngd_fill_noalloc
+ *       (PRNGD_ERR_UNSUPPORTED); any map.
  *
  * Conventions for every call:
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
@@ -73,7 +89,8 @@ typedef enum {
     PRNGD_PHILOX4X32_10 = 0,
     PRNGD_MRG32K3A = 1,
     PRNGD_PHILOX_X1_MRG32K3A_X2 = 2,
-    PRNGD_ENUMERATE = 3
+    PRNGD_ENUMERATE = 3,
+    PRNGD_RANMAR = 4
 } prngd_generator_t;
 
 /* How an accepted pair becomes an output (Section 2 of the paper):
@@ -236,6 +253,16 @@ prngd_status_t prngd_create_many(uint64_t seed, prngd_generator_t generator,
                                  double k, uint64_t min, uint64_t max,
                                  uint32_t first_stream_id, uint32_t count,
                                  prngd_handle_t *handles);
+
+/*
+ * RANMAR state of stream (seed, stream_id) of PRNGD_RANMAR at pair
+ * position pair_counter (word 2 pair_counter), host only:
+ * out[0 .. 96] = L[W - 96 .. W] and out[97] = C[W] in units of 2^-24
+ * (W = 2 pair_counter; see PRNGD_RANMAR above), the values a handle keeps
+ * on the device there.  Errors: PRNGD_ERR_INVALID_ARGUMENT for a NULL out.
+ */
+prngd_status_t prngd_ranmar_state(uint64_t seed, uint32_t stream_id, uint64_t pair_counter,
+                                  uint32_t out[98]);
 
 /* Choose the map of the handle's later outputs (PRNGD_MAP_EQ5 after
  * prngd_create).  Host only; fills already enqueued are not affected.

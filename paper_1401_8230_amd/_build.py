@@ -14,9 +14,9 @@ OBJ_DIR = os.path.join(HERE, "_build")
 # units are built twice: the kernels of the default Eq. (5) map, and the
 # kernels that take the map's constants from the launch (FAM_ANY_MAP).
 FAMILY_SOURCES = ["prngd_k_spec.hip", "prngd_k_philox.hip", "prngd_k_single.hip",
-                  "prngd_k_mrg.hip"]
+                  "prngd_k_mrg.hip", "prngd_k_ranmar.hip"]
 SOURCES = ["prngd_k_triple.hip", "prngd_k_misc.hip", "prngd_noalloc.hip", "prngd_probes.hip",
-           "prngd_runtime.cpp"]
+           "prngd_runtime.cpp", "prngd_ranmar_host.cpp"]
 UNITS = ([(src, "eq5", ["-DPRNGD_MAPF=0u"]) for src in FAMILY_SOURCES]
          + [(src, "anymap", ["-DPRNGD_MAPF=FAM_ANY_MAP"]) for src in FAMILY_SOURCES]
          + [(src, "", []) for src in SOURCES])

@@ -2191,9 +2191,22 @@ struct WaveChunk {
                                                    bool full)
     {
         const uint32_t lane = threadIdx.x & 63u;
+        return emit(args, seg, words(args, seg, win, lane), win * kChunk, lo_off, excl,
+                    next_counter, store, full);
+    }
+
+    // The same for a window whose words the caller made: lane l holds
+    // pairs 2l and 2l + 1 (x1 - a0 - 1, x2 - b0), the window's first pair
+    // is pair0 of the stream.
+    __device__ __forceinline__ static uint32_t emit(const LaunchArgs &args, const Segment &seg,
+                                                    const HiLo &p, uint64_t pair0,
+                                                    uint32_t lo_off, uint64_t excl,
+                                                    uint64_t *next_counter, bool store,
+                                                    bool full)
+    {
+        const uint32_t lane = threadIdx.x & 63u;
         const uint32_t hm = fam_base(FAM) == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
         const double tw = fam_base(FAM) == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
-        const HiLo p = words(args, seg, win, lane);
         // the ballots straight from the compares; pairs below lo_off
         // (2l < lo_off, 2l + 1 < lo_off) are masked out on the scalar unit
         uint64_t ka = __builtin_amdgcn_ballot_w64(p.ha < hm);
@@ -2237,9 +2250,9 @@ struct WaveChunk {
         if (okb && pos_b < left)
             store_one(o + pos_b, zb, args.store_mode);
         if (oka && pos_a + 1 == left)
-            *next_counter = win * kChunk + q + 1;
+            *next_counter = pair0 + q + 1;
         if (okb && pos_b + 1 == left)
-            *next_counter = win * kChunk + q + 2;
+            *next_counter = pair0 + q + 2;
         return kept;
     }
 };

@@ -12,7 +12,8 @@ enum Family : uint32_t {
     FAM_MRG = 1,      // pair p = MRG32k3a outputs 2p, 2p+1
     FAM_MIXED = 2,    // pair p = (Philox word p, MRG32k3a output p)
     FAM_ENUM = 3,     // pair p = ((p >> w) mod 2^w, p mod 2^w)
-    FAM_PHILOX32 = 4  // FAM_PHILOX at w = 32 (x in [0, 2^32 - 1], no shift)
+    FAM_PHILOX32 = 4, // FAM_PHILOX at w = 32 (x in [0, 2^32 - 1], no shift)
+    FAM_RANMAR = 5    // pair p = RANMAR words 2p, 2p+1 (24 bits), from a window in memory
 };
 
 // Flag on a kernel's family: the output map's constants come from the
@@ -42,7 +43,8 @@ constexpr uint64_t kMaxOutputs = kValueMask;   // per segment (one fill)
 // One fill of one handle inside a launch.  80 bytes; an array of these is
 // device-resident for batched launches.
 struct Segment {
-    uint64_t seed;        // Philox key (seed lo, seed hi)
+    uint64_t seed;        // Philox key (seed lo, seed hi); RANMAR: device address of
+                          // the handle's two state slots (RanmarState)
     uint64_t n;           // outputs wanted
     uint64_t planned;     // pairs the tiles were planned for (host bookkeeping)
     double *out;          // device output, 8-byte aligned
@@ -153,6 +155,34 @@ struct LaunchArgs {
     uint32_t *chunk_counts;
     uint32_t *chunk_offs;
     uint64_t *block_offs;
+    // RANMAR fills: the jump table (row g, kRanmarRow words: the
+    // coefficients of x^(2 g P) mod (x^97 + x^64 - 1) over the integers mod
+    // 2^24, then (2 g P * 7654321) mod 16777213) and the pairs P of a segment
+    const uint32_t *ranmar_jump;
+    uint32_t ranmar_seg_pairs;
+};
+
+// RANMAR (Marsaglia, Zaman, Tsang 1990) in integer units of 2^-24: lagged
+// values L[n] = (L[n-97] - L[n-33]) mod 2^24, an arithmetic part C[n] =
+// (C[n-1] - 7654321) mod 16777213, word j = (L[j+1] - C[j+1]) mod 2^24.
+// A handle's state at word position W = 2 * pair counter: L[W-96 .. W] and
+// C[W], in one of two slots (read slot parity, write the other, as the
+// pair counters).
+constexpr uint32_t kRanmarMask = 0xFFFFFFu;
+constexpr uint32_t kRanmarCD = 7654321u;
+constexpr uint32_t kRanmarCM = 16777213u;
+constexpr uint32_t kRanmarC0 = 362436u;
+constexpr uint32_t kRanmarRow = 128;       // words of a state slot and of a jump-table row
+struct RanmarState {
+    uint32_t slot[2][kRanmarRow];          // [0..96] L[W-96 .. W], [97] C[W]
+};
+// One state to set: both slots of dst, and both pair counters of slot when
+// it is not null.
+struct RanmarInit {
+    RanmarState *dst;
+    uint64_t *slot;
+    uint64_t counter;
+    uint32_t words[kRanmarRow];
 };
 
 // Chunks per block of the counted fill's two-level scan (one workgroup of
@@ -185,9 +215,23 @@ template <uint32_t MAPF>
 const void *philox_chunk_kernel_for(uint32_t fam, bool repair, uint32_t windows);
 template <uint32_t MAPF>
 const void *philox_counted_kernel_for(uint32_t fam, bool produce);
+// RANMAR: mode 0 one wave per request (batches, short fills), 1 count the
+// accepted pairs of each segment, 2 produce each segment at its offset
+template <uint32_t MAPF>
+const void *ranmar_kernel_for(uint32_t mode);
+
+// RANMAR on the host: the sequence (ij, kl) of a stream, the state (window
+// and C, kRanmarRow words) at word position word_hi 2^64 + word_lo, and
+// rows [first, first + count) of the jump table for segments of seg_pairs
+// pairs (kRanmarRow words each).
+void ranmar_sequence_of(uint64_t seed, uint32_t stream, uint32_t *ij, uint32_t *kl);
+void ranmar_window_at(uint64_t seed, uint32_t stream, uint64_t word_lo, uint64_t word_hi,
+                      uint32_t out[kRanmarRow]);
+void ranmar_jump_rows(uint32_t seg_pairs, uint32_t first, uint32_t count, uint32_t *rows);
 
 // Device error codes (bit flags in the error word).
 constexpr uint32_t kErrLookbackStall = 1;
 constexpr uint32_t kErrSpecList = 2;       // rejection list out of its bounds
+constexpr uint32_t kErrRanmarRunaway = 4;  // a RANMAR wave passed its bound on windows
 
 }  // namespace prngd

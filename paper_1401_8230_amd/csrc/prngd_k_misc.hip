@@ -21,6 +21,33 @@ __global__ void set_counter_kernel(uint64_t *slot, uint64_t value)
     slot[1] = value;
 }
 
+// RANMAR states: both slots of handle state `dst` (and, if `slot` is not
+// null, both pair counters) set from words [0, kRanmarRow) of one record.
+__global__ void ranmar_set_states_kernel(const RanmarInit *inits, uint32_t count)
+{
+    const RanmarInit &r = inits[blockIdx.x];
+    for (uint32_t i = threadIdx.x; i < kRanmarRow; i += blockDim.x) {
+        r.dst->slot[0][i] = r.words[i];
+        r.dst->slot[1][i] = r.words[i];
+    }
+    if (threadIdx.x == 0 && r.slot) {
+        r.slot[0] = r.counter;
+        r.slot[1] = r.counter;
+    }
+}
+
+__global__ void ranmar_set_state_kernel(RanmarInit r)
+{
+    for (uint32_t i = threadIdx.x; i < kRanmarRow; i += blockDim.x) {
+        r.dst->slot[0][i] = r.words[i];
+        r.dst->slot[1][i] = r.words[i];
+    }
+    if (threadIdx.x == 0 && r.slot) {
+        r.slot[0] = r.counter;
+        r.slot[1] = r.counter;
+    }
+}
+
 __global__ void zero_words_kernel(uint64_t *p, size_t n)
 {
     for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
@@ -139,6 +166,13 @@ const void *counted_kernel_for(uint32_t fam, bool produce)
     });
 }
 
+// A RANMAR kernel (256 threads; mode 0 one wave per request, 1 count, 2
+// produce), for the map of family fam.
+const void *ranmar_kernel_for(uint32_t fam, uint32_t mode)
+{
+    return by_map(fam, [&](auto m) { return ranmar_kernel_for<decltype(m)::value>(mode); });
+}
+
 // The two levels of its scan (1024 threads each).
 const void *counted_scan_kernel_ptr(bool top)
 {
@@ -185,6 +219,20 @@ hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads, cons
 hipError_t launch_set_counter(uint64_t *slot, uint64_t value, hipStream_t stream)
 {
     hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(1), 0, stream, slot, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranmar_set(const RanmarInit &r, hipStream_t stream)
+{
+    hipLaunchKernelGGL(ranmar_set_state_kernel, dim3(1), dim3(128), 0, stream, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranmar_set_many(const RanmarInit *inits, uint32_t count, hipStream_t stream)
+{
+    if (count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(ranmar_set_states_kernel, dim3(count), dim3(128), 0, stream, inits, count);
     return hipGetLastError();
 }
 

@@ -37,6 +37,9 @@ hipError_t launch_fill(const void *kernel, uint32_t grid, uint32_t threads,
 hipError_t launch_expand_tiles(const Segment *segs, uint32_t nseg, uint32_t *tile_seg,
                                hipStream_t stream);
 hipError_t launch_set_counter(uint64_t *slot, uint64_t value, hipStream_t stream);
+hipError_t launch_ranmar_set(const RanmarInit &r, hipStream_t stream);
+hipError_t launch_ranmar_set_many(const RanmarInit *inits, uint32_t count, hipStream_t stream);
+const void *ranmar_kernel_for(uint32_t fam, uint32_t mode);
 hipError_t launch_zero_words(uint64_t *p, size_t n, hipStream_t stream);
 hipError_t noalloc_setup(int dev);
 Control *noalloc_control(int dev);
@@ -203,6 +206,7 @@ uint32_t kernel_family(prngd_generator_t gen, uint32_t w)
     case PRNGD_MRG32K3A: return FAM_MRG;
     case PRNGD_PHILOX_X1_MRG32K3A_X2: return FAM_MIXED;
     case PRNGD_ENUMERATE: return FAM_ENUM;
+    case PRNGD_RANMAR: return FAM_RANMAR;
     default: return w == 32 ? FAM_PHILOX32 : FAM_PHILOX;
     }
 }
@@ -210,7 +214,7 @@ uint32_t kernel_family(prngd_generator_t gen, uint32_t w)
 prngd_status_t make_config(prngd_generator_t gen, double k, uint64_t min, uint64_t max,
                            Config *c)
 {
-    if (gen < PRNGD_PHILOX4X32_10 || gen > PRNGD_ENUMERATE)
+    if (gen < PRNGD_PHILOX4X32_10 || gen > PRNGD_RANMAR)
         return fail(PRNGD_ERR_UNSUPPORTED, "unknown generator %d", int(gen));
     if (!(k > 0) || !std::isfinite(k))
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "k must be 2^-w");
@@ -220,14 +224,17 @@ prngd_status_t make_config(prngd_generator_t gen, double k, uint64_t min, uint64
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "k = %a is not a power of two", k);
     const int w = 1 - e;
     c->w = uint32_t(w);
-    const int wmax = gen == PRNGD_ENUMERATE ? 16 : 32;
-    const int wmin = (gen == PRNGD_MRG32K3A || gen == PRNGD_PHILOX_X1_MRG32K3A_X2) ? 32 : 2;
+    const int wmax = gen == PRNGD_ENUMERATE ? 16 : gen == PRNGD_RANMAR ? 24 : 32;
+    const int wmin = (gen == PRNGD_MRG32K3A || gen == PRNGD_PHILOX_X1_MRG32K3A_X2) ? 32
+                     : gen == PRNGD_RANMAR                                         ? 24
+                                                                                   : 2;
     if (w < wmin || w > wmax)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "k = 2^-%d out of range for this generator", w);
     const uint64_t top = (uint64_t(1) << w) - 1;
     switch (gen) {
     case PRNGD_PHILOX4X32_10:
     case PRNGD_ENUMERATE:
+    case PRNGD_RANMAR:
         c->a0 = 0; c->a = top; c->b0 = 0; c->b = top;
         break;
     case PRNGD_MRG32K3A:
@@ -425,6 +432,13 @@ struct DeviceInfo {
     // recorded after each (both set up here, never by the entry point)
     uint64_t noalloc_launches = 0;
     hipEvent_t noalloc_event = nullptr;
+    // RANMAR: handle states from slabs, and the jump table of the fills'
+    // segments (rows of kRanmarRow words)
+    std::vector<void *> rm_slabs;
+    std::vector<RanmarState *> rm_free;
+    uint32_t *rm_jump[2] = {nullptr, nullptr};    // fine and coarse segments
+    uint32_t rm_jump_rows[2] = {0, 0};
+    std::vector<uint32_t> rm_jump_host[2];
 };
 
 std::map<int, DeviceInfo> g_devices;
@@ -497,6 +511,48 @@ prngd_status_t alloc_slot(DeviceInfo *d, uint64_t **slot)
     HIP_TRY(hipMemcpy(s, zero, sizeof zero, hipMemcpyHostToDevice));
     d->free_slots.pop_back();
     *slot = s;
+    return PRNGD_OK;
+}
+
+// RANMAR handle states come from slabs of 1024 (1 KB each).
+prngd_status_t alloc_ranmar(DeviceInfo *d, RanmarState **out)
+{
+    if (d->rm_free.empty()) {
+        constexpr size_t kSlab = 1024;
+        void *p = nullptr;
+        HIP_TRY(hipMalloc(&p, kSlab * sizeof(RanmarState)));
+        d->rm_slabs.push_back(p);
+        RanmarState *base = static_cast<RanmarState *>(p);
+        for (size_t i = kSlab; i-- > 0;)
+            d->rm_free.push_back(base + i);
+    }
+    *out = d->rm_free.back();
+    d->rm_free.pop_back();
+    return PRNGD_OK;
+}
+
+// The states of new RANMAR handles at word 0 of their streams, set at once
+// (a staging copy and one kernel, then a wait: handle creation only).
+prngd_status_t ranmar_init_states(const std::vector<std::pair<RanmarState *, const void *>> &hs,
+                                  uint64_t seed, uint32_t first_stream)
+{
+    std::vector<RanmarInit> inits(hs.size());
+    for (size_t i = 0; i < hs.size(); ++i) {
+        inits[i].dst = hs[i].first;
+        inits[i].slot = nullptr;
+        inits[i].counter = 0;
+        ranmar_window_at(seed, uint32_t(first_stream + i), 0, 0, inits[i].words);
+    }
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, inits.size() * sizeof(RanmarInit)));
+    hipError_t e = hipMemcpy(p, inits.data(), inits.size() * sizeof(RanmarInit),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_ranmar_set_many(static_cast<RanmarInit *>(p), uint32_t(inits.size()), nullptr);
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
+    (void)hipFree(p);
+    HIP_TRY(e);
     return PRNGD_OK;
 }
 
@@ -833,6 +889,7 @@ struct prngd_handle_s {
     uint32_t stream_id = 0;
     uint32_t mrg[6] = {0, 0, 0, 0, 0, 0};
     uint64_t *slot = nullptr;          // device: counter[2]
+    RanmarState *rm = nullptr;         // device: RANMAR state slots (RANMAR handles)
     uint32_t parity = 0;               // counter[parity] is current
     hipEvent_t last_event = nullptr;   // borrowed: last work on this handle
     hipStream_t last_stream = nullptr;
@@ -1619,6 +1676,15 @@ prngd_status_t prngd_create(uint64_t seed, prngd_generator_t generator, double k
     }
     if ((st = alloc_slot(d, &h->slot)) != PRNGD_OK)
         return st;
+    if (cfg.fam == FAM_RANMAR) {
+        if ((st = alloc_ranmar(d, &h->rm)) != PRNGD_OK ||
+            (st = ranmar_init_states({{h->rm, nullptr}}, seed, 0)) != PRNGD_OK) {
+            d->free_slots.push_back(h->slot);
+            if (h->rm)
+                d->rm_free.push_back(h->rm);
+            return st;
+        }
+    }
     *out_handle = h.release();
     return PRNGD_OK;
 }
@@ -1664,6 +1730,25 @@ prngd_status_t prngd_create_many(uint64_t seed, prngd_generator_t generator, dou
         }
         handles[i] = h.release();
     }
+    if (cfg.fam == FAM_RANMAR && count) {
+        std::vector<std::pair<RanmarState *, const void *>> hs;
+        for (uint32_t i = 0; i < count && st == PRNGD_OK; ++i) {
+            st = alloc_ranmar(d, &handles[i]->rm);
+            hs.push_back({handles[i]->rm, nullptr});
+        }
+        if (st == PRNGD_OK)
+            st = ranmar_init_states(hs, seed, first_stream_id);
+        if (st != PRNGD_OK) {
+            for (uint32_t i = 0; i < count; ++i) {
+                d->free_slots.push_back(handles[i]->slot);
+                if (handles[i]->rm)
+                    d->rm_free.push_back(handles[i]->rm);
+                delete handles[i];
+                handles[i] = nullptr;
+            }
+            return st;
+        }
+    }
     return PRNGD_OK;
 }
 
@@ -1677,9 +1762,24 @@ prngd_status_t prngd_destroy(prngd_handle_t h)
     if (h->last_event)
         HIP_TRY(hipEventSynchronize(h->last_event));
     auto it = g_devices.find(h->device);
-    if (it != g_devices.end())
+    if (it != g_devices.end()) {
         it->second.free_slots.push_back(h->slot);
+        if (h->rm)
+            it->second.rm_free.push_back(h->rm);
+    }
     delete h;
+    return PRNGD_OK;
+}
+
+prngd_status_t prngd_ranmar_state(uint64_t seed, uint32_t stream_id, uint64_t pair_counter,
+                                  uint32_t out[98])
+{
+    if (!out)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "out is NULL");
+    uint32_t w[kRanmarRow];
+    const unsigned __int128 word = static_cast<unsigned __int128>(pair_counter) * 2u;
+    ranmar_window_at(seed, stream_id, uint64_t(word), uint64_t(word >> 64), w);
+    std::memcpy(out, w, 98 * sizeof(uint32_t));
     return PRNGD_OK;
 }
 
@@ -1701,7 +1801,18 @@ prngd_status_t prngd_set_position(prngd_handle_t h, uint32_t stream_id, uint64_t
     h->stream_id = stream_id;
     if (h->cfg.fam == FAM_MRG || h->cfg.fam == FAM_MIXED)
         mrg_stream_base(h->seed, stream_id, h->mrg);
-    HIP_TRY(launch_set_counter(h->slot, pair_counter, s));
+    if (h->cfg.fam == FAM_RANMAR) {
+        // the window at word 2 pair_counter of the stream, both slots
+        RanmarInit r{};
+        r.dst = h->rm;
+        r.slot = h->slot;
+        r.counter = pair_counter;
+        const unsigned __int128 word = static_cast<unsigned __int128>(pair_counter) * 2u;
+        ranmar_window_at(h->seed, stream_id, uint64_t(word), uint64_t(word >> 64), r.words);
+        HIP_TRY(launch_ranmar_set(r, s));
+    } else {
+        HIP_TRY(launch_set_counter(h->slot, pair_counter, s));
+    }
     HIP_TRY(hipEventRecord(ws->last, s));
     h->last_event = ws->last;
     h->last_stream = s;
@@ -1737,6 +1848,201 @@ prngd_status_t prngd_get_position(prngd_handle_t h, uint32_t *stream_id, uint64_
 static prngd_status_t fill_batch_impl(const prngd_request_t *reqs, uint32_t count,
                                       void *stream);
 
+// ------------------------------------------------------------------ RANMAR
+// Pairs of a segment of a long RANMAR fill (one wave each): fine segments
+// while a fill needs at most kRanmarFineSegs of them (more waves for fills
+// of up to 2^22 pairs), coarse ones beyond (each wave's jump is then a
+// smaller share of its work, and the table stays small).  Requests of a
+// batch up to kRanmarWaveMax planned pairs take one wave each; longer ones
+// are filled one by one in segments.
+constexpr uint32_t kRanmarSegPairs[2] = {1024, 8192};
+constexpr uint64_t kRanmarFineSegs = 4096;
+constexpr uint64_t kRanmarWaveMax = 32768;
+
+// Rows [0, rows) of jump table `which` on the device; new rows are computed
+// on the host (one polynomial product each) and the table is copied whole.
+static prngd_status_t ranmar_jump_table(DeviceInfo *d, int which, uint32_t rows)
+{
+    if (rows <= d->rm_jump_rows[which])
+        return PRNGD_OK;
+    std::vector<uint32_t> &host = d->rm_jump_host[which];
+    const uint32_t have = uint32_t(host.size() / kRanmarRow);
+    const uint32_t cap = std::max<uint32_t>({rows, 2 * have, 256u});
+    host.resize(size_t(cap) * kRanmarRow);
+    ranmar_jump_rows(kRanmarSegPairs[which], have, cap - have,
+                     host.data() + size_t(have) * kRanmarRow);
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, host.size() * sizeof(uint32_t)));
+    HIP_TRY(hipMemcpy(p, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (d->rm_jump[which]) {
+        HIP_TRY(hipDeviceSynchronize());       // no launch reads the old table any more
+        HIP_TRY(hipFree(d->rm_jump[which]));
+    }
+    d->rm_jump[which] = static_cast<uint32_t *>(p);
+    d->rm_jump_rows[which] = cap;
+    return PRNGD_OK;
+}
+
+static LaunchArgs ranmar_args(DeviceInfo *d, const Config &c)
+{
+    LaunchArgs a{};
+    a.store_mode = 0;
+    a.w = c.w;
+    a.a0 = uint32_t(c.a0);
+    a.a = uint32_t(c.a);
+    a.b0 = uint32_t(c.b0);
+    const MapConsts mc = map_consts(c);
+    a.S = mc.S;
+    a.nadd = mc.nadd;
+    a.osign = mc.osign;
+    a.ooff = mc.ooff;
+    a.flip = d->zero_word;
+    a.error = d->error_dev;
+    a.ranmar_seg_pairs = kRanmarSegPairs[0];
+    return a;
+}
+
+static uint32_t ranmar_kfam(const Config &c)
+{
+    return FAM_RANMAR | (c.map == PRNGD_MAP_EQ5 ? 0u : FAM_ANY_MAP);
+}
+
+// Enqueue the fill of one RANMAR handle: one wave if it plans at most one
+// segment; else count every segment's accepted pairs, scan, produce.
+static prngd_status_t ranmar_fill(DeviceInfo *d, prngd_handle_t h, uint64_t n, double *out,
+                                  Workspace *ws, hipStream_t s)
+{
+    Segment seg{};
+    uint64_t ntiles = 0;
+    prngd_status_t st = make_segment(h, n, out, kRanmarSegPairs[0], 0, 0, &seg, &ntiles);
+    if (st != PRNGD_OK)
+        return st;
+    seg.seed = reinterpret_cast<uint64_t>(h->rm);
+    const int which = ntiles <= kRanmarFineSegs ? 0 : 1;
+    const uint64_t P = kRanmarSegPairs[which];
+    const uint64_t segs = std::max<uint64_t>(1, (seg.planned + P - 1) / P);
+    if (segs > uint64_t(kScanBlock) * kScanBlocksMax)
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "n = %llu: too large for one RANMAR fill",
+                    (unsigned long long)n);
+    LaunchArgs a = ranmar_args(d, h->cfg);
+    a.seg0 = seg;
+    a.nseg = 1;
+    a.ranmar_seg_pairs = uint32_t(P);
+    const uint32_t kfam = ranmar_kfam(h->cfg);
+    if (segs == 1) {
+        a.total_tiles = 1;
+        HIP_TRY(launch_fill(ranmar_kernel_for(kfam, 0), 1, 256, a, s));
+        return PRNGD_OK;
+    }
+    if ((st = ranmar_jump_table(d, which, uint32_t(segs))) != PRNGD_OK)
+        return st;
+    if ((st = ws_prepare_counted(ws, segs)) != PRNGD_OK)
+        return st;
+    a.ranmar_jump = d->rm_jump[which];
+    a.chunk_counts = ws->counts;
+    a.chunk_offs = ws->count_offs;
+    a.block_offs = ws->block_offs;
+    a.total_tiles = uint32_t(segs);
+    const uint32_t grid = uint32_t((segs + 3) / 4);
+    const uint32_t nblocks = uint32_t((segs + kScanBlock - 1) / kScanBlock);
+    HIP_TRY(launch_fill(ranmar_kernel_for(kfam, 1), grid, 256, a, s));
+    HIP_TRY(launch_fill(counted_scan_kernel_ptr(false), nblocks, 1024, a, s));
+    HIP_TRY(launch_fill(counted_scan_kernel_ptr(true), 1, 1024, a, s));
+    HIP_TRY(launch_fill(ranmar_kernel_for(kfam, 2), grid, 256, a, s));
+    return PRNGD_OK;
+}
+
+// A batch of RANMAR requests: short ones one wave each in one launch, long
+// ones as single fills, all on `s`.
+static prngd_status_t ranmar_batch(DeviceInfo *d, const prngd_request_t *reqs, uint32_t count,
+                                   hipStream_t s)
+{
+    std::unordered_set<prngd_handle_t> seen;
+    const prngd_handle_t first = reqs[0].h;
+    for (uint32_t i = 0; i < count; ++i) {
+        const prngd_request_t &r = reqs[i];
+        if (!r.h)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "request %u has a NULL handle", i);
+        if (!seen.insert(r.h).second)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle of request %u repeats", i);
+        if (!same_config(r.h->cfg, first->cfg) || r.h->device != first->device)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT,
+                        "request %u: all handles of a batch must share generator, k, min, max",
+                        i);
+        if (r.h->plan)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "request %u: handle bound to a plan", i);
+        if (r.n > kMaxOutputs)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "request %u: n exceeds 2^38 - 1 outputs", i);
+        if (r.n && (!r.out || (reinterpret_cast<uintptr_t>(r.out) & 7u)))
+            return fail(PRNGD_ERR_INVALID_ARGUMENT,
+                        "request %u: out must be a non-null 8-byte aligned pointer", i);
+    }
+    Workspace *ws = nullptr;
+    prngd_status_t st = stream_workspace(first->device, s, &ws);
+    if (st != PRNGD_OK)
+        return st;
+    std::unordered_set<hipEvent_t> waited;
+    for (uint32_t i = 0; i < count; ++i) {
+        const prngd_handle_t h = reqs[i].h;
+        if (reqs[i].n && h->last_event && h->last_stream != s && waited.insert(h->last_event).second)
+            HIP_TRY(hipStreamWaitEvent(s, h->last_event, 0));
+    }
+    std::vector<Segment> segs;
+    for (uint32_t i = 0; i < count; ++i) {
+        const prngd_request_t &r = reqs[i];
+        if (r.n == 0)
+            continue;
+        if (planned_pairs(r.h->cfg, r.n, 0) > kRanmarWaveMax) {
+            if ((st = ranmar_fill(d, r.h, r.n, r.out, ws, s)) != PRNGD_OK)
+                return st;
+            continue;
+        }
+        Segment seg{};
+        uint64_t ntiles = 0;
+        if ((st = make_segment(r.h, r.n, r.out, kRanmarSegPairs[0], 0, 0, &seg, &ntiles)) != PRNGD_OK)
+            return st;
+        seg.seed = reinterpret_cast<uint64_t>(r.h->rm);
+        segs.push_back(seg);
+    }
+    if (!segs.empty()) {
+        const size_t nseg = segs.size();
+        if ((st = ws_grow(ws, &ws->dsegs, &ws->dsegs_cap, nseg, s)) != PRNGD_OK)
+            return st;
+        const int slot = ws->hcur;
+        ws->hcur ^= 1;
+        HIP_TRY(hipEventSynchronize(ws->hsegs_done[slot]));
+        if (ws->hsegs_cap[slot] < nseg) {
+            if (ws->hsegs[slot])
+                ws->retired_host.push_back(ws->hsegs[slot]);
+            void *p = nullptr;
+            const size_t cap = std::max<size_t>({nseg, size_t(1024), 2 * ws->hsegs_cap[slot]});
+            HIP_TRY(hipHostMalloc(&p, cap * sizeof(Segment), hipHostMallocDefault));
+            ws->hsegs[slot] = static_cast<Segment *>(p);
+            ws->hsegs_cap[slot] = cap;
+        }
+        std::copy(segs.begin(), segs.end(), ws->hsegs[slot]);
+        HIP_TRY(hipMemcpyAsync(ws->dsegs, ws->hsegs[slot], nseg * sizeof(Segment),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(ws->hsegs_done[slot], s));
+        LaunchArgs a = ranmar_args(d, first->cfg);
+        a.segs = ws->dsegs;
+        a.nseg = uint32_t(nseg);
+        a.total_tiles = uint32_t(nseg);
+        HIP_TRY(launch_fill(ranmar_kernel_for(ranmar_kfam(first->cfg), 0),
+                            uint32_t((nseg + 3) / 4), 256, a, s));
+    }
+    HIP_TRY(hipEventRecord(ws->last, s));
+    for (uint32_t i = 0; i < count; ++i) {
+        const prngd_handle_t h = reqs[i].h;
+        if (reqs[i].n == 0)
+            continue;
+        h->parity ^= 1u;
+        h->last_event = ws->last;
+        h->last_stream = s;
+    }
+    return PRNGD_OK;
+}
+
 prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *stream)
 {
     if (!h)
@@ -1752,6 +2058,21 @@ prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *strea
         return st;
     if ((st = check_device_errors(d)) != PRNGD_OK)
         return st;
+    if (h->cfg.fam == FAM_RANMAR) {
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        Workspace *ws = nullptr;
+        if ((st = stream_workspace(h->device, s, &ws)) != PRNGD_OK)
+            return st;
+        if ((st = order_after(h, s)) != PRNGD_OK)
+            return st;
+        if ((st = ranmar_fill(d, h, n, out, ws, s)) != PRNGD_OK)
+            return st;
+        HIP_TRY(hipEventRecord(ws->last, s));
+        h->parity ^= 1u;
+        h->last_event = ws->last;
+        h->last_stream = s;
+        return PRNGD_OK;
+    }
     LaunchArgs args{};
     LaunchPlan lp{};
     if ((st = plan_launch(d, h->cfg, &args, &lp)) != PRNGD_OK)
@@ -1835,6 +2156,8 @@ prngd_status_t prngd_fill_noalloc(prngd_handle_t h, uint64_t n, double *out, voi
         return st;
     if (h->cfg.consume != PRNGD_CONSUME_PAIR)
         return fail(PRNGD_ERR_UNSUPPORTED, "prngd_fill_noalloc takes pair consumption only");
+    if (h->cfg.fam == FAM_RANMAR)
+        return fail(PRNGD_ERR_UNSUPPORTED, "prngd_fill_noalloc takes no RANMAR handles");
     Control *ctl = noalloc_control(h->device);
     uint64_t *status = noalloc_status(h->device);
     if (!ctl || !status)
@@ -1905,6 +2228,8 @@ static prngd_status_t fill_batch_impl(const prngd_request_t *reqs, uint32_t coun
     if ((st = check_device_errors(d)) != PRNGD_OK)
         return st;
     const Config cfg = reqs[0].h->cfg;
+    if (cfg.fam == FAM_RANMAR)
+        return ranmar_batch(d, reqs, count, static_cast<hipStream_t>(stream));
     LaunchArgs args{};
     LaunchPlan lp{};
     if ((st = plan_launch(d, cfg, &args, &lp)) != PRNGD_OK)
@@ -2006,6 +2331,8 @@ prngd_status_t prngd_plan_create(const prngd_request_t *reqs, uint32_t count,
     if (st != PRNGD_OK)
         return st;
     const Config cfg = reqs[0].h->cfg;
+    if (cfg.fam == FAM_RANMAR)
+        return fail(PRNGD_ERR_UNSUPPORTED, "RANMAR handles take no plans");
     std::unique_ptr<prngd_plan_s> p(new prngd_plan_s);
     p->device = dev;
     LaunchArgs args{};

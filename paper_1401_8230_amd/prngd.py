@@ -15,6 +15,7 @@ PHILOX4X32_10 = 0
 MRG32K3A = 1
 PHILOX_X1_MRG32K3A_X2 = 2
 ENUMERATE = 3
+RANMAR = 4
 
 MAP_EQ5 = 0
 MAP_EQ4 = 1
@@ -32,6 +33,7 @@ GENERATORS = {
     "mixed": PHILOX_X1_MRG32K3A_X2,
     "philox_x1_mrg32k3a_x2": PHILOX_X1_MRG32K3A_X2,
     "enumerate": ENUMERATE,
+    "ranmar": RANMAR,
 }
 
 M1 = 4294967087
@@ -109,6 +111,8 @@ _SIGNATURES = [
     ("prngd_set_consume", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("prngd_get_consume", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
     ("prngd_get_map", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
+    ("prngd_ranmar_state", ctypes.c_int,
+     [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32)]),
     ("prngd_set_arity", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     ("prngd_get_arity", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
     ("prngd_probe_write", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
@@ -186,6 +190,14 @@ def describe(generator, k, min, max):
                                 ctypes.byref(b0), ctypes.byref(b), ctypes.byref(D),
                                 ctypes.byref(S)))
     return {"w": w.value, "b0": b0.value, "b": b.value, "D": D.value, "S": S.value}
+
+
+def ranmar_state(seed, stream_id, pair_counter):
+    """The RANMAR state (L[W - 96 .. W], C[W]) of stream (seed, stream_id)
+    at word W = 2 pair_counter, host only: a list of 98 integers."""
+    out = (ctypes.c_uint32 * 98)()
+    _check(lib().prngd_ranmar_state(seed, stream_id, pair_counter, out))
+    return list(out)
 
 
 def _map(m):
