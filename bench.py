@@ -61,7 +61,8 @@ def parse():
                     help="timed step: the resident many-streams batch (default), or one "
                          "prngd_fill of --single-outputs outputs of one Philox stream")
     ap.add_argument("--single-outputs", type=int, default=1 << 30)
-    ap.add_argument("--generator", choices=["philox", "mrg32k3a", "mixed"], default="philox",
+    ap.add_argument("--generator", choices=["philox", "mrg32k3a", "mixed", "ranmar"],
+                    default="philox",
                     help="base generator of the single-stream workload (mixed: x1 from "
                          "Philox4x32-10, x2 from MRG32k3a)")
     ap.add_argument("--width", type=int, default=32,
@@ -158,7 +159,8 @@ def cpu_baseline_all_cores(streams, n_each, seed, max_threads=16):
 
 def cpu_baseline_single(n, seed, generator="philox", w=32):
     import oracle as O
-    gen = {"philox": O.GEN_PHILOX, "mrg32k3a": O.GEN_MRG32K3A, "mixed": O.GEN_MIXED}[generator]
+    gen = {"philox": O.GEN_PHILOX, "mrg32k3a": O.GEN_MRG32K3A, "mixed": O.GEN_MIXED,
+           "ranmar": O.GEN_RANMAR}[generator]
     t0 = time.perf_counter()
     O.PRNGD(gen, w, seed=seed, stream=0).fill(n)
     dt = time.perf_counter() - t0
@@ -264,7 +266,7 @@ def run_many_streams(args, result):
 
 
 GENERATOR_NAMES = {"philox": "Philox4x32-10", "mrg32k3a": "MRG32k3a",
-                   "mixed": "Philox4x32-10 (x1) and MRG32k3a (x2)"}
+                   "mixed": "Philox4x32-10 (x1) and MRG32k3a (x2)", "ranmar": "RANMAR"}
 
 
 def measured_leg_traffic(gen, w, n):
@@ -324,7 +326,7 @@ def single_leg(gen, w, n, steps, warmup, seed=42, map="eq5", consume="pair", cal
 
 # the single-stream legs of the default run: (generator, w, outputs per fill)
 SINGLE_LEGS = [("philox", 32, 1 << 30), ("mixed", 32, 1 << 28), ("mrg32k3a", 32, 1 << 28),
-               ("philox", 24, 1 << 28)]
+               ("philox", 24, 1 << 28), ("ranmar", 24, 1 << 28)]
 
 
 def run_single(args, result):

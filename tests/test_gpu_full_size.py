@@ -9,7 +9,8 @@ final position, at the sizes and in the launch forms the benchmark times.
   stream's start and from an odd (mid-block) start, each followed by a
   second fill that continues the stream;
 * one stream of 2^28 outputs (2 GiB): mixed Philox/MRG32k3a, MRG32k3a
-  alone, and Philox at w = 24 (x = u >> 8), two consecutive fills each;
+  alone, Philox at w = 24 (x = u >> 8; the counted form) and RANMAR (in
+  coarse segments through the jump table), two consecutive fills each;
 * the uneven batch: 4096 requests with sizes log-uniform in [1e3, 1e7]
   (about 4.5e9 outputs, 36 GB), each with its own seed, substream and
   start position, as a resident plan in every launch shape the autotuner
@@ -31,7 +32,8 @@ from paper_1401_8230_amd import autotune, prngd, workloads  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-OGEN = {"philox": O.GEN_PHILOX, "mrg32k3a": O.GEN_MRG32K3A, "mixed": O.GEN_MIXED}
+OGEN = {"philox": O.GEN_PHILOX, "mrg32k3a": O.GEN_MRG32K3A, "mixed": O.GEN_MIXED,
+        "ranmar": O.GEN_RANMAR}
 
 
 def release():
@@ -111,7 +113,8 @@ def test_single_philox_stream_2_30(start):
     long_stream("philox", 32, 1 << 30, start)
 
 
-@pytest.mark.parametrize("gen,w", [("mixed", 32), ("mrg32k3a", 32), ("philox", 24)])
+@pytest.mark.parametrize("gen,w", [("mixed", 32), ("mrg32k3a", 32), ("philox", 24),
+                                   ("ranmar", 24)])
 def test_single_stream_2_28(gen, w):
     long_stream(gen, w, 1 << 28, 0)
 
