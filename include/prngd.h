@@ -299,7 +299,10 @@ prngd_status_t prngd_get_consume(prngd_handle_t h, prngd_consume_t *consume);
  * The position then counts triples (prngd_set_position's pair_counter is a
  * triple counter; it is not converted).  Philox4x32-10 (any w) and the test
  * generator only, with PRNGD_MAP_EQ5 and PRNGD_CONSUME_PAIR; such handles
- * fill through the ordered kernels, in batches and plans too.  Handles of
+ * fill through the ordered kernels in batches and plans, and a single fill
+ * of at least 16384 triples counts the kept triples of every 4096-triple
+ * window, scans the counts and produces every window at its offset (path 1
+ * of prngd_set_tuning keeps the ordered kernels).  Handles of
  * one batch must share it.  Errors: PRNGD_ERR_INVALID_ARGUMENT (NULL
  * handle, words not 2 or 3, handle bound to a live plan),
  * PRNGD_ERR_UNSUPPORTED (another generator, map or consumption; setting a

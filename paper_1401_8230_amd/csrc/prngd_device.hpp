@@ -2768,6 +2768,44 @@ __global__ __launch_bounds__(256) void counted_produce_kernel(LaunchArgs args)
     }
 }
 
+// Counted fill of one long stream of triples: window k of the fill (T
+// triples on the stream's own grid; window 0 from the start position) is
+// one workgroup.  Without PRODUCE it counts the window's kept triples; with
+// it, after the scan of those counts, it produces the window at its exact
+// offset, and the fill's last window continues until n outputs.
+template <int NW, int G, uint32_t FAM, bool PRODUCE>
+__global__ __launch_bounds__(64 * NW) void counted_triple_kernel(LaunchArgs args)
+{
+    using Tile = TripleTile<NW, G, FAM>;
+    __shared__ uint32_t s_off[Tile::kOffWords];
+    const uint32_t k = blockIdx.x;
+    const TileStart ts = tile_start<true>(args, 0);
+    const Segment &seg = ts.seg;
+    const uint64_t w0 = ts.c0 / Tile::T;
+    const uint32_t lo0 = uint32_t(ts.c0 % Tile::T);
+    Tile tile;
+    if (!PRODUCE) {
+        const uint32_t kept = tile.generate(args, seg, (w0 + k) * Tile::T, k == 0 ? lo0 : 0u,
+                                            s_off);
+        if (threadIdx.x == 0)
+            args.chunk_counts[k] = kept;
+        return;
+    }
+    uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
+    uint64_t excl = __builtin_amdgcn_readfirstlane(args.block_offs[k / kScanBlock]) +
+                    __builtin_amdgcn_readfirstlane(args.chunk_offs[k]);
+    const bool last = k == args.total_tiles - 1;
+    uint32_t lo = k == 0 ? lo0 : 0u;
+    for (uint64_t w = w0 + k; uniform_lt(excl, seg.n); ++w, lo = 0u) {
+        const uint32_t kept = tile.generate(args, seg, w * Tile::T, lo, s_off);
+        tile.store(args, seg, w * Tile::T, excl, next_counter, s_off);
+        excl += kept;
+        if (!last)
+            break;
+        __syncthreads();                              // s_off is written again
+    }
+}
+
 // Whether chunk g (of the single segment) has to be produced again, and
 // at which true offset: the rules of needs_redo with chunk hints.
 template <uint32_t P>

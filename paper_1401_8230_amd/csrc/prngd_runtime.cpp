@@ -26,6 +26,7 @@ const void *spec_wave_kernel_for(uint32_t fam, bool repair, uint32_t windows);
 const void *single_kernel_for(uint32_t fam);
 const void *spec_words_kernel_for(uint32_t fam, bool repair);
 const void *triple_kernel_for(uint32_t fam, bool seq);
+const void *counted_triple_kernel_for(uint32_t fam, bool produce);
 const void *chunk_kernel_for(uint32_t fam, bool repair, uint32_t cpw);
 const void *chunk_prep_kernel_ptr();
 const void *counted_kernel_for(uint32_t fam, bool produce);
@@ -965,6 +966,7 @@ struct LaunchPlan {
     const void *chunk_repair_kernel;
     bool wave;                // single fills take the wave-granular form
     const void *counted_kernels[2];   // counted single fill: count, produce
+    bool counted_triples;     // ... of three words per output (one workgroup a window)
     bool counted;             // a single fill takes the counted form
     bool chunk;               // batches take the chunk-speculative form
     double expected_rejections;  // of the launch, as choose_path estimated
@@ -997,6 +999,8 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
         lp->tune.pairs_per_lane = 16;
         lp->kernel = triple_kernel_for(cfg.fam, false);
         lp->seq_kernel = triple_kernel_for(cfg.fam, true);
+        lp->counted_kernels[0] = counted_triple_kernel_for(cfg.fam, false);
+        lp->counted_kernels[1] = counted_triple_kernel_for(cfg.fam, true);
         if (!lp->kernel || !lp->seq_kernel)
             return fail(PRNGD_ERR_UNSUPPORTED, "three words per output: no kernel for this "
                                                "generator");
@@ -1035,9 +1039,12 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     lp->chunk_pairs = kChunkPairs * lp->chunk_windows;
     lp->chunk_kernel = two ? chunk_kernel_for(kfam, false, lp->chunk_windows) : nullptr;
     lp->chunk_repair_kernel = two ? chunk_kernel_for(kfam, true, lp->chunk_windows) : nullptr;
-    lp->counted_kernels[0] = two ? counted_kernel_for(kfam, false) : nullptr;
-    lp->counted_kernels[1] = two ? counted_kernel_for(kfam, true) : nullptr;
+    if (two) {
+        lp->counted_kernels[0] = counted_kernel_for(kfam, false);
+        lp->counted_kernels[1] = counted_kernel_for(kfam, true);
+    }
     lp->counted = false;
+    lp->counted_triples = false;
     lp->wave_kernel = two ? spec_wave_kernel_for(kfam, false, lp->chunk_windows) : nullptr;
     lp->wave_repair_kernel = two ? spec_wave_kernel_for(kfam, true, lp->chunk_windows) : nullptr;
     lp->wave = false;
@@ -1085,6 +1092,9 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
 // 655 us.
 constexpr uint64_t kCountedPairs = 512;
 constexpr double kCountedMinRejections = 2.0;
+// Triples a single fill of three words per output needs to take the counted
+// form (four windows of 4096).
+constexpr uint64_t kTripleCountedMin = 4 * 4096;
 
 // The longest request (planned pairs) the chunk form takes automatically:
 // its repair produces a dirty request again on one wave, about 0.2 us per
@@ -1112,6 +1122,16 @@ void choose_path(LaunchPlan *lp, const Config &c, uint64_t pairs, uint64_t longe
     lp->wave = false;
     lp->chunk = false;
     lp->counted = false;
+    lp->counted_triples = false;
+    // three words per output: a single fill of at least kTripleCountedMin
+    // triples is counted (path 1 keeps the ordered kernels)
+    if (c.arity == 3 && single && lp->tune.path != 1 && lp->counted_kernels[0] &&
+        lp->counted_kernels[1] && pairs >= kTripleCountedMin &&
+        pairs / lp->T + 2 <= uint64_t(kScanBlock) * kScanBlocksMax) {
+        lp->counted = true;
+        lp->counted_triples = true;
+        return;
+    }
     if (!lp->repair_kernel || lp->tune.path == 1 || c.consume == PRNGD_CONSUME_SINGLE)
         return;
     const double rho = 2.0 / double(c.a - c.a0 + 1);
@@ -1348,8 +1368,9 @@ prngd_status_t launch_chunk(DeviceInfo *d, const LaunchPlan &lp, Workspace *ws,
 prngd_status_t launch_counted(const LaunchPlan &lp, Workspace *ws, LaunchArgs args,
                               hipStream_t s)
 {
-    const uint64_t chunks =
-        std::max<uint64_t>(1, (args.seg0.planned + kCountedPairs - 1) / kCountedPairs);
+    // pairs per chunk of one wave, or triples per window of one workgroup
+    const uint64_t unit = lp.counted_triples ? lp.T : kCountedPairs;
+    const uint64_t chunks = std::max<uint64_t>(1, (args.seg0.planned + unit - 1) / unit);
     if (chunks > uint64_t(kScanBlock) * kScanBlocksMax)
         return fail(PRNGD_ERR_INVALID_ARGUMENT, "fill too large for the counted form");
     prngd_status_t st;
@@ -1361,7 +1382,7 @@ prngd_status_t launch_counted(const LaunchPlan &lp, Workspace *ws, LaunchArgs ar
     args.total_tiles = uint32_t(chunks);
     if (!args.flip)
         args.flip = lp.zero_word;
-    const uint32_t grid = uint32_t((chunks + 3) / 4);
+    const uint32_t grid = uint32_t(lp.counted_triples ? chunks : (chunks + 3) / 4);
     const uint32_t nblocks = uint32_t((chunks + kScanBlock - 1) / kScanBlock);
     HIP_TRY(launch_fill(lp.counted_kernels[0], grid, 256, args, s));
     HIP_TRY(launch_fill(counted_scan_kernel_ptr(false), nblocks, 1024, args, s));

@@ -11,6 +11,9 @@ with k' = k^3.  Cases:
   several windows;
 * every triple of the test generator at w = 4 (the whole grid, each value
   once);
+* single fills of at least 16384 triples in the counted form (and, for
+  comparison, in the ordered look-back), consecutive, from starts anywhere
+  in a 4096-triple window;
 * an uneven batch, its plan replayed twice, and consecutive fills;
 * 2^28 outputs at w = 24 and w = 17, every output and the final position;
 * the refusals of other generators, maps and consumption.
@@ -20,7 +23,7 @@ import pytest
 
 import oracle as O
 import oracle_parallel as OP
-from gpu_util import DEV, Arena, assert_device_bits_equal, note, upload
+from gpu_util import DEV, NAN_BITS, Arena, assert_device_bits_equal, note, upload
 
 torch = pytest.importorskip("torch")
 from paper_1401_8230_amd import prngd, workloads  # noqa: E402
@@ -43,6 +46,38 @@ def test_single_fill(w, counter, n):
     assert_device_bits_equal(out.data, upload([ref.fill(n)]), f"w={w}")
     assert g.get_position() == (9, ref.counter)
     g.close()
+
+
+@pytest.mark.parametrize("path", ["auto", "ordered"])
+@pytest.mark.parametrize("gen,w", [("philox", 3), ("philox", 8), ("philox", 17), ("philox", 24),
+                                   ("philox", 32), ("enumerate", 6)])
+def test_long_single_fills_counted_and_ordered(gen, w, path):
+    """Single fills of at least 16384 triples take the counted form (count
+    every 4096-triple window, scan, produce each at its offset; the last
+    window continues); path 1 keeps the ordered look-back.  Consecutive
+    fills from starts anywhere in a window, sizes around windows."""
+    ogen = {"philox": O.GEN_PHILOX, "enumerate": O.GEN_ENUMERATE}[gen]
+    for counter, sizes in [(0, [16384, 16385, 4096 * 5 + 3]), (4095, [100003, 20000]),
+                           (2**33 + 7, [1 << 20, 16384])]:
+        if gen == "enumerate" and counter > 2**30:
+            continue
+        prngd.set_tuning(gen, w, path=path)
+        g = prngd.Generator(33, gen, w=w, words=3)
+        g.set_position(4, counter)
+        ref = O.PRNGD(ogen, w, seed=33, stream=4, counter=counter, arity=3)
+        for i, n in enumerate(sizes):
+            note(f"triples {path} {gen} w={w} from {ref.counter} n={n}")
+            out = Arena([n + 2])
+            out.poison()
+            g.fill(out.views[0][:n])
+            torch.cuda.synchronize()
+            expect = ref.fill(n)
+            got = out.views[0].cpu().numpy()
+            assert np.array_equal(got[:n].view(np.uint64), expect.view(np.uint64)), f"fill {i}"
+            assert np.all(got[n:].view(np.uint64) == np.uint64(NAN_BITS)), "guard overwritten"
+            assert g.get_position() == (4, ref.counter), f"fill {i}"
+        g.close()
+        prngd.reset_tuning(gen, w)
 
 
 def test_every_triple_of_the_test_generator():
