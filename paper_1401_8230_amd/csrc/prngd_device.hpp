@@ -2148,22 +2148,24 @@ struct WaveChunk {
     using HiLo = typename SpecTile<4, 4, FAM>::HiLo;
 
     // Window `win` of 128 pairs: lane l holds pairs 2l and 2l + 1.  The
-    // window's first Philox block is a multiple of 64, so a lane's block
-    // index carries nothing into its high word.
+    // windows are counted from Philox block blk0 (pair 2 blk0): window w's
+    // first block is blk0 + 64 w.  With blk0 = 0 a lane's block index
+    // carries nothing into its high word.
     __device__ __forceinline__ static HiLo words(const LaunchArgs &args, const Segment &seg,
-                                                 uint64_t win, uint32_t lane)
+                                                 uint64_t win, uint32_t lane, uint64_t blk0 = 0)
     {
         uint32_t x1a, x2a, x1b, x2b;
         if (fam_base(FAM) == FAM_ENUM) {
-            const uint64_t q = win * kChunk + 2u * lane;
+            const uint64_t q = 2u * blk0 + win * kChunk + 2u * lane;
             const uint64_t mask = (uint64_t(1) << args.w) - 1;
             x1a = uint32_t((q >> args.w) & mask);
             x2a = uint32_t(q & mask);
             x1b = uint32_t(((q + 1) >> args.w) & mask);
             x2b = uint32_t((q + 1) & mask);
         } else {
-            const uint32_t blk_lo = uint32_t(win << 6) | lane;
-            const uint32_t blk_hi = uint32_t(win >> 26);
+            const uint64_t blk = blk0 + (win << 6) + lane;
+            const uint32_t blk_lo = uint32_t(blk);
+            const uint32_t blk_hi = uint32_t(blk >> 32);
             const Words4 r = philox4x32_10(blk_lo, blk_hi, 0u, seg.stream_id,
                                            uint32_t(seg.seed), uint32_t(seg.seed >> 32));
             if (fam_base(FAM) == FAM_PHILOX32) {
@@ -2188,11 +2190,11 @@ struct WaveChunk {
     __device__ __forceinline__ static uint32_t run(const LaunchArgs &args, const Segment &seg,
                                                    uint64_t win, uint32_t lo_off, uint64_t excl,
                                                    uint64_t *next_counter, bool store,
-                                                   bool full)
+                                                   bool full, uint64_t blk0 = 0)
     {
         const uint32_t lane = threadIdx.x & 63u;
-        return emit(args, seg, words(args, seg, win, lane), win * kChunk, lo_off, excl,
-                    next_counter, store, full);
+        return emit(args, seg, words(args, seg, win, lane, blk0), 2u * blk0 + win * kChunk,
+                    lo_off, excl, next_counter, store, full);
     }
 
     // The same for a window whose words the caller made: lane l holds
@@ -2329,7 +2331,7 @@ struct BatchChunk {
     template <int V>
     __device__ __forceinline__ static uint32_t store_windows(const LaunchArgs &args,
                                                              const Segment &seg, uint64_t ch,
-                                                             double *o)
+                                                             double *o, uint64_t blk0)
     {
         const uint32_t lane = threadIdx.x & 63u;
         const double tw = fam_base(FAM) == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
@@ -2338,7 +2340,7 @@ struct BatchChunk {
         uint32_t mx = 0;
 #pragma unroll
         for (uint32_t j = 0; j < NWIN; ++j) {
-            const auto p = WaveChunk<FAM>::words(args, seg, ch * NWIN + j, lane);
+            const auto p = WaveChunk<FAM>::words(args, seg, ch * NWIN + j, lane, blk0);
             mx = max(mx, max(p.ha, p.hb));
             const double za = map_hi_lo<FAM>(p.ha, p.la, tw, args);
             const double zb = map_hi_lo<FAM>(p.hb, p.lb, tw, args);
@@ -2365,18 +2367,19 @@ struct BatchChunk {
     // n - 1, stored at segment offset excl as if it rejected no pair;
     // returns whether that held.
     __device__ __forceinline__ static bool run_clean(const LaunchArgs &args, const Segment &seg,
-                                                     uint64_t ch, uint64_t excl)
+                                                     uint64_t ch, uint64_t excl,
+                                                     uint64_t blk0 = 0)
     {
         const uint32_t hm = fam_base(FAM) == FAM_PHILOX32 ? 0xFFFFFFFEu : args.a - args.a0 - 1u;
         double *o = seg.out + excl;
         const bool aligned = (reinterpret_cast<uintptr_t>(o) & 15u) == 0;
         uint32_t mx;
         if (args.store_mode != 1 && aligned)
-            mx = store_windows<0>(args, seg, ch, o);
+            mx = store_windows<0>(args, seg, ch, o, blk0);
         else if (args.store_mode != 1)
-            mx = store_windows<1>(args, seg, ch, o);
+            mx = store_windows<1>(args, seg, ch, o, blk0);
         else
-            mx = store_windows<2>(args, seg, ch, o);
+            mx = store_windows<2>(args, seg, ch, o, blk0);
         return __builtin_amdgcn_ballot_w64(mx >= hm) == 0;
     }
 
@@ -2389,7 +2392,8 @@ struct BatchChunk {
     __device__ __forceinline__ static uint32_t run_exact(const LaunchArgs &args,
                                                          const Segment &seg, uint64_t ch,
                                                          uint32_t lo_off, uint64_t excl,
-                                                         uint64_t *next_counter)
+                                                         uint64_t *next_counter,
+                                                         uint64_t blk0 = 0)
     {
         uint64_t running = excl;
         uint32_t kept = 0;
@@ -2401,7 +2405,7 @@ struct BatchChunk {
                 return P - lo_off;
             const uint32_t kj =
                 WaveChunk<FAM>::run(args, seg, ch * NWIN + j, lo_j, running, next_counter, store,
-                                    store && lo_j == 0 && chunk_fits(running, seg.n));
+                                    store && lo_j == 0 && chunk_fits(running, seg.n), blk0);
             running += kj;
             kept += kj;
         }
@@ -2554,7 +2558,9 @@ __global__ __launch_bounds__(64 * kRepairWaves) void chunk_repair_kernel(LaunchA
 
 // ======================================================================
 // Wave-granular speculative fill of one segment: the one-shot grid of its
-// chunks (NWIN windows of 128 pairs), one per wave.  A wave reads the
+// chunks (NWIN windows of 128 pairs), one per wave, counted from the fill's
+// start pair rounded down to even (so that an even start puts every chunk
+// before the first rejection on a cache line of the output).  A wave reads the
 // rejection list once at its start; chunk k stores at the offset that the
 // rejections published so far by chunks before it give (its hint,
 // recorded when nonzero, tagged with the launch epoch).  A chunk whose
@@ -2586,8 +2592,11 @@ __global__ __launch_bounds__(256) void spec_wave_kernel(LaunchArgs args)
     const TileStart ts = tile_start<true>(args, 0);
     const Segment &seg = ts.seg;
     uint64_t *next_counter = seg.counter + (ts.par ^ 1u);
-    const uint64_t w0 = ts.c0 / P;
-    const uint32_t lo0 = uint32_t(ts.c0 % P);
+    // chunks from the fill's start pair (rounded down to even, so that a
+    // lane's pairs are one Philox block): chunk k's outputs start at k P -
+    // lo0 less the rejections before it, on a cache line when lo0 = 0
+    const uint64_t blk0 = ts.c0 >> 1;
+    const uint32_t lo0 = uint32_t(ts.c0 & 1u);
     uint32_t used = 0;
     {
         const uint32_t et = uint32_t(entry >> 32);     // chunk + 1; 0 = none
@@ -2602,16 +2611,16 @@ __global__ __launch_bounds__(256) void spec_wave_kernel(LaunchArgs args)
                 args.hint64[k] = (args.epoch << 24) | used;
         }
     }
-    const uint64_t ch = w0 + k;
+    const uint64_t ch = k;
     const uint32_t lo_off = k == 0 ? lo0 : 0u;
     const uint64_t excl = (k == 0 ? 0 : uint64_t(k) * P - lo0) - used;
     uint32_t kept;
     if (lo_off == 0 && C::fits(excl, seg.n))
-        kept = C::run_clean(args, seg, ch, excl)
+        kept = C::run_clean(args, seg, ch, excl, blk0)
                    ? P
-                   : C::template run_exact<true>(args, seg, ch, 0u, excl, next_counter);
+                   : C::template run_exact<true>(args, seg, ch, 0u, excl, next_counter, blk0);
     else
-        kept = C::template run_exact<true>(args, seg, ch, lo_off, excl, next_counter);
+        kept = C::template run_exact<true>(args, seg, ch, lo_off, excl, next_counter, blk0);
     const uint32_t rej = (P - lo_off) - kept;
     if (rej != 0 && lane == 0) {
         const uint32_t slot = __hip_atomic_fetch_add(&args.spec->count, 1u, __ATOMIC_RELAXED,
@@ -2627,7 +2636,8 @@ __global__ __launch_bounds__(256) void spec_wave_kernel(LaunchArgs args)
     if (k == total - 1) {
         uint64_t running = excl + kept;
         for (uint64_t c2 = ch + 1; uniform_lt(running, seg.n); ++c2)
-            running += C::template run_exact<false>(args, seg, c2, 0u, running, next_counter);
+            running += C::template run_exact<false>(args, seg, c2, 0u, running, next_counter,
+                                                    blk0);
     }
 }
 
@@ -2866,8 +2876,8 @@ __global__ __launch_bounds__(256) void spec_wave_repair_kernel(LaunchArgs args)
     const uint32_t par = (seg.parity ^ flip) & 1u;
     const uint64_t c0 = load_start(seg, par);
     uint64_t *next_counter = seg.counter + (par ^ 1u);
-    const uint64_t w0 = c0 / P;
-    const uint32_t lo0 = uint32_t(c0 - w0 * P);
+    const uint64_t blk0 = c0 >> 1;                      // the chunk grid of the fill
+    const uint32_t lo0 = uint32_t(c0 & 1u);
     // each wave checks 64 chunks per pass, one per lane, spread over waves
     const uint64_t wid = blockIdx.x * 4u + (tid >> 6);
     const uint64_t W = uint64_t(gridDim.x) * 4u;
@@ -2884,11 +2894,11 @@ __global__ __launch_bounds__(256) void spec_wave_repair_kernel(LaunchArgs args)
             const uint64_t o = uint64_t(uint32_t(__shfl(uint32_t(off), l, 64))) |
                                uint64_t(uint32_t(__shfl(uint32_t(off >> 32), l, 64))) << 32;
             uint64_t running =
-                o + C::template run_exact<false>(args, seg, w0 + g, 0u, o, next_counter);
+                o + C::template run_exact<false>(args, seg, g, 0u, o, next_counter, blk0);
             if (g == total - 1)
-                for (uint64_t c2 = w0 + g + 1; uniform_lt(running, seg.n); ++c2)
+                for (uint64_t c2 = uint64_t(g) + 1; uniform_lt(running, seg.n); ++c2)
                     running += C::template run_exact<false>(args, seg, c2, 0u, running,
-                                                            next_counter);
+                                                            next_counter, blk0);
         }
     }
     __shared__ bool s_last;
