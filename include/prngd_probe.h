@@ -38,6 +38,14 @@ int prngd_probe_philox(uint32_t *sink, uint64_t sink_words, uint64_t blocks, voi
  * compaction or the cross-block scan. */
 int prngd_probe_philox_store(double *out, uint64_t n, void *stream);
 
+/* For tests of the stall path of the ordered look-back: the polls a
+ * look-back wait makes before it reports a stall, for launches planned
+ * after the call (0 restores the default, 2^20).  A small value makes
+ * waits that a correct launch would finish end early: that launch drains
+ * (every wait is bounded, its outputs are not defined) and the next call
+ * on the device returns PRNGD_ERR_DEVICE.  Host only; returns 0. */
+int prngd_probe_set_spin_limit(uint32_t polls);
+
 #ifdef __cplusplus
 }
 #endif

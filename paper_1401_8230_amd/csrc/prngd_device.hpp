@@ -271,11 +271,12 @@ __device__ __forceinline__ void publish(uint64_t *status, uint32_t g, uint64_t w
 // Exclusive output offset of tile g, the t-th tile of its segment, from the
 // status words of tiles g - t .. g - 1.  Run by one whole wave.  Status
 // words of another launch carry another epoch and read as "not ready".
-// The spin is bounded; a stall (impossible when every earlier tile is
-// running) raises the error word and the launch's abort flag, which makes
-// every other waiting tile and every idle workgroup give up at once.
+// The spin is bounded (`limit` polls); a stall (impossible when every
+// earlier tile is running and the limit is the default) raises the error
+// word and the launch's abort flag, which makes every other waiting tile
+// and every idle workgroup give up at once.
 __device__ inline uint64_t look_back(uint64_t *status, uint32_t g, uint32_t t, uint32_t epoch,
-                              Control *ctl, uint32_t *error, uint32_t lane)
+                              Control *ctl, uint32_t *error, uint32_t lane, uint32_t limit)
 {
     uint64_t excl = 0;
     uint32_t left = t;
@@ -305,7 +306,7 @@ __device__ inline uint64_t look_back(uint64_t *status, uint32_t g, uint32_t t, u
             if ((polls & 255u) == 0 &&
                 __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                 return excl;
-            if (polls > (1u << 20)) {
+            if (polls > limit) {
                 if (lane == 0) {
                     __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
@@ -1175,7 +1176,8 @@ __device__ __forceinline__ void lookback_loop(const LaunchArgs &args, Scratch &s
                 publish(args.status, ticket, pack_status(st.epoch, kFlagAggregate, agg));
             if (tid < 64) {
                 const uint64_t excl =
-                    look_back(args.status, ticket, t, st.epoch, args.ctl, args.error, lane);
+                    look_back(args.status, ticket, t, st.epoch, args.ctl, args.error, lane,
+                              args.spin_limit ? args.spin_limit : kSpinLimit);
                 if (tid == 0) {
                     publish(args.status, ticket, pack_status(st.epoch, kFlagPrefix, excl + agg));
                     sh.excl = excl;

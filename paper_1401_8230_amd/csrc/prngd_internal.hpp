@@ -160,7 +160,11 @@ struct LaunchArgs {
     // 2^24, then (2 g P * 7654321) mod 16777213) and the pairs P of a segment
     const uint32_t *ranmar_jump;
     uint32_t ranmar_seg_pairs;
+    uint32_t spin_limit;      // polls of a look-back wait before a stall (0: kSpinLimit)
 };
+
+// Polls of a look-back wait before it reports a stall.
+constexpr uint32_t kSpinLimit = 1u << 20;
 
 // RANMAR (Marsaglia, Zaman, Tsang 1990) in integer units of 2^-24: lagged
 // values L[n] = (L[n-97] - L[n-33]) mod 2^24, an arithmetic part C[n] =

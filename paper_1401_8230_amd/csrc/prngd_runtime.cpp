@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -17,6 +18,7 @@
 
 #include "../../include/prngd.h"
 #include "prngd_internal.hpp"
+#include "prngd_probe.h"
 
 namespace prngd {
 const void *fill_kernel_for(uint32_t fam, uint32_t threads, uint32_t ppl, bool seq);
@@ -54,6 +56,10 @@ namespace {
 
 // ----------------------------------------------------------------- errors
 thread_local std::string g_last_error;
+
+// Polls of a look-back wait before it reports a stall, for launches
+// planned from now on (0: the default); set by prngd_probe_set_spin_limit.
+std::atomic<uint32_t> g_spin_limit{0};
 
 prngd_status_t fail(prngd_status_t st, const char *fmt, ...)
 {
@@ -1053,6 +1059,7 @@ prngd_status_t plan_launch(DeviceInfo *d, const Config &cfg, LaunchArgs *args, L
     lp->zero_word = d->zero_word;
     lp->spec = false;                  // decided per launch by choose_path
     args->store_mode = lp->tune.store_mode;
+    args->spin_limit = g_spin_limit.load(std::memory_order_relaxed);
     args->w = cfg.w;
     args->a0 = uint32_t(cfg.a0);
     args->a = uint32_t(cfg.a);
@@ -1790,6 +1797,12 @@ prngd_status_t prngd_destroy(prngd_handle_t h)
     }
     delete h;
     return PRNGD_OK;
+}
+
+int prngd_probe_set_spin_limit(uint32_t polls)
+{
+    g_spin_limit.store(polls, std::memory_order_relaxed);
+    return 0;
 }
 
 prngd_status_t prngd_ranmar_state(uint64_t seed, uint32_t stream_id, uint64_t pair_counter,

@@ -120,6 +120,7 @@ _SIGNATURES = [
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     ("prngd_probe_philox", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]),
+    ("prngd_probe_set_spin_limit", ctypes.c_int, [ctypes.c_uint32]),
     ("prngd_probe_philox_store", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
 ]
@@ -461,6 +462,12 @@ def probe_copy(dst, src, stream=None):
 def probe_philox(sink, blocks, stream=None):
     """`blocks` Philox4x32-10 blocks folded into `sink` (int32 CUDA tensor)."""
     _probe(lib().prngd_probe_philox(sink.data_ptr(), sink.numel(), blocks, _stream_ptr(stream)))
+
+
+def probe_set_spin_limit(polls):
+    """Polls of a look-back wait before it reports a stall, for launches
+    planned from now on (0: the default).  For tests of the stall path."""
+    lib().prngd_probe_set_spin_limit(polls)
 
 
 def probe_philox_store(out, stream=None):
