@@ -51,8 +51,9 @@
  *       them on the host (x^n mod (x^97 + x^64 - 1), about a millisecond),
  *       and a long fill starts its segments by the same jump, from a table
  *       the library builds on the host once per size.  Pair consumption,
- *       two words per output, no plans and no prngd_fill_noalloc
- *       (PRNGD_ERR_UNSUPPORTED); any map.
+ *       two words per output, any map; resident plans of requests of at
+ *       most 32768 planned pairs; no prngd_fill_noalloc
+ *       (PRNGD_ERR_UNSUPPORTED for what is not offered).
  *
  * Conventions for every call:
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).

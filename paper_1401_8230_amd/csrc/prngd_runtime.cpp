@@ -2077,6 +2077,96 @@ static prngd_status_t ranmar_batch(DeviceInfo *d, const prngd_request_t *reqs, u
     return PRNGD_OK;
 }
 
+// A resident batch of RANMAR requests: one wave per request (each of at
+// most kRanmarWaveMax planned pairs), then the replay-parity toggle, in a
+// HIP graph.
+static prngd_status_t ranmar_plan_create(DeviceInfo *d, const prngd_request_t *reqs,
+                                         uint32_t count, prngd_plan_t *out_plan)
+{
+    std::unordered_set<prngd_handle_t> seen;
+    const prngd_handle_t first = reqs[0].h;
+    std::vector<Segment> segs;
+    std::unique_ptr<prngd_plan_s> p(new prngd_plan_s);
+    p->device = first->device;
+    for (uint32_t i = 0; i < count; ++i) {
+        const prngd_request_t &r = reqs[i];
+        if (!r.h)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "request %u has a NULL handle", i);
+        if (!seen.insert(r.h).second)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "handle of request %u repeats", i);
+        if (!same_config(r.h->cfg, first->cfg) || r.h->device != first->device)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT,
+                        "request %u: all handles of a batch must share generator, k, min, max",
+                        i);
+        if (r.h->plan)
+            return fail(PRNGD_ERR_INVALID_ARGUMENT, "request %u: handle bound to a plan", i);
+        if (r.n == 0)
+            continue;
+        if (planned_pairs(r.h->cfg, r.n, 0) > kRanmarWaveMax)
+            return fail(PRNGD_ERR_UNSUPPORTED,
+                        "request %u: RANMAR plans take requests of at most %llu planned pairs", i,
+                        (unsigned long long)kRanmarWaveMax);
+        Segment seg{};
+        uint64_t ntiles = 0;
+        prngd_status_t st = make_segment(r.h, r.n, r.out, kRanmarSegPairs[0], 0, 0, &seg, &ntiles);
+        if (st != PRNGD_OK)
+            return st;
+        seg.seed = reinterpret_cast<uint64_t>(r.h->rm);
+        segs.push_back(seg);
+        p->handles.push_back(r.h);
+    }
+    if (segs.empty())
+        return fail(PRNGD_ERR_INVALID_ARGUMENT, "a plan needs at least one request with n > 0");
+    prngd_status_t st = ws_init(&p->ws, p->device);
+    if (st != PRNGD_OK)
+        return st;
+    for (prngd_handle_t h : p->handles)
+        if (h->last_event)
+            HIP_TRY(hipEventSynchronize(h->last_event));
+    void *dp = nullptr;
+    HIP_TRY(hipMalloc(&dp, segs.size() * sizeof(Segment)));
+    p->dsegs = static_cast<Segment *>(dp);
+    HIP_TRY(hipMalloc(&dp, sizeof(uint32_t)));
+    p->flip = static_cast<uint32_t *>(dp);
+    HIP_TRY(hipMemcpy(p->dsegs, segs.data(), segs.size() * sizeof(Segment),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(p->flip, 0, sizeof(uint32_t)));
+    HIP_TRY(hipDeviceSynchronize());
+    p->spec = true;                          // no look-back status words to renew
+    p->lb_args = ranmar_args(d, first->cfg);
+    p->lb_args.segs = p->dsegs;
+    p->lb_args.nseg = uint32_t(segs.size());
+    p->lb_args.total_tiles = uint32_t(segs.size());
+    p->lb_args.flip = p->flip;
+    HIP_TRY(hipGraphCreate(&p->graph, 0));
+    hipKernelNodeParams kp{};
+    void *params[] = {&p->lb_args};
+    kp.func = const_cast<void *>(ranmar_kernel_for(ranmar_kfam(first->cfg), 0));
+    kp.gridDim = dim3(uint32_t((segs.size() + 3) / 4));
+    kp.blockDim = dim3(256);
+    kp.kernelParams = params;
+    hipGraphNode_t fill_node, toggle_node;
+    HIP_TRY(hipGraphAddKernelNode(&fill_node, p->graph, nullptr, 0, &kp));
+    uint32_t *flip = p->flip;
+    void *tparams[] = {&flip};
+    hipKernelNodeParams tp{};
+    tp.func = const_cast<void *>(toggle_flip_kernel_ptr());
+    tp.gridDim = dim3(1);
+    tp.blockDim = dim3(1);
+    tp.kernelParams = tparams;
+    HIP_TRY(hipGraphAddKernelNode(&toggle_node, p->graph, &fill_node, 1, &tp));
+    HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    p->ws.launches = 0;
+    for (size_t i = 0; i < p->handles.size(); ++i) {
+        prngd_handle_t h = p->handles[i];
+        p->base_parity.push_back(h->parity);
+        h->plan = p.get();
+        h->plan_index = i;
+    }
+    *out_plan = p.release();
+    return PRNGD_OK;
+}
+
 prngd_status_t prngd_fill(prngd_handle_t h, uint64_t n, double *out, void *stream)
 {
     if (!h)
@@ -2366,7 +2456,7 @@ prngd_status_t prngd_plan_create(const prngd_request_t *reqs, uint32_t count,
         return st;
     const Config cfg = reqs[0].h->cfg;
     if (cfg.fam == FAM_RANMAR)
-        return fail(PRNGD_ERR_UNSUPPORTED, "RANMAR handles take no plans");
+        return ranmar_plan_create(d, reqs, count, out_plan);
     std::unique_ptr<prngd_plan_s> p(new prngd_plan_s);
     p->device = dev;
     LaunchArgs args{};

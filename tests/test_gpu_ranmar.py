@@ -16,8 +16,9 @@ segments.  Cases:
 * the maps of Eq. (4) and 1 - z;
 * batches mixing one-wave requests and segmented ones, twice in a row, and
   handles made by prngd_create_many;
-* the refusals (plans, the allocation-free fill, one-word consumption,
-  three words per output).
+* a resident plan replayed three times, and fills after it;
+* the refusals (plans of long requests, the allocation-free fill, one-word
+  consumption, three words per output).
 """
 import numpy as np
 import pytest
@@ -150,11 +151,39 @@ def test_create_many_streams():
         g.close()
 
 
+def test_resident_plans():
+    reqs = workloads.uneven_batch(count=50, lo=1, hi=3e4, rng_seed=17)
+    gens, refs = [], []
+    for r in reqs:
+        g = prngd.Generator(r.seed, "ranmar", w=24)
+        g.set_position(r.stream_id, r.counter)
+        gens.append(g)
+        refs.append(O.PRNGD(O.GEN_RANMAR, 24, seed=r.seed, stream=r.stream_id, counter=r.counter))
+    outs = [torch.empty(r.n, dtype=torch.float64, device=DEV) for r in reqs]
+    plan = prngd.Plan(list(zip(gens, outs)))
+    for rep in range(3):
+        note(f"ranmar plan replay {rep}")
+        plan.launch()
+        torch.cuda.synchronize()
+        for i, (r, o) in enumerate(zip(reqs, outs)):
+            assert_bits_equal(o.cpu().numpy(), refs[i].fill(r.n), f"replay {rep} request {i}")
+            assert gens[i].get_position() == (r.stream_id, refs[i].counter), f"request {i}"
+    plan.close()
+    # the handles go on from where the plan left them
+    note("ranmar fills after the plan")
+    gens[0].fill(outs[0])
+    torch.cuda.synchronize()
+    assert_bits_equal(outs[0].cpu().numpy(), refs[0].fill(reqs[0].n), "after the plan")
+    for g in gens:
+        g.close()
+
+
 def test_refusals():
     g = prngd.Generator(1, "ranmar", w=24)
     out = torch.empty(10, dtype=torch.float64, device=DEV)
+    big = torch.empty(40000, dtype=torch.float64, device=DEV)
     with pytest.raises(prngd.PrngdError):
-        prngd.Plan([(g, out)])
+        prngd.Plan([(g, big)])                 # plans take requests of one wave
     with pytest.raises(prngd.PrngdError):
         g.fill_noalloc(out)
     with pytest.raises(prngd.PrngdError):
