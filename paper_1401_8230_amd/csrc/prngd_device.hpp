@@ -66,6 +66,35 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     return {c0, c1, c2, c3};
 }
 
+// The same function for arguments that are equal on every lane of a wave,
+// written with plain XORs (the three-way bitop exists only as a vector
+// instruction): the compiler keeps the whole block on the scalar unit,
+// which issues beside the vector work of the other waves.
+__device__ __forceinline__ Words4 philox4x32_10_uniform(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                       uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    c0 = __builtin_amdgcn_readfirstlane(c0);
+    c1 = __builtin_amdgcn_readfirstlane(c1);
+    c2 = __builtin_amdgcn_readfirstlane(c2);
+    c3 = __builtin_amdgcn_readfirstlane(c3);
+    k0 = __builtin_amdgcn_readfirstlane(k0);
+    k1 = __builtin_amdgcn_readfirstlane(k1);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = uint64_t(kPhiloxM0) * c0;
+        const uint64_t p1 = uint64_t(kPhiloxM1) * c2;
+        const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
+        c1 = uint32_t(p1);
+        c3 = uint32_t(p0);
+        c0 = n0;
+        c2 = n2;
+        k0 += kWeyl0;
+        k1 += kWeyl1;
+    }
+    return {c0, c1, c2, c3};
+}
+
 // -------------------------------------------------------------- MRG32k3a
 // L'Ecuyer 1999.  Moduli m1 = 2^32 - 209, m2 = 2^32 - 22853.  Reductions
 // fold the high word with 2^32 = c (mod m), as many times as the operand's
@@ -557,19 +586,58 @@ struct PhiloxTile {
         if (runs) {
             uint32_t a1[J], a2[J], b1[J], b2[J];
             const uint64_t run0 = blk0 + uint64_t(wave) * (64u * J);
+            // J blocks per lane on the vector unit and the block after the
+            // run, the same for every lane of the wave, on the scalar unit:
+            // its rounds are interleaved with the vector rounds so that they
+            // issue beside them
+            uint32_t c0[J], c1[J], c2[J], c3[J];
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 const uint64_t blk = run0 + uint32_t(j) * 64u + lane;
-                const Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u,
-                                               seg.stream_id, k0, k1);
-                a1[j] = r.v2;
-                a2[j] = r.v3;
-                b1[j] = r.v0;       // this block's first pair goes to the lane before
-                b2[j] = r.v1;
+                c0[j] = uint32_t(blk);
+                c1[j] = uint32_t(blk >> 32);
+                c2[j] = 0u;
+                c3[j] = seg.stream_id;
             }
             const uint64_t nb = run0 + 64u * J;
-            const Words4 rn = philox4x32_10(uint32_t(nb), uint32_t(nb >> 32), 0u, seg.stream_id,
-                                            k0, k1);
+            uint32_t u0 = __builtin_amdgcn_readfirstlane(uint32_t(nb));
+            uint32_t u1 = __builtin_amdgcn_readfirstlane(uint32_t(nb >> 32));
+            uint32_t u2 = 0u;
+            uint32_t u3 = __builtin_amdgcn_readfirstlane(seg.stream_id);
+            uint32_t r0 = __builtin_amdgcn_readfirstlane(k0);
+            uint32_t r1 = __builtin_amdgcn_readfirstlane(k1);
+#pragma unroll
+            for (int r = 0; r < 10; ++r) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const uint64_t p0 = uint64_t(kPhiloxM0) * c0[j];
+                    const uint64_t p1 = uint64_t(kPhiloxM1) * c2[j];
+                    const uint32_t n0 = __builtin_amdgcn_bitop3_b32(uint32_t(p1 >> 32), c1[j], r0, 0x96);
+                    const uint32_t n2 = __builtin_amdgcn_bitop3_b32(uint32_t(p0 >> 32), c3[j], r1, 0x96);
+                    c1[j] = uint32_t(p1);
+                    c3[j] = uint32_t(p0);
+                    c0[j] = n0;
+                    c2[j] = n2;
+                }
+                const uint64_t q0 = uint64_t(kPhiloxM0) * u0;
+                const uint64_t q1 = uint64_t(kPhiloxM1) * u2;
+                const uint32_t m0 = uint32_t(q1 >> 32) ^ u1 ^ r0;
+                const uint32_t m2 = uint32_t(q0 >> 32) ^ u3 ^ r1;
+                u1 = uint32_t(q1);
+                u3 = uint32_t(q0);
+                u0 = m0;
+                u2 = m2;
+                r0 += kWeyl0;
+                r1 += kWeyl1;
+            }
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                a1[j] = c2[j];
+                a2[j] = c3[j];
+                b1[j] = c0[j];      // this block's first pair goes to the lane before
+                b2[j] = c1[j];
+            }
+            const Words4 rn{u0, u1, u2, u3};
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 uint32_t n1 = uint32_t(__shfl_down(int(b1[j]), 1u, 64));
