@@ -95,6 +95,45 @@ __device__ __forceinline__ Words4 philox4x32_10_uniform(uint32_t c0, uint32_t c1
     return {c0, c1, c2, c3};
 }
 
+// A block per lane (counter c) and a block that is the same on every lane
+// of the wave (counter u), with the rounds of the second on the scalar unit
+// interleaved with those of the first so that the two issue side by side.
+__device__ __forceinline__ void philox4x32_10_lane_and_uniform(const Words4 c, Words4 u,
+                                                               uint32_t k0, uint32_t k1,
+                                                               Words4 *rc, Words4 *ru)
+{
+    uint32_t c0 = c.v0, c1 = c.v1, c2 = c.v2, c3 = c.v3;
+    uint32_t u0 = __builtin_amdgcn_readfirstlane(u.v0);
+    uint32_t u1 = __builtin_amdgcn_readfirstlane(u.v1);
+    uint32_t u2 = __builtin_amdgcn_readfirstlane(u.v2);
+    uint32_t u3 = __builtin_amdgcn_readfirstlane(u.v3);
+    k0 = __builtin_amdgcn_readfirstlane(k0);
+    k1 = __builtin_amdgcn_readfirstlane(k1);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = uint64_t(kPhiloxM0) * c0;
+        const uint64_t p1 = uint64_t(kPhiloxM1) * c2;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(uint32_t(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(uint32_t(p0 >> 32), c3, k1, 0x96);
+        c1 = uint32_t(p1);
+        c3 = uint32_t(p0);
+        c0 = n0;
+        c2 = n2;
+        const uint64_t q0 = uint64_t(kPhiloxM0) * u0;
+        const uint64_t q1 = uint64_t(kPhiloxM1) * u2;
+        const uint32_t m0 = uint32_t(q1 >> 32) ^ u1 ^ k0;
+        const uint32_t m2 = uint32_t(q0 >> 32) ^ u3 ^ k1;
+        u1 = uint32_t(q1);
+        u3 = uint32_t(q0);
+        u0 = m0;
+        u2 = m2;
+        k0 += kWeyl0;
+        k1 += kWeyl1;
+    }
+    *rc = Words4{c0, c1, c2, c3};
+    *ru = Words4{u0, u1, u2, u3};
+}
+
 // -------------------------------------------------------------- MRG32k3a
 // L'Ecuyer 1999.  Moduli m1 = 2^32 - 209, m2 = 2^32 - 22853.  Reductions
 // fold the high word with 2^32 = c (mod m), as many times as the operand's
@@ -857,15 +896,28 @@ struct SpecTile {
             x2b = uint32_t((q + 1) & mask);
         } else {
             const uint64_t blk = (wb >> 1) + uint32_t(j) * B + tid;
-            Words4 r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u, seg.stream_id,
-                                     uint32_t(seg.seed), uint32_t(seg.seed >> 32));
+            const uint32_t k0 = uint32_t(seg.seed), k1 = uint32_t(seg.seed >> 32);
+            Words4 r;
             if (wb & 1u) {
                 // the window starts on a block's second pair: this thread's
-                // pairs are its block's second and the next block's first
-                const Words4 nx = philox4x32_10(uint32_t(blk + 1), uint32_t((blk + 1) >> 32), 0u,
-                                                seg.stream_id, uint32_t(seg.seed),
-                                                uint32_t(seg.seed >> 32));
-                r = Words4{r.v2, r.v3, nx.v0, nx.v1};
+                // pairs are its block's second and the next block's first,
+                // which lane + 1 computes; for lane 63 that is the block
+                // opening the next wave's slot, the same for the whole wave
+                // (all lanes must be here for the shuffle)
+                const uint64_t nb = (wb >> 1) + uint32_t(j) * B + 64u * ((tid >> 6) + 1u);
+                Words4 u;
+                philox4x32_10_lane_and_uniform(
+                    Words4{uint32_t(blk), uint32_t(blk >> 32), 0u, seg.stream_id},
+                    Words4{uint32_t(nb), uint32_t(nb >> 32), 0u, seg.stream_id}, k0, k1, &r, &u);
+                uint32_t n0 = uint32_t(__shfl_down(int(r.v0), 1u, 64));
+                uint32_t n1 = uint32_t(__shfl_down(int(r.v1), 1u, 64));
+                if ((tid & 63u) == 63u) {
+                    n0 = u.v0;
+                    n1 = u.v1;
+                }
+                r = Words4{r.v2, r.v3, n0, n1};
+            } else {
+                r = philox4x32_10(uint32_t(blk), uint32_t(blk >> 32), 0u, seg.stream_id, k0, k1);
             }
             if (fam_base(FAM) == FAM_PHILOX32) {
                 x1a = r.v0; x2a = r.v1; x1b = r.v2; x2b = r.v3;
@@ -1027,8 +1079,8 @@ struct SpecTile {
             const uint32_t pos_a = s_off[j * NW + wave] +
                                    uint32_t(__popcll(ba & lt) + __popcll(bb & lt));
             const uint32_t pos_b = pos_a + (oka ? 1u : 0u);
+            const HiLo p = words(args, seg, wb, j);    // every lane: words() may shuffle
             if (oka || okb) {
-                const HiLo p = words(args, seg, wb, j);
                 const double za = map_hi_lo<FAM>(p.ha, p.la, tw, args);
                 const double zb = map_hi_lo<FAM>(p.hb, p.lb, tw, args);
                 if (oka && pos_a < left)
