@@ -66,35 +66,6 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     return {c0, c1, c2, c3};
 }
 
-// The same function for arguments that are equal on every lane of a wave,
-// written with plain XORs (the three-way bitop exists only as a vector
-// instruction): the compiler keeps the whole block on the scalar unit,
-// which issues beside the vector work of the other waves.
-__device__ __forceinline__ Words4 philox4x32_10_uniform(uint32_t c0, uint32_t c1, uint32_t c2,
-                                                       uint32_t c3, uint32_t k0, uint32_t k1)
-{
-    c0 = __builtin_amdgcn_readfirstlane(c0);
-    c1 = __builtin_amdgcn_readfirstlane(c1);
-    c2 = __builtin_amdgcn_readfirstlane(c2);
-    c3 = __builtin_amdgcn_readfirstlane(c3);
-    k0 = __builtin_amdgcn_readfirstlane(k0);
-    k1 = __builtin_amdgcn_readfirstlane(k1);
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = uint64_t(kPhiloxM0) * c0;
-        const uint64_t p1 = uint64_t(kPhiloxM1) * c2;
-        const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
-        c1 = uint32_t(p1);
-        c3 = uint32_t(p0);
-        c0 = n0;
-        c2 = n2;
-        k0 += kWeyl0;
-        k1 += kWeyl1;
-    }
-    return {c0, c1, c2, c3};
-}
-
 // A block per lane (counter c) and a block that is the same on every lane
 // of the wave (counter u), with the rounds of the second on the scalar unit
 // interleaved with those of the first so that the two issue side by side.
@@ -2802,68 +2773,6 @@ __global__ __launch_bounds__(256) void counted_count_kernel(LaunchArgs args)
     }
     if (lane == 0)
         args.chunk_counts[k] = kept;
-}
-
-// Level 1: workgroup b scans the counts of chunks [b B, (b + 1) B)
-// (B = kScanBlock, 4 per thread), writes each chunk's offset in its block
-// and the block's total to block_offs[b].
-__global__ __launch_bounds__(1024) void counted_scan_blocks_kernel(LaunchArgs args)
-{
-    __shared__ uint32_t s_wave[16];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    const uint32_t total = args.total_tiles;
-    const uint64_t c0 = uint64_t(blockIdx.x) * kScanBlock + 4u * tid;
-    uint32_t v[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        v[i] = c0 + uint32_t(i) < total ? args.chunk_counts[c0 + i] : 0u;
-    const uint32_t mine = v[0] + v[1] + v[2] + v[3];
-    const uint32_t incl = wave_incl_scan(mine, lane);
-    if (lane == 63)
-        s_wave[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0, sum = 0;
-#pragma unroll
-    for (uint32_t w = 0; w < 16; ++w) {
-        const uint32_t t = s_wave[w];
-        before += w < wave ? t : 0u;
-        sum += t;
-    }
-    uint32_t run = before + incl - mine;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        if (c0 + uint32_t(i) < total)
-            args.chunk_offs[c0 + i] = run;
-        run += v[i];
-    }
-    if (tid == 0)
-        args.block_offs[blockIdx.x] = sum;
-}
-
-// Level 2: one workgroup turns the block totals (at most kScanBlocksMax)
-// into exclusive offsets, in place.
-__global__ __launch_bounds__(1024) void counted_scan_top_kernel(LaunchArgs args)
-{
-    __shared__ uint64_t s_wave[16];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    const uint32_t nblocks = (args.total_tiles + kScanBlock - 1) / kScanBlock;
-    const uint64_t mine = tid < nblocks ? args.block_offs[tid] : 0u;
-    uint64_t incl = mine;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint64_t u = uint64_t(uint32_t(__shfl_up(uint32_t(incl), d, 64))) |
-                           uint64_t(uint32_t(__shfl_up(uint32_t(incl >> 32), d, 64))) << 32;
-        if (lane >= uint32_t(d))
-            incl += u;
-    }
-    if (lane == 63)
-        s_wave[wave] = incl;
-    __syncthreads();
-    uint64_t before = 0;
-    for (uint32_t w = 0; w < wave; ++w)
-        before += s_wave[w];
-    if (tid < nblocks)
-        args.block_offs[tid] = before + incl - mine;
 }
 
 template <uint32_t FAM>

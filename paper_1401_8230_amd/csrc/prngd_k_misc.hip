@@ -8,6 +8,69 @@
 namespace prngd {
 namespace {
 
+// The two-level scan of the counted single fill.
+// Level 1: workgroup b scans the counts of chunks [b B, (b + 1) B)
+// (B = kScanBlock, 4 per thread), writes each chunk's offset in its block
+// and the block's total to block_offs[b].
+__global__ __launch_bounds__(1024) void counted_scan_blocks_kernel(LaunchArgs args)
+{
+    __shared__ uint32_t s_wave[16];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t total = args.total_tiles;
+    const uint64_t c0 = uint64_t(blockIdx.x) * kScanBlock + 4u * tid;
+    uint32_t v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        v[i] = c0 + uint32_t(i) < total ? args.chunk_counts[c0 + i] : 0u;
+    const uint32_t mine = v[0] + v[1] + v[2] + v[3];
+    const uint32_t incl = wave_incl_scan(mine, lane);
+    if (lane == 63)
+        s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, sum = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < 16; ++w) {
+        const uint32_t t = s_wave[w];
+        before += w < wave ? t : 0u;
+        sum += t;
+    }
+    uint32_t run = before + incl - mine;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (c0 + uint32_t(i) < total)
+            args.chunk_offs[c0 + i] = run;
+        run += v[i];
+    }
+    if (tid == 0)
+        args.block_offs[blockIdx.x] = sum;
+}
+
+// Level 2: one workgroup turns the block totals (at most kScanBlocksMax)
+// into exclusive offsets, in place.
+__global__ __launch_bounds__(1024) void counted_scan_top_kernel(LaunchArgs args)
+{
+    __shared__ uint64_t s_wave[16];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t nblocks = (args.total_tiles + kScanBlock - 1) / kScanBlock;
+    const uint64_t mine = tid < nblocks ? args.block_offs[tid] : 0u;
+    uint64_t incl = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t u = uint64_t(uint32_t(__shfl_up(uint32_t(incl), d, 64))) |
+                           uint64_t(uint32_t(__shfl_up(uint32_t(incl >> 32), d, 64))) << 32;
+        if (lane >= uint32_t(d))
+            incl += u;
+    }
+    if (lane == 63)
+        s_wave[wave] = incl;
+    __syncthreads();
+    uint64_t before = 0;
+    for (uint32_t w = 0; w < wave; ++w)
+        before += s_wave[w];
+    if (tid < nblocks)
+        args.block_offs[tid] = before + incl - mine;
+}
+
 // Toggles a resident plan's replay parity after all of a replay's fills.
 __global__ void toggle_flip_kernel(uint32_t *flip)
 {
