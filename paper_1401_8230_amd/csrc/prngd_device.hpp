@@ -230,6 +230,19 @@ __device__ __forceinline__ double wave_shr1(double v)
     return __builtin_bit_cast(double, uint64_t(hi) << 32 | lo);
 }
 
+// Lane i receives lane i + 1's value and lane 63 keeps `fill`: one DPP
+// wave_shl:1 move whose invalid source lane leaves the old value in place.
+__device__ __forceinline__ uint32_t wave_shl1_fill(uint32_t v, uint32_t fill)
+{
+    return uint32_t(__builtin_amdgcn_update_dpp(int(fill), int(v), 0x130, 0xF, 0xF, false));
+}
+
+// Lane i receives lane i + 1's value, lane 63 lane 0's (DPP wave_rol:1).
+__device__ __forceinline__ uint32_t wave_rol1(uint32_t v)
+{
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x134, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt(uint32_t lane)
 {
     return (uint64_t(1) << lane) - 1;
@@ -648,30 +661,39 @@ struct PhiloxTile {
                 b2[j] = c1[j];
             }
             const Words4 rn{u0, u1, u2, u3};
+            // each lane's second pair is lane + 1's first; lane 63's is lane
+            // 0's of the next slot (a rotation leaves it in lane 63) or the
+            // first pair of the block after the run
 #pragma unroll
             for (int j = 0; j < J; ++j) {
-                uint32_t n1 = uint32_t(__shfl_down(int(b1[j]), 1u, 64));
-                uint32_t n2 = uint32_t(__shfl_down(int(b2[j]), 1u, 64));
-                const uint32_t l1 = j + 1 < J ? uint32_t(__builtin_amdgcn_readlane(int(b1[j + 1 < J ? j + 1 : j]), 0)) : rn.v0;
-                const uint32_t l2 = j + 1 < J ? uint32_t(__builtin_amdgcn_readlane(int(b2[j + 1 < J ? j + 1 : j]), 0)) : rn.v1;
-                if (lane == 63) {
-                    n1 = l1;
-                    n2 = l2;
-                }
-                b1[j] = n1;
-                b2[j] = n2;
+                const uint32_t f1 = j + 1 < J ? wave_rol1(b1[j + 1 < J ? j + 1 : j]) : rn.v0;
+                const uint32_t f2 = j + 1 < J ? wave_rol1(b2[j + 1 < J ? j + 1 : j]) : rn.v1;
+                b1[j] = wave_shl1_fill(b1[j], f1);
+                b2[j] = wave_shl1_fill(b2[j], f2);
             }
-            const uint32_t shift = fam_base(FAM) == FAM_PHILOX32 ? 0u : 32u - args.w;
-            const double two_w = fam_base(FAM) == FAM_PHILOX32 ? 4294967296.0 : double(uint64_t(1) << args.w);
+            if (fam_base(FAM) == FAM_PHILOX32) {
+                // x in [0, 2^32 - 1]: as for windows on a block boundary
 #pragma unroll
-            for (int j = 0; j < J; ++j) {
-                const uint32_t x1a = a1[j] >> shift, x2a = a2[j] >> shift;
-                const uint32_t x1b = b1[j] >> shift, x2b = b2[j] >> shift;
-                const bool oka = x1a != args.a0 && x1a != args.a;
-                const bool okb = x1b != args.a0 && x1b != args.a;
-                v[2 * j] = prngd_map<FAM>(x1a, x2a, args, two_w);
-                v[2 * j + 1] = prngd_map<FAM>(x1b, x2b, args, two_w);
-                acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
+                for (int j = 0; j < J; ++j) {
+                    const bool oka = a1[j] + 1u >= 2u;
+                    const bool okb = b1[j] + 1u >= 2u;
+                    v[2 * j] = map_hi_lo<FAM>(a1[j] - 1u, a2[j], 4294967296.0, args);
+                    v[2 * j + 1] = map_hi_lo<FAM>(b1[j] - 1u, b2[j], 4294967296.0, args);
+                    acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
+                }
+            } else {
+                const uint32_t shift = 32u - args.w;
+                const double two_w = double(uint64_t(1) << args.w);
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const uint32_t x1a = a1[j] >> shift, x2a = a2[j] >> shift;
+                    const uint32_t x1b = b1[j] >> shift, x2b = b2[j] >> shift;
+                    const bool oka = x1a != args.a0 && x1a != args.a;
+                    const bool okb = x1b != args.a0 && x1b != args.a;
+                    v[2 * j] = prngd_map<FAM>(x1a, x2a, args, two_w);
+                    v[2 * j + 1] = prngd_map<FAM>(x1b, x2b, args, two_w);
+                    acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
+                }
             }
         } else if (fam_base(FAM) == FAM_PHILOX32) {
             // x in [0, 2^32 - 1]: keep x1 unless x1 + 1 wraps to 0 or is 1
