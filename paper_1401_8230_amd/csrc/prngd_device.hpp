@@ -966,6 +966,70 @@ struct SpecTile {
         return kept;
     }
 
+    // Window `wb` produced exactly (from window offset lo_off on) at segment
+    // offset excl, writing nothing but its own outputs; returns its number
+    // of accepted pairs.  The words are generated once and kept in
+    // registers for the ranks and the stores (4 J registers, so only for
+    // up to 8 slots).
+    __device__ __forceinline__ uint32_t run_exact(const LaunchArgs &args, const Segment &seg,
+                                                  uint64_t wb, uint32_t lo_off, uint64_t excl,
+                                                  uint64_t *next_counter, uint32_t *s_off)
+    {
+        const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+        double *o = seg.out + excl;
+        const uint64_t left = seg.n - excl;   // outputs still wanted, >= 1
+        const uint32_t hm = hmax(args);
+        const double tw = two_w(args);
+        HiLo ps[J];
+        uint32_t acc = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint32_t q = 2u * (uint32_t(j) * B + tid);
+            ps[j] = words(args, seg, wb, j);
+            const bool oka = ps[j].ha < hm && q >= lo_off;
+            const bool okb = ps[j].hb < hm && q + 1 >= lo_off;
+            acc |= (uint32_t(oka) << (2 * j)) | (uint32_t(okb) << (2 * j + 1));
+        }
+        __syncthreads();                      // earlier readers of s_off are done
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint64_t ba = __ballot((acc >> (2 * j)) & 1u);
+            const uint64_t bb = __ballot((acc >> (2 * j + 1)) & 1u);
+            if (lane == 0)
+                s_off[j * NW + wave] = uint32_t(__popcll(ba) + __popcll(bb));
+        }
+        __syncthreads();
+        if (wave == 0)
+            wave0_scan<E>(s_off, lane);
+        __syncthreads();
+        const uint64_t lt = lanemask_lt(lane);
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const bool oka = (acc >> (2 * j)) & 1u;
+            const bool okb = (acc >> (2 * j + 1)) & 1u;
+            const uint64_t ba = __ballot(oka), bb = __ballot(okb);
+            const uint32_t pos_a = s_off[j * NW + wave] +
+                                   uint32_t(__popcll(ba & lt) + __popcll(bb & lt));
+            const uint32_t pos_b = pos_a + (oka ? 1u : 0u);
+            if (oka || okb) {
+                const double za = map_hi_lo<FAM>(ps[j].ha, ps[j].la, tw, args);
+                const double zb = map_hi_lo<FAM>(ps[j].hb, ps[j].lb, tw, args);
+                if (oka && pos_a < left)
+                    store_one(o + pos_a, za, args.store_mode);
+                if (okb && pos_b < left)
+                    store_one(o + pos_b, zb, args.store_mode);
+            }
+            const uint32_t q = 2u * (uint32_t(j) * B + tid);
+            if (oka && pos_a + 1 == left)
+                *next_counter = wb + q + 1;
+            if (okb && pos_b + 1 == left)
+                *next_counter = wb + q + 2;
+        }
+        const uint32_t total = uniform_u32(s_off[E]);
+        __syncthreads();
+        return total;
+    }
+
     // Produce window `wb` (from window offset lo_off on) at segment offset
     // excl; returns the window's number of accepted pairs.  With kSpec the
     // pairs are stored as they are generated (a window that turns out not
@@ -977,6 +1041,8 @@ struct SpecTile {
                                             uint64_t wb, uint32_t lo_off, uint64_t excl,
                                             uint64_t *next_counter, uint32_t *s_off)
     {
+        if constexpr (!kSpec && J <= 8)
+            return run_exact(args, seg, wb, lo_off, excl, next_counter, s_off);
         const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
         const uint64_t n = seg.n;
         double *o = seg.out + excl;
